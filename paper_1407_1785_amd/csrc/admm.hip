@@ -1,0 +1,153 @@
+// Small kernels of the ADMM drivers: the per-iteration control step, the
+// data norm of the stopping rule, the completion output and fills.
+//
+// Control step (one workgroup per problem), after the fused epilogue has
+// written its FP64 residual partial sums:
+//   primal = sqrt(sum p0), change = sqrt(sum p1) (completion) or
+//   max(sqrt(sum p1), sqrt(sum p2)) (RPCA);
+//   stop when max(primal, change) <= tol * ||data||_F;
+//   otherwise rho' = min(growth * rho, rho_max) and the stored dual is read
+//   as (rho / rho') times its value from then on (scaled-dual ADMM with a
+//   penalty schedule; the completion recursion of Sec. 4 and the RPCA
+//   recursion of Sec. 5 keep rho fixed, the growth is the workloads').
+// The partial sums are reduced in a fixed order, so a run is deterministic.
+
+#include "kernels.h"
+
+namespace tsvd {
+
+namespace {
+
+__device__ double block_sum_fixed(const double* p, int nparts, int stride, int c, double* scratch) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) s += p[(int64_t)i * stride + c];
+    scratch[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) scratch[threadIdx.x] += scratch[threadIdx.x + w];
+        __syncthreads();
+    }
+    const double r = scratch[0];
+    __syncthreads();
+    return r;
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(kBlock) void admm_ctrl_kernel(Ctrl* c, const double* partials, int nparts,
+                                                          int rpca) {
+    __shared__ double scratch[kBlock];
+    const double p0 = block_sum_fixed(partials, nparts, kNumPartials, 0, scratch);
+    const double p1 = block_sum_fixed(partials, nparts, kNumPartials, 1, scratch);
+    const double p2 = block_sum_fixed(partials, nparts, kNumPartials, 2, scratch);
+    if (threadIdx.x != 0) return;
+    const double primal = sqrt(p0);
+    const double change = rpca ? fmax(sqrt(p1), sqrt(p2)) : sqrt(p1);
+    c->primal = primal;
+    c->change = change;
+    c->iter += 1;
+    c->rho_used = c->rho;
+    c->dscale_used = c->dscale;
+    if (!isfinite(primal) || !isfinite(change)) {
+        c->nonfinite = 1;
+        c->done = 1;
+        return;
+    }
+    if (fmax(primal, change) <= c->tol_abs) {
+        c->done = 1;
+        c->dscale = 1.0;   // a converged solve keeps the dual unscaled
+        return;
+    }
+    const double rho = c->rho;
+    const double next = fmin(c->growth * rho, c->rho_max);
+    c->dscale = rho / next;
+    c->rho = next;
+    c->tau = 1.0 / next;
+    c->shrink = c->lambda / next;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void sumsq_kernel(const T* x, const uint8_t* mask, int64_t n,
+                                                      double* partials) {
+    __shared__ double scratch[kBlock];
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double v = (mask == nullptr || mask[i]) ? (double)x[i] : 0.0;
+        s += v * v;
+    }
+    scratch[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) scratch[threadIdx.x] += scratch[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[(int64_t)blockIdx.x * kNumPartials] = scratch[0];
+}
+
+__global__ __launch_bounds__(kBlock) void set_tol_kernel(Ctrl* c, const double* partials, int nparts,
+                                                        double tol) {
+    __shared__ double scratch[kBlock];
+    const double s = block_sum_fixed(partials, nparts, kNumPartials, 0, scratch);
+    if (threadIdx.x == 0) c->tol_abs = tol * sqrt(s);
+}
+
+// X = Omega.Y + (1 - Omega).(Z - Q) with Q = dscale_used * stored dual
+template <typename T>
+__global__ __launch_bounds__(kBlock) void complete_output_kernel(const T* y, const uint8_t* mask,
+                                                                const T* z, const T* dual,
+                                                                const Ctrl* c, T* out, int64_t n) {
+    const double ds = c->dscale_used;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const T q = (T)(ds * (double)dual[i]);
+        out[i] = mask[i] ? y[i] : (T)(z[i] - q);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void fill_kernel(T* p, T v, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+static int grid_for(int64_t n) {
+    const int64_t g = (n + kBlock - 1) / kBlock;
+    return (int)(g < 2048 ? (g < 1 ? 1 : g) : 2048);
+}
+
+void launch_admm_ctrl(Ctrl* c, const double* partials, int nparts, int rpca, hipStream_t st) {
+    hipLaunchKernelGGL(admm_ctrl_kernel, dim3(1), dim3(kBlock), 0, st, c, partials, nparts, rpca);
+}
+
+template <typename T>
+void launch_sumsq(const T* x, const uint8_t* mask, int64_t n, double* partials, int nparts,
+                  hipStream_t st) {
+    hipLaunchKernelGGL((sumsq_kernel<T>), dim3(nparts), dim3(kBlock), 0, st, x, mask, n, partials);
+}
+
+void launch_set_tol(Ctrl* c, const double* partials, int nparts, double tol, hipStream_t st) {
+    hipLaunchKernelGGL(set_tol_kernel, dim3(1), dim3(kBlock), 0, st, c, partials, nparts, tol);
+}
+
+template <typename T>
+void launch_complete_output(const T* y, const uint8_t* mask, const T* z, const T* dual,
+                            const Ctrl* c, T* out, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL((complete_output_kernel<T>), dim3(grid_for(n)), dim3(kBlock), 0, st, y, mask, z,
+                       dual, c, out, n);
+}
+
+template <typename T>
+void launch_fill(T* p, T v, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL((fill_kernel<T>), dim3(grid_for(n)), dim3(kBlock), 0, st, p, v, n);
+}
+
+template void launch_sumsq<double>(const double*, const uint8_t*, int64_t, double*, int, hipStream_t);
+template void launch_complete_output<double>(const double*, const uint8_t*, const double*,
+                                             const double*, const Ctrl*, double*, int64_t,
+                                             hipStream_t);
+template void launch_fill<double>(double*, double, int64_t, hipStream_t);
+template void launch_fill<int>(int*, int, int64_t, hipStream_t);
+
+}  // namespace tsvd

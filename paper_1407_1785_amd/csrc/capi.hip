@@ -1,0 +1,891 @@
+// C ABI of the gfx950 t-SVT library: handles, workspace, the t-SVT step and
+// the completion / RPCA ADMM drivers (declarations and contracts in
+// include/tsvd.h).
+//
+// One ADMM iteration on the device is
+//   dft_forward (fused prologue)  ->  Jacobi sweeps  ->  svt weights+rebuild
+//   ->  dft_inverse (fused epilogue + residual partials)  ->  admm_ctrl,
+// all on the handle's stream, with the control scalars in device memory.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/tsvd.h"
+#include "kernels.h"
+
+using namespace tsvd;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct Failure {
+    tsvd_status status;
+    std::string msg;
+};
+
+[[noreturn]] void fail(tsvd_status s, const std::string& msg) { throw Failure{s, msg}; }
+
+void hip_check(hipError_t e, const char* what) {
+    if (e != hipSuccess) fail(TSVD_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void launch_check(const char* what) { hip_check(hipGetLastError(), what); }
+
+int env_int(const char* name, int dflt) {
+    const char* v = std::getenv(name);
+    return v && *v ? std::atoi(v) : dflt;
+}
+
+double env_double(const char* name, double dflt) {
+    const char* v = std::getenv(name);
+    return v && *v ? std::atof(v) : dflt;
+}
+
+// Largest supported sizes (LDS staging of the DFT tiles and Jacobi blocks).
+constexpr int kMaxTube = 512;
+constexpr int kMaxSlices = 300;
+
+}  // namespace
+
+struct tsvd_handle_s {
+    int device = 0;
+    size_t budget = 0;
+    hipStream_t stream = nullptr;
+    // workspace arena: one allocation, carved per call
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    // small device objects
+    Ctrl* ctrl = nullptr;
+    int* flag = nullptr;            // non-finite flag
+    cplx<double>* tw = nullptr;     // twiddles of the current tube length
+    int tw_len = 0;
+    // pinned host staging
+    int* host_ints = nullptr;
+    int host_ints_len = 0;
+    Ctrl* host_ctrl = nullptr;
+    // profiling (tsvd_profile)
+    struct Pending {
+        int kind;
+        hipEvent_t a, b;
+        double work;
+    };
+    struct Agg {
+        int64_t launches = 0;
+        double ms = 0.0, work = 0.0;
+    };
+    bool prof_on = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<Pending> pending;
+    std::vector<Agg> agg;
+    unsigned long long* rot_counter = nullptr;   // [0] self, [1] cross
+};
+
+namespace {
+
+struct Device {
+    explicit Device(int d) {
+        hip_check(hipGetDevice(&prev), "hipGetDevice");
+        if (prev != d) hip_check(hipSetDevice(d), "hipSetDevice");
+        target = d;
+    }
+    ~Device() {
+        if (prev != target) (void)hipSetDevice(prev);
+    }
+    int prev = 0, target = 0;
+};
+
+Geometry make_geometry(const tsvd_shape& s) {
+    if (s.ndim != 3 && s.ndim != 4) fail(TSVD_E_SHAPE, "ndim must be 3 or 4");
+    for (int k = 0; k < s.ndim; ++k)
+        if (s.n[k] < 1) fail(TSVD_E_SHAPE, "every dimension must be >= 1");
+    Geometry g{};
+    g.n1 = s.n[0];
+    g.n2 = s.n[1];
+    if (s.ndim == 3) {
+        g.P = 1;
+        g.Q = (int)s.n[2];
+        if (s.n[2] > kMaxTube) fail(TSVD_E_SHAPE, "tube length above the supported maximum");
+    } else {
+        if (s.n[2] * s.n[3] > kMaxTube) fail(TSVD_E_SHAPE, "tube length above the supported maximum");
+        g.P = (int)s.n[2];
+        g.Q = (int)s.n[3];
+    }
+    g.L = g.P * g.Q;
+    g.Qh = g.Q / 2 + 1;
+    g.h = g.P * g.Qh;
+    if (g.h > kMaxSlices) fail(TSVD_E_SHAPE, "too many Fourier slices");
+    g.trans = g.n1 < g.n2;
+    const int64_t m = std::max(g.n1, g.n2), n = std::min(g.n1, g.n2);
+    if (m > 4096) fail(TSVD_E_SHAPE, "matrix mode above the supported maximum");
+    g.m = (int)m;
+    g.n = (int)n;
+    g.ntubes = g.n1 * g.n2;
+    g.numel = g.ntubes * g.L;
+    if (!jacobi_supported(g.m, g.n, 8)) fail(TSVD_E_SHAPE, "slice too large for the Jacobi kernels");
+    return g;
+}
+
+// Bump allocator over the handle's workspace.
+struct Carver {
+    char* base;
+    size_t off = 0;
+    template <typename U>
+    U* take(int64_t count) {
+        off = (off + 255) & ~size_t(255);
+        U* p = reinterpret_cast<U*>(base + off);
+        off += (size_t)count * sizeof(U);
+        return p;
+    }
+};
+
+template <typename T>
+struct SvtBuffers {
+    cplx<T>* A;
+    cplx<T>* Z;
+    cplx<T>* V;
+    T* d;
+    int* kept;
+    int* rank;
+    int* rot;
+    int* sweeps;
+    double* partials;
+    int nparts;
+};
+
+template <typename T>
+size_t svt_bytes(const Geometry& g, int nparts) {
+    const int64_t slice = (int64_t)g.h * g.m * g.n;
+    size_t b = 0;
+    b += 2 * slice * sizeof(cplx<T>) + 512;
+    b += (int64_t)g.h * g.n * g.n * sizeof(cplx<T>) + 256;
+    b += (int64_t)g.h * g.n * (sizeof(T) + sizeof(int)) + 512;
+    b += (int64_t)g.h * 5 * sizeof(int) + 768;
+    b += (int64_t)nparts * kNumPartials * sizeof(double) + 256;
+    return b;
+}
+
+template <typename T>
+SvtBuffers<T> carve_svt(Carver& c, const Geometry& g, int nparts) {
+    SvtBuffers<T> s{};
+    const int64_t slice = (int64_t)g.h * g.m * g.n;
+    s.A = c.take<cplx<T>>(slice);
+    s.Z = c.take<cplx<T>>(slice);
+    s.V = c.take<cplx<T>>((int64_t)g.h * g.n * g.n);
+    s.d = c.take<T>((int64_t)g.h * g.n);
+    s.kept = c.take<int>((int64_t)g.h * g.n);
+    s.rank = c.take<int>(g.h);
+    s.rot = c.take<int>(3 * g.h);
+    s.sweeps = c.take<int>(g.h);
+    s.partials = c.take<double>((int64_t)nparts * kNumPartials);
+    s.nparts = nparts;
+    return s;
+}
+
+void ensure_workspace(tsvd_handle h, size_t bytes) {
+    if (bytes <= h->ws_bytes) return;
+    if (h->budget && bytes > h->budget)
+        fail(TSVD_E_NOMEM, "workspace of " + std::to_string(bytes) + " bytes exceeds the handle budget");
+    if (h->ws) hip_check(hipFree(h->ws), "hipFree");
+    h->ws = nullptr;
+    h->ws_bytes = 0;
+    hipError_t e = hipMalloc(&h->ws, bytes);
+    if (e != hipSuccess) fail(TSVD_E_NOMEM, std::string("hipMalloc workspace: ") + hipGetErrorString(e));
+    h->ws_bytes = bytes;
+}
+
+void ensure_host_ints(tsvd_handle h, int count) {
+    if (count <= h->host_ints_len) return;
+    if (h->host_ints) hip_check(hipHostFree(h->host_ints), "hipHostFree");
+    h->host_ints = nullptr;
+    hip_check(hipHostMalloc(reinterpret_cast<void**>(&h->host_ints), sizeof(int) * count, 0),
+              "hipHostMalloc");
+    h->host_ints_len = count;
+}
+
+// FP64 twiddles exp(-2 pi i u / L); the quarter points are exact.
+void ensure_twiddles(tsvd_handle h, int L) {
+    if (h->tw_len == L) return;
+    if (h->tw) hip_check(hipFree(h->tw), "hipFree");
+    h->tw = nullptr;
+    h->tw_len = 0;
+    std::vector<cplx<double>> tw(L);
+    for (int u = 0; u < L; ++u) {
+        if ((4 * u) % L == 0) {
+            const int q = (4 * u) / L;
+            const double c[4] = {1.0, 0.0, -1.0, 0.0}, s[4] = {0.0, -1.0, 0.0, 1.0};
+            tw[u] = cplx<double>{c[q], s[q]};
+        } else {
+            const double a = -2.0 * M_PI * (double)u / (double)L;
+            tw[u] = cplx<double>{std::cos(a), std::sin(a)};
+        }
+    }
+    hip_check(hipMalloc(&h->tw, sizeof(cplx<double>) * L), "hipMalloc twiddles");
+    hip_check(hipMemcpy(h->tw, tw.data(), sizeof(cplx<double>) * L, hipMemcpyHostToDevice),
+              "hipMemcpy twiddles");
+    h->tw_len = L;
+}
+
+// Kernel families reported by tsvd_profile_read.
+enum Kind : int {
+    K_DFT_FWD = 0, K_JAC_INIT, K_JAC_SELF, K_JAC_CROSS, K_SVT_W, K_SVT_REBUILD, K_DFT_INV,
+    K_CTRL, K_OTHER, K_COUNT
+};
+const char* kKindName[K_COUNT] = {"dft_forward", "jacobi_init", "jacobi_self", "jacobi_cross",
+                                  "svt_weights", "svt_rebuild", "dft_inverse", "admm_ctrl", "other"};
+const bool kKindBytes[K_COUNT] = {true, true, false, false, true, true, true, true, true};
+
+hipEvent_t take_event(tsvd_handle h) {
+    if (!h->ev_pool.empty()) {
+        hipEvent_t e = h->ev_pool.back();
+        h->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    hip_check(hipEventCreate(&e), "hipEventCreate");
+    return e;
+}
+
+void prof_harvest(tsvd_handle h) {
+    if (h->pending.empty()) return;
+    hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+    for (auto& p : h->pending) {
+        float ms = 0.f;
+        hip_check(hipEventElapsedTime(&ms, p.a, p.b), "hipEventElapsedTime");
+        auto& g = h->agg[p.kind];
+        g.launches += 1;
+        g.ms += ms;
+        g.work += p.work;
+        h->ev_pool.push_back(p.a);
+        h->ev_pool.push_back(p.b);
+    }
+    h->pending.clear();
+}
+
+// Run `launch` (which enqueues one kernel on h->stream), timing it when
+// profiling is on.  Returns the index of the pending record or -1.
+template <typename F>
+int prof_launch(tsvd_handle h, int kind, double work, F&& launch) {
+    if (!h->prof_on) {
+        launch();
+        return -1;
+    }
+    tsvd_handle_s::Pending p{kind, take_event(h), take_event(h), work};
+    hip_check(hipEventRecord(p.a, h->stream), "hipEventRecord");
+    launch();
+    hip_check(hipEventRecord(p.b, h->stream), "hipEventRecord");
+    h->pending.push_back(p);
+    if (h->pending.size() >= 4096) {
+        prof_harvest(h);
+        return -1;
+    }
+    return (int)h->pending.size() - 1;
+}
+
+int blk_start_host(int b, int n, int nb) { return (int)(((int64_t)b * n) / nb); }
+
+// column pairs visited by one self launch / one cross round, per slice
+int64_t self_pairs(int n, int nb) {
+    int64_t p = 0;
+    for (int b = 0; b < nb; ++b) {
+        const int64_t w = blk_start_host(b + 1, n, nb) - blk_start_host(b, n, nb);
+        p += w * (w - 1) / 2;
+    }
+    return p;
+}
+
+int64_t cross_pairs(int n, int nb, int round) {
+    int64_t p = 0;
+    auto player = [&](int pos) { return pos == 0 ? 0 : 1 + (pos - 1 + round) % (nb - 1); };
+    for (int pr = 0; pr < nb / 2; ++pr) {
+        const int bi = player(pr), bj = player(nb - 1 - pr);
+        const int64_t wi = blk_start_host(bi + 1, n, nb) - blk_start_host(bi, n, nb);
+        const int64_t wj = blk_start_host(bj + 1, n, nb) - blk_start_host(bj, n, nb);
+        p += wi * wj;
+    }
+    return p;
+}
+
+struct SweepStats {
+    int sweeps = 0;
+};
+
+// Jacobi sweeps + shrink + rebuild on the slices in sb.A; output in sb.Z.
+//
+// Work model of the Jacobi kernels (FP operations): every visited column
+// pair costs 16 m (the three dot products over the m slice rows), and every
+// applied rotation another 16 (m + n) (the 2 x 2 complex update of the m
+// slice rows and n V rows of both columns).
+template <typename T>
+SweepStats run_svt(tsvd_handle h, const Geometry& g, const SvtBuffers<T>& sb, int max_sweeps) {
+    hipStream_t st = h->stream;
+    JacArgs<T> ja{};
+    ja.A = sb.A;
+    ja.V = sb.V;
+    ja.m = g.m;
+    ja.n = g.n;
+    ja.h = g.h;
+    int bw = env_int("TSVD_JACOBI_BW", 0);
+    if (bw != 4 && bw != 8 && bw != 16) bw = jacobi_block_width(g.m, g.n, sizeof(T), g.h);
+    ja.nb = jacobi_num_blocks(g.n, bw);
+    ja.rot = sb.rot;
+    ja.sweeps = sb.sweeps;
+    ja.tol = (T)env_double("TSVD_JACOBI_TOL", std::sqrt((double)g.m) * 2.220446049250313e-16);
+    ja.rotations = h->rot_counter;
+    prof_launch(h, K_JAC_INIT, (double)g.h * g.n * g.n * sizeof(cplx<T>),
+                [&] { launch_jacobi_init(ja, st); });
+    launch_check("jacobi_init");
+    const int check_every = std::max(1, env_int("TSVD_CHECK_EVERY", 1));
+    ensure_host_ints(h, g.h);
+    SweepStats stats;
+    int active = g.h;   // slices still rotating, as last observed
+    const double dot_flops = 16.0 * g.m;
+    for (int sw = 0; sw < max_sweeps; ++sw) {
+        ja.sweep = sw;
+        ja.rotations = h->rot_counter;
+        prof_launch(h, K_JAC_SELF, dot_flops * active * self_pairs(g.n, ja.nb),
+                    [&] { launch_jacobi_self(ja, bw, st); });
+        launch_check("jacobi_self");
+        ja.rotations = h->rot_counter + 1;
+        for (int r = 0; r < ja.nb - 1; ++r) {
+            ja.round = r;
+            prof_launch(h, K_JAC_CROSS, dot_flops * active * cross_pairs(g.n, ja.nb, r),
+                        [&] { launch_jacobi_cross(ja, bw, st); });
+            launch_check("jacobi_cross");
+        }
+        stats.sweeps = sw + 1;
+        if ((sw + 1) % check_every == 0 || sw + 1 == max_sweeps) {
+            hip_check(hipMemcpyAsync(h->host_ints, sb.rot + (sw % 3) * g.h, sizeof(int) * g.h,
+                                     hipMemcpyDeviceToHost, st),
+                      "hipMemcpyAsync rot");
+            hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+            active = 0;
+            for (int s = 0; s < g.h; ++s) active += h->host_ints[s] != 0;
+            if (!active) break;
+        }
+    }
+    SvtArgs<T> sa{};
+    sa.W = sb.A;
+    sa.V = sb.V;
+    sa.Z = sb.Z;
+    sa.d = sb.d;
+    sa.kept = sb.kept;
+    sa.rank = sb.rank;
+    sa.ctrl = h->ctrl;
+    sa.m = g.m;
+    sa.n = g.n;
+    sa.h = g.h;
+    const int64_t slice_bytes = (int64_t)g.h * g.m * g.n * sizeof(cplx<T>);
+    prof_launch(h, K_SVT_W, (double)slice_bytes, [&] { launch_svt_weights(sa, st); });
+    launch_check("svt_weights");
+    const int ir = prof_launch(h, K_SVT_REBUILD, 0.0, [&] { launch_svt_rebuild(sa, st); });
+    launch_check("svt_rebuild");
+    if (h->prof_on) {
+        // rotation work and the rebuild's bytes need device counts
+        unsigned long long rots[2] = {0, 0};
+        hip_check(hipMemcpyAsync(rots, h->rot_counter, sizeof(rots), hipMemcpyDeviceToHost, st),
+                  "hipMemcpyAsync rotations");
+        ensure_host_ints(h, g.h);
+        hip_check(hipMemcpyAsync(h->host_ints, sb.rank, sizeof(int) * g.h, hipMemcpyDeviceToHost, st),
+                  "hipMemcpyAsync rank");
+        hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+        hip_check(hipMemsetAsync(h->rot_counter, 0, 2 * sizeof(unsigned long long), st),
+                  "hipMemsetAsync rotations");
+        int64_t kept = 0;
+        for (int s = 0; s < g.h; ++s) kept += h->host_ints[s];
+        const double rot_flops = 16.0 * (g.m + g.n);
+        if (ir >= 0) h->pending[ir].work = (double)slice_bytes + (double)kept * (g.m + g.n) * sizeof(cplx<T>);
+        prof_harvest(h);
+        h->agg[K_JAC_SELF].work += rot_flops * (double)rots[0];
+        h->agg[K_JAC_CROSS].work += rot_flops * (double)rots[1];
+    }
+    return stats;
+}
+
+void put_ctrl(tsvd_handle h, const Ctrl& c) {
+    *h->host_ctrl = c;
+    hip_check(hipMemcpyAsync(h->ctrl, h->host_ctrl, sizeof(Ctrl), hipMemcpyHostToDevice, h->stream),
+              "hipMemcpyAsync ctrl");
+    hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+}
+
+Ctrl get_ctrl(tsvd_handle h) {
+    hip_check(hipMemcpyAsync(h->host_ctrl, h->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, h->stream),
+              "hipMemcpyAsync ctrl");
+    hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+    return *h->host_ctrl;
+}
+
+void clear_flag(tsvd_handle h) { launch_fill<int>(h->flag, 0, 1, h->stream); }
+
+bool read_flag(tsvd_handle h) {
+    ensure_host_ints(h, 1);
+    hip_check(hipMemcpyAsync(h->host_ints, h->flag, sizeof(int), hipMemcpyDeviceToHost, h->stream),
+              "hipMemcpyAsync flag");
+    hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+    return h->host_ints[0] != 0;
+}
+
+template <typename F>
+tsvd_status guarded(F&& f) {
+    try {
+        f();
+        g_last_error.clear();
+        return TSVD_OK;
+    } catch (const Failure& e) {
+        g_last_error = e.msg;
+        return e.status;
+    } catch (const std::bad_alloc&) {
+        g_last_error = "host allocation failed";
+        return TSVD_E_NOMEM;
+    } catch (...) {
+        g_last_error = "unexpected failure";
+        return TSVD_E_HIP;
+    }
+}
+
+void check_handle(tsvd_handle h) {
+    if (!h) fail(TSVD_E_INVALID, "null handle");
+}
+
+void check_precision(tsvd_dtype dtype, int precision) {
+    if (dtype != TSVD_F64 && dtype != TSVD_F32) fail(TSVD_E_INVALID, "unknown dtype");
+    if (precision != TSVD_PREC_FP64 && precision != TSVD_PREC_FP32)
+        fail(TSVD_E_INVALID, "unknown precision");
+    if (!(dtype == TSVD_F64 && precision == TSVD_PREC_FP64))
+        fail(TSVD_E_UNSUPPORTED, "only FP64 data with FP64 precision is built");
+}
+
+struct AdmmSettings {
+    double growth, rho_max;
+    int max_iter, precision, max_sweeps;
+};
+
+AdmmSettings settings(const tsvd_admm_opts* o, double growth, double rho_max, int max_iter) {
+    AdmmSettings s{growth, rho_max, max_iter, TSVD_PREC_FP64, 30};
+    if (o) {
+        if (o->reserved != 0) fail(TSVD_E_INVALID, "opts.reserved must be 0");
+        if (o->growth > 0) s.growth = o->growth;
+        if (o->rho_max > 0) s.rho_max = o->rho_max;
+        if (o->max_iter > 0) s.max_iter = o->max_iter;
+        s.precision = o->precision;
+        if (o->max_sweeps > 0) s.max_sweeps = o->max_sweeps;
+    }
+    if (!(s.growth >= 1.0) || !std::isfinite(s.growth)) fail(TSVD_E_INVALID, "growth must be >= 1");
+    return s;
+}
+
+int elementwise_parts() { return 1024; }
+
+}  // namespace
+
+// ---------------------------------------------------------------- C ABI
+
+extern "C" {
+
+tsvd_status tsvd_create(int device, size_t hbm_budget_bytes, tsvd_handle* out) {
+    return guarded([&] {
+        if (!out) fail(TSVD_E_INVALID, "out is NULL");
+        *out = nullptr;
+        int count = 0;
+        hip_check(hipGetDeviceCount(&count), "hipGetDeviceCount");
+        if (device < 0 || device >= count) fail(TSVD_E_INVALID, "no such device");
+        Device dev(device);
+        tsvd_handle h = new tsvd_handle_s();
+        h->device = device;
+        h->budget = hbm_budget_bytes;
+        hipError_t e = hipMalloc(reinterpret_cast<void**>(&h->ctrl), sizeof(Ctrl));
+        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&h->flag), sizeof(int));
+        if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&h->host_ctrl), sizeof(Ctrl), 0);
+        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&h->rot_counter), 2 * sizeof(unsigned long long));
+        if (e == hipSuccess) e = hipMemset(h->rot_counter, 0, 2 * sizeof(unsigned long long));
+        h->agg.assign(K_COUNT, tsvd_handle_s::Agg{});
+        if (e != hipSuccess) {
+            if (h->ctrl) (void)hipFree(h->ctrl);
+            if (h->flag) (void)hipFree(h->flag);
+            delete h;
+            fail(TSVD_E_HIP, std::string("handle allocation: ") + hipGetErrorString(e));
+        }
+        *out = h;
+    });
+}
+
+tsvd_status tsvd_destroy(tsvd_handle h) {
+    if (!h) return TSVD_OK;
+    return guarded([&] {
+        Device dev(h->device);
+        if (h->stream) (void)hipStreamSynchronize(h->stream);
+        else (void)hipDeviceSynchronize();
+        if (h->ws) (void)hipFree(h->ws);
+        if (h->tw) (void)hipFree(h->tw);
+        if (h->ctrl) (void)hipFree(h->ctrl);
+        if (h->flag) (void)hipFree(h->flag);
+        if (h->host_ints) (void)hipHostFree(h->host_ints);
+        if (h->host_ctrl) (void)hipHostFree(h->host_ctrl);
+        if (h->rot_counter) (void)hipFree(h->rot_counter);
+        for (auto& p : h->pending) {
+            (void)hipEventDestroy(p.a);
+            (void)hipEventDestroy(p.b);
+        }
+        for (auto e : h->ev_pool) (void)hipEventDestroy(e);
+        delete h;
+    });
+}
+
+tsvd_status tsvd_set_stream(tsvd_handle h, void* hip_stream) {
+    return guarded([&] {
+        check_handle(h);
+        h->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    });
+}
+
+tsvd_status tsvt(tsvd_handle h, const void* X, tsvd_shape shape, tsvd_dtype dtype, double tau,
+                 tsvd_precision precision, void* Z, int32_t* multirank_host) {
+    return guarded([&] {
+        check_handle(h);
+        if (!X || !Z) fail(TSVD_E_INVALID, "null tensor pointer");
+        if (!(tau >= 0.0) || !std::isfinite(tau)) fail(TSVD_E_INVALID, "tau must be finite and >= 0");
+        check_precision(dtype, precision);
+        const Geometry g = make_geometry(shape);
+        Device dev(h->device);
+        using T = double;
+        const int nparts = (int)dft_grid(g, dft_inverse_tile(g, EPI_STORE));
+        ensure_workspace(h, svt_bytes<T>(g, nparts) + 4096);
+        Carver cv{reinterpret_cast<char*>(h->ws)};
+        SvtBuffers<T> sb = carve_svt<T>(cv, g, nparts);
+        ensure_twiddles(h, g.L);
+        Ctrl c{};
+        c.rho = tau > 0 ? 1.0 / tau : INFINITY;
+        c.tau = tau;
+        c.dscale = 1.0;
+        put_ctrl(h, c);
+        clear_flag(h);
+
+        FwdArgs<T> fa{};
+        fa.x = static_cast<const T*>(X);
+        fa.ctrl = h->ctrl;
+        fa.tw = h->tw;
+        fa.out = sb.A;
+        fa.nonfinite = h->flag;
+        fa.g = g;
+        fa.tile = dft_forward_tile(g);
+        const double slice_bytes = (double)g.h * g.m * g.n * sizeof(cplx<T>);
+        prof_launch(h, K_DFT_FWD, slice_bytes + (double)g.numel * sizeof(T),
+                    [&] { launch_dft_forward(PRO_COPY, fa, h->stream); });
+        launch_check("dft_forward");
+        run_svt<T>(h, g, sb, 30);
+        InvArgs<T> ia{};
+        ia.in = sb.Z;
+        ia.tw = h->tw;
+        ia.ctrl = h->ctrl;
+        ia.g = g;
+        ia.tile = dft_inverse_tile(g, EPI_STORE);
+        ia.out = static_cast<T*>(Z);
+        prof_launch(h, K_DFT_INV, slice_bytes + (double)g.numel * sizeof(T),
+                    [&] { launch_dft_inverse(EPI_STORE, ia, h->stream); });
+        launch_check("dft_inverse");
+        if (multirank_host) {
+            ensure_host_ints(h, g.h);
+            hip_check(hipMemcpyAsync(h->host_ints, sb.rank, sizeof(int) * g.h, hipMemcpyDeviceToHost,
+                                     h->stream),
+                      "hipMemcpyAsync rank");
+        }
+        hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+        if (multirank_host) std::memcpy(multirank_host, h->host_ints, sizeof(int) * g.h);
+        prof_harvest(h);
+        if (read_flag(h)) fail(TSVD_E_NONFINITE, "non-finite input");
+    });
+}
+
+tsvd_status tsvd_complete(tsvd_handle h, const void* X_obs, const uint8_t* mask, tsvd_shape shape,
+                          tsvd_dtype dtype, double rho, double tol, const tsvd_admm_opts* opts,
+                          void* X_out, tsvd_info* info_host) {
+    return guarded([&] {
+        const auto t0 = std::chrono::steady_clock::now();
+        check_handle(h);
+        if (!X_obs || !mask || !X_out) fail(TSVD_E_INVALID, "null tensor pointer");
+        if (!(rho > 0.0) || !std::isfinite(rho)) fail(TSVD_E_INVALID, "rho must be > 0");
+        if (!(tol >= 0.0) || !std::isfinite(tol)) fail(TSVD_E_INVALID, "tol must be >= 0");
+        const AdmmSettings s = settings(opts, 1.1, 1e3, 300);
+        if (s.rho_max < rho) fail(TSVD_E_INVALID, "rho_max must be >= rho");
+        check_precision(dtype, s.precision);
+        const Geometry g = make_geometry(shape);
+        Device dev(h->device);
+        using T = double;
+        const int tile_i = dft_inverse_tile(g, EPI_COMPLETE);
+        const int nparts = (int)std::max<int64_t>(dft_grid(g, tile_i), elementwise_parts());
+        const int64_t N = g.numel;
+        ensure_workspace(h, svt_bytes<T>(g, nparts) + 4 * (N * sizeof(T) + 256) + 4096);
+        Carver cv{reinterpret_cast<char*>(h->ws)};
+        SvtBuffers<T> sb = carve_svt<T>(cv, g, nparts);
+        T* Zb[2] = {cv.take<T>(N), cv.take<T>(N)};
+        T* Qb[2] = {cv.take<T>(N), cv.take<T>(N)};
+        ensure_twiddles(h, g.L);
+        hipStream_t st = h->stream;
+        const T* Y = static_cast<const T*>(X_obs);
+        launch_fill<T>(Zb[0], 0.0, N, st);
+        launch_fill<T>(Qb[0], 0.0, N, st);
+        Ctrl c{};
+        c.rho = rho;
+        c.tau = 1.0 / rho;
+        c.dscale = 1.0;
+        c.dscale_used = 1.0;
+        c.growth = s.growth;
+        c.rho_max = s.rho_max;
+        c.rho_used = rho;
+        put_ctrl(h, c);
+        launch_sumsq<T>(Y, mask, N, sb.partials, elementwise_parts(), st);
+        launch_set_tol(h->ctrl, sb.partials, elementwise_parts(), tol, st);
+        launch_check("setup");
+        clear_flag(h);
+
+        FwdArgs<T> fa{};
+        fa.x = Y;
+        fa.mask = mask;
+        fa.ctrl = h->ctrl;
+        fa.tw = h->tw;
+        fa.out = sb.A;
+        fa.nonfinite = h->flag;
+        fa.g = g;
+        fa.tile = dft_forward_tile(g);
+        InvArgs<T> ia{};
+        ia.in = sb.Z;
+        ia.tw = h->tw;
+        ia.ctrl = h->ctrl;
+        ia.g = g;
+        ia.tile = tile_i;
+        ia.y = Y;
+        ia.mask = mask;
+        ia.partials = sb.partials;
+        const int inv_parts = (int)dft_grid(g, tile_i);
+        const double slice_bytes = (double)g.h * g.m * g.n * sizeof(cplx<T>);
+        int sweeps_total = 0, sweeps_last = 0, iters = 0;
+        Ctrl hc{};
+        for (int k = 0; k < s.max_iter; ++k) {
+            fa.z = Zb[k % 2];
+            fa.dual = Qb[k % 2];
+            // Y, mask, Z, Q in; slices out
+            prof_launch(h, K_DFT_FWD, slice_bytes + (double)N * (3 * sizeof(T) + 1),
+                        [&] { launch_dft_forward(PRO_COMPLETE, fa, st); });
+            launch_check("dft_forward");
+            const SweepStats ss = run_svt<T>(h, g, sb, s.max_sweeps);
+            sweeps_total += ss.sweeps;
+            sweeps_last = ss.sweeps;
+            ia.out = Zb[(k + 1) % 2];
+            ia.z_old = Zb[k % 2];
+            ia.dual_old = Qb[k % 2];
+            ia.dual_new = Qb[(k + 1) % 2];
+            // slices, Y, mask, Z, Q in; Z', Q~ out
+            prof_launch(h, K_DFT_INV, slice_bytes + (double)N * (5 * sizeof(T) + 1),
+                        [&] { launch_dft_inverse(EPI_COMPLETE, ia, st); });
+            launch_check("dft_inverse");
+            prof_launch(h, K_CTRL, (double)inv_parts * kNumPartials * sizeof(double),
+                        [&] { launch_admm_ctrl(h->ctrl, sb.partials, inv_parts, 0, st); });
+            launch_check("admm_ctrl");
+            hc = get_ctrl(h);
+            iters = k + 1;
+            if (hc.done) break;
+        }
+        launch_complete_output<T>(Y, mask, Zb[(iters - 1) % 2], Qb[(iters - 1) % 2], h->ctrl,
+                                  static_cast<T*>(X_out), N, st);
+        launch_check("complete_output");
+        hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+        prof_harvest(h);
+        if (hc.nonfinite || read_flag(h)) fail(TSVD_E_NONFINITE, "non-finite input or iterate");
+        if (info_host) {
+            info_host->iters = iters;
+            info_host->converged = hc.done ? 1 : 0;
+            info_host->sweeps_total = sweeps_total;
+            info_host->sweeps_last = sweeps_last;
+            info_host->primal = hc.primal;
+            info_host->change = hc.change;
+            info_host->rho_final = hc.rho_used;
+            info_host->seconds =
+                std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        }
+    });
+}
+
+tsvd_status trpca(tsvd_handle h, const void* X, tsvd_shape shape, tsvd_dtype dtype, double lambda,
+                  double mu, double tol, tsvd_shrink shrink, const tsvd_admm_opts* opts, void* L_out,
+                  void* S_out, tsvd_info* info_host) {
+    return guarded([&] {
+        const auto t0 = std::chrono::steady_clock::now();
+        check_handle(h);
+        if (!X || !L_out || !S_out) fail(TSVD_E_INVALID, "null tensor pointer");
+        if (!(lambda > 0.0) || !std::isfinite(lambda)) fail(TSVD_E_INVALID, "lambda must be > 0");
+        if (!(mu > 0.0) || !std::isfinite(mu)) fail(TSVD_E_INVALID, "mu must be > 0");
+        if (!(tol >= 0.0) || !std::isfinite(tol)) fail(TSVD_E_INVALID, "tol must be >= 0");
+        if (shrink != TSVD_SHRINK_L1 && shrink != TSVD_SHRINK_L112) fail(TSVD_E_INVALID, "unknown shrink");
+        const AdmmSettings s = settings(opts, 1.2, 1e10, 500);
+        if (s.rho_max < mu) fail(TSVD_E_INVALID, "rho_max must be >= mu");
+        check_precision(dtype, s.precision);
+        const Geometry g = make_geometry(shape);
+        Device dev(h->device);
+        using T = double;
+        const int epi = shrink == TSVD_SHRINK_L1 ? EPI_RPCA_L1 : EPI_RPCA_L112;
+        const int tile_i = dft_inverse_tile(g, epi);
+        const int nparts = (int)std::max<int64_t>(dft_grid(g, tile_i), elementwise_parts());
+        const int64_t N = g.numel;
+        ensure_workspace(h, svt_bytes<T>(g, nparts) + 6 * (N * sizeof(T) + 256) + 4096);
+        Carver cv{reinterpret_cast<char*>(h->ws)};
+        SvtBuffers<T> sb = carve_svt<T>(cv, g, nparts);
+        T* Lb[2] = {cv.take<T>(N), cv.take<T>(N)};
+        T* Sb[2] = {cv.take<T>(N), cv.take<T>(N)};
+        T* Wb[2] = {cv.take<T>(N), cv.take<T>(N)};
+        ensure_twiddles(h, g.L);
+        hipStream_t st = h->stream;
+        const T* M = static_cast<const T*>(X);
+        launch_fill<T>(Lb[0], 0.0, N, st);
+        launch_fill<T>(Sb[0], 0.0, N, st);
+        launch_fill<T>(Wb[0], 0.0, N, st);
+        Ctrl c{};
+        c.rho = mu;
+        c.tau = 1.0 / mu;
+        c.dscale = 1.0;
+        c.dscale_used = 1.0;
+        c.growth = s.growth;
+        c.rho_max = s.rho_max;
+        c.lambda = lambda;
+        c.shrink = lambda / mu;
+        c.rho_used = mu;
+        put_ctrl(h, c);
+        launch_sumsq<T>(M, nullptr, N, sb.partials, elementwise_parts(), st);
+        launch_set_tol(h->ctrl, sb.partials, elementwise_parts(), tol, st);
+        launch_check("setup");
+        clear_flag(h);
+
+        FwdArgs<T> fa{};
+        fa.x = M;
+        fa.ctrl = h->ctrl;
+        fa.tw = h->tw;
+        fa.out = sb.A;
+        fa.nonfinite = h->flag;
+        fa.g = g;
+        fa.tile = dft_forward_tile(g);
+        InvArgs<T> ia{};
+        ia.in = sb.Z;
+        ia.tw = h->tw;
+        ia.ctrl = h->ctrl;
+        ia.g = g;
+        ia.tile = tile_i;
+        ia.m = M;
+        ia.partials = sb.partials;
+        const int inv_parts = (int)dft_grid(g, tile_i);
+        const double slice_bytes = (double)g.h * g.m * g.n * sizeof(cplx<T>);
+        int sweeps_total = 0, sweeps_last = 0, iters = 0;
+        Ctrl hc{};
+        for (int k = 0; k < s.max_iter; ++k) {
+            fa.s = Sb[k % 2];
+            fa.dual = Wb[k % 2];
+            // M, S, W in; slices out
+            prof_launch(h, K_DFT_FWD, slice_bytes + (double)N * 3 * sizeof(T),
+                        [&] { launch_dft_forward(PRO_RPCA, fa, st); });
+            launch_check("dft_forward");
+            const SweepStats ss = run_svt<T>(h, g, sb, s.max_sweeps);
+            sweeps_total += ss.sweeps;
+            sweeps_last = ss.sweeps;
+            ia.out = Lb[(k + 1) % 2];
+            ia.l_old = Lb[k % 2];
+            ia.s_old = Sb[k % 2];
+            ia.s_new = Sb[(k + 1) % 2];
+            ia.dual_old = Wb[k % 2];
+            ia.dual_new = Wb[(k + 1) % 2];
+            // slices, M, W, S, L in; L', S', W~ out
+            prof_launch(h, K_DFT_INV, slice_bytes + (double)N * 7 * sizeof(T),
+                        [&] { launch_dft_inverse(epi, ia, st); });
+            launch_check("dft_inverse");
+            prof_launch(h, K_CTRL, (double)inv_parts * kNumPartials * sizeof(double),
+                        [&] { launch_admm_ctrl(h->ctrl, sb.partials, inv_parts, 1, st); });
+            launch_check("admm_ctrl");
+            hc = get_ctrl(h);
+            iters = k + 1;
+            if (hc.done) break;
+        }
+        hip_check(hipMemcpyAsync(L_out, Lb[iters % 2], N * sizeof(T), hipMemcpyDeviceToDevice, st),
+                  "hipMemcpyAsync L");
+        hip_check(hipMemcpyAsync(S_out, Sb[iters % 2], N * sizeof(T), hipMemcpyDeviceToDevice, st),
+                  "hipMemcpyAsync S");
+        hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+        prof_harvest(h);
+        if (hc.nonfinite || read_flag(h)) fail(TSVD_E_NONFINITE, "non-finite input or iterate");
+        if (info_host) {
+            info_host->iters = iters;
+            info_host->converged = hc.done ? 1 : 0;
+            info_host->sweeps_total = sweeps_total;
+            info_host->sweeps_last = sweeps_last;
+            info_host->primal = hc.primal;
+            info_host->change = hc.change;
+            info_host->rho_final = hc.rho_used;
+            info_host->seconds =
+                std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        }
+    });
+}
+
+tsvd_status tsvd_profile(tsvd_handle h, int enable) {
+    return guarded([&] {
+        check_handle(h);
+        Device dev(h->device);
+        prof_harvest(h);
+        if (enable) {
+            h->agg.assign(K_COUNT, tsvd_handle_s::Agg{});
+            hip_check(hipMemsetAsync(h->rot_counter, 0, 2 * sizeof(unsigned long long), h->stream),
+                      "hipMemsetAsync rotations");
+            hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+        }
+        h->prof_on = enable != 0;
+    });
+}
+
+tsvd_status tsvd_profile_read(tsvd_handle h, tsvd_kernel_stat* out_host, int capacity,
+                              int* count_host) {
+    return guarded([&] {
+        check_handle(h);
+        if (!count_host || (capacity > 0 && !out_host)) fail(TSVD_E_INVALID, "null output");
+        Device dev(h->device);
+        prof_harvest(h);
+        int c = 0;
+        for (int k = 0; k < K_COUNT; ++k) {
+            const auto& g = h->agg[k];
+            if (g.launches == 0) continue;
+            if (c < capacity) {
+                tsvd_kernel_stat& o = out_host[c];
+                std::memset(&o, 0, sizeof(o));
+                std::snprintf(o.name, sizeof(o.name), "%s", kKindName[k]);
+                o.launches = g.launches;
+                o.total_ms = g.ms;
+                o.work = g.work;
+                o.work_is_bytes = kKindBytes[k] ? 1 : 0;
+            }
+            ++c;
+        }
+        *count_host = c;
+    });
+}
+
+const char* tsvd_status_string(tsvd_status s) {
+    switch (s) {
+        case TSVD_OK: return "ok";
+        case TSVD_E_INVALID: return "invalid argument";
+        case TSVD_E_SHAPE: return "unsupported or invalid shape";
+        case TSVD_E_NOMEM: return "out of memory or over budget";
+        case TSVD_E_HIP: return "HIP runtime error";
+        case TSVD_E_NONFINITE: return "non-finite value";
+        case TSVD_E_UNSUPPORTED: return "unsupported request";
+    }
+    return "unknown status";
+}
+
+const char* tsvd_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

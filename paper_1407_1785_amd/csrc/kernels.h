@@ -1,0 +1,120 @@
+// Kernel argument blocks and launchers of the gfx950 t-SVT library (internal).
+#pragma once
+
+#include "common.h"
+
+namespace tsvd {
+
+// Fused prologues of the forward DFT: what tensor is transformed.
+enum Prologue : int {
+    PRO_COPY = 0,      // A = X                                   (t-SVT)
+    PRO_COMPLETE = 1,  // A = X + Q, X = Omega.Y + (1-Omega).(Z - Q) (completion)
+    PRO_RPCA = 2,      // A = M - S - W                           (RPCA)
+};
+
+// Fused epilogues of the inverse DFT: what is done with the prox output.
+enum Epilogue : int {
+    EPI_STORE = 0,       // Z = prox output
+    EPI_COMPLETE = 1,    // completion dual update + residual partial sums
+    EPI_RPCA_L1 = 2,     // RPCA entrywise shrink + dual update + residuals
+    EPI_RPCA_L112 = 3,   // RPCA tube-group shrink + dual update + residuals
+};
+
+template <typename T>
+struct FwdArgs {
+    const T* x;              // COPY: X; COMPLETE: observed Y; RPCA: M
+    const uint8_t* mask;     // COMPLETE: 1 = observed
+    const T* z;              // COMPLETE: Z_k
+    const T* dual;           // COMPLETE: Q stored; RPCA: W stored (times ctrl->dscale)
+    const T* s;              // RPCA: S_k
+    const Ctrl* ctrl;
+    const cplx<double>* tw;  // L twiddles exp(-2 pi i u / L), u = 0..L-1
+    cplx<T>* out;            // h slices, m x n column-major each
+    int* nonfinite;          // set to 1 if a transformed value is not finite
+    Geometry g;
+    int tile;                // tubes per workgroup
+};
+
+template <typename T>
+struct InvArgs {
+    const cplx<T>* in;       // h slices of the prox output
+    const cplx<double>* tw;
+    const Ctrl* ctrl;
+    Geometry g;
+    int tile;
+    T* out;                  // Z (STORE/COMPLETE) or L (RPCA), next iterate
+    // completion
+    const T* y;
+    const uint8_t* mask;
+    const T* z_old;
+    const T* dual_old;       // stored dual of the current iteration
+    T* dual_new;             // stored dual of the next iteration (unscaled)
+    // RPCA
+    const T* m;
+    const T* s_old;
+    T* s_new;
+    const T* l_old;
+    double* partials;        // kNumPartials per workgroup
+};
+
+template <typename T>
+struct JacArgs {
+    cplx<T>* A;     // h slices m x n; overwritten by W = A V
+    cplx<T>* V;     // h slices n x n
+    int m, n, h;
+    int nb;         // column blocks (even)
+    int round;      // tournament round of jacobi_cross
+    int sweep;      // sweep index; rot is a ring of 3 x h flags
+    int* rot;       // rot[(sweep % 3) * h + s] = 1 if sweep rotated slice s
+    int* sweeps;    // sweeps run per slice
+    unsigned long long* rotations;  // running count of applied rotations
+    T tol;          // rotate when |a_p^H a_q| > tol ||a_p|| ||a_q||
+};
+
+template <typename T>
+struct SvtArgs {
+    const cplx<T>* W;   // h slices m x n (Jacobi output)
+    const cplx<T>* V;   // h slices n x n
+    cplx<T>* Z;         // h slices m x n (rebuild output)
+    T* d;               // h x n shrink factors (1 - tau/sigma)_+ of kept columns
+    int* kept;          // h x n kept column indices
+    int* rank;          // h kept counts (multi-rank)
+    const Ctrl* ctrl;   // tau
+    int m, n, h;
+};
+
+template <typename T>
+void launch_dft_forward(int prologue, const FwdArgs<T>& a, hipStream_t st);
+template <typename T>
+void launch_dft_inverse(int epilogue, const InvArgs<T>& a, hipStream_t st);
+int dft_forward_tile(const Geometry& g);
+int dft_inverse_tile(const Geometry& g, int epilogue);
+int64_t dft_grid(const Geometry& g, int tile);
+
+template <typename T>
+void launch_jacobi_init(const JacArgs<T>& a, hipStream_t st);
+template <typename T>
+void launch_jacobi_self(const JacArgs<T>& a, int bw, hipStream_t st);
+template <typename T>
+void launch_jacobi_cross(const JacArgs<T>& a, int bw, hipStream_t st);
+int jacobi_block_width(int m, int n, int elem_bytes, int h);
+inline int jacobi_num_blocks(int n, int bw) { int nb = 2 * ((n + 2 * bw - 1) / (2 * bw)); return nb < 2 ? 2 : nb; }
+bool jacobi_supported(int m, int n, int elem_bytes);
+
+template <typename T>
+void launch_svt_weights(const SvtArgs<T>& a, hipStream_t st);
+template <typename T>
+void launch_svt_rebuild(const SvtArgs<T>& a, hipStream_t st);
+
+void launch_admm_ctrl(Ctrl* c, const double* partials, int nparts, int rpca, hipStream_t st);
+template <typename T>
+void launch_sumsq(const T* x, const uint8_t* mask, int64_t n, double* partials, int nparts,
+                  hipStream_t st);
+void launch_set_tol(Ctrl* c, const double* partials, int nparts, double tol, hipStream_t st);
+template <typename T>
+void launch_complete_output(const T* y, const uint8_t* mask, const T* z, const T* dual,
+                            const Ctrl* c, T* out, int64_t n, hipStream_t st);
+template <typename T>
+void launch_fill(T* p, T v, int64_t n, hipStream_t st);
+
+}  // namespace tsvd

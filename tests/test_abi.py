@@ -1,0 +1,73 @@
+"""The C-ABI library loads and exports every entry point declared in
+include/*.h, and the ctypes structs match the C layout (CPU only: no compute
+call is made)."""
+
+import ctypes
+import glob
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_1407_1785_amd as lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for header in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(header).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*([A-Za-z_][A-Za-z0-9_]*)\s*\(",
+                             text, flags=re.M):
+            names.add(m.group(1))
+    return names
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for fn in ("tsvt", "tsvd_complete", "trpca", "tsvd_create", "tsvd_destroy", "tsvd_set_stream",
+               "tsvd_status_string", "tsvd_last_error"):
+        assert fn in names
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(lib.library_path()):
+        pytest.skip("libtsvd.so not built")
+    so = ctypes.CDLL(lib.library_path())
+    missing = [n for n in sorted(declared_functions()) if not hasattr(so, n)]
+    assert not missing, missing
+    # every declared function has a binding signature
+    assert declared_functions() <= set(lib._SIGNATURES)
+
+
+def test_status_strings_without_gpu():
+    if not os.path.exists(lib.library_path()):
+        pytest.skip("libtsvd.so not built")
+    so = lib.load_library()
+    assert so.tsvd_status_string(0) == b"ok"
+    assert so.tsvd_status_string(-5) == b"non-finite value"
+
+
+def test_struct_layouts_match_c(tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "tsvd.h"\n'
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu\\n\", sizeof(tsvd_shape), sizeof(tsvd_admm_opts),"
+        " sizeof(tsvd_info), offsetof(tsvd_shape, n), offsetof(tsvd_info, primal),"
+        " offsetof(tsvd_admm_opts, max_sweeps));return 0;}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = list(map(int, subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()))
+    want = [ctypes.sizeof(lib.Shape), ctypes.sizeof(lib.AdmmOpts), ctypes.sizeof(lib.Info),
+            lib.Shape.n.offset, lib.Info.primal.offset, lib.AdmmOpts.max_sweeps.offset]
+    assert got == want
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    monkeypatch.setattr(lib, "_lib", None)
+    monkeypatch.setenv("TSVD_LIBRARY", str(tmp_path / "absent.so"))
+    with pytest.raises(lib.LibraryNotBuilt):
+        lib.load_library()

@@ -1,0 +1,80 @@
+"""Completion and tensor-RPCA ADMM on the GPU against the FP64 oracle, at a
+fixed iteration count (tol = 0) and through convergence."""
+
+import numpy as np
+import pytest
+
+import paper_1407_1785_amd as lib
+from oracle import admm, metrics
+import workloads
+from tests.gpu_util import announce, rel_fro, to_gpu, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.mark.parametrize("iters", [1, 5, 40])
+def test_completion_fixed_iterations(iters):
+    torch = torch_cuda()
+    w = workloads.completion_small(0)
+    ref = admm.complete(w["M_obs"], w["mask"], max_iter=iters, tol=0.0)
+    announce("complete fixed", iters)
+    x, info = lib.tsvd_complete(to_gpu(torch, w["M_obs"]), to_gpu(torch, w["mask"]), 1e-2, 0.0,
+                                max_iter=iters)
+    assert info.iters == iters and info.converged == 0
+    assert rel_fro(x.cpu().numpy(), ref["X"]) <= TOL
+    assert np.isclose(info.rho_final, ref["rho"], rtol=1e-15)
+
+
+def test_completion_converges_like_oracle():
+    torch = torch_cuda()
+    w = workloads.completion_small(0)
+    ref = admm.complete(w["M_obs"], w["mask"], w["rho"], w["growth"], w["rho_max"], w["max_iter"],
+                        w["tol"])
+    announce("complete converge")
+    x, info = lib.tsvd_complete(to_gpu(torch, w["M_obs"]), to_gpu(torch, w["mask"]), w["rho"],
+                                w["tol"])
+    x = x.cpu().numpy()
+    assert info.converged == 1
+    assert abs(info.iters - ref["iters"]) <= 1
+    assert metrics.rse(x, w["X"]) <= 1e-6
+    omega = w["mask"].astype(bool)
+    np.testing.assert_array_equal(x[omega], w["X"][omega])
+
+
+@pytest.mark.parametrize("shape", [(24, 17, 9), (15, 26, 4, 3)])
+def test_completion_ragged_and_4d(shape):
+    torch = torch_cuda()
+    rng = np.random.default_rng(11)
+    x_true = rng.normal(size=shape)
+    mask = (rng.random(shape) < 0.6).astype(np.uint8)
+    ref = admm.complete(x_true * mask, mask, max_iter=12, tol=0.0)
+    announce("complete ragged", shape)
+    x, info = lib.tsvd_complete(to_gpu(torch, x_true * mask), to_gpu(torch, mask), 1e-2, 0.0,
+                                max_iter=12)
+    assert rel_fro(x.cpu().numpy(), ref["X"]) <= TOL
+
+
+@pytest.mark.parametrize("shrink", ["l1", "l112"])
+def test_trpca_fixed_iterations(shrink):
+    torch = torch_cuda()
+    p = workloads.trpca_problem(0, shape=(48, 40, 16), rank=3)
+    ref = admm.trpca(p["M"], p["lam"], max_iter=30, tol=0.0, shrink=shrink)
+    announce("trpca fixed", shrink)
+    code = lib.SHRINK_L1 if shrink == "l1" else lib.SHRINK_L112
+    lo, sp, info = lib.trpca(to_gpu(torch, p["M"]), p["lam"], 1e-3, 0.0, shrink=code, max_iter=30)
+    assert info.iters == 30
+    assert rel_fro(lo.cpu().numpy(), ref["L"]) <= TOL
+    assert rel_fro(sp.cpu().numpy(), ref["S"]) <= 1e-9
+
+
+def test_trpca_recovers_planted():
+    torch = torch_cuda()
+    p = workloads.trpca_problem(0, shape=(48, 48, 16), rank=3)
+    ref = admm.trpca(p["M"], p["lam"], p["mu"], p["growth"], p["mu_max"], p["max_iter"], p["tol"])
+    announce("trpca converge")
+    lo, sp, info = lib.trpca(to_gpu(torch, p["M"]), p["lam"], p["mu"], p["tol"])
+    assert info.converged == 1 and abs(info.iters - ref["iters"]) <= 1
+    assert metrics.rse(lo.cpu().numpy(), p["L"]) <= 1e-5
+    assert metrics.support_f1(sp.cpu().numpy(), p["S"], p["M"]) >= 0.99

@@ -1,0 +1,99 @@
+"""t-SVT on the GPU (C ABI through the binding) against the FP64 oracle."""
+
+import numpy as np
+import pytest
+
+import paper_1407_1785_amd as lib
+from oracle.tsvt import tsvt as tsvt_oracle
+from oracle import tensor as T
+from tests.gpu_util import announce, rel_fro, to_gpu, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10   # relative Frobenius error of the FP64 path
+
+SHAPES = [
+    (32, 32, 16),     # small plain workload, square slices
+    (20, 13, 7),      # n1 > n2, odd tube length
+    (13, 20, 8),      # n1 < n2 (transposed slices), even tube length
+    (40, 33, 1),      # n3 = 1: matrix SVT
+    (70, 45, 5),      # several Jacobi blocks and a ragged last block
+    (9, 12, 3, 4),    # 4-D: complex DFT along mode 3, real along mode 4
+    (1, 7, 6),        # one column
+    (100, 3, 11),     # tall, prime tube length
+]
+
+
+def sigma_scale(x):
+    """A threshold halfway between the two singular values around the
+    median, so no singular value sits at the threshold."""
+    sv = np.sort(np.concatenate([np.linalg.svd(s, compute_uv=False) for s in np.moveaxis(
+        T.fourier_half(x).reshape(x.shape[0], x.shape[1], -1), 2, 0)]))
+    k = len(sv) // 2
+    return float(0.5 * (sv[k - 1] + sv[k])) if len(sv) > 1 else float(0.5 * sv[0])
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_tsvt_matches_oracle(shape):
+    torch = torch_cuda()
+    rng = np.random.default_rng(sum(shape))
+    x = rng.normal(size=shape)
+    tau = sigma_scale(x)
+    z_ref, r_ref = tsvt_oracle(x, tau)
+    announce("tsvt", shape, tau)
+    z, ranks = lib.tsvt(to_gpu(torch, x), tau)
+    z = z.cpu().numpy()
+    assert rel_fro(z, z_ref) <= TOL
+    assert np.abs(z - z_ref).max() <= TOL * np.abs(z_ref).max()
+    assert ranks == list(r_ref)
+
+
+def test_tsvt_low_rank_input_and_extreme_thresholds():
+    torch = torch_cuda()
+    rng = np.random.default_rng(5)
+    a, b = rng.normal(size=(48, 3, 16)), rng.normal(size=(3, 40, 16))
+    x = np.einsum("ikt,kjt->ijt", np.fft.rfft(a, axis=2), np.fft.rfft(b, axis=2))
+    x = np.fft.irfft(x, n=16, axis=2)
+    xg = to_gpu(torch, x)
+    for tau in (0.0, 1e-3, 5.0, 1e6):
+        announce("tsvt low-rank", tau)
+        z_ref, r_ref = tsvt_oracle(x, tau)
+        z, ranks = lib.tsvt(xg, tau)
+        z = z.cpu().numpy()
+        if np.abs(z_ref).max() == 0:
+            assert np.abs(z).max() == 0
+        else:
+            assert rel_fro(z, z_ref) <= TOL
+        assert ranks == list(r_ref)
+
+
+def test_tsvt_video_shape_sampled():
+    """Full video-shaped slice size (128 x 160 x 64): whole-tensor parity."""
+    torch = torch_cuda()
+    import workloads
+
+    w = workloads.video_completion(0)
+    x = w["X"].astype(np.float64)
+    tau = 5.0
+    z_ref, r_ref = tsvt_oracle(x, tau)
+    announce("tsvt video", x.shape)
+    z, ranks = lib.tsvt(to_gpu(torch, x), tau)
+    assert rel_fro(z.cpu().numpy(), z_ref) <= TOL
+    assert ranks == list(r_ref)
+
+
+def test_tsvt_errors():
+    torch = torch_cuda()
+    x = torch.zeros((4, 5, 6), dtype=torch.float64, device="cuda")
+    announce("tsvt errors")
+    with pytest.raises(lib.TsvdError) as e:
+        lib.tsvt(x, -1.0)
+    assert e.value.status == -1
+    bad = x.clone()
+    bad[1, 2, 3] = float("nan")
+    with pytest.raises(lib.TsvdError) as e:
+        lib.tsvt(bad, 1.0)
+    assert e.value.status == -5
+    with pytest.raises(lib.TsvdError) as e:
+        lib.tsvt(x.float(), 1.0)
+    assert e.value.status == -6
