@@ -88,6 +88,8 @@ struct tsvd_handle_s {
     std::vector<Pending> pending;
     std::vector<Agg> agg;
     unsigned long long* rot_counter = nullptr;   // [0] self, [1] cross
+    int cus = 0;
+    size_t lds_cap = 0;
 };
 
 namespace {
@@ -150,26 +152,39 @@ struct Carver {
 
 template <typename T>
 struct SvtBuffers {
-    cplx<T>* A;
-    cplx<T>* Z;
-    cplx<T>* V;
+    cplx<T>* A;       // slices in (and Jacobi work array on a cold start)
+    cplx<T>* Z;       // second slice buffer
+    cplx<T>* V[2];    // right singular vectors, ping-pong for re-orthonormalisation
+    cplx<T>* G;       // n x n Gram scratch
     T* d;
     int* kept;
     int* rank;
     int* rot;
     int* sweeps;
+    int* pbar;        // persistent Jacobi: h barrier counters, 3h flags, 1 error word
     double* partials;
     int nparts;
+};
+
+// Warm-start state carried across the iterations of one solve.
+struct WarmState {
+    bool enabled = false;   // pre-rotate by the previous V
+    bool valid = false;     // V[vcur] holds the previous iteration's V
+    int vcur = 0;
+    int iter = 0;
+    int reorth_every = 4;
 };
 
 template <typename T>
 size_t svt_bytes(const Geometry& g, int nparts) {
     const int64_t slice = (int64_t)g.h * g.m * g.n;
+    const int64_t vv = (int64_t)g.h * g.n * g.n;
     size_t b = 0;
     b += 2 * slice * sizeof(cplx<T>) + 512;
-    b += (int64_t)g.h * g.n * g.n * sizeof(cplx<T>) + 256;
+    b += 3 * vv * sizeof(cplx<T>) + 768;
     b += (int64_t)g.h * g.n * (sizeof(T) + sizeof(int)) + 512;
     b += (int64_t)g.h * 5 * sizeof(int) + 768;
+    b += (int64_t)(4 * g.h + 1) * sizeof(int) + 256;
     b += (int64_t)nparts * kNumPartials * sizeof(double) + 256;
     return b;
 }
@@ -178,14 +193,18 @@ template <typename T>
 SvtBuffers<T> carve_svt(Carver& c, const Geometry& g, int nparts) {
     SvtBuffers<T> s{};
     const int64_t slice = (int64_t)g.h * g.m * g.n;
+    const int64_t vv = (int64_t)g.h * g.n * g.n;
     s.A = c.take<cplx<T>>(slice);
     s.Z = c.take<cplx<T>>(slice);
-    s.V = c.take<cplx<T>>((int64_t)g.h * g.n * g.n);
+    s.V[0] = c.take<cplx<T>>(vv);
+    s.V[1] = c.take<cplx<T>>(vv);
+    s.G = c.take<cplx<T>>(vv);
     s.d = c.take<T>((int64_t)g.h * g.n);
     s.kept = c.take<int>((int64_t)g.h * g.n);
     s.rank = c.take<int>(g.h);
     s.rot = c.take<int>(3 * g.h);
     s.sweeps = c.take<int>(g.h);
+    s.pbar = c.take<int>(4 * g.h + 1);
     s.partials = c.take<double>((int64_t)nparts * kNumPartials);
     s.nparts = nparts;
     return s;
@@ -238,11 +257,12 @@ void ensure_twiddles(tsvd_handle h, int L) {
 // Kernel families reported by tsvd_profile_read.
 enum Kind : int {
     K_DFT_FWD = 0, K_JAC_INIT, K_JAC_SELF, K_JAC_CROSS, K_SVT_W, K_SVT_REBUILD, K_DFT_INV,
-    K_CTRL, K_OTHER, K_COUNT
+    K_CTRL, K_GEMM, K_JAC_PERSIST, K_OTHER, K_COUNT
 };
 const char* kKindName[K_COUNT] = {"dft_forward", "jacobi_init", "jacobi_self", "jacobi_cross",
-                                  "svt_weights", "svt_rebuild", "dft_inverse", "admm_ctrl", "other"};
-const bool kKindBytes[K_COUNT] = {true, true, false, false, true, true, true, true, true};
+                                  "svt_weights", "svt_rebuild", "dft_inverse", "admm_ctrl",
+                                  "warm_gemm", "jacobi_persistent", "other"};
+const bool kKindBytes[K_COUNT] = {true, true, false, false, true, true, true, true, false, false, true};
 
 hipEvent_t take_event(tsvd_handle h) {
     if (!h->ev_pool.empty()) {
@@ -317,6 +337,7 @@ int64_t cross_pairs(int n, int nb, int round) {
 
 struct SweepStats {
     int sweeps = 0;
+    const void* out = nullptr;   // slice buffer holding the prox output
 };
 
 // Jacobi sweeps + shrink + rebuild on the slices in sb.A; output in sb.Z.
@@ -326,14 +347,52 @@ struct SweepStats {
 // applied rotation another 16 (m + n) (the 2 x 2 complex update of the m
 // slice rows and n V rows of both columns).
 template <typename T>
-SweepStats run_svt(tsvd_handle h, const Geometry& g, const SvtBuffers<T>& sb, int max_sweeps) {
+SweepStats run_svt(tsvd_handle h, const Geometry& g, const SvtBuffers<T>& sb, int max_sweeps,
+                   WarmState* warm = nullptr) {
     hipStream_t st = h->stream;
+    const bool use_warm = warm && warm->enabled && warm->valid;
+    const int64_t nn = (int64_t)g.n * g.n, mn = (int64_t)g.m * g.n;
+    cplx<T>* work = sb.A;   // Jacobi work array
+    cplx<T>* out = sb.Z;    // rebuild output
+    int vc = warm ? warm->vcur : 0;
+    if (use_warm) {
+        if (warm->reorth_every > 0 && warm->iter % warm->reorth_every == 0) {
+            // V <- 1.5 V - 0.5 V (V^H V): one Newton-Schulz step towards unitary
+            GemmArgs<T> gg{};
+            gg.A = sb.V[vc]; gg.B = sb.V[vc]; gg.C = sb.G;
+            gg.M = gg.N = gg.K = g.n;
+            gg.lda = gg.ldb = gg.ldc = gg.ldd = g.n;
+            gg.sA = gg.sB = gg.sC = gg.sD = nn;
+            gg.alpha = (T)1; gg.beta = (T)0; gg.opA_h = 1; gg.batch = g.h;
+            prof_launch(h, K_GEMM, 8.0 * g.n * g.n * g.n * g.h, [&] { launch_cgemm(gg, st); });
+            launch_check("gemm gram");
+            GemmArgs<T> gn = gg;
+            gn.A = sb.V[vc]; gn.B = sb.G; gn.D = sb.V[vc]; gn.C = sb.V[1 - vc];
+            gn.alpha = (T)-0.5; gn.beta = (T)1.5; gn.opA_h = 0;
+            prof_launch(h, K_GEMM, 8.0 * g.n * g.n * g.n * g.h, [&] { launch_cgemm(gn, st); });
+            launch_check("gemm newton-schulz");
+            vc = 1 - vc;
+            warm->vcur = vc;
+        }
+        // pre-rotate: work = A V_prev
+        GemmArgs<T> ga{};
+        ga.A = sb.A; ga.B = sb.V[vc]; ga.C = sb.Z;
+        ga.M = g.m; ga.N = g.n; ga.K = g.n;
+        ga.lda = g.m; ga.ldb = g.n; ga.ldc = g.m; ga.ldd = g.m;
+        ga.sA = mn; ga.sB = nn; ga.sC = mn; ga.sD = mn;
+        ga.alpha = (T)1; ga.beta = (T)0; ga.opA_h = 0; ga.batch = g.h;
+        prof_launch(h, K_GEMM, 8.0 * g.m * g.n * g.n * g.h, [&] { launch_cgemm(ga, st); });
+        launch_check("gemm prerotate");
+        work = sb.Z;
+        out = sb.A;
+    }
     JacArgs<T> ja{};
-    ja.A = sb.A;
-    ja.V = sb.V;
+    ja.A = work;
+    ja.V = sb.V[vc];
     ja.m = g.m;
     ja.n = g.n;
     ja.h = g.h;
+    ja.reset_v = use_warm ? 0 : 1;
     int bw = env_int("TSVD_JACOBI_BW", 0);
     if (bw != 4 && bw != 8 && bw != 16) bw = jacobi_block_width(g.m, g.n, sizeof(T), g.h);
     ja.nb = jacobi_num_blocks(g.n, bw);
@@ -341,14 +400,77 @@ SweepStats run_svt(tsvd_handle h, const Geometry& g, const SvtBuffers<T>& sb, in
     ja.sweeps = sb.sweeps;
     ja.tol = (T)env_double("TSVD_JACOBI_TOL", std::sqrt((double)g.m) * 2.220446049250313e-16);
     ja.rotations = h->rot_counter;
-    prof_launch(h, K_JAC_INIT, (double)g.h * g.n * g.n * sizeof(cplx<T>),
-                [&] { launch_jacobi_init(ja, st); });
-    launch_check("jacobi_init");
     const int check_every = std::max(1, env_int("TSVD_CHECK_EVERY", 1));
     ensure_host_ints(h, g.h);
     SweepStats stats;
-    int active = g.h;   // slices still rotating, as last observed
     const double dot_flops = 16.0 * g.m;
+    const bool persist = env_int("TSVD_PERSIST", 1) != 0 &&
+                         jacobi_persistent_fits(g.m, g.n, g.h, sizeof(T), h->cus, h->lds_cap);
+    bool done_persist = false;
+    if (persist) {
+        // one cooperative launch runs every sweep
+        ja.nb = jacobi_persistent_blocks(g.n);
+        ja.rotations = h->rot_counter + 1;
+        prof_launch(h, K_JAC_INIT, (double)g.h * g.n * g.n * sizeof(cplx<T>),
+                    [&] { launch_jacobi_init(ja, st); });
+        launch_check("jacobi_init");
+        launch_fill<int>(sb.pbar, 0, 4 * g.h, st);   // the error word is cleared per call
+        launch_check("fill");
+        PersistArgs pa{sb.pbar, sb.pbar + g.h, sb.pbar + 4 * g.h, max_sweeps, nullptr};
+        static long long* trace_buf = nullptr;
+        const bool tracing = env_int("TSVD_TRACE", 0) != 0;
+        if (tracing) {
+            if (!trace_buf) hip_check(hipMalloc(&trace_buf, 64 * sizeof(long long)), "hipMalloc trace");
+            hip_check(hipMemsetAsync(trace_buf, 0, 64 * sizeof(long long), st), "hipMemsetAsync trace");
+            pa.trace = trace_buf;
+        }
+        hipError_t e = hipSuccess;
+        const int ip = prof_launch(h, K_JAC_PERSIST, 0.0,
+                                   [&] { e = launch_jacobi_persistent(ja, pa, h->cus, st); });
+        if (e == hipSuccess && tracing) {
+            long long tb[64];
+            hip_check(hipMemcpyAsync(tb, trace_buf, sizeof(tb), hipMemcpyDeviceToHost, st), "trace copy");
+            hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+            int rate_khz = 0;
+            (void)hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, h->device);
+            std::fprintf(stderr, "[tsvd trace] us since start:");
+            for (int i = 1; i < 64 && tb[i]; ++i)
+                std::fprintf(stderr, " %.1f", (double)(tb[i] - tb[0]) * 1e3 / (double)rate_khz);
+            std::fprintf(stderr, "\n");
+        }
+        if (e == hipSuccess) {
+            done_persist = true;
+            stats.sweeps = -1;   // known on the device only
+            if (h->prof_on) {
+                // visited pairs: n(n-1)/2 per slice per sweep run
+                hip_check(hipMemcpyAsync(h->host_ints, sb.sweeps, sizeof(int) * g.h, hipMemcpyDeviceToHost, st),
+                          "hipMemcpyAsync sweeps");
+                hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+                int64_t sw = 0;
+                int smax = 0;
+                for (int s = 0; s < g.h; ++s) {
+                    sw += h->host_ints[s];
+                    smax = std::max(smax, h->host_ints[s]);
+                }
+                if (ip >= 0) h->pending[ip].work = dot_flops * (double)sw * g.n * (g.n - 1) / 2.0;
+                stats.sweeps = smax;
+            }
+        } else {
+            (void)hipGetLastError();
+            if (ip >= 0) {
+                // the timing events bracket nothing; drop the record
+                h->ev_pool.push_back(h->pending[ip].a);
+                h->ev_pool.push_back(h->pending[ip].b);
+                h->pending.erase(h->pending.begin() + ip);
+            }
+        }
+    }
+    if (!done_persist) {
+    ja.nb = jacobi_num_blocks(g.n, bw);
+    prof_launch(h, K_JAC_INIT, (double)g.h * g.n * g.n * sizeof(cplx<T>),
+                [&] { launch_jacobi_init(ja, st); });
+    launch_check("jacobi_init");
+    int active = g.h;   // slices still rotating, as last observed
     for (int sw = 0; sw < max_sweeps; ++sw) {
         ja.sweep = sw;
         ja.rotations = h->rot_counter;
@@ -373,10 +495,11 @@ SweepStats run_svt(tsvd_handle h, const Geometry& g, const SvtBuffers<T>& sb, in
             if (!active) break;
         }
     }
+    }
     SvtArgs<T> sa{};
-    sa.W = sb.A;
-    sa.V = sb.V;
-    sa.Z = sb.Z;
+    sa.W = work;
+    sa.V = sb.V[vc];
+    sa.Z = out;
     sa.d = sb.d;
     sa.kept = sb.kept;
     sa.rank = sb.rank;
@@ -406,8 +529,13 @@ SweepStats run_svt(tsvd_handle h, const Geometry& g, const SvtBuffers<T>& sb, in
         if (ir >= 0) h->pending[ir].work = (double)slice_bytes + (double)kept * (g.m + g.n) * sizeof(cplx<T>);
         prof_harvest(h);
         h->agg[K_JAC_SELF].work += rot_flops * (double)rots[0];
-        h->agg[K_JAC_CROSS].work += rot_flops * (double)rots[1];
+        h->agg[done_persist ? K_JAC_PERSIST : K_JAC_CROSS].work += rot_flops * (double)rots[1];
     }
+    if (warm) {
+        warm->valid = true;
+        warm->iter += 1;
+    }
+    stats.out = out;
     return stats;
 }
 
@@ -426,6 +554,28 @@ Ctrl get_ctrl(tsvd_handle h) {
 }
 
 void clear_flag(tsvd_handle h) { launch_fill<int>(h->flag, 0, 1, h->stream); }
+
+// error word of the persistent Jacobi barriers (last int of the pbar area)
+template <typename T>
+void clear_persist_err(tsvd_handle h, const Geometry& g, const SvtBuffers<T>& sb) {
+    launch_fill<int>(sb.pbar + 4 * g.h, 0, 1, h->stream);
+}
+
+template <typename T>
+void check_persist_err(tsvd_handle h, const Geometry& g, const SvtBuffers<T>& sb) {
+    ensure_host_ints(h, 1);
+    hip_check(hipMemcpyAsync(h->host_ints, sb.pbar + 4 * g.h, sizeof(int), hipMemcpyDeviceToHost, h->stream),
+              "hipMemcpyAsync err");
+    hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+    if (h->host_ints[0]) fail(TSVD_E_HIP, "Jacobi slice barrier wait ran out");
+}
+
+// largest per-slice sweep count of the last SVD (read after a sync)
+int max_sweeps_of(tsvd_handle h, int nslices) {
+    int mx = 0;
+    for (int s = 0; s < nslices; ++s) mx = std::max(mx, h->host_ints[s]);
+    return mx;
+}
 
 bool read_flag(tsvd_handle h) {
     ensure_host_ints(h, 1);
@@ -500,8 +650,15 @@ tsvd_status tsvd_create(int device, size_t hbm_budget_bytes, tsvd_handle* out) {
         hip_check(hipGetDeviceCount(&count), "hipGetDeviceCount");
         if (device < 0 || device >= count) fail(TSVD_E_INVALID, "no such device");
         Device dev(device);
+        int lds_max = 0;
+        if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, device) ==
+                hipSuccess &&
+            lds_max > 0)
+            jacobi_set_lds_limit((size_t)std::min(lds_max, env_int("TSVD_LDS_LIMIT", lds_max)));
         tsvd_handle h = new tsvd_handle_s();
         h->device = device;
+        (void)hipDeviceGetAttribute(&h->cus, hipDeviceAttributeMultiprocessorCount, device);
+        h->lds_cap = lds_max > 0 ? (size_t)lds_max : 65536;
         h->budget = hbm_budget_bytes;
         hipError_t e = hipMalloc(reinterpret_cast<void**>(&h->ctrl), sizeof(Ctrl));
         if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&h->flag), sizeof(int));
@@ -569,6 +726,7 @@ tsvd_status tsvt(tsvd_handle h, const void* X, tsvd_shape shape, tsvd_dtype dtyp
         c.dscale = 1.0;
         put_ctrl(h, c);
         clear_flag(h);
+        clear_persist_err(h, g, sb);
 
         FwdArgs<T> fa{};
         fa.x = static_cast<const T*>(X);
@@ -582,9 +740,9 @@ tsvd_status tsvt(tsvd_handle h, const void* X, tsvd_shape shape, tsvd_dtype dtyp
         prof_launch(h, K_DFT_FWD, slice_bytes + (double)g.numel * sizeof(T),
                     [&] { launch_dft_forward(PRO_COPY, fa, h->stream); });
         launch_check("dft_forward");
-        run_svt<T>(h, g, sb, 30);
+        const SweepStats ss = run_svt<T>(h, g, sb, 30);
         InvArgs<T> ia{};
-        ia.in = sb.Z;
+        ia.in = static_cast<const cplx<T>*>(ss.out);
         ia.tw = h->tw;
         ia.ctrl = h->ctrl;
         ia.g = g;
@@ -602,6 +760,7 @@ tsvd_status tsvt(tsvd_handle h, const void* X, tsvd_shape shape, tsvd_dtype dtyp
         hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
         if (multirank_host) std::memcpy(multirank_host, h->host_ints, sizeof(int) * g.h);
         prof_harvest(h);
+        check_persist_err(h, g, sb);
         if (read_flag(h)) fail(TSVD_E_NONFINITE, "non-finite input");
     });
 }
@@ -647,6 +806,7 @@ tsvd_status tsvd_complete(tsvd_handle h, const void* X_obs, const uint8_t* mask,
         launch_set_tol(h->ctrl, sb.partials, elementwise_parts(), tol, st);
         launch_check("setup");
         clear_flag(h);
+        clear_persist_err(h, g, sb);
 
         FwdArgs<T> fa{};
         fa.x = Y;
@@ -670,6 +830,9 @@ tsvd_status tsvd_complete(tsvd_handle h, const void* X_obs, const uint8_t* mask,
         const double slice_bytes = (double)g.h * g.m * g.n * sizeof(cplx<T>);
         int sweeps_total = 0, sweeps_last = 0, iters = 0;
         Ctrl hc{};
+        WarmState warm;
+        warm.enabled = env_int("TSVD_WARM", 1) != 0;
+        warm.reorth_every = env_int("TSVD_REORTH_EVERY", 4);
         for (int k = 0; k < s.max_iter; ++k) {
             fa.z = Zb[k % 2];
             fa.dual = Qb[k % 2];
@@ -677,9 +840,13 @@ tsvd_status tsvd_complete(tsvd_handle h, const void* X_obs, const uint8_t* mask,
             prof_launch(h, K_DFT_FWD, slice_bytes + (double)N * (3 * sizeof(T) + 1),
                         [&] { launch_dft_forward(PRO_COMPLETE, fa, st); });
             launch_check("dft_forward");
-            const SweepStats ss = run_svt<T>(h, g, sb, s.max_sweeps);
-            sweeps_total += ss.sweeps;
-            sweeps_last = ss.sweeps;
+            const SweepStats ss = run_svt<T>(h, g, sb, s.max_sweeps, &warm);
+            if (ss.sweeps < 0) {
+                ensure_host_ints(h, g.h);
+                hip_check(hipMemcpyAsync(h->host_ints, sb.sweeps, sizeof(int) * g.h, hipMemcpyDeviceToHost, st),
+                          "hipMemcpyAsync sweeps");
+            }
+            ia.in = static_cast<const cplx<T>*>(ss.out);
             ia.out = Zb[(k + 1) % 2];
             ia.z_old = Zb[k % 2];
             ia.dual_old = Qb[k % 2];
@@ -692,6 +859,8 @@ tsvd_status tsvd_complete(tsvd_handle h, const void* X_obs, const uint8_t* mask,
                         [&] { launch_admm_ctrl(h->ctrl, sb.partials, inv_parts, 0, st); });
             launch_check("admm_ctrl");
             hc = get_ctrl(h);
+            sweeps_last = ss.sweeps >= 0 ? ss.sweeps : max_sweeps_of(h, g.h);
+            sweeps_total += sweeps_last;
             iters = k + 1;
             if (hc.done) break;
         }
@@ -700,6 +869,7 @@ tsvd_status tsvd_complete(tsvd_handle h, const void* X_obs, const uint8_t* mask,
         launch_check("complete_output");
         hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
         prof_harvest(h);
+        check_persist_err(h, g, sb);
         if (hc.nonfinite || read_flag(h)) fail(TSVD_E_NONFINITE, "non-finite input or iterate");
         if (info_host) {
             info_host->iters = iters;
@@ -763,6 +933,7 @@ tsvd_status trpca(tsvd_handle h, const void* X, tsvd_shape shape, tsvd_dtype dty
         launch_set_tol(h->ctrl, sb.partials, elementwise_parts(), tol, st);
         launch_check("setup");
         clear_flag(h);
+        clear_persist_err(h, g, sb);
 
         FwdArgs<T> fa{};
         fa.x = M;
@@ -784,6 +955,9 @@ tsvd_status trpca(tsvd_handle h, const void* X, tsvd_shape shape, tsvd_dtype dty
         const double slice_bytes = (double)g.h * g.m * g.n * sizeof(cplx<T>);
         int sweeps_total = 0, sweeps_last = 0, iters = 0;
         Ctrl hc{};
+        WarmState warm;
+        warm.enabled = env_int("TSVD_WARM", 1) != 0;
+        warm.reorth_every = env_int("TSVD_REORTH_EVERY", 4);
         for (int k = 0; k < s.max_iter; ++k) {
             fa.s = Sb[k % 2];
             fa.dual = Wb[k % 2];
@@ -791,9 +965,13 @@ tsvd_status trpca(tsvd_handle h, const void* X, tsvd_shape shape, tsvd_dtype dty
             prof_launch(h, K_DFT_FWD, slice_bytes + (double)N * 3 * sizeof(T),
                         [&] { launch_dft_forward(PRO_RPCA, fa, st); });
             launch_check("dft_forward");
-            const SweepStats ss = run_svt<T>(h, g, sb, s.max_sweeps);
-            sweeps_total += ss.sweeps;
-            sweeps_last = ss.sweeps;
+            const SweepStats ss = run_svt<T>(h, g, sb, s.max_sweeps, &warm);
+            if (ss.sweeps < 0) {
+                ensure_host_ints(h, g.h);
+                hip_check(hipMemcpyAsync(h->host_ints, sb.sweeps, sizeof(int) * g.h, hipMemcpyDeviceToHost, st),
+                          "hipMemcpyAsync sweeps");
+            }
+            ia.in = static_cast<const cplx<T>*>(ss.out);
             ia.out = Lb[(k + 1) % 2];
             ia.l_old = Lb[k % 2];
             ia.s_old = Sb[k % 2];
@@ -808,6 +986,8 @@ tsvd_status trpca(tsvd_handle h, const void* X, tsvd_shape shape, tsvd_dtype dty
                         [&] { launch_admm_ctrl(h->ctrl, sb.partials, inv_parts, 1, st); });
             launch_check("admm_ctrl");
             hc = get_ctrl(h);
+            sweeps_last = ss.sweeps >= 0 ? ss.sweeps : max_sweeps_of(h, g.h);
+            sweeps_total += sweeps_last;
             iters = k + 1;
             if (hc.done) break;
         }
@@ -817,6 +997,7 @@ tsvd_status trpca(tsvd_handle h, const void* X, tsvd_shape shape, tsvd_dtype dty
                   "hipMemcpyAsync S");
         hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
         prof_harvest(h);
+        check_persist_err(h, g, sb);
         if (hc.nonfinite || read_flag(h)) fail(TSVD_E_NONFINITE, "non-finite input or iterate");
         if (info_host) {
             info_host->iters = iters;

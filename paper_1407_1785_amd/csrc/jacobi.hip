@@ -4,35 +4,43 @@
 // problem per Fourier slice (Sec. 4.1, eq. shrink2), each solved by the
 // singular value shrinkage lemma of Sec. 4.1, which needs an SVD of the
 // slice.  Here every m x n slice (m >= n) is orthogonalised column-wise:
-// plane rotations J are applied on the right, A <- A J and V <- V J (V
-// starts at the identity), until every column pair satisfies
-// |a_p^H a_q| <= tol ||a_p|| ||a_q||.  Then A = W with orthogonal columns,
-// sigma_j = ||w_j||, and the slice equals W V^H.
+// plane rotations J are applied on the right, A <- A J and V <- V J, until
+// every column pair satisfies |a_p^H a_q| <= tol ||a_p|| ||a_q||.  Then
+// A = W with orthogonal columns, sigma_j = ||w_j||, and the slice is W V^H.
+// V starts at the identity (cold start) or at the previous ADMM iteration's
+// V with A pre-rotated to A V (warm start, see gemm.hip).
 //
 // Rotation of a pair (alpha = ||a_p||^2, beta = ||a_q||^2,
 // gamma = a_p^H a_q = |gamma| e):
 //   zeta = (beta - alpha) / (2 |gamma|),
 //   t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), c = 1/sqrt(1 + t^2), s = c t,
 //   a_p <- c a_p - s conj(e) a_q,   a_q <- s e a_p + c a_q,
-// which makes the new pair orthogonal.
+// which makes the new pair orthogonal.  The rotation is unitary whatever
+// the rounding of t, because c is computed from t (to full precision) and
+// |e| = 1 (to full precision); t itself only has to be close.
 //
 // Parallel ordering (block round-robin).  The n columns are cut into nb
 // blocks of at most BW columns.  One sweep visits every column pair once:
 //   * jacobi_self: every block orthogonalises its own columns (round-robin
-//     over the block, BW/2 pairs at a time), one workgroup per block;
+//     over the block), one workgroup per block;
 //   * jacobi_cross, rounds 0..nb-2 of a round-robin tournament over the
 //     blocks: every workgroup takes one block pair (I, J) and visits the
-//     BW x BW cross pairs in BW steps.  Group g of the workgroup keeps
-//     column g of I in registers; the J block sits in LDS and column
-//     (g + step) mod BW is the partner at each step.
-// A column's V entries ride along as extra rows (rows m..m+n-1 of the
-// stacked column), so they are rotated with the same coefficients and are
-// excluded from the dot products.
+//     BW x BW cross pairs in BW steps.  Wavefront g keeps column g of I in
+//     registers; the J block sits in LDS and column (g + step) mod BW is its
+//     partner at each step.
+// One column pair = one wavefront: each lane holds rows lane + 64 k of the
+// stacked column (the m slice rows, then the n rows of V, which are rotated
+// with the same coefficients but excluded from the dot products).  The
+// three dot products are reduced across the wavefront with DPP row
+// operations and readlane, so the rotation parameters are wave-uniform.
 //
 // Convergence is tracked per slice: sweep k sets rot[k % 3][s] when any
 // pair of slice s was rotated; a slice whose previous sweep rotated nothing
-// is skipped.  Sweep k also clears ring entry (k+1) % 3, which nobody reads
-// or writes during sweep k.
+// is skipped.  Sweep k also clears ring entry (k+1) % 3 of every slice,
+// skipped or not, which nobody reads or writes during sweep k.
+//
+// Work model (floating-point operations): a visited pair costs 16 m for the
+// three dot products; an applied rotation another 16 (m + n).
 
 #include "kernels.h"
 
@@ -46,47 +54,82 @@ __device__ __forceinline__ int blk_start(int b, int n, int nb) {
     return (int)(((int64_t)b * n) / nb);
 }
 
-// round-robin (circle method) partner lists: player at position pos in round r
+// round-robin (circle method): player at position pos in round r
 __device__ __forceinline__ int rr_player(int pos, int r, int nplayers) {
     return pos == 0 ? 0 : 1 + (pos - 1 + r) % (nplayers - 1);
 }
 
-template <int TPG, typename T>
-__device__ __forceinline__ T group_sum(T v) {
-#pragma unroll
-    for (int off = TPG / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+// ---- wave-wide FP64 sum: DPP within 16-lane rows, readlane across rows
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
 }
 
-template <typename T>
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+
+// every lane receives the same sum (rows summed in a fixed order)
+__device__ __forceinline__ double wave_sum(double v) {
+    v += dpp_f64<0xB1>(v);    // quad_perm [1,0,3,2]: lane ^ 1
+    v += dpp_f64<0x4E>(v);    // quad_perm [2,3,0,1]: lane ^ 2
+    v += dpp_f64<0x141>(v);   // row_half_mirror: the other quad of the half row
+    v += dpp_f64<0x140>(v);   // row_mirror: the other half of the row
+    return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
+}
+
+// ---- rotation parameters (FP64, wave-uniform)
+
+__device__ __forceinline__ double rsqrt_acc(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    y = y * (1.5 - 0.5 * x * y * y);
+    y = y * (1.5 - 0.5 * x * y * y);
+    return y;
+}
+
+__device__ __forceinline__ double rcp_close(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    y = y * (2.0 - x * y);
+    return y;
+}
+
 struct Rot {
-    T c, s, er, ei;
+    double c, s, er, ei;
 };
 
-// Rotation parameters from the reduced pair sums; false when the pair is
-// already orthogonal to tolerance (or a column is zero).
-template <typename T>
-__device__ __forceinline__ bool make_rotation(T al, T be, T gr, T gi, T tol, Rot<T>& r) {
-    const T g = sqrt(gr * gr + gi * gi);
-    if (!(g > tol * sqrt(al) * sqrt(be))) return false;
-    const T zeta = (be - al) / (g + g);
-    const T t = (zeta >= (T)0 ? (T)1 : (T)-1) / (fabs(zeta) + sqrt((T)1 + zeta * zeta));
-    r.c = (T)1 / sqrt((T)1 + t * t);
-    r.s = r.c * t;
-    r.er = gr / g;
-    r.ei = gi / g;
+// False when the pair is already orthogonal to tolerance (or a column is 0).
+__device__ __forceinline__ bool make_rotation(double al, double be, double gr, double gi, double tol,
+                                              Rot& r) {
+    const double g2 = gr * gr + gi * gi;
+    if (!(g2 > (tol * tol) * al * be) || !(g2 > 0.0)) return false;
+    const double rg = rsqrt_acc(g2);
+    const double zeta = (be - al) * 0.5 * rg;
+    const double az = fabs(zeta);
+    const double q = 1.0 + zeta * zeta;
+    const double t = rcp_close(az + q * rsqrt_acc(q));
+    const double ts = zeta >= 0.0 ? t : -t;
+    r.c = rsqrt_acc(1.0 + ts * ts);
+    r.s = r.c * ts;
+    r.er = gr * rg;
+    r.ei = gi * rg;
     return true;
 }
 
 // (x, y) <- (c x - s conj(e) y, s e x + c y)
 template <typename T>
-__device__ __forceinline__ void apply_rotation(const Rot<T>& r, cplx<T>& x, cplx<T>& y) {
-    const T ycr = r.er * y.re + r.ei * y.im;   // conj(e) y
-    const T yci = r.er * y.im - r.ei * y.re;
-    const T exr = r.er * x.re - r.ei * x.im;   // e x
-    const T exi = r.er * x.im + r.ei * x.re;
-    const cplx<T> xn{r.c * x.re - r.s * ycr, r.c * x.im - r.s * yci};
-    const cplx<T> yn{r.s * exr + r.c * y.re, r.s * exi + r.c * y.im};
+__device__ __forceinline__ void apply_rotation(const Rot& rd, cplx<T>& x, cplx<T>& y) {
+    const T c = (T)rd.c, s = (T)rd.s, er = (T)rd.er, ei = (T)rd.ei;
+    const T ycr = er * y.re + ei * y.im;   // conj(e) y
+    const T yci = er * y.im - ei * y.re;
+    const T exr = er * x.re - ei * x.im;   // e x
+    const T exi = er * x.im + ei * x.re;
+    const cplx<T> xn{c * x.re - s * ycr, c * x.im - s * yci};
+    const cplx<T> yn{s * exr + c * y.re, s * exi + c * y.im};
     x = xn;
     y = yn;
 }
@@ -100,18 +143,45 @@ __device__ __forceinline__ void accum_pair(const cplx<T>& x, const cplx<T>& y, T
     gi += x.re * y.im - x.im * y.re;   // Im(conj(x) y)
 }
 
+// pointer to row r of stacked column `col` of slice s (A rows, then V rows)
 template <typename T>
-__device__ __forceinline__ cplx<T> load_stacked(const JacArgs<T>& a, int s, int col, int r) {
-    if (r < a.m) return a.A[((int64_t)s * a.n + col) * a.m + r];
-    return a.V[((int64_t)s * a.n + col) * a.n + (r - a.m)];
+__device__ __forceinline__ cplx<T>* stacked(const JacArgs<T>& a, int s, int col, int r) {
+    return r < a.m ? a.A + ((int64_t)s * a.n + col) * a.m + r
+                   : a.V + ((int64_t)s * a.n + col) * a.n + (r - a.m);
+}
+
+// Copy w stacked columns of slice s from global memory to LDS (column-major,
+// `rows` per column), four independent loads in flight per thread.
+template <typename T>
+__device__ __forceinline__ void block_to_lds(const JacArgs<T>& a, int s, int c0, int w, int rows,
+                                             cplx<T>* lds) {
+    const int total = w * rows;
+    for (int base = threadIdx.x; base < total; base += 4 * blockDim.x) {
+        cplx<T> v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int idx = base + u * blockDim.x;
+            if (idx < total) {
+                const int c = idx / rows, r = idx - c * rows;
+                v[u] = *stacked(a, s, c0 + c, r);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int idx = base + u * blockDim.x;
+            if (idx < total) lds[idx] = v[u];
+        }
+    }
 }
 
 template <typename T>
-__device__ __forceinline__ void store_stacked(const JacArgs<T>& a, int s, int col, int r, cplx<T> v) {
-    if (r < a.m)
-        a.A[((int64_t)s * a.n + col) * a.m + r] = v;
-    else
-        a.V[((int64_t)s * a.n + col) * a.n + (r - a.m)] = v;
+__device__ __forceinline__ void lds_to_block(const JacArgs<T>& a, int s, int c0, int w, int rows,
+                                             const cplx<T>* lds) {
+    const int total = w * rows;
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+        const int c = idx / rows, r = idx - c * rows;
+        *stacked(a, s, c0 + c, r) = lds[idx];
+    }
 }
 
 // true when slice s converged in an earlier sweep
@@ -120,16 +190,44 @@ __device__ __forceinline__ bool slice_done(const JacArgs<T>& a, int s) {
     return a.sweep > 0 && a.rot[((a.sweep - 1) % 3) * a.h + s] == 0;
 }
 
+// One pair step for a wavefront: x (registers) against column y in LDS.
+// Returns true when a rotation was applied.
+template <typename T, int RPT>
+__device__ __forceinline__ bool pair_step(cplx<T> (&x)[RPT], cplx<T>* y_lds, int rows, int m, int lane,
+                                          double tol) {
+    cplx<T> y[RPT];
+    T al = 0, be = 0, gr = 0, gi = 0;
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+        const int r = lane + 64 * k;
+        y[k] = r < rows ? y_lds[r] : cplx<T>{(T)0, (T)0};
+        if (r < m) accum_pair(x[k], y[k], al, be, gr, gi);
+    }
+    const double sal = wave_sum((double)al), sbe = wave_sum((double)be);
+    const double sgr = wave_sum((double)gr), sgi = wave_sum((double)gi);
+    Rot rt;
+    if (!make_rotation(sal, sbe, sgr, sgi, tol, rt)) return false;
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+        const int r = lane + 64 * k;
+        apply_rotation(rt, x[k], y[k]);
+        if (r < rows) y_lds[r] = y[k];
+    }
+    return true;
+}
+
 }  // namespace
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void jacobi_init_kernel(JacArgs<T> a) {
     const int s = blockIdx.y;
     const int64_t nn = (int64_t)a.n * a.n;
-    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < nn;
-         idx += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t c = idx / a.n, r = idx - c * a.n;
-        a.V[(int64_t)s * nn + idx] = cplx<T>{r == c ? (T)1 : (T)0, (T)0};
+    if (a.reset_v) {
+        for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < nn;
+             idx += (int64_t)gridDim.x * blockDim.x) {
+            const int64_t c = idx / a.n, r = idx - c * a.n;
+            a.V[(int64_t)s * nn + idx] = cplx<T>{r == c ? (T)1 : (T)0, (T)0};
+        }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         a.rot[s] = 0;   // ring entry 0 is written by sweep 0
@@ -137,72 +235,68 @@ __global__ __launch_bounds__(kBlock) void jacobi_init_kernel(JacArgs<T> a) {
     }
 }
 
-template <typename T, int BW>
-__global__ __launch_bounds__(kBlock) void jacobi_self_kernel(JacArgs<T> a) {
+// Intra-block pairs: BW/2 wavefronts, one column pair each per step.
+template <typename T, int BW, int RPT>
+__global__ __launch_bounds__(32 * BW) void jacobi_self_kernel(JacArgs<T> a) {
     extern __shared__ __align__(16) unsigned char smem[];
     cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem);
+    __shared__ int any_rot;
     const int s = blockIdx.y, b = blockIdx.x;
+    // the ring entry of the next sweep is cleared for every slice, converged or not
+    if (b == 0 && threadIdx.x == 0) a.rot[((a.sweep + 1) % 3) * a.h + s] = 0;
     if (slice_done(a, s)) return;
-    if (b == 0 && threadIdx.x == 0) {
-        a.rot[((a.sweep + 1) % 3) * a.h + s] = 0;
-        a.sweeps[s] += 1;
-    }
+    if (b == 0 && threadIdx.x == 0) a.sweeps[s] += 1;
     const int c0 = blk_start(b, a.n, a.nb);
     const int w = blk_start(b + 1, a.n, a.nb) - c0;
     if (w < 2) return;
     const int rows = a.m + a.n;
-    for (int idx = threadIdx.x; idx < w * rows; idx += blockDim.x) {
-        const int c = idx / rows, r = idx - c * rows;
-        lds[c * rows + r] = load_stacked(a, s, c0 + c, r);
-    }
+    if (threadIdx.x == 0) any_rot = 0;
+    block_to_lds(a, s, c0, w, rows, lds);
     __syncthreads();
 
-    // threads per pair; a pair's lanes stay inside one wavefront
-    constexpr int TPP = (kBlock / (BW / 2)) > 64 ? 64 : (kBlock / (BW / 2));
-    const int grp = threadIdx.x / TPP, lane = threadIdx.x - grp * TPP;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int wp = w + (w & 1);
-    bool any = false;
     unsigned nrot = 0;
     for (int st = 0; st < wp - 1; ++st) {
-        if (grp < wp / 2 && grp < kBlock / TPP) {
-            const int p = rr_player(grp, st, wp);
-            const int q = rr_player(wp - 1 - grp, st, wp);
+        if (wave < wp / 2) {
+            const int p = rr_player(wave, st, wp);
+            const int q = rr_player(wp - 1 - wave, st, wp);
             if (p < w && q < w) {
                 cplx<T>* cp = lds + p * rows;
-                cplx<T>* cq = lds + q * rows;
-                T al = 0, be = 0, gr = 0, gi = 0;
-                for (int r = lane; r < a.m; r += TPP) accum_pair(cp[r], cq[r], al, be, gr, gi);
-                al = group_sum<TPP>(al);
-                be = group_sum<TPP>(be);
-                gr = group_sum<TPP>(gr);
-                gi = group_sum<TPP>(gi);
-                Rot<T> rt;
-                if (make_rotation(al, be, gr, gi, a.tol, rt)) {
-                    any = true;
-                    nrot += lane == 0;
-                    for (int r = lane; r < rows; r += TPP) {
-                        cplx<T> x = cp[r], y = cq[r];
-                        apply_rotation(rt, x, y);
-                        cp[r] = x;
-                        cq[r] = y;
+                cplx<T> x[RPT];
+#pragma unroll
+                for (int k = 0; k < RPT; ++k) {
+                    const int r = lane + 64 * k;
+                    x[k] = r < rows ? cp[r] : cplx<T>{(T)0, (T)0};
+                }
+                if (pair_step<T, RPT>(x, lds + q * rows, rows, a.m, lane, (double)a.tol)) {
+                    ++nrot;
+#pragma unroll
+                    for (int k = 0; k < RPT; ++k) {
+                        const int r = lane + 64 * k;
+                        if (r < rows) cp[r] = x[k];
                     }
                 }
             }
         }
         __syncthreads();
     }
-    if (any) a.rot[(a.sweep % 3) * a.h + s] = 1;
-    if (nrot) atomicAdd(a.rotations, (unsigned long long)nrot);
-    for (int idx = threadIdx.x; idx < w * rows; idx += blockDim.x) {
-        const int c = idx / rows, r = idx - c * rows;
-        store_stacked(a, s, c0 + c, r, lds[c * rows + r]);
+    if (nrot && lane == 0) {
+        any_rot = 1;
+        atomicAdd(a.rotations, (unsigned long long)nrot);
     }
+    __syncthreads();
+    if (threadIdx.x == 0 && any_rot) a.rot[(a.sweep % 3) * a.h + s] = 1;
+    lds_to_block(a, s, c0, w, rows, lds);
 }
 
+// Cross pairs of one tournament round: BW wavefronts, wave g owns column g
+// of block I and meets every column of block J once.
 template <typename T, int BW, int RPT>
-__global__ __launch_bounds__(kBlock) void jacobi_cross_kernel(JacArgs<T> a) {
+__global__ __launch_bounds__(64 * BW) void jacobi_cross_kernel(JacArgs<T> a) {
     extern __shared__ __align__(16) unsigned char smem[];
     cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem);
+    __shared__ int any_rot;
     const int s = blockIdx.y, pr = blockIdx.x;
     if (slice_done(a, s)) return;
     const int bi = rr_player(pr, a.round, a.nb);
@@ -211,97 +305,88 @@ __global__ __launch_bounds__(kBlock) void jacobi_cross_kernel(JacArgs<T> a) {
     const int cj0 = blk_start(bj, a.n, a.nb), wj = blk_start(bj + 1, a.n, a.nb) - cj0;
     if (wi == 0 || wj == 0) return;
     const int rows = a.m + a.n;
+    const int g = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (threadIdx.x == 0) any_rot = 0;
 
-    constexpr int TPG = kBlock / BW;   // threads per I column
-    const int g = threadIdx.x / TPG, lane = threadIdx.x - g * TPG;
-    for (int idx = threadIdx.x; idx < wj * rows; idx += blockDim.x) {
-        const int c = idx / rows, r = idx - c * rows;
-        lds[c * rows + r] = load_stacked(a, s, cj0 + c, r);
-    }
     cplx<T> xi[RPT];
+    if (g < wi) {
+        const cplx<T>* colA = a.A + ((int64_t)s * a.n + ci0 + g) * a.m;
+        const cplx<T>* colV = a.V + ((int64_t)s * a.n + ci0 + g) * a.n;
 #pragma unroll
-    for (int k = 0; k < RPT; ++k) {
-        const int r = lane + k * TPG;
-        xi[k] = (g < wi && r < rows) ? load_stacked(a, s, ci0 + g, r) : cplx<T>{(T)0, (T)0};
+        for (int k = 0; k < RPT; ++k) {
+            const int r = lane + 64 * k;
+            xi[k] = r < a.m ? colA[r] : (r < rows ? colV[r - a.m] : cplx<T>{(T)0, (T)0});
+        }
     }
+    block_to_lds(a, s, cj0, wj, rows, lds);
     __syncthreads();
 
-    bool any = false;
     unsigned nrot = 0;
     for (int st = 0; st < BW; ++st) {
         const int jc = (g + st) % BW;
-        if (g < wi && jc < wj) {
-            cplx<T>* cq = lds + jc * rows;
-            cplx<T> yq[RPT];
-            T al = 0, be = 0, gr = 0, gi = 0;
-#pragma unroll
-            for (int k = 0; k < RPT; ++k) {
-                const int r = lane + k * TPG;
-                yq[k] = r < rows ? cq[r] : cplx<T>{(T)0, (T)0};
-                if (r < a.m) accum_pair(xi[k], yq[k], al, be, gr, gi);
-            }
-            al = group_sum<TPG>(al);
-            be = group_sum<TPG>(be);
-            gr = group_sum<TPG>(gr);
-            gi = group_sum<TPG>(gi);
-            Rot<T> rt;
-            if (make_rotation(al, be, gr, gi, a.tol, rt)) {
-                any = true;
-                nrot += lane == 0;
-#pragma unroll
-                for (int k = 0; k < RPT; ++k) {
-                    const int r = lane + k * TPG;
-                    apply_rotation(rt, xi[k], yq[k]);
-                    if (r < rows) cq[r] = yq[k];
-                }
-            }
-        }
+        if (g < wi && jc < wj) nrot += pair_step<T, RPT>(xi, lds + jc * rows, rows, a.m, lane, (double)a.tol);
         __syncthreads();
     }
-    if (any) a.rot[(a.sweep % 3) * a.h + s] = 1;
-    if (nrot) atomicAdd(a.rotations, (unsigned long long)nrot);
+    if (nrot && lane == 0) {
+        any_rot = 1;
+        atomicAdd(a.rotations, (unsigned long long)nrot);
+    }
+    if (g < wi) {
+        cplx<T>* colA = a.A + ((int64_t)s * a.n + ci0 + g) * a.m;
+        cplx<T>* colV = a.V + ((int64_t)s * a.n + ci0 + g) * a.n;
 #pragma unroll
-    for (int k = 0; k < RPT; ++k) {
-        const int r = lane + k * TPG;
-        if (g < wi && r < rows) store_stacked(a, s, ci0 + g, r, xi[k]);
+        for (int k = 0; k < RPT; ++k) {
+            const int r = lane + 64 * k;
+            if (r < a.m)
+                colA[r] = xi[k];
+            else if (r < rows)
+                colV[r - a.m] = xi[k];
+        }
     }
-    for (int idx = threadIdx.x; idx < wj * rows; idx += blockDim.x) {
-        const int c = idx / rows, r = idx - c * rows;
-        store_stacked(a, s, cj0 + c, r, lds[c * rows + r]);
-    }
+    lds_to_block(a, s, cj0, wj, rows, lds);
+    __syncthreads();
+    if (threadIdx.x == 0 && any_rot) a.rot[(a.sweep % 3) * a.h + s] = 1;
 }
 
 // ------------------------------------------------------------------ host
 
 namespace {
 
-constexpr int kRptSizes[] = {2, 4, 6, 8, 10, 12, 14, 16, 18, 20, 24, 28, 32, 40};
-constexpr size_t kLdsCap = 64 * 1024;
+constexpr int kRpt[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 16};
 
-int pick_rpt(int rows, int bw) {
-    const int tpg = kBlock / bw;
-    const int need = (rows + tpg - 1) / tpg;
-    for (int r : kRptSizes)
+int pick_rpt(int rows) {
+    const int need = (rows + 63) / 64;
+    for (int r : kRpt)
         if (r >= need) return r;
     return -1;
 }
 
+size_t g_lds_cap = 64 * 1024;   // set from the device by jacobi_set_lds_limit
+
+template <typename K>
+void allow_lds(K kernel, size_t bytes) {
+    if (bytes > 64 * 1024)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
 }  // namespace
 
+void jacobi_set_lds_limit(size_t bytes) { g_lds_cap = bytes; }
+
 int jacobi_block_width(int m, int n, int elem_bytes, int h) {
-    // Largest block width whose cross phase still gives about one workgroup
-    // per CU; smaller blocks mean more launches per sweep.
+    // Widest block (most pairs per workgroup, fewest launches per sweep)
+    // whose LDS block fits; narrower if that leaves most CUs idle.
     const int rows = m + n;
-    int fallback = -1;
+    if (pick_rpt(rows) < 0) return -1;
+    int best = -1;
     for (int bw : {16, 8, 4}) {
-        if ((size_t)bw * rows * 2 * elem_bytes > kLdsCap) continue;
-        const int rpt = pick_rpt(rows, bw);
-        if (rpt < 0) continue;
-        fallback = bw;
-        const int nb = std::max(2, 2 * ((n + 2 * bw - 1) / (2 * bw)));
-        if ((int64_t)(nb / 2) * h >= 240 && rpt <= 24) return bw;
+        if ((size_t)bw * rows * 2 * elem_bytes > g_lds_cap) continue;
+        if (best < 0) best = bw;
+        const int nb = jacobi_num_blocks(n, bw);
+        if ((int64_t)(nb / 2) * h >= 128) return bw;
     }
-    return fallback;
+    return best;
 }
 
 bool jacobi_supported(int m, int n, int elem_bytes) { return jacobi_block_width(m, n, elem_bytes, 1) > 0; }
@@ -314,37 +399,42 @@ void launch_jacobi_init(const JacArgs<T>& a, hipStream_t st) {
 }
 
 template <typename T, int BW, int RPT>
-static void launch_cross(const JacArgs<T>& a, size_t lds, hipStream_t st) {
-    hipLaunchKernelGGL((jacobi_cross_kernel<T, BW, RPT>), dim3(a.nb / 2, a.h), dim3(kBlock), lds, st, a);
+static void launch_cross_t(const JacArgs<T>& a, size_t lds, hipStream_t st) {
+    allow_lds(jacobi_cross_kernel<T, BW, RPT>, lds);
+    hipLaunchKernelGGL((jacobi_cross_kernel<T, BW, RPT>), dim3(a.nb / 2, a.h), dim3(64 * BW), lds, st, a);
 }
 
-template <typename T, int BW>
-static void dispatch_cross(const JacArgs<T>& a, int rpt, size_t lds, hipStream_t st) {
-    switch (rpt) {
-        case 2: launch_cross<T, BW, 2>(a, lds, st); break;
-        case 4: launch_cross<T, BW, 4>(a, lds, st); break;
-        case 6: launch_cross<T, BW, 6>(a, lds, st); break;
-        case 8: launch_cross<T, BW, 8>(a, lds, st); break;
-        case 10: launch_cross<T, BW, 10>(a, lds, st); break;
-        case 12: launch_cross<T, BW, 12>(a, lds, st); break;
-        case 14: launch_cross<T, BW, 14>(a, lds, st); break;
-        case 16: launch_cross<T, BW, 16>(a, lds, st); break;
-        case 18: launch_cross<T, BW, 18>(a, lds, st); break;
-        case 20: launch_cross<T, BW, 20>(a, lds, st); break;
-        case 24: launch_cross<T, BW, 24>(a, lds, st); break;
-        case 28: launch_cross<T, BW, 28>(a, lds, st); break;
-        case 32: launch_cross<T, BW, 32>(a, lds, st); break;
-        default: launch_cross<T, BW, 40>(a, lds, st); break;
-    }
+template <typename T, int BW, int RPT>
+static void launch_self_t(const JacArgs<T>& a, size_t lds, hipStream_t st) {
+    allow_lds(jacobi_self_kernel<T, BW, RPT>, lds);
+    hipLaunchKernelGGL((jacobi_self_kernel<T, BW, RPT>), dim3(a.nb, a.h), dim3(32 * BW), lds, st, a);
 }
+
+#define TSVD_RPT_SWITCH(FN, BW)                           \
+    switch (rpt) {                                        \
+        case 1: FN<T, BW, 1>(a, lds, st); break;          \
+        case 2: FN<T, BW, 2>(a, lds, st); break;          \
+        case 3: FN<T, BW, 3>(a, lds, st); break;          \
+        case 4: FN<T, BW, 4>(a, lds, st); break;          \
+        case 5: FN<T, BW, 5>(a, lds, st); break;          \
+        case 6: FN<T, BW, 6>(a, lds, st); break;          \
+        case 8: FN<T, BW, 8>(a, lds, st); break;          \
+        case 10: FN<T, BW, 10>(a, lds, st); break;        \
+        case 12: FN<T, BW, 12>(a, lds, st); break;        \
+        default: FN<T, BW, 16>(a, lds, st); break;        \
+    }
 
 template <typename T>
 void launch_jacobi_self(const JacArgs<T>& a, int bw, hipStream_t st) {
-    const size_t lds = (size_t)bw * (a.m + a.n) * sizeof(cplx<T>);
-    switch (bw) {
-        case 16: hipLaunchKernelGGL((jacobi_self_kernel<T, 16>), dim3(a.nb, a.h), dim3(kBlock), lds, st, a); break;
-        case 8: hipLaunchKernelGGL((jacobi_self_kernel<T, 8>), dim3(a.nb, a.h), dim3(kBlock), lds, st, a); break;
-        default: hipLaunchKernelGGL((jacobi_self_kernel<T, 4>), dim3(a.nb, a.h), dim3(kBlock), lds, st, a); break;
+    const int rows = a.m + a.n;
+    const size_t lds = (size_t)bw * rows * sizeof(cplx<T>);
+    const int rpt = pick_rpt(rows);
+    if (bw == 16) {
+        TSVD_RPT_SWITCH(launch_self_t, 16)
+    } else if (bw == 8) {
+        TSVD_RPT_SWITCH(launch_self_t, 8)
+    } else {
+        TSVD_RPT_SWITCH(launch_self_t, 4)
     }
 }
 
@@ -353,13 +443,17 @@ template <typename T>
 void launch_jacobi_cross(const JacArgs<T>& a, int bw, hipStream_t st) {
     const int rows = a.m + a.n;
     const size_t lds = (size_t)bw * rows * sizeof(cplx<T>);
-    const int rpt = pick_rpt(rows, bw);
-    switch (bw) {
-        case 16: dispatch_cross<T, 16>(a, rpt, lds, st); break;
-        case 8: dispatch_cross<T, 8>(a, rpt, lds, st); break;
-        default: dispatch_cross<T, 4>(a, rpt, lds, st); break;
+    const int rpt = pick_rpt(rows);
+    if (bw == 16) {
+        TSVD_RPT_SWITCH(launch_cross_t, 16)
+    } else if (bw == 8) {
+        TSVD_RPT_SWITCH(launch_cross_t, 8)
+    } else {
+        TSVD_RPT_SWITCH(launch_cross_t, 4)
     }
 }
+
+#undef TSVD_RPT_SWITCH
 
 template void launch_jacobi_init<double>(const JacArgs<double>&, hipStream_t);
 template void launch_jacobi_self<double>(const JacArgs<double>&, int, hipStream_t);

@@ -1,0 +1,435 @@
+// Persistent one-sided Jacobi SVD: one cooperative launch runs every sweep
+// of every Fourier slice (same method, ordering and stopping rule as the
+// per-round kernels in jacobi.hip, which remain the path for shapes that do
+// not fit this one).
+//
+// Layout.  Slice s gets G = nb/2 workgroups; workgroup p holds the blocks at
+// tournament positions p and nb-1-p in LDS (two BW-column blocks of stacked
+// columns: m slice rows, then n rows of V).  A round of the block tournament
+// orthogonalises the two resident blocks against each other; between rounds
+// every block except the one at position 0 moves to the next position
+// (circle method), so a workgroup writes its moving blocks back to their
+// home columns in global memory, meets the other workgroups of its slice at
+// a barrier, and reads the blocks of its next positions.  The first round of
+// every sweep also orthogonalises each block internally.
+//
+// Work split.  A column pair is handled by a 16-lane group (one DPP row), so
+// a 256-thread workgroup works on BW = 16 pairs per step; each lane holds
+// rows lane16 + 16 k of its columns, the dot products are reduced inside the
+// row with DPP, and the rotation parameters are computed per group in FP64.
+//
+// Synchronisation.  The per-slice barrier is a counter in global memory:
+// each workgroup publishes its block writes (agent-scope release fence),
+// increments the counter and waits for G arrivals per round.  The launch is
+// cooperative, so all workgroups are co-resident; the wait is also bounded
+// (a spin limit sets an error flag and lets the kernel finish, so a launch
+// can never hang).
+//
+// Convergence: workgroups OR a per-slice flag when they rotated during the
+// sweep; after the sweep's last barrier all workgroups of the slice read the
+// same flag and stop together when it is clear.
+
+#include "kernels.h"
+
+#include <algorithm>
+
+namespace tsvd {
+
+namespace {
+
+constexpr int PG = 16;                  // lanes per column pair (one DPP row)
+constexpr int PBW = kBlock / PG;        // 16 columns per block, 16 pairs per step
+constexpr long long kSpinLimit = 1LL << 21;   // about a second of polling
+
+__device__ __forceinline__ int pblk_start(int b, int n, int nb) {
+    return (int)(((int64_t)b * n) / nb);
+}
+
+__device__ __forceinline__ int ppos_player(int pos, int r, int nb) {
+    return pos == 0 ? 0 : 1 + (pos - 1 + r) % (nb - 1);
+}
+
+template <int CTRL>
+__device__ __forceinline__ double pdpp(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// sum over the 16 lanes of a DPP row; every lane of the row gets it
+__device__ __forceinline__ double row_sum(double v) {
+    v += pdpp<0xB1>(v);    // lane ^ 1
+    v += pdpp<0x4E>(v);    // lane ^ 2
+    v += pdpp<0x141>(v);   // other quad of the half row
+    v += pdpp<0x140>(v);   // other half of the row
+    return v;
+}
+
+__device__ __forceinline__ double prsqrt(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    y = y * (1.5 - 0.5 * x * y * y);
+    y = y * (1.5 - 0.5 * x * y * y);
+    return y;
+}
+
+__device__ __forceinline__ double prcp(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    return y * (2.0 - x * y);
+}
+
+struct PRot {
+    double c, s, er, ei;
+    bool on;
+};
+
+__device__ __forceinline__ PRot prot(double al, double be, double gr, double gi, double tol) {
+    PRot r{1.0, 0.0, 1.0, 0.0, false};
+    const double g2 = gr * gr + gi * gi;
+    if (!(g2 > (tol * tol) * al * be) || !(g2 > 0.0)) return r;
+    const double rg = prsqrt(g2);
+    const double zeta = (be - al) * 0.5 * rg;
+    const double q = 1.0 + zeta * zeta;
+    const double t = prcp(fabs(zeta) + q * prsqrt(q));
+    const double ts = zeta >= 0.0 ? t : -t;
+    r.c = prsqrt(1.0 + ts * ts);
+    r.s = r.c * ts;
+    r.er = gr * rg;
+    r.ei = gi * rg;
+    r.on = true;
+    return r;
+}
+
+template <typename T>
+__device__ __forceinline__ void prot_apply(const PRot& rd, cplx<T>& x, cplx<T>& y) {
+    const T c = (T)rd.c, s = (T)rd.s, er = (T)rd.er, ei = (T)rd.ei;
+    const T ycr = er * y.re + ei * y.im;
+    const T yci = er * y.im - ei * y.re;
+    const T exr = er * x.re - ei * x.im;
+    const T exi = er * x.im + ei * x.re;
+    const cplx<T> xn{c * x.re - s * ycr, c * x.im - s * yci};
+    const cplx<T> yn{s * exr + c * y.re, s * exi + c * y.im};
+    x = xn;
+    y = yn;
+}
+
+// Orthogonalise column x (registers) against column y_lds (LDS).  Each lane
+// holds rows l16 + 16 k; the first KA row groups are slice rows (their dot
+// products count), the rest are V rows.  Padding rows are zero throughout.
+template <typename T, int RPT>
+__device__ __forceinline__ bool ppair(cplx<T> (&x)[RPT], cplx<T>* y_lds, int ka, int l16, double tol) {
+    cplx<T> y[RPT];
+    T al = 0, be = 0, gr = 0, gi = 0;
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+        y[k] = y_lds[l16 + PG * k];
+        if (k < ka) {
+            al += x[k].re * x[k].re + x[k].im * x[k].im;
+            be += y[k].re * y[k].re + y[k].im * y[k].im;
+            gr += x[k].re * y[k].re + x[k].im * y[k].im;
+            gi += x[k].re * y[k].im - x[k].im * y[k].re;
+        }
+    }
+    const PRot rt = prot(row_sum((double)al), row_sum((double)be), row_sum((double)gr),
+                         row_sum((double)gi), tol);
+    if (!rt.on) return false;
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+        prot_apply(rt, x[k], y[k]);
+        y_lds[l16 + PG * k] = y[k];
+    }
+    return true;
+}
+
+// LDS column of a block: slice rows 0..m-1 at 0..m-1, V rows at mp..mp+n-1
+// (mp = m rounded up to 16), zeros elsewhere.  In global memory the block's
+// slice part (w columns of m) and V part (w columns of n) are each one
+// contiguous range, so each is copied by a branch-free loop with eight
+// independent accesses in flight per thread (addresses clamped in range).
+template <typename T>
+__device__ __forceinline__ void pcopy_in(const cplx<T>* src, int count, int len, int ldc, int off,
+                                         cplx<T>* lds) {
+    if (count <= 0) return;
+    for (int base = threadIdx.x; base < count; base += 8 * kBlock) {
+        cplx<T> v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = src[min(base + u * kBlock, count - 1)];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int idx = base + u * kBlock;
+            if (idx < count) {
+                const int c = idx / len;
+                lds[c * ldc + off + (idx - c * len)] = v[u];
+            }
+        }
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void pcopy_out(cplx<T>* dst, int count, int len, int ldc, int off,
+                                          const cplx<T>* lds) {
+    for (int idx = threadIdx.x; idx < count; idx += kBlock) {
+        const int c = idx / len;
+        dst[idx] = lds[c * ldc + off + (idx - c * len)];
+    }
+}
+
+template <typename T>
+__device__ void pload_block(const JacArgs<T>& a, int s, int blk, int mp, int ldc, cplx<T>* lds) {
+    const int c0 = pblk_start(blk, a.n, a.nb), w = pblk_start(blk + 1, a.n, a.nb) - c0;
+    pcopy_in(a.A + ((int64_t)s * a.n + c0) * a.m, w * a.m, a.m, ldc, 0, lds);
+    pcopy_in(a.V + ((int64_t)s * a.n + c0) * a.n, w * a.n, a.n, ldc, mp, lds);
+}
+
+template <typename T>
+__device__ void pstore_block(const JacArgs<T>& a, int s, int blk, int mp, int ldc, const cplx<T>* lds) {
+    const int c0 = pblk_start(blk, a.n, a.nb), w = pblk_start(blk + 1, a.n, a.nb) - c0;
+    pcopy_out(a.A + ((int64_t)s * a.n + c0) * a.m, w * a.m, a.m, ldc, 0, lds);
+    pcopy_out(a.V + ((int64_t)s * a.n + c0) * a.n, w * a.n, a.n, ldc, mp, lds);
+}
+
+// Slice barrier: returns false if the bounded wait ran out.
+__device__ bool slice_barrier(int* counter, int target, int* err) {
+    __shared__ int ok;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ok = 1;
+        __threadfence();
+        atomicAdd(counter, 1);
+        long long spins = 0;
+        while (__hip_atomic_load(counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(2);
+            // another workgroup gave up: stop waiting at once
+            if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+                ++spins > kSpinLimit) {
+                atomicExch(err, 1);
+                ok = 0;
+                break;
+            }
+        }
+        __threadfence();
+    }
+    __syncthreads();
+    return ok != 0;
+}
+
+}  // namespace
+
+template <typename T, int RPT>
+__global__ __launch_bounds__(kBlock) void jacobi_persistent_kernel(JacArgs<T> a, PersistArgs p) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int rot_any;
+    __shared__ int stop;
+    const int G = a.nb / 2;
+    const int s = blockIdx.x / G, wg = blockIdx.x - s * G;
+    if (s >= a.h) return;
+    const int ka = (a.m + PG - 1) / PG;   // row groups holding slice rows
+    const int mp = ka * PG;
+    // column stride: the padded stacked column plus one element, so the four
+    // pair groups of a wavefront read different LDS banks
+    const int ldc = PG * RPT + 1;
+    cplx<T>* const blk0 = reinterpret_cast<cplx<T>*>(smem);
+    cplx<T>* const blk1 = blk0 + (size_t)PBW * ldc;
+    long long* trace = (p.trace && s == 0 && wg == 0 && threadIdx.x == 0) ? p.trace : nullptr;
+    int nev = 0;
+    auto mark = [&]() {
+        if (trace && nev < 64) trace[nev++] = (long long)wall_clock64();
+    };
+    mark();
+    const int pos0 = wg, pos1 = a.nb - 1 - wg;
+    const int g = threadIdx.x / PG, l16 = threadIdx.x - g * PG;
+    const double tol = (double)a.tol;
+    int* counter = p.barrier + s;
+    int arrivals = 0;
+
+    // zero both blocks once: padding rows stay zero under every rotation
+    for (int idx = threadIdx.x; idx < 2 * PBW * ldc; idx += kBlock) blk0[idx] = cplx<T>{(T)0, (T)0};
+    __syncthreads();
+    int player0 = ppos_player(pos0, 0, a.nb), player1 = ppos_player(pos1, 0, a.nb);
+    pload_block(a, s, player0, mp, ldc, blk0);
+    pload_block(a, s, player1, mp, ldc, blk1);
+    if (wg == 0 && threadIdx.x == 0) a.sweeps[s] = 0;
+    __syncthreads();
+
+    unsigned nrot_total = 0;
+    bool alive = true;
+    for (int sweep = 0; sweep < p.max_sweeps && alive; ++sweep) {
+        if (threadIdx.x == 0) rot_any = 0;
+        if (wg == 0 && threadIdx.x == 0) {
+            p.rotflag[((sweep + 1) % 3) * a.h + s] = 0;
+            a.sweeps[s] = sweep + 1;
+        }
+        __syncthreads();
+        unsigned nrot = 0;
+        {
+            // internal pairs of both resident blocks: waves 0-1 take block 0,
+            // waves 2-3 block 1
+            const bool second = g >= PBW / 2;
+            const int gi = second ? g - PBW / 2 : g;
+            const int pl = second ? player1 : player0;
+            cplx<T>* const base = second ? blk1 : blk0;
+            const int w = pblk_start(pl + 1, a.n, a.nb) - pblk_start(pl, a.n, a.nb);
+            const int wp = w + (w & 1);
+            for (int st = 0; st < PBW - 1; ++st) {
+                if (st < wp - 1 && gi < wp / 2) {
+                    const int pp = ppos_player(gi, st, wp);
+                    const int qq = ppos_player(wp - 1 - gi, st, wp);
+                    if (pp < w && qq < w) {
+                        cplx<T>* cp = base + pp * ldc;
+                        cplx<T> x[RPT];
+#pragma unroll
+                        for (int k = 0; k < RPT; ++k) x[k] = cp[l16 + PG * k];
+                        if (ppair<T, RPT>(x, base + qq * ldc, ka, l16, tol)) {
+                            ++nrot;
+#pragma unroll
+                            for (int k = 0; k < RPT; ++k) cp[l16 + PG * k] = x[k];
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        mark();
+        for (int rd = 0; rd < a.nb - 1; ++rd) {
+            // cross pairs: column g of block 0 (registers) meets every column of block 1
+            const int wi = pblk_start(player0 + 1, a.n, a.nb) - pblk_start(player0, a.n, a.nb);
+            const int wj = pblk_start(player1 + 1, a.n, a.nb) - pblk_start(player1, a.n, a.nb);
+            cplx<T> xi[RPT];
+#pragma unroll
+            for (int k = 0; k < RPT; ++k) xi[k] = blk0[g * ldc + l16 + PG * k];
+            for (int st = 0; st < PBW; ++st) {
+                const int jc = (g + st) & (PBW - 1);
+                if (g < wi && jc < wj) nrot += ppair<T, RPT>(xi, blk1 + jc * ldc, ka, l16, tol);
+                __syncthreads();
+            }
+            if (g < wi) {
+#pragma unroll
+                for (int k = 0; k < RPT; ++k) blk0[g * ldc + l16 + PG * k] = xi[k];
+            }
+            // end of the sweep: publish whether this workgroup rotated
+            const bool last = rd == a.nb - 2;
+            if (last) {
+                if (nrot && l16 == 0) rot_any = 1;
+                __syncthreads();
+                if (threadIdx.x == 0 && rot_any) atomicOr(p.rotflag + (sweep % 3) * a.h + s, 1);
+            }
+            // the next round's players (after the last round: round 0 of the next sweep)
+            const int nr = (rd + 1) % (a.nb - 1);
+            const int next0 = ppos_player(pos0, nr, a.nb), next1 = ppos_player(pos1, nr, a.nb);
+            __syncthreads();
+            mark();
+            if (next0 != player0) pstore_block(a, s, player0, mp, ldc, blk0);
+            if (next1 != player1) pstore_block(a, s, player1, mp, ldc, blk1);
+            mark();
+            arrivals += G;
+            if (!slice_barrier(counter, arrivals, p.err)) {
+                alive = false;
+                break;
+            }
+            mark();
+            if (last) {
+                if (threadIdx.x == 0) stop = __hip_atomic_load(p.rotflag + (sweep % 3) * a.h + s,
+                                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+                __syncthreads();
+                if (stop) {
+                    // converged: the blocks that did not move go home too
+                    if (next0 == player0) pstore_block(a, s, player0, mp, ldc, blk0);
+                    if (next1 == player1) pstore_block(a, s, player1, mp, ldc, blk1);
+                    alive = false;
+                    break;
+                }
+            }
+            if (next0 != player0) {
+                player0 = next0;
+                pload_block(a, s, player0, mp, ldc, blk0);
+            }
+            if (next1 != player1) {
+                player1 = next1;
+                pload_block(a, s, player1, mp, ldc, blk1);
+            }
+            __syncthreads();
+            mark();
+        }
+        nrot_total += nrot;
+    }
+    if (alive) {
+        // sweep cap reached: every resident block goes home
+        __syncthreads();
+        pstore_block(a, s, player0, mp, ldc, blk0);
+        pstore_block(a, s, player1, mp, ldc, blk1);
+    }
+    mark();
+    if (l16 == 0 && nrot_total) atomicAdd(a.rotations, (unsigned long long)nrot_total);
+}
+
+// ------------------------------------------------------------------ host
+
+namespace {
+
+// row groups of 16 per stacked column: slice rows and V rows each padded to 16
+int persist_rpt(int m, int n) {
+    const int need = (m + PG - 1) / PG + (n + PG - 1) / PG;
+    for (int r : {2, 4, 6, 8, 10, 12, 14, 16, 18, 20, 24})
+        if (r >= need) return r;
+    return -1;
+}
+
+size_t persist_lds(int rpt, int elem_bytes) { return 2 * (size_t)PBW * (PG * rpt + 1) * 2 * elem_bytes; }
+
+}  // namespace
+
+namespace {
+
+template <typename T, int RPT>
+hipError_t launch_persist_t(const JacArgs<T>& a, const PersistArgs& p, size_t lds, hipStream_t st,
+                            int max_wg_per_cu_check, int cus) {
+    auto* fn = jacobi_persistent_kernel<T, RPT>;
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlock, lds);
+    if (e != hipSuccess) return e;
+    const int grid = a.h * (a.nb / 2);
+    if ((int64_t)per_cu * cus < grid) return hipErrorCooperativeLaunchTooLarge;
+    (void)max_wg_per_cu_check;
+    JacArgs<T> aa = a;
+    PersistArgs pp = p;
+    void* args[] = {&aa, &pp};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(fn), dim3(grid), dim3(kBlock), args,
+                                      (unsigned)lds, st);
+}
+
+}  // namespace
+
+int jacobi_persistent_blocks(int n) { return jacobi_num_blocks(n, PBW); }
+
+bool jacobi_persistent_fits(int m, int n, int h, int elem_bytes, int cus, size_t lds_cap) {
+    const int rpt = persist_rpt(m, n);
+    if (rpt < 0 || n < 2) return false;
+    if (persist_lds(rpt, elem_bytes) + 64 > lds_cap) return false;
+    const int64_t grid = (int64_t)h * (jacobi_persistent_blocks(n) / 2);
+    return grid <= (int64_t)cus;   // one 256-thread workgroup per CU is always resident
+}
+
+template <typename T>
+hipError_t launch_jacobi_persistent(const JacArgs<T>& a, const PersistArgs& p, int cus, hipStream_t st) {
+    const int rpt = persist_rpt(a.m, a.n);
+    const size_t lds = persist_lds(rpt, sizeof(T));
+    switch (rpt) {
+        case 2: return launch_persist_t<T, 2>(a, p, lds, st, 0, cus);
+        case 4: return launch_persist_t<T, 4>(a, p, lds, st, 0, cus);
+        case 6: return launch_persist_t<T, 6>(a, p, lds, st, 0, cus);
+        case 8: return launch_persist_t<T, 8>(a, p, lds, st, 0, cus);
+        case 10: return launch_persist_t<T, 10>(a, p, lds, st, 0, cus);
+        case 12: return launch_persist_t<T, 12>(a, p, lds, st, 0, cus);
+        case 14: return launch_persist_t<T, 14>(a, p, lds, st, 0, cus);
+        case 16: return launch_persist_t<T, 16>(a, p, lds, st, 0, cus);
+        case 18: return launch_persist_t<T, 18>(a, p, lds, st, 0, cus);
+        case 20: return launch_persist_t<T, 20>(a, p, lds, st, 0, cus);
+        default: return launch_persist_t<T, 24>(a, p, lds, st, 0, cus);
+    }
+}
+
+template hipError_t launch_jacobi_persistent<double>(const JacArgs<double>&, const PersistArgs&, int,
+                                                     hipStream_t);
+
+}  // namespace tsvd

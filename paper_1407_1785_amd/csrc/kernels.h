@@ -69,6 +69,7 @@ struct JacArgs {
     int* sweeps;    // sweeps run per slice
     unsigned long long* rotations;  // running count of applied rotations
     T tol;          // rotate when |a_p^H a_q| > tol ||a_p|| ||a_q||
+    int reset_v;    // jacobi_init: 1 = start from V = I, 0 = keep V (warm start)
 };
 
 template <typename T>
@@ -82,6 +83,25 @@ struct SvtArgs {
     const Ctrl* ctrl;   // tau
     int m, n, h;
 };
+
+// C[s] = alpha * op(A[s]) * B[s] + beta * D[s] over `batch` slices,
+// column-major complex; op(A) = A^H when opA_h (A stored K x M).
+template <typename T>
+struct GemmArgs {
+    const cplx<T>* A;
+    const cplx<T>* B;
+    const cplx<T>* D;   // may be null (beta ignored)
+    cplx<T>* C;         // must not alias A or B
+    int M, N, K;
+    int lda, ldb, ldc, ldd;
+    int64_t sA, sB, sC, sD;
+    T alpha, beta;
+    int opA_h;
+    int batch;
+};
+
+template <typename T>
+void launch_cgemm(const GemmArgs<T>& g, hipStream_t st);
 
 template <typename T>
 void launch_dft_forward(int prologue, const FwdArgs<T>& a, hipStream_t st);
@@ -100,6 +120,21 @@ void launch_jacobi_cross(const JacArgs<T>& a, int bw, hipStream_t st);
 int jacobi_block_width(int m, int n, int elem_bytes, int h);
 inline int jacobi_num_blocks(int n, int bw) { int nb = 2 * ((n + 2 * bw - 1) / (2 * bw)); return nb < 2 ? 2 : nb; }
 bool jacobi_supported(int m, int n, int elem_bytes);
+// LDS bytes one workgroup may use on the current device
+void jacobi_set_lds_limit(size_t bytes);
+
+// Persistent Jacobi (jacobi_persist.hip): one cooperative launch per SVD.
+struct PersistArgs {
+    int* barrier;    // h arrival counters, zero before the launch
+    int* rotflag;    // 3 x h sweep flags, zero before the launch
+    int* err;        // set to 1 if a barrier wait ran out
+    int max_sweeps;
+    long long* trace;  // optional: 64 timestamps of workgroup 0 of slice 0
+};
+int jacobi_persistent_blocks(int n);
+bool jacobi_persistent_fits(int m, int n, int h, int elem_bytes, int cus, size_t lds_cap);
+template <typename T>
+hipError_t launch_jacobi_persistent(const JacArgs<T>& a, const PersistArgs& p, int cus, hipStream_t st);
 
 template <typename T>
 void launch_svt_weights(const SvtArgs<T>& a, hipStream_t st);
