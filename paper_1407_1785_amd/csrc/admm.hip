@@ -150,4 +150,10 @@ template void launch_complete_output<double>(const double*, const uint8_t*, cons
 template void launch_fill<double>(double*, double, int64_t, hipStream_t);
 template void launch_fill<int>(int*, int, int64_t, hipStream_t);
 
+template void launch_sumsq<float>(const float*, const uint8_t*, int64_t, double*, int, hipStream_t);
+template void launch_complete_output<float>(const float*, const uint8_t*, const float*,
+                                            const float*, const Ctrl*, float*, int64_t,
+                                            hipStream_t);
+template void launch_fill<float>(float*, float, int64_t, hipStream_t);
+
 }  // namespace tsvd

@@ -133,7 +133,6 @@ Geometry make_geometry(const tsvd_shape& s) {
     g.n = (int)n;
     g.ntubes = g.n1 * g.n2;
     g.numel = g.ntubes * g.L;
-    if (!jacobi_supported(g.m, g.n, 8)) fail(TSVD_E_SHAPE, "slice too large for the Jacobi kernels");
     return g;
 }
 
@@ -398,7 +397,8 @@ SweepStats run_svt(tsvd_handle h, const Geometry& g, const SvtBuffers<T>& sb, in
     ja.nb = jacobi_num_blocks(g.n, bw);
     ja.rot = sb.rot;
     ja.sweeps = sb.sweeps;
-    ja.tol = (T)env_double("TSVD_JACOBI_TOL", std::sqrt((double)g.m) * 2.220446049250313e-16);
+    const double eps = sizeof(T) == 4 ? 1.1920928955078125e-07 : 2.220446049250313e-16;
+    ja.tol = (T)env_double("TSVD_JACOBI_TOL", std::sqrt((double)g.m) * eps);
     ja.rotations = h->rot_counter;
     const int check_every = std::max(1, env_int("TSVD_CHECK_EVERY", 1));
     ensure_host_ints(h, g.h);
@@ -607,12 +607,14 @@ void check_handle(tsvd_handle h) {
     if (!h) fail(TSVD_E_INVALID, "null handle");
 }
 
-void check_precision(tsvd_dtype dtype, int precision) {
+// true for the FP32 form (FP32 data), false for the plain FP64 path
+bool check_precision(int dtype, int precision) {
     if (dtype != TSVD_F64 && dtype != TSVD_F32) fail(TSVD_E_INVALID, "unknown dtype");
     if (precision != TSVD_PREC_FP64 && precision != TSVD_PREC_FP32)
         fail(TSVD_E_INVALID, "unknown precision");
-    if (!(dtype == TSVD_F64 && precision == TSVD_PREC_FP64))
-        fail(TSVD_E_UNSUPPORTED, "only FP64 data with FP64 precision is built");
+    if (dtype == TSVD_F64 && precision == TSVD_PREC_FP64) return false;
+    if (dtype == TSVD_F32 && precision == TSVD_PREC_FP32) return true;
+    fail(TSVD_E_UNSUPPORTED, "FP64 data needs TSVD_PREC_FP64 and FP32 data TSVD_PREC_FP32");
 }
 
 struct AdmmSettings {
@@ -637,6 +639,311 @@ AdmmSettings settings(const tsvd_admm_opts* o, double growth, double rho_max, in
 int elementwise_parts() { return 1024; }
 
 }  // namespace
+
+template <typename T>
+void do_tsvt(tsvd_handle h, const void* X, tsvd_shape shape, tsvd_dtype dtype, double tau,
+                 tsvd_precision precision, void* Z, int32_t* multirank_host) {
+        check_handle(h);
+        if (!X || !Z) fail(TSVD_E_INVALID, "null tensor pointer");
+        if (!(tau >= 0.0) || !std::isfinite(tau)) fail(TSVD_E_INVALID, "tau must be finite and >= 0");
+        
+        const Geometry g = make_geometry(shape);
+        if (!jacobi_supported(g.m, g.n, sizeof(T))) fail(TSVD_E_SHAPE, "slice too large for the Jacobi kernels");
+        Device dev(h->device);
+        const int nparts = (int)dft_grid(g, dft_inverse_tile(g, EPI_STORE));
+        ensure_workspace(h, svt_bytes<T>(g, nparts) + 4096);
+        Carver cv{reinterpret_cast<char*>(h->ws)};
+        SvtBuffers<T> sb = carve_svt<T>(cv, g, nparts);
+        ensure_twiddles(h, g.L);
+        Ctrl c{};
+        c.rho = tau > 0 ? 1.0 / tau : INFINITY;
+        c.tau = tau;
+        c.dscale = 1.0;
+        put_ctrl(h, c);
+        clear_flag(h);
+        clear_persist_err(h, g, sb);
+
+        FwdArgs<T> fa{};
+        fa.x = static_cast<const T*>(X);
+        fa.ctrl = h->ctrl;
+        fa.tw = h->tw;
+        fa.out = sb.A;
+        fa.nonfinite = h->flag;
+        fa.g = g;
+        fa.tile = dft_forward_tile(g);
+        const double slice_bytes = (double)g.h * g.m * g.n * sizeof(cplx<T>);
+        prof_launch(h, K_DFT_FWD, slice_bytes + (double)g.numel * sizeof(T),
+                    [&] { launch_dft_forward(PRO_COPY, fa, h->stream); });
+        launch_check("dft_forward");
+        const SweepStats ss = run_svt<T>(h, g, sb, 30);
+        InvArgs<T> ia{};
+        ia.in = static_cast<const cplx<T>*>(ss.out);
+        ia.tw = h->tw;
+        ia.ctrl = h->ctrl;
+        ia.g = g;
+        ia.tile = dft_inverse_tile(g, EPI_STORE);
+        ia.out = static_cast<T*>(Z);
+        prof_launch(h, K_DFT_INV, slice_bytes + (double)g.numel * sizeof(T),
+                    [&] { launch_dft_inverse(EPI_STORE, ia, h->stream); });
+        launch_check("dft_inverse");
+        if (multirank_host) {
+            ensure_host_ints(h, g.h);
+            hip_check(hipMemcpyAsync(h->host_ints, sb.rank, sizeof(int) * g.h, hipMemcpyDeviceToHost,
+                                     h->stream),
+                      "hipMemcpyAsync rank");
+        }
+        hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+        if (multirank_host) std::memcpy(multirank_host, h->host_ints, sizeof(int) * g.h);
+        prof_harvest(h);
+        check_persist_err(h, g, sb);
+        if (read_flag(h)) fail(TSVD_E_NONFINITE, "non-finite input");
+}
+
+template <typename T>
+void do_complete(tsvd_handle h, const void* X_obs, const uint8_t* mask, tsvd_shape shape,
+                          tsvd_dtype dtype, double rho, double tol, const tsvd_admm_opts* opts,
+                          void* X_out, tsvd_info* info_host) {
+        const auto t0 = std::chrono::steady_clock::now();
+        check_handle(h);
+        if (!X_obs || !mask || !X_out) fail(TSVD_E_INVALID, "null tensor pointer");
+        if (!(rho > 0.0) || !std::isfinite(rho)) fail(TSVD_E_INVALID, "rho must be > 0");
+        if (!(tol >= 0.0) || !std::isfinite(tol)) fail(TSVD_E_INVALID, "tol must be >= 0");
+        const AdmmSettings s = settings(opts, 1.1, 1e3, 300);
+        if (s.rho_max < rho) fail(TSVD_E_INVALID, "rho_max must be >= rho");
+        
+        const Geometry g = make_geometry(shape);
+        if (!jacobi_supported(g.m, g.n, sizeof(T))) fail(TSVD_E_SHAPE, "slice too large for the Jacobi kernels");
+        Device dev(h->device);
+        const int tile_i = dft_inverse_tile(g, EPI_COMPLETE);
+        const int nparts = (int)std::max<int64_t>(dft_grid(g, tile_i), elementwise_parts());
+        const int64_t N = g.numel;
+        ensure_workspace(h, svt_bytes<T>(g, nparts) + 4 * (N * sizeof(T) + 256) + 4096);
+        Carver cv{reinterpret_cast<char*>(h->ws)};
+        SvtBuffers<T> sb = carve_svt<T>(cv, g, nparts);
+        T* Zb[2] = {cv.take<T>(N), cv.take<T>(N)};
+        T* Qb[2] = {cv.take<T>(N), cv.take<T>(N)};
+        ensure_twiddles(h, g.L);
+        hipStream_t st = h->stream;
+        const T* Y = static_cast<const T*>(X_obs);
+        launch_fill<T>(Zb[0], 0.0, N, st);
+        launch_fill<T>(Qb[0], 0.0, N, st);
+        Ctrl c{};
+        c.rho = rho;
+        c.tau = 1.0 / rho;
+        c.dscale = 1.0;
+        c.dscale_used = 1.0;
+        c.growth = s.growth;
+        c.rho_max = s.rho_max;
+        c.rho_used = rho;
+        put_ctrl(h, c);
+        launch_sumsq<T>(Y, mask, N, sb.partials, elementwise_parts(), st);
+        launch_set_tol(h->ctrl, sb.partials, elementwise_parts(), tol, st);
+        launch_check("setup");
+        clear_flag(h);
+        clear_persist_err(h, g, sb);
+
+        FwdArgs<T> fa{};
+        fa.x = Y;
+        fa.mask = mask;
+        fa.ctrl = h->ctrl;
+        fa.tw = h->tw;
+        fa.out = sb.A;
+        fa.nonfinite = h->flag;
+        fa.g = g;
+        fa.tile = dft_forward_tile(g);
+        InvArgs<T> ia{};
+        ia.in = sb.Z;
+        ia.tw = h->tw;
+        ia.ctrl = h->ctrl;
+        ia.g = g;
+        ia.tile = tile_i;
+        ia.y = Y;
+        ia.mask = mask;
+        ia.partials = sb.partials;
+        const int inv_parts = (int)dft_grid(g, tile_i);
+        const double slice_bytes = (double)g.h * g.m * g.n * sizeof(cplx<T>);
+        int sweeps_total = 0, sweeps_last = 0, iters = 0;
+        Ctrl hc{};
+        WarmState warm;
+        warm.enabled = env_int("TSVD_WARM", 1) != 0;
+        warm.reorth_every = env_int("TSVD_REORTH_EVERY", sizeof(T) == 4 ? 1 : 4);
+        for (int k = 0; k < s.max_iter; ++k) {
+            fa.z = Zb[k % 2];
+            fa.dual = Qb[k % 2];
+            // Y, mask, Z, Q in; slices out
+            prof_launch(h, K_DFT_FWD, slice_bytes + (double)N * (3 * sizeof(T) + 1),
+                        [&] { launch_dft_forward(PRO_COMPLETE, fa, st); });
+            launch_check("dft_forward");
+            const SweepStats ss = run_svt<T>(h, g, sb, s.max_sweeps, &warm);
+            if (ss.sweeps < 0) {
+                ensure_host_ints(h, g.h);
+                hip_check(hipMemcpyAsync(h->host_ints, sb.sweeps, sizeof(int) * g.h, hipMemcpyDeviceToHost, st),
+                          "hipMemcpyAsync sweeps");
+            }
+            ia.in = static_cast<const cplx<T>*>(ss.out);
+            ia.out = Zb[(k + 1) % 2];
+            ia.z_old = Zb[k % 2];
+            ia.dual_old = Qb[k % 2];
+            ia.dual_new = Qb[(k + 1) % 2];
+            // slices, Y, mask, Z, Q in; Z', Q~ out
+            prof_launch(h, K_DFT_INV, slice_bytes + (double)N * (5 * sizeof(T) + 1),
+                        [&] { launch_dft_inverse(EPI_COMPLETE, ia, st); });
+            launch_check("dft_inverse");
+            prof_launch(h, K_CTRL, (double)inv_parts * kNumPartials * sizeof(double),
+                        [&] { launch_admm_ctrl(h->ctrl, sb.partials, inv_parts, 0, st); });
+            launch_check("admm_ctrl");
+            hc = get_ctrl(h);
+            sweeps_last = ss.sweeps >= 0 ? ss.sweeps : max_sweeps_of(h, g.h);
+            sweeps_total += sweeps_last;
+            iters = k + 1;
+            if (hc.done) break;
+        }
+        launch_complete_output<T>(Y, mask, Zb[(iters - 1) % 2], Qb[(iters - 1) % 2], h->ctrl,
+                                  static_cast<T*>(X_out), N, st);
+        launch_check("complete_output");
+        hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+        prof_harvest(h);
+        check_persist_err(h, g, sb);
+        if (hc.nonfinite || read_flag(h)) fail(TSVD_E_NONFINITE, "non-finite input or iterate");
+        if (info_host) {
+            info_host->iters = iters;
+            info_host->converged = hc.done ? 1 : 0;
+            info_host->sweeps_total = sweeps_total;
+            info_host->sweeps_last = sweeps_last;
+            info_host->primal = hc.primal;
+            info_host->change = hc.change;
+            info_host->rho_final = hc.rho_used;
+            info_host->seconds =
+                std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        }
+}
+
+template <typename T>
+void do_trpca(tsvd_handle h, const void* X, tsvd_shape shape, tsvd_dtype dtype, double lambda,
+                  double mu, double tol, tsvd_shrink shrink, const tsvd_admm_opts* opts, void* L_out,
+                  void* S_out, tsvd_info* info_host) {
+        const auto t0 = std::chrono::steady_clock::now();
+        check_handle(h);
+        if (!X || !L_out || !S_out) fail(TSVD_E_INVALID, "null tensor pointer");
+        if (!(lambda > 0.0) || !std::isfinite(lambda)) fail(TSVD_E_INVALID, "lambda must be > 0");
+        if (!(mu > 0.0) || !std::isfinite(mu)) fail(TSVD_E_INVALID, "mu must be > 0");
+        if (!(tol >= 0.0) || !std::isfinite(tol)) fail(TSVD_E_INVALID, "tol must be >= 0");
+        if (shrink != TSVD_SHRINK_L1 && shrink != TSVD_SHRINK_L112) fail(TSVD_E_INVALID, "unknown shrink");
+        const AdmmSettings s = settings(opts, 1.2, 1e10, 500);
+        if (s.rho_max < mu) fail(TSVD_E_INVALID, "rho_max must be >= mu");
+        
+        const Geometry g = make_geometry(shape);
+        if (!jacobi_supported(g.m, g.n, sizeof(T))) fail(TSVD_E_SHAPE, "slice too large for the Jacobi kernels");
+        Device dev(h->device);
+        const int epi = shrink == TSVD_SHRINK_L1 ? EPI_RPCA_L1 : EPI_RPCA_L112;
+        const int tile_i = dft_inverse_tile(g, epi);
+        const int nparts = (int)std::max<int64_t>(dft_grid(g, tile_i), elementwise_parts());
+        const int64_t N = g.numel;
+        ensure_workspace(h, svt_bytes<T>(g, nparts) + 6 * (N * sizeof(T) + 256) + 4096);
+        Carver cv{reinterpret_cast<char*>(h->ws)};
+        SvtBuffers<T> sb = carve_svt<T>(cv, g, nparts);
+        T* Lb[2] = {cv.take<T>(N), cv.take<T>(N)};
+        T* Sb[2] = {cv.take<T>(N), cv.take<T>(N)};
+        T* Wb[2] = {cv.take<T>(N), cv.take<T>(N)};
+        ensure_twiddles(h, g.L);
+        hipStream_t st = h->stream;
+        const T* M = static_cast<const T*>(X);
+        launch_fill<T>(Lb[0], 0.0, N, st);
+        launch_fill<T>(Sb[0], 0.0, N, st);
+        launch_fill<T>(Wb[0], 0.0, N, st);
+        Ctrl c{};
+        c.rho = mu;
+        c.tau = 1.0 / mu;
+        c.dscale = 1.0;
+        c.dscale_used = 1.0;
+        c.growth = s.growth;
+        c.rho_max = s.rho_max;
+        c.lambda = lambda;
+        c.shrink = lambda / mu;
+        c.rho_used = mu;
+        put_ctrl(h, c);
+        launch_sumsq<T>(M, nullptr, N, sb.partials, elementwise_parts(), st);
+        launch_set_tol(h->ctrl, sb.partials, elementwise_parts(), tol, st);
+        launch_check("setup");
+        clear_flag(h);
+        clear_persist_err(h, g, sb);
+
+        FwdArgs<T> fa{};
+        fa.x = M;
+        fa.ctrl = h->ctrl;
+        fa.tw = h->tw;
+        fa.out = sb.A;
+        fa.nonfinite = h->flag;
+        fa.g = g;
+        fa.tile = dft_forward_tile(g);
+        InvArgs<T> ia{};
+        ia.in = sb.Z;
+        ia.tw = h->tw;
+        ia.ctrl = h->ctrl;
+        ia.g = g;
+        ia.tile = tile_i;
+        ia.m = M;
+        ia.partials = sb.partials;
+        const int inv_parts = (int)dft_grid(g, tile_i);
+        const double slice_bytes = (double)g.h * g.m * g.n * sizeof(cplx<T>);
+        int sweeps_total = 0, sweeps_last = 0, iters = 0;
+        Ctrl hc{};
+        WarmState warm;
+        warm.enabled = env_int("TSVD_WARM", 1) != 0;
+        warm.reorth_every = env_int("TSVD_REORTH_EVERY", sizeof(T) == 4 ? 1 : 4);
+        for (int k = 0; k < s.max_iter; ++k) {
+            fa.s = Sb[k % 2];
+            fa.dual = Wb[k % 2];
+            // M, S, W in; slices out
+            prof_launch(h, K_DFT_FWD, slice_bytes + (double)N * 3 * sizeof(T),
+                        [&] { launch_dft_forward(PRO_RPCA, fa, st); });
+            launch_check("dft_forward");
+            const SweepStats ss = run_svt<T>(h, g, sb, s.max_sweeps, &warm);
+            if (ss.sweeps < 0) {
+                ensure_host_ints(h, g.h);
+                hip_check(hipMemcpyAsync(h->host_ints, sb.sweeps, sizeof(int) * g.h, hipMemcpyDeviceToHost, st),
+                          "hipMemcpyAsync sweeps");
+            }
+            ia.in = static_cast<const cplx<T>*>(ss.out);
+            ia.out = Lb[(k + 1) % 2];
+            ia.l_old = Lb[k % 2];
+            ia.s_old = Sb[k % 2];
+            ia.s_new = Sb[(k + 1) % 2];
+            ia.dual_old = Wb[k % 2];
+            ia.dual_new = Wb[(k + 1) % 2];
+            // slices, M, W, S, L in; L', S', W~ out
+            prof_launch(h, K_DFT_INV, slice_bytes + (double)N * 7 * sizeof(T),
+                        [&] { launch_dft_inverse(epi, ia, st); });
+            launch_check("dft_inverse");
+            prof_launch(h, K_CTRL, (double)inv_parts * kNumPartials * sizeof(double),
+                        [&] { launch_admm_ctrl(h->ctrl, sb.partials, inv_parts, 1, st); });
+            launch_check("admm_ctrl");
+            hc = get_ctrl(h);
+            sweeps_last = ss.sweeps >= 0 ? ss.sweeps : max_sweeps_of(h, g.h);
+            sweeps_total += sweeps_last;
+            iters = k + 1;
+            if (hc.done) break;
+        }
+        hip_check(hipMemcpyAsync(L_out, Lb[iters % 2], N * sizeof(T), hipMemcpyDeviceToDevice, st),
+                  "hipMemcpyAsync L");
+        hip_check(hipMemcpyAsync(S_out, Sb[iters % 2], N * sizeof(T), hipMemcpyDeviceToDevice, st),
+                  "hipMemcpyAsync S");
+        hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+        prof_harvest(h);
+        check_persist_err(h, g, sb);
+        if (hc.nonfinite || read_flag(h)) fail(TSVD_E_NONFINITE, "non-finite input or iterate");
+        if (info_host) {
+            info_host->iters = iters;
+            info_host->converged = hc.done ? 1 : 0;
+            info_host->sweeps_total = sweeps_total;
+            info_host->sweeps_last = sweeps_last;
+            info_host->primal = hc.primal;
+            info_host->change = hc.change;
+            info_host->rho_final = hc.rho_used;
+            info_host->seconds =
+                std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        }
+}
 
 // ---------------------------------------------------------------- C ABI
 
@@ -709,59 +1016,10 @@ tsvd_status tsvt(tsvd_handle h, const void* X, tsvd_shape shape, tsvd_dtype dtyp
                  tsvd_precision precision, void* Z, int32_t* multirank_host) {
     return guarded([&] {
         check_handle(h);
-        if (!X || !Z) fail(TSVD_E_INVALID, "null tensor pointer");
-        if (!(tau >= 0.0) || !std::isfinite(tau)) fail(TSVD_E_INVALID, "tau must be finite and >= 0");
-        check_precision(dtype, precision);
-        const Geometry g = make_geometry(shape);
-        Device dev(h->device);
-        using T = double;
-        const int nparts = (int)dft_grid(g, dft_inverse_tile(g, EPI_STORE));
-        ensure_workspace(h, svt_bytes<T>(g, nparts) + 4096);
-        Carver cv{reinterpret_cast<char*>(h->ws)};
-        SvtBuffers<T> sb = carve_svt<T>(cv, g, nparts);
-        ensure_twiddles(h, g.L);
-        Ctrl c{};
-        c.rho = tau > 0 ? 1.0 / tau : INFINITY;
-        c.tau = tau;
-        c.dscale = 1.0;
-        put_ctrl(h, c);
-        clear_flag(h);
-        clear_persist_err(h, g, sb);
-
-        FwdArgs<T> fa{};
-        fa.x = static_cast<const T*>(X);
-        fa.ctrl = h->ctrl;
-        fa.tw = h->tw;
-        fa.out = sb.A;
-        fa.nonfinite = h->flag;
-        fa.g = g;
-        fa.tile = dft_forward_tile(g);
-        const double slice_bytes = (double)g.h * g.m * g.n * sizeof(cplx<T>);
-        prof_launch(h, K_DFT_FWD, slice_bytes + (double)g.numel * sizeof(T),
-                    [&] { launch_dft_forward(PRO_COPY, fa, h->stream); });
-        launch_check("dft_forward");
-        const SweepStats ss = run_svt<T>(h, g, sb, 30);
-        InvArgs<T> ia{};
-        ia.in = static_cast<const cplx<T>*>(ss.out);
-        ia.tw = h->tw;
-        ia.ctrl = h->ctrl;
-        ia.g = g;
-        ia.tile = dft_inverse_tile(g, EPI_STORE);
-        ia.out = static_cast<T*>(Z);
-        prof_launch(h, K_DFT_INV, slice_bytes + (double)g.numel * sizeof(T),
-                    [&] { launch_dft_inverse(EPI_STORE, ia, h->stream); });
-        launch_check("dft_inverse");
-        if (multirank_host) {
-            ensure_host_ints(h, g.h);
-            hip_check(hipMemcpyAsync(h->host_ints, sb.rank, sizeof(int) * g.h, hipMemcpyDeviceToHost,
-                                     h->stream),
-                      "hipMemcpyAsync rank");
-        }
-        hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
-        if (multirank_host) std::memcpy(multirank_host, h->host_ints, sizeof(int) * g.h);
-        prof_harvest(h);
-        check_persist_err(h, g, sb);
-        if (read_flag(h)) fail(TSVD_E_NONFINITE, "non-finite input");
+        if (check_precision(dtype, precision))
+            do_tsvt<float>(h, X, shape, dtype, tau, precision, Z, multirank_host);
+        else
+            do_tsvt<double>(h, X, shape, dtype, tau, precision, Z, multirank_host);
     });
 }
 
@@ -769,119 +1027,11 @@ tsvd_status tsvd_complete(tsvd_handle h, const void* X_obs, const uint8_t* mask,
                           tsvd_dtype dtype, double rho, double tol, const tsvd_admm_opts* opts,
                           void* X_out, tsvd_info* info_host) {
     return guarded([&] {
-        const auto t0 = std::chrono::steady_clock::now();
         check_handle(h);
-        if (!X_obs || !mask || !X_out) fail(TSVD_E_INVALID, "null tensor pointer");
-        if (!(rho > 0.0) || !std::isfinite(rho)) fail(TSVD_E_INVALID, "rho must be > 0");
-        if (!(tol >= 0.0) || !std::isfinite(tol)) fail(TSVD_E_INVALID, "tol must be >= 0");
-        const AdmmSettings s = settings(opts, 1.1, 1e3, 300);
-        if (s.rho_max < rho) fail(TSVD_E_INVALID, "rho_max must be >= rho");
-        check_precision(dtype, s.precision);
-        const Geometry g = make_geometry(shape);
-        Device dev(h->device);
-        using T = double;
-        const int tile_i = dft_inverse_tile(g, EPI_COMPLETE);
-        const int nparts = (int)std::max<int64_t>(dft_grid(g, tile_i), elementwise_parts());
-        const int64_t N = g.numel;
-        ensure_workspace(h, svt_bytes<T>(g, nparts) + 4 * (N * sizeof(T) + 256) + 4096);
-        Carver cv{reinterpret_cast<char*>(h->ws)};
-        SvtBuffers<T> sb = carve_svt<T>(cv, g, nparts);
-        T* Zb[2] = {cv.take<T>(N), cv.take<T>(N)};
-        T* Qb[2] = {cv.take<T>(N), cv.take<T>(N)};
-        ensure_twiddles(h, g.L);
-        hipStream_t st = h->stream;
-        const T* Y = static_cast<const T*>(X_obs);
-        launch_fill<T>(Zb[0], 0.0, N, st);
-        launch_fill<T>(Qb[0], 0.0, N, st);
-        Ctrl c{};
-        c.rho = rho;
-        c.tau = 1.0 / rho;
-        c.dscale = 1.0;
-        c.dscale_used = 1.0;
-        c.growth = s.growth;
-        c.rho_max = s.rho_max;
-        c.rho_used = rho;
-        put_ctrl(h, c);
-        launch_sumsq<T>(Y, mask, N, sb.partials, elementwise_parts(), st);
-        launch_set_tol(h->ctrl, sb.partials, elementwise_parts(), tol, st);
-        launch_check("setup");
-        clear_flag(h);
-        clear_persist_err(h, g, sb);
-
-        FwdArgs<T> fa{};
-        fa.x = Y;
-        fa.mask = mask;
-        fa.ctrl = h->ctrl;
-        fa.tw = h->tw;
-        fa.out = sb.A;
-        fa.nonfinite = h->flag;
-        fa.g = g;
-        fa.tile = dft_forward_tile(g);
-        InvArgs<T> ia{};
-        ia.in = sb.Z;
-        ia.tw = h->tw;
-        ia.ctrl = h->ctrl;
-        ia.g = g;
-        ia.tile = tile_i;
-        ia.y = Y;
-        ia.mask = mask;
-        ia.partials = sb.partials;
-        const int inv_parts = (int)dft_grid(g, tile_i);
-        const double slice_bytes = (double)g.h * g.m * g.n * sizeof(cplx<T>);
-        int sweeps_total = 0, sweeps_last = 0, iters = 0;
-        Ctrl hc{};
-        WarmState warm;
-        warm.enabled = env_int("TSVD_WARM", 1) != 0;
-        warm.reorth_every = env_int("TSVD_REORTH_EVERY", 4);
-        for (int k = 0; k < s.max_iter; ++k) {
-            fa.z = Zb[k % 2];
-            fa.dual = Qb[k % 2];
-            // Y, mask, Z, Q in; slices out
-            prof_launch(h, K_DFT_FWD, slice_bytes + (double)N * (3 * sizeof(T) + 1),
-                        [&] { launch_dft_forward(PRO_COMPLETE, fa, st); });
-            launch_check("dft_forward");
-            const SweepStats ss = run_svt<T>(h, g, sb, s.max_sweeps, &warm);
-            if (ss.sweeps < 0) {
-                ensure_host_ints(h, g.h);
-                hip_check(hipMemcpyAsync(h->host_ints, sb.sweeps, sizeof(int) * g.h, hipMemcpyDeviceToHost, st),
-                          "hipMemcpyAsync sweeps");
-            }
-            ia.in = static_cast<const cplx<T>*>(ss.out);
-            ia.out = Zb[(k + 1) % 2];
-            ia.z_old = Zb[k % 2];
-            ia.dual_old = Qb[k % 2];
-            ia.dual_new = Qb[(k + 1) % 2];
-            // slices, Y, mask, Z, Q in; Z', Q~ out
-            prof_launch(h, K_DFT_INV, slice_bytes + (double)N * (5 * sizeof(T) + 1),
-                        [&] { launch_dft_inverse(EPI_COMPLETE, ia, st); });
-            launch_check("dft_inverse");
-            prof_launch(h, K_CTRL, (double)inv_parts * kNumPartials * sizeof(double),
-                        [&] { launch_admm_ctrl(h->ctrl, sb.partials, inv_parts, 0, st); });
-            launch_check("admm_ctrl");
-            hc = get_ctrl(h);
-            sweeps_last = ss.sweeps >= 0 ? ss.sweeps : max_sweeps_of(h, g.h);
-            sweeps_total += sweeps_last;
-            iters = k + 1;
-            if (hc.done) break;
-        }
-        launch_complete_output<T>(Y, mask, Zb[(iters - 1) % 2], Qb[(iters - 1) % 2], h->ctrl,
-                                  static_cast<T*>(X_out), N, st);
-        launch_check("complete_output");
-        hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
-        prof_harvest(h);
-        check_persist_err(h, g, sb);
-        if (hc.nonfinite || read_flag(h)) fail(TSVD_E_NONFINITE, "non-finite input or iterate");
-        if (info_host) {
-            info_host->iters = iters;
-            info_host->converged = hc.done ? 1 : 0;
-            info_host->sweeps_total = sweeps_total;
-            info_host->sweeps_last = sweeps_last;
-            info_host->primal = hc.primal;
-            info_host->change = hc.change;
-            info_host->rho_final = hc.rho_used;
-            info_host->seconds =
-                std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-        }
+        if (check_precision(dtype, opts ? opts->precision : TSVD_PREC_FP64))
+            do_complete<float>(h, X_obs, mask, shape, dtype, rho, tol, opts, X_out, info_host);
+        else
+            do_complete<double>(h, X_obs, mask, shape, dtype, rho, tol, opts, X_out, info_host);
     });
 }
 
@@ -889,127 +1039,11 @@ tsvd_status trpca(tsvd_handle h, const void* X, tsvd_shape shape, tsvd_dtype dty
                   double mu, double tol, tsvd_shrink shrink, const tsvd_admm_opts* opts, void* L_out,
                   void* S_out, tsvd_info* info_host) {
     return guarded([&] {
-        const auto t0 = std::chrono::steady_clock::now();
         check_handle(h);
-        if (!X || !L_out || !S_out) fail(TSVD_E_INVALID, "null tensor pointer");
-        if (!(lambda > 0.0) || !std::isfinite(lambda)) fail(TSVD_E_INVALID, "lambda must be > 0");
-        if (!(mu > 0.0) || !std::isfinite(mu)) fail(TSVD_E_INVALID, "mu must be > 0");
-        if (!(tol >= 0.0) || !std::isfinite(tol)) fail(TSVD_E_INVALID, "tol must be >= 0");
-        if (shrink != TSVD_SHRINK_L1 && shrink != TSVD_SHRINK_L112) fail(TSVD_E_INVALID, "unknown shrink");
-        const AdmmSettings s = settings(opts, 1.2, 1e10, 500);
-        if (s.rho_max < mu) fail(TSVD_E_INVALID, "rho_max must be >= mu");
-        check_precision(dtype, s.precision);
-        const Geometry g = make_geometry(shape);
-        Device dev(h->device);
-        using T = double;
-        const int epi = shrink == TSVD_SHRINK_L1 ? EPI_RPCA_L1 : EPI_RPCA_L112;
-        const int tile_i = dft_inverse_tile(g, epi);
-        const int nparts = (int)std::max<int64_t>(dft_grid(g, tile_i), elementwise_parts());
-        const int64_t N = g.numel;
-        ensure_workspace(h, svt_bytes<T>(g, nparts) + 6 * (N * sizeof(T) + 256) + 4096);
-        Carver cv{reinterpret_cast<char*>(h->ws)};
-        SvtBuffers<T> sb = carve_svt<T>(cv, g, nparts);
-        T* Lb[2] = {cv.take<T>(N), cv.take<T>(N)};
-        T* Sb[2] = {cv.take<T>(N), cv.take<T>(N)};
-        T* Wb[2] = {cv.take<T>(N), cv.take<T>(N)};
-        ensure_twiddles(h, g.L);
-        hipStream_t st = h->stream;
-        const T* M = static_cast<const T*>(X);
-        launch_fill<T>(Lb[0], 0.0, N, st);
-        launch_fill<T>(Sb[0], 0.0, N, st);
-        launch_fill<T>(Wb[0], 0.0, N, st);
-        Ctrl c{};
-        c.rho = mu;
-        c.tau = 1.0 / mu;
-        c.dscale = 1.0;
-        c.dscale_used = 1.0;
-        c.growth = s.growth;
-        c.rho_max = s.rho_max;
-        c.lambda = lambda;
-        c.shrink = lambda / mu;
-        c.rho_used = mu;
-        put_ctrl(h, c);
-        launch_sumsq<T>(M, nullptr, N, sb.partials, elementwise_parts(), st);
-        launch_set_tol(h->ctrl, sb.partials, elementwise_parts(), tol, st);
-        launch_check("setup");
-        clear_flag(h);
-        clear_persist_err(h, g, sb);
-
-        FwdArgs<T> fa{};
-        fa.x = M;
-        fa.ctrl = h->ctrl;
-        fa.tw = h->tw;
-        fa.out = sb.A;
-        fa.nonfinite = h->flag;
-        fa.g = g;
-        fa.tile = dft_forward_tile(g);
-        InvArgs<T> ia{};
-        ia.in = sb.Z;
-        ia.tw = h->tw;
-        ia.ctrl = h->ctrl;
-        ia.g = g;
-        ia.tile = tile_i;
-        ia.m = M;
-        ia.partials = sb.partials;
-        const int inv_parts = (int)dft_grid(g, tile_i);
-        const double slice_bytes = (double)g.h * g.m * g.n * sizeof(cplx<T>);
-        int sweeps_total = 0, sweeps_last = 0, iters = 0;
-        Ctrl hc{};
-        WarmState warm;
-        warm.enabled = env_int("TSVD_WARM", 1) != 0;
-        warm.reorth_every = env_int("TSVD_REORTH_EVERY", 4);
-        for (int k = 0; k < s.max_iter; ++k) {
-            fa.s = Sb[k % 2];
-            fa.dual = Wb[k % 2];
-            // M, S, W in; slices out
-            prof_launch(h, K_DFT_FWD, slice_bytes + (double)N * 3 * sizeof(T),
-                        [&] { launch_dft_forward(PRO_RPCA, fa, st); });
-            launch_check("dft_forward");
-            const SweepStats ss = run_svt<T>(h, g, sb, s.max_sweeps, &warm);
-            if (ss.sweeps < 0) {
-                ensure_host_ints(h, g.h);
-                hip_check(hipMemcpyAsync(h->host_ints, sb.sweeps, sizeof(int) * g.h, hipMemcpyDeviceToHost, st),
-                          "hipMemcpyAsync sweeps");
-            }
-            ia.in = static_cast<const cplx<T>*>(ss.out);
-            ia.out = Lb[(k + 1) % 2];
-            ia.l_old = Lb[k % 2];
-            ia.s_old = Sb[k % 2];
-            ia.s_new = Sb[(k + 1) % 2];
-            ia.dual_old = Wb[k % 2];
-            ia.dual_new = Wb[(k + 1) % 2];
-            // slices, M, W, S, L in; L', S', W~ out
-            prof_launch(h, K_DFT_INV, slice_bytes + (double)N * 7 * sizeof(T),
-                        [&] { launch_dft_inverse(epi, ia, st); });
-            launch_check("dft_inverse");
-            prof_launch(h, K_CTRL, (double)inv_parts * kNumPartials * sizeof(double),
-                        [&] { launch_admm_ctrl(h->ctrl, sb.partials, inv_parts, 1, st); });
-            launch_check("admm_ctrl");
-            hc = get_ctrl(h);
-            sweeps_last = ss.sweeps >= 0 ? ss.sweeps : max_sweeps_of(h, g.h);
-            sweeps_total += sweeps_last;
-            iters = k + 1;
-            if (hc.done) break;
-        }
-        hip_check(hipMemcpyAsync(L_out, Lb[iters % 2], N * sizeof(T), hipMemcpyDeviceToDevice, st),
-                  "hipMemcpyAsync L");
-        hip_check(hipMemcpyAsync(S_out, Sb[iters % 2], N * sizeof(T), hipMemcpyDeviceToDevice, st),
-                  "hipMemcpyAsync S");
-        hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
-        prof_harvest(h);
-        check_persist_err(h, g, sb);
-        if (hc.nonfinite || read_flag(h)) fail(TSVD_E_NONFINITE, "non-finite input or iterate");
-        if (info_host) {
-            info_host->iters = iters;
-            info_host->converged = hc.done ? 1 : 0;
-            info_host->sweeps_total = sweeps_total;
-            info_host->sweeps_last = sweeps_last;
-            info_host->primal = hc.primal;
-            info_host->change = hc.change;
-            info_host->rho_final = hc.rho_used;
-            info_host->seconds =
-                std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-        }
+        if (check_precision(dtype, opts ? opts->precision : TSVD_PREC_FP64))
+            do_trpca<float>(h, X, shape, dtype, lambda, mu, tol, shrink, opts, L_out, S_out, info_host);
+        else
+            do_trpca<double>(h, X, shape, dtype, lambda, mu, tol, shrink, opts, L_out, S_out, info_host);
     });
 }
 

@@ -17,8 +17,8 @@
 // along the slice row mode, at one slice column.  The tile's tubes are
 // staged through LDS, so tube-contiguous HBM traffic on one side and
 // row-contiguous slice traffic on the other are both coalesced.
-// Transform: direct DFT against an FP64 twiddle table held in LDS (L is at
-// most a few hundred on this path, and the pass is bandwidth-bound there).
+// Transform: direct DFT against a twiddle table held in LDS (FP64 table,
+// rounded to the element type; L is at most a few hundred on this path).
 
 #include "kernels.h"
 
@@ -66,10 +66,10 @@ __global__ __launch_bounds__(kBlock) void dft_forward_kernel(FwdArgs<T> a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const Geometry& g = a.g;
     const int L = g.L, tile = a.tile, ldb = L + 1;
-    cplx<double>* tw = reinterpret_cast<cplx<double>*>(smem);
+    cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem);
     T* buf = reinterpret_cast<T*>(tw + L);
 
-    for (int u = threadIdx.x; u < L; u += blockDim.x) tw[u] = a.tw[u];
+    for (int u = threadIdx.x; u < L; u += blockDim.x) tw[u] = cplx<T>{(T)a.tw[u].re, (T)a.tw[u].im};
 
     const int row_tiles = (g.m + tile - 1) / tile;
     const int col = blockIdx.x / row_tiles;
@@ -105,13 +105,13 @@ __global__ __launch_bounds__(kBlock) void dft_forward_kernel(FwdArgs<T> a) {
         const int k3 = s / Qh, k4 = s - k3 * Qh;
         const int step3 = (k3 * Q) % L, step4 = (k4 * P) % L;
         const T* xb = buf + r * ldb;
-        double re = 0.0, im = 0.0;
+        T re = 0, im = 0;
         int u3 = 0;
         for (int t3 = 0; t3 < P; ++t3) {
             int u = u3;
             const T* xr = xb + t3 * Q;
             for (int t4 = 0; t4 < Q; ++t4) {
-                const double v = (double)xr[t4];
+                const T v = xr[t4];
                 re += v * tw[u].re;
                 im += v * tw[u].im;
                 u += step4;
@@ -121,7 +121,7 @@ __global__ __launch_bounds__(kBlock) void dft_forward_kernel(FwdArgs<T> a) {
             if (u3 >= L) u3 -= L;
         }
         const int64_t dst = ((int64_t)s * g.n + col) * g.m + row0 + r;
-        a.out[dst] = cplx<T>{(T)re, (T)im};
+        a.out[dst] = cplx<T>{re, im};
     }
 }
 
@@ -130,7 +130,7 @@ __global__ __launch_bounds__(kBlock) void dft_inverse_kernel(InvArgs<T> a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const Geometry& g = a.g;
     const int L = g.L, tile = a.tile, h = g.h;
-    cplx<double>* tw = reinterpret_cast<cplx<double>*>(smem);
+    cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem);
     cplx<T>* zb = reinterpret_cast<cplx<T>*>(tw + L);               // h x tile
     // L112 only: prox output and D of the tile, tile x L each
     T* lb = reinterpret_cast<T*>(zb + (int64_t)h * tile);
@@ -138,7 +138,7 @@ __global__ __launch_bounds__(kBlock) void dft_inverse_kernel(InvArgs<T> a) {
     // reduction scratch (64 doubles) followed by the per-tube shrink factors
     double* red = reinterpret_cast<double*>(db + (EPI == EPI_RPCA_L112 ? (int64_t)tile * L : 0));
 
-    for (int u = threadIdx.x; u < L; u += blockDim.x) tw[u] = a.tw[u];
+    for (int u = threadIdx.x; u < L; u += blockDim.x) tw[u] = cplx<T>{(T)a.tw[u].re, (T)a.tw[u].im};
 
     const int row_tiles = (g.m + tile - 1) / tile;
     const int col = blockIdx.x / row_tiles;
@@ -152,7 +152,7 @@ __global__ __launch_bounds__(kBlock) void dft_inverse_kernel(InvArgs<T> a) {
     __syncthreads();
 
     const int P = g.P, Q = g.Q, Qh = g.Qh;
-    const double inv_l = 1.0 / (double)L;
+    const T inv_l = (T)1 / (T)L;
     double part[kNumPartials] = {0.0, 0.0, 0.0, 0.0};
     double ds = 1.0, thr = 0.0;
     if (EPI != EPI_STORE) {
@@ -164,22 +164,22 @@ __global__ __launch_bounds__(kBlock) void dft_inverse_kernel(InvArgs<T> a) {
     auto synth = [&](int r, int t) -> T {
         const int t3 = t / Q, t4 = t - t3 * Q;
         const int step3 = (t3 * Q) % L, step4 = (t4 * P) % L;
-        double acc = 0.0;
+        T acc = 0;
         int u3 = 0;
         for (int k3 = 0; k3 < P; ++k3) {
             int u = u3;
             const cplx<T>* zr = zb + (k3 * Qh) * tile + r;
             for (int k4 = 0; k4 < Qh; ++k4) {
                 const cplx<T> z = zr[k4 * tile];
-                const double wgt = (k4 == 0 || 2 * k4 == Q) ? 1.0 : 2.0;
-                acc += wgt * ((double)z.re * tw[u].re + (double)z.im * tw[u].im);
+                const T wgt = (k4 == 0 || 2 * k4 == Q) ? (T)1 : (T)2;
+                acc += wgt * (z.re * tw[u].re + z.im * tw[u].im);
                 u += step4;
                 if (u >= L) u -= L;
             }
             u3 += step3;
             if (u3 >= L) u3 -= L;
         }
-        return (T)(acc * inv_l);
+        return acc * inv_l;
     };
 
     if (EPI == EPI_RPCA_L112) {
@@ -280,7 +280,7 @@ int64_t dft_grid(const Geometry& g, int tile) {
 template <typename T>
 void launch_dft_forward(int prologue, const FwdArgs<T>& a, hipStream_t st) {
     const int64_t grid = dft_grid(a.g, a.tile);
-    const size_t lds = (size_t)a.g.L * sizeof(cplx<double>) + (size_t)a.tile * (a.g.L + 1) * sizeof(T);
+    const size_t lds = (size_t)a.g.L * sizeof(cplx<T>) + (size_t)a.tile * (a.g.L + 1) * sizeof(T);
     switch (prologue) {
         case PRO_COPY:
             hipLaunchKernelGGL((dft_forward_kernel<T, PRO_COPY>), dim3(grid), dim3(kBlock), lds, st, a);
@@ -297,7 +297,7 @@ void launch_dft_forward(int prologue, const FwdArgs<T>& a, hipStream_t st) {
 template <typename T>
 void launch_dft_inverse(int epilogue, const InvArgs<T>& a, hipStream_t st) {
     const int64_t grid = dft_grid(a.g, a.tile);
-    size_t lds = (size_t)a.g.L * sizeof(cplx<double>) + (size_t)a.g.h * a.tile * sizeof(cplx<T>);
+    size_t lds = (size_t)a.g.L * sizeof(cplx<T>) + (size_t)a.g.h * a.tile * sizeof(cplx<T>);
     if (epilogue == EPI_RPCA_L112) lds += 2 * (size_t)a.tile * a.g.L * sizeof(T);
     lds += 64 * sizeof(double) + (size_t)a.tile * sizeof(T) + 16;
     switch (epilogue) {
@@ -318,5 +318,7 @@ void launch_dft_inverse(int epilogue, const InvArgs<T>& a, hipStream_t st) {
 
 template void launch_dft_forward<double>(int, const FwdArgs<double>&, hipStream_t);
 template void launch_dft_inverse<double>(int, const InvArgs<double>&, hipStream_t);
+template void launch_dft_forward<float>(int, const FwdArgs<float>&, hipStream_t);
+template void launch_dft_inverse<float>(int, const InvArgs<float>&, hipStream_t);
 
 }  // namespace tsvd

@@ -106,4 +106,6 @@ void launch_cgemm(const GemmArgs<T>& g, hipStream_t st) {
 
 template void launch_cgemm<double>(const GemmArgs<double>&, hipStream_t);
 
+template void launch_cgemm<float>(const GemmArgs<float>&, hipStream_t);
+
 }  // namespace tsvd

@@ -459,4 +459,8 @@ template void launch_jacobi_init<double>(const JacArgs<double>&, hipStream_t);
 template void launch_jacobi_self<double>(const JacArgs<double>&, int, hipStream_t);
 template void launch_jacobi_cross<double>(const JacArgs<double>&, int, hipStream_t);
 
+template void launch_jacobi_init<float>(const JacArgs<float>&, hipStream_t);
+template void launch_jacobi_self<float>(const JacArgs<float>&, int, hipStream_t);
+template void launch_jacobi_cross<float>(const JacArgs<float>&, int, hipStream_t);
+
 }  // namespace tsvd

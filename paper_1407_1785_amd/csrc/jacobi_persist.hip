@@ -432,4 +432,7 @@ hipError_t launch_jacobi_persistent(const JacArgs<T>& a, const PersistArgs& p, i
 template hipError_t launch_jacobi_persistent<double>(const JacArgs<double>&, const PersistArgs&, int,
                                                      hipStream_t);
 
+template hipError_t launch_jacobi_persistent<float>(const JacArgs<float>&, const PersistArgs&, int,
+                                                    hipStream_t);
+
 }  // namespace tsvd

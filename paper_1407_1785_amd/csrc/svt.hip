@@ -129,4 +129,7 @@ void launch_svt_rebuild(const SvtArgs<T>& a, hipStream_t st) {
 template void launch_svt_weights<double>(const SvtArgs<double>&, hipStream_t);
 template void launch_svt_rebuild<double>(const SvtArgs<double>&, hipStream_t);
 
+template void launch_svt_weights<float>(const SvtArgs<float>&, hipStream_t);
+template void launch_svt_rebuild<float>(const SvtArgs<float>&, hipStream_t);
+
 }  // namespace tsvd

@@ -1,0 +1,81 @@
+"""FP32 precision form (FP32 transforms, sweeps and rebuild; FP64 rotation
+parameters, residual norms and stopping test) against the FP64 oracle.
+The stated bar for this form is a relative error of at most 1e-4."""
+
+import numpy as np
+import pytest
+
+import paper_1407_1785_amd as lib
+from oracle import admm
+from oracle.tsvt import tsvt as tsvt_oracle
+import workloads
+from tests.gpu_util import announce, rel_fro, to_gpu, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+BAR = 1e-4
+
+
+@pytest.mark.parametrize("shape", [(32, 32, 16), (20, 13, 7), (13, 20, 8), (9, 12, 3, 4), (70, 45, 5)])
+def test_tsvt_fp32_form(shape):
+    torch = torch_cuda()
+    rng = np.random.default_rng(sum(shape) + 1)
+    x = rng.normal(size=shape).astype(np.float32)
+    tau = 1.3
+    z_ref, _ = tsvt_oracle(x.astype(np.float64), tau)
+    announce("tsvt fp32", shape)
+    z, _ = lib.tsvt(to_gpu(torch, x), tau, precision=lib.PREC_FP32)
+    assert z.dtype == torch.float32
+    assert rel_fro(z.cpu().numpy(), z_ref) <= BAR
+
+
+def test_tsvt_fp32_video_shape():
+    torch = torch_cuda()
+    w = workloads.video_completion(0)
+    z_ref, _ = tsvt_oracle(w["X"].astype(np.float64), 5.0)
+    announce("tsvt fp32 video")
+    z, _ = lib.tsvt(to_gpu(torch, w["X"]), 5.0, precision=lib.PREC_FP32)
+    assert rel_fro(z.cpu().numpy(), z_ref) <= BAR
+
+
+@pytest.mark.parametrize("iters", [5, 60])
+def test_completion_fp32_form(iters):
+    torch = torch_cuda()
+    w = workloads.completion_small(0)
+    ref = admm.complete(w["M_obs"], w["mask"], max_iter=iters, tol=0.0)
+    announce("complete fp32", iters)
+    x, info = lib.tsvd_complete(to_gpu(torch, w["M_obs"].astype(np.float32)), to_gpu(torch, w["mask"]),
+                                1e-2, 0.0, max_iter=iters, precision=lib.PREC_FP32)
+    assert info.iters == iters
+    assert rel_fro(x.cpu().numpy(), ref["X"]) <= BAR
+
+
+def test_completion_fp32_video_prefix():
+    """First 12 iterations of the video-shaped workload, FP32 form vs oracle."""
+    torch = torch_cuda()
+    w = workloads.video_completion(0)
+    ref = admm.complete(w["M_obs"].astype(np.float64), w["mask"], w["rho"], w["growth"], w["rho_max"],
+                        max_iter=12, tol=0.0)
+    announce("complete fp32 video prefix")
+    x, _ = lib.tsvd_complete(to_gpu(torch, w["M_obs"]), to_gpu(torch, w["mask"]), w["rho"], 0.0,
+                             max_iter=12, precision=lib.PREC_FP32)
+    assert rel_fro(x.cpu().numpy(), ref["X"]) <= BAR
+
+
+def test_trpca_fp32_form():
+    torch = torch_cuda()
+    p = workloads.trpca_problem(0, shape=(48, 40, 16), rank=3)
+    ref = admm.trpca(p["M"], p["lam"], max_iter=40, tol=0.0)
+    announce("trpca fp32")
+    lo, sp, info = lib.trpca(to_gpu(torch, p["M"].astype(np.float32)), p["lam"], 1e-3, 0.0,
+                             max_iter=40, precision=lib.PREC_FP32)
+    assert rel_fro(lo.cpu().numpy(), ref["L"]) <= BAR
+
+
+def test_precision_dtype_mismatch_is_rejected():
+    torch = torch_cuda()
+    x = torch.zeros((4, 5, 6), dtype=torch.float64, device="cuda")
+    announce("fp32 mismatch")
+    with pytest.raises(lib.TsvdError) as e:
+        lib.tsvt(x, 1.0, precision=lib.PREC_FP32)
+    assert e.value.status == -6

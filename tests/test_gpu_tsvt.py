@@ -95,5 +95,5 @@ def test_tsvt_errors():
         lib.tsvt(bad, 1.0)
     assert e.value.status == -5
     with pytest.raises(lib.TsvdError) as e:
-        lib.tsvt(x.float(), 1.0)
+        lib.tsvt(x.float(), 1.0)   # FP32 data needs the FP32 form
     assert e.value.status == -6
