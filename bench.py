@@ -111,6 +111,10 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--only", choices=["fp32", "fp64"], default=None,
+                    help="run one form only (for profiler runs); prints its timing line")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one plain device copy of 1 GiB (reference for HBM byte counters) and exit")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -128,6 +132,14 @@ def main() -> int:
         print("bench.py needs a GPU", file=sys.stderr)
         return 2
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "device copy", "bytes_read": src.numel() * 8,
+                          "bytes_written": dst.numel() * 8}), flush=True)
+        return 0
     w = workloads.video_completion(0, shape=SHAPE)
     mask = torch.from_numpy(w["mask"]).to(dev)
     obs32 = torch.from_numpy(np.asarray(w["M_obs"], dtype=np.float32)).to(dev)
@@ -135,6 +147,20 @@ def main() -> int:
     handle = lib.handle_for(obs32)
     kw = dict(rho=w["rho"], tol=0.0, growth=w["growth"], rho_max=w["rho_max"])
     fp32 = dict(precision=lib.PREC_FP32)
+
+    if args.only:
+        obs = obs32 if args.only == "fp32" else obs64
+        extra = fp32 if args.only == "fp32" else {}
+        if args.warmup > 0:
+            lib.tsvd_complete(obs, mask, max_iter=args.warmup, **kw, **extra)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info = lib.tsvd_complete(obs, mask, max_iter=args.steps, **kw, **extra)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        print(json.dumps({"form": args.only, "iters_per_s": args.steps / dt, "steps": args.steps,
+                          "sweeps_per_iter": info.sweeps_total / max(1, info.iters)}), flush=True)
+        return 0
 
     def timed(obs, **extra):
         if args.warmup > 0:

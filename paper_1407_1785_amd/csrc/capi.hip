@@ -416,7 +416,8 @@ SweepStats run_svt(tsvd_handle h, const Geometry& g, const SvtBuffers<T>& sb, in
         launch_check("jacobi_init");
         launch_fill<int>(sb.pbar, 0, 4 * g.h, st);   // the error word is cleared per call
         launch_check("fill");
-        PersistArgs pa{sb.pbar, sb.pbar + g.h, sb.pbar + 4 * g.h, max_sweeps, nullptr};
+        PersistArgs pa{sb.pbar, sb.pbar + g.h, sb.pbar + 4 * g.h, max_sweeps, nullptr,
+                       env_int("TSVD_COOP", 1) != 0 ? 1 : 0};
         static long long* trace_buf = nullptr;
         const bool tracing = env_int("TSVD_TRACE", 0) != 0;
         if (tracing) {

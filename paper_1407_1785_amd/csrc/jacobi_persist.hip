@@ -13,10 +13,13 @@
 // a barrier, and reads the blocks of its next positions.  The first round of
 // every sweep also orthogonalises each block internally.
 //
-// Work split.  A column pair is handled by a 16-lane group (one DPP row), so
-// a 256-thread workgroup works on BW = 16 pairs per step; each lane holds
-// rows lane16 + 16 k of its columns, the dot products are reduced inside the
-// row with DPP, and the rotation parameters are computed per group in FP64.
+// Work split.  A column pair is handled by a group of PG = 32 lanes (two DPP
+// rows), so a 512-thread workgroup (two waves per SIMD) works on BW = 16
+// pairs per step; each lane holds rows lane + 32 k of its columns, the
+// cross product is reduced with DPP and readlane, and the rotation
+// parameters are computed per group in FP64.  Column norms are computed
+// exactly at the start of every round and tracked through the rotations of
+// the round (a rotation moves t |gamma| from one squared norm to the other).
 //
 // Synchronisation.  The per-slice barrier is a counter in global memory:
 // each workgroup publishes its block writes (agent-scope release fence),
@@ -37,8 +40,7 @@ namespace tsvd {
 
 namespace {
 
-constexpr int PG = 16;                  // lanes per column pair (one DPP row)
-constexpr int PBW = kBlock / PG;        // 16 columns per block, 16 pairs per step
+constexpr int PBW = 16;                       // columns per block = pairs per step
 constexpr long long kSpinLimit = 1LL << 21;   // about a second of polling
 
 __device__ __forceinline__ int pblk_start(int b, int n, int nb) {
@@ -56,12 +58,26 @@ __device__ __forceinline__ double pdpp(double v) {
     return __hiloint2double(hi, lo);
 }
 
-// sum over the 16 lanes of a DPP row; every lane of the row gets it
-__device__ __forceinline__ double row_sum(double v) {
+__device__ __forceinline__ double preadlane(double v, int lane) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the PG lanes of a pair group; every lane of the group gets the
+// same value.  16 lanes = one DPP row; 32 lanes = two rows combined through
+// readlane in a fixed order.
+template <int PG>
+__device__ __forceinline__ double group_sum(double v) {
     v += pdpp<0xB1>(v);    // lane ^ 1
     v += pdpp<0x4E>(v);    // lane ^ 2
     v += pdpp<0x141>(v);   // other quad of the half row
     v += pdpp<0x140>(v);   // other half of the row
+    if (PG == 32) {
+        const double lo = preadlane(v, 0) + preadlane(v, 16);
+        const double hi = preadlane(v, 32) + preadlane(v, 48);
+        v = (__lane_id() < 32) ? lo : hi;
+    }
     return v;
 }
 
@@ -77,13 +93,15 @@ __device__ __forceinline__ double prcp(double x) {
     return y * (2.0 - x * y);
 }
 
+// Rotation of a pair from alpha, beta, gamma (FP64): c, and s e = a + i b.
+// Also returns t |gamma|, the amount that moves from ||x||^2 to ||y||^2.
 struct PRot {
-    double c, s, er, ei;
+    double c, a, b, tg;
     bool on;
 };
 
 __device__ __forceinline__ PRot prot(double al, double be, double gr, double gi, double tol) {
-    PRot r{1.0, 0.0, 1.0, 0.0, false};
+    PRot r{1.0, 0.0, 0.0, 0.0, false};
     const double g2 = gr * gr + gi * gi;
     if (!(g2 > (tol * tol) * al * be) || !(g2 > 0.0)) return r;
     const double rg = prsqrt(g2);
@@ -92,99 +110,106 @@ __device__ __forceinline__ PRot prot(double al, double be, double gr, double gi,
     const double t = prcp(fabs(zeta) + q * prsqrt(q));
     const double ts = zeta >= 0.0 ? t : -t;
     r.c = prsqrt(1.0 + ts * ts);
-    r.s = r.c * ts;
-    r.er = gr * rg;
-    r.ei = gi * rg;
+    const double s = r.c * ts;
+    r.a = s * (gr * rg);
+    r.b = s * (gi * rg);
+    r.tg = ts * (g2 * rg);
     r.on = true;
     return r;
 }
 
+// x <- c x - s conj(e) y,  y <- s e x + c y   with s e = a + i b
 template <typename T>
 __device__ __forceinline__ void prot_apply(const PRot& rd, cplx<T>& x, cplx<T>& y) {
-    const T c = (T)rd.c, s = (T)rd.s, er = (T)rd.er, ei = (T)rd.ei;
-    const T ycr = er * y.re + ei * y.im;
-    const T yci = er * y.im - ei * y.re;
-    const T exr = er * x.re - ei * x.im;
-    const T exi = er * x.im + ei * x.re;
-    const cplx<T> xn{c * x.re - s * ycr, c * x.im - s * yci};
-    const cplx<T> yn{s * exr + c * y.re, s * exi + c * y.im};
+    const T c = (T)rd.c, a = (T)rd.a, b = (T)rd.b;
+    const cplx<T> xn{c * x.re - a * y.re - b * y.im, c * x.im - a * y.im + b * y.re};
+    const cplx<T> yn{c * y.re + a * x.re - b * x.im, c * y.im + a * x.im + b * x.re};
     x = xn;
     y = yn;
 }
 
-// Orthogonalise column x (registers) against column y_lds (LDS).  Each lane
-// holds rows l16 + 16 k; the first KA row groups are slice rows (their dot
-// products count), the rest are V rows.  Padding rows are zero throughout.
-template <typename T, int RPT>
-__device__ __forceinline__ bool ppair(cplx<T> (&x)[RPT], cplx<T>* y_lds, int ka, int l16, double tol) {
+// Squared norm of the slice rows of a column held in registers.
+template <typename T, int PG, int RPT>
+__device__ __forceinline__ double pnorm2(const cplx<T> (&x)[RPT], int ka) {
+    T acc = 0;
+#pragma unroll
+    for (int k = 0; k < RPT; ++k)
+        if (k < ka) acc += x[k].re * x[k].re + x[k].im * x[k].im;
+    return group_sum<PG>((double)acc);
+}
+
+// Orthogonalise column x (registers, squared norm al) against column y in
+// LDS (squared norm be).  Lane l of the pair group holds rows l + PG k; the
+// first ka row groups are slice rows, the rest V rows, padding rows are zero.
+// On a rotation the norms are updated in place (al -= t|gamma|, be += t|gamma|).
+template <typename T, int PG, int RPT>
+__device__ __forceinline__ bool ppair(cplx<T> (&x)[RPT], cplx<T>* y_lds, double& al, double& be, int ka,
+                                      int l, double tol) {
     cplx<T> y[RPT];
-    T al = 0, be = 0, gr = 0, gi = 0;
+    T gr = 0, gi = 0;
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
-        y[k] = y_lds[l16 + PG * k];
+        y[k] = y_lds[l + PG * k];
         if (k < ka) {
-            al += x[k].re * x[k].re + x[k].im * x[k].im;
-            be += y[k].re * y[k].re + y[k].im * y[k].im;
             gr += x[k].re * y[k].re + x[k].im * y[k].im;
             gi += x[k].re * y[k].im - x[k].im * y[k].re;
         }
     }
-    const PRot rt = prot(row_sum((double)al), row_sum((double)be), row_sum((double)gr),
-                         row_sum((double)gi), tol);
+    const PRot rt = prot(al, be, group_sum<PG>((double)gr), group_sum<PG>((double)gi), tol);
     if (!rt.on) return false;
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
         prot_apply(rt, x[k], y[k]);
-        y_lds[l16 + PG * k] = y[k];
+        y_lds[l + PG * k] = y[k];
     }
+    al -= rt.tg;
+    be += rt.tg;
     return true;
 }
 
 // LDS column of a block: slice rows 0..m-1 at 0..m-1, V rows at mp..mp+n-1
-// (mp = m rounded up to 16), zeros elsewhere.  In global memory the block's
-// slice part (w columns of m) and V part (w columns of n) are each one
-// contiguous range, so each is copied by a branch-free loop with eight
-// independent accesses in flight per thread (addresses clamped in range).
-template <typename T>
-__device__ __forceinline__ void pcopy_in(const cplx<T>* src, int count, int len, int ldc, int off,
-                                         cplx<T>* lds) {
-    if (count <= 0) return;
-    for (int base = threadIdx.x; base < count; base += 8 * kBlock) {
+// (mp = m rounded up to PG), zeros elsewhere.  The NT threads split into
+// PBW column teams of NT / PBW threads; a team copies one column, striding
+// over its rows, eight independent loads in flight per thread (addresses
+// clamped in range), with no integer division.
+template <typename T, int NT>
+__device__ __forceinline__ void pcol_in(const cplx<T>* src, int len, cplx<T>* dst) {
+    constexpr int TT = NT / PBW;
+    const int t = threadIdx.x % TT;
+    for (int base = t; base < len; base += 8 * TT) {
         cplx<T> v[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = src[min(base + u * kBlock, count - 1)];
+        for (int u = 0; u < 8; ++u) v[u] = src[min(base + u * TT, len - 1)];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int idx = base + u * kBlock;
-            if (idx < count) {
-                const int c = idx / len;
-                lds[c * ldc + off + (idx - c * len)] = v[u];
-            }
-        }
+        for (int u = 0; u < 8; ++u)
+            if (base + u * TT < len) dst[base + u * TT] = v[u];
     }
 }
 
-template <typename T>
-__device__ __forceinline__ void pcopy_out(cplx<T>* dst, int count, int len, int ldc, int off,
-                                          const cplx<T>* lds) {
-    for (int idx = threadIdx.x; idx < count; idx += kBlock) {
-        const int c = idx / len;
-        dst[idx] = lds[c * ldc + off + (idx - c * len)];
-    }
+template <typename T, int NT>
+__device__ __forceinline__ void pcol_out(const cplx<T>* src, int len, cplx<T>* dst) {
+    constexpr int TT = NT / PBW;
+    for (int r = threadIdx.x % TT; r < len; r += TT) dst[r] = src[r];
 }
 
-template <typename T>
+template <typename T, int NT>
 __device__ void pload_block(const JacArgs<T>& a, int s, int blk, int mp, int ldc, cplx<T>* lds) {
     const int c0 = pblk_start(blk, a.n, a.nb), w = pblk_start(blk + 1, a.n, a.nb) - c0;
-    pcopy_in(a.A + ((int64_t)s * a.n + c0) * a.m, w * a.m, a.m, ldc, 0, lds);
-    pcopy_in(a.V + ((int64_t)s * a.n + c0) * a.n, w * a.n, a.n, ldc, mp, lds);
+    const int c = threadIdx.x / (NT / PBW);
+    if (c < w) {
+        pcol_in<T, NT>(a.A + ((int64_t)s * a.n + c0 + c) * a.m, a.m, lds + c * ldc);
+        pcol_in<T, NT>(a.V + ((int64_t)s * a.n + c0 + c) * a.n, a.n, lds + c * ldc + mp);
+    }
 }
 
-template <typename T>
+template <typename T, int NT>
 __device__ void pstore_block(const JacArgs<T>& a, int s, int blk, int mp, int ldc, const cplx<T>* lds) {
     const int c0 = pblk_start(blk, a.n, a.nb), w = pblk_start(blk + 1, a.n, a.nb) - c0;
-    pcopy_out(a.A + ((int64_t)s * a.n + c0) * a.m, w * a.m, a.m, ldc, 0, lds);
-    pcopy_out(a.V + ((int64_t)s * a.n + c0) * a.n, w * a.n, a.n, ldc, mp, lds);
+    const int c = threadIdx.x / (NT / PBW);
+    if (c < w) {
+        pcol_out<T, NT>(lds + c * ldc, a.m, a.A + ((int64_t)s * a.n + c0 + c) * a.m);
+        pcol_out<T, NT>(lds + c * ldc + mp, a.n, a.V + ((int64_t)s * a.n + c0 + c) * a.n);
+    }
 }
 
 // Slice barrier: returns false if the bounded wait ran out.
@@ -214,18 +239,20 @@ __device__ bool slice_barrier(int* counter, int target, int* err) {
 
 }  // namespace
 
-template <typename T, int RPT>
-__global__ __launch_bounds__(kBlock) void jacobi_persistent_kernel(JacArgs<T> a, PersistArgs p) {
+template <typename T, int PG, int RPT>
+__global__ __launch_bounds__(PBW * PG) void jacobi_persistent_kernel(JacArgs<T> a, PersistArgs p) {
+    constexpr int NT = PBW * PG;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int rot_any;
     __shared__ int stop;
+    __shared__ double jnorm[PBW];
     const int G = a.nb / 2;
     const int s = blockIdx.x / G, wg = blockIdx.x - s * G;
     if (s >= a.h) return;
     const int ka = (a.m + PG - 1) / PG;   // row groups holding slice rows
     const int mp = ka * PG;
-    // column stride: the padded stacked column plus one element, so the four
-    // pair groups of a wavefront read different LDS banks
+    // column stride: the padded stacked column plus one element, so the pair
+    // groups of a wavefront read different LDS banks
     const int ldc = PG * RPT + 1;
     cplx<T>* const blk0 = reinterpret_cast<cplx<T>*>(smem);
     cplx<T>* const blk1 = blk0 + (size_t)PBW * ldc;
@@ -236,17 +263,17 @@ __global__ __launch_bounds__(kBlock) void jacobi_persistent_kernel(JacArgs<T> a,
     };
     mark();
     const int pos0 = wg, pos1 = a.nb - 1 - wg;
-    const int g = threadIdx.x / PG, l16 = threadIdx.x - g * PG;
+    const int g = threadIdx.x / PG, l = threadIdx.x - g * PG;
     const double tol = (double)a.tol;
     int* counter = p.barrier + s;
     int arrivals = 0;
 
     // zero both blocks once: padding rows stay zero under every rotation
-    for (int idx = threadIdx.x; idx < 2 * PBW * ldc; idx += kBlock) blk0[idx] = cplx<T>{(T)0, (T)0};
+    for (int idx = threadIdx.x; idx < 2 * PBW * ldc; idx += NT) blk0[idx] = cplx<T>{(T)0, (T)0};
     __syncthreads();
     int player0 = ppos_player(pos0, 0, a.nb), player1 = ppos_player(pos1, 0, a.nb);
-    pload_block(a, s, player0, mp, ldc, blk0);
-    pload_block(a, s, player1, mp, ldc, blk1);
+    pload_block<T, NT>(a, s, player0, mp, ldc, blk0);
+    pload_block<T, NT>(a, s, player1, mp, ldc, blk1);
     if (wg == 0 && threadIdx.x == 0) a.sweeps[s] = 0;
     __syncthreads();
 
@@ -261,8 +288,8 @@ __global__ __launch_bounds__(kBlock) void jacobi_persistent_kernel(JacArgs<T> a,
         __syncthreads();
         unsigned nrot = 0;
         {
-            // internal pairs of both resident blocks: waves 0-1 take block 0,
-            // waves 2-3 block 1
+            // internal pairs of both resident blocks: groups 0-7 take block 0,
+            // groups 8-15 block 1
             const bool second = g >= PBW / 2;
             const int gi = second ? g - PBW / 2 : g;
             const int pl = second ? player1 : player0;
@@ -275,13 +302,18 @@ __global__ __launch_bounds__(kBlock) void jacobi_persistent_kernel(JacArgs<T> a,
                     const int qq = ppos_player(wp - 1 - gi, st, wp);
                     if (pp < w && qq < w) {
                         cplx<T>* cp = base + pp * ldc;
-                        cplx<T> x[RPT];
+                        cplx<T>* cq = base + qq * ldc;
+                        cplx<T> x[RPT], y[RPT];
 #pragma unroll
-                        for (int k = 0; k < RPT; ++k) x[k] = cp[l16 + PG * k];
-                        if (ppair<T, RPT>(x, base + qq * ldc, ka, l16, tol)) {
+                        for (int k = 0; k < RPT; ++k) {
+                            x[k] = cp[l + PG * k];
+                            y[k] = cq[l + PG * k];
+                        }
+                        double al = pnorm2<T, PG, RPT>(x, ka), be = pnorm2<T, PG, RPT>(y, ka);
+                        if (ppair<T, PG, RPT>(x, cq, al, be, ka, l, tol)) {
                             ++nrot;
 #pragma unroll
-                            for (int k = 0; k < RPT; ++k) cp[l16 + PG * k] = x[k];
+                            for (int k = 0; k < RPT; ++k) cp[l + PG * k] = x[k];
                         }
                     }
                 }
@@ -295,20 +327,36 @@ __global__ __launch_bounds__(kBlock) void jacobi_persistent_kernel(JacArgs<T> a,
             const int wj = pblk_start(player1 + 1, a.n, a.nb) - pblk_start(player1, a.n, a.nb);
             cplx<T> xi[RPT];
 #pragma unroll
-            for (int k = 0; k < RPT; ++k) xi[k] = blk0[g * ldc + l16 + PG * k];
+            for (int k = 0; k < RPT; ++k) xi[k] = blk0[g * ldc + l + PG * k];
+            // exact squared norms at the start of the round, tracked within it
+            double al = pnorm2<T, PG, RPT>(xi, ka);
+            {
+                cplx<T> yj[RPT];
+#pragma unroll
+                for (int k = 0; k < RPT; ++k) yj[k] = blk1[g * ldc + l + PG * k];
+                const double bj = pnorm2<T, PG, RPT>(yj, ka);
+                if (l == 0) jnorm[g] = bj;
+            }
+            __syncthreads();
             for (int st = 0; st < PBW; ++st) {
                 const int jc = (g + st) & (PBW - 1);
-                if (g < wi && jc < wj) nrot += ppair<T, RPT>(xi, blk1 + jc * ldc, ka, l16, tol);
+                if (g < wi && jc < wj) {
+                    double be = jnorm[jc];
+                    if (ppair<T, PG, RPT>(xi, blk1 + jc * ldc, al, be, ka, l, tol)) {
+                        ++nrot;
+                        if (l == 0) jnorm[jc] = be;
+                    }
+                }
                 __syncthreads();
             }
             if (g < wi) {
 #pragma unroll
-                for (int k = 0; k < RPT; ++k) blk0[g * ldc + l16 + PG * k] = xi[k];
+                for (int k = 0; k < RPT; ++k) blk0[g * ldc + l + PG * k] = xi[k];
             }
             // end of the sweep: publish whether this workgroup rotated
             const bool last = rd == a.nb - 2;
             if (last) {
-                if (nrot && l16 == 0) rot_any = 1;
+                if (nrot && l == 0) rot_any = 1;
                 __syncthreads();
                 if (threadIdx.x == 0 && rot_any) atomicOr(p.rotflag + (sweep % 3) * a.h + s, 1);
             }
@@ -317,8 +365,8 @@ __global__ __launch_bounds__(kBlock) void jacobi_persistent_kernel(JacArgs<T> a,
             const int next0 = ppos_player(pos0, nr, a.nb), next1 = ppos_player(pos1, nr, a.nb);
             __syncthreads();
             mark();
-            if (next0 != player0) pstore_block(a, s, player0, mp, ldc, blk0);
-            if (next1 != player1) pstore_block(a, s, player1, mp, ldc, blk1);
+            if (next0 != player0) pstore_block<T, NT>(a, s, player0, mp, ldc, blk0);
+            if (next1 != player1) pstore_block<T, NT>(a, s, player1, mp, ldc, blk1);
             mark();
             arrivals += G;
             if (!slice_barrier(counter, arrivals, p.err)) {
@@ -332,19 +380,19 @@ __global__ __launch_bounds__(kBlock) void jacobi_persistent_kernel(JacArgs<T> a,
                 __syncthreads();
                 if (stop) {
                     // converged: the blocks that did not move go home too
-                    if (next0 == player0) pstore_block(a, s, player0, mp, ldc, blk0);
-                    if (next1 == player1) pstore_block(a, s, player1, mp, ldc, blk1);
+                    if (next0 == player0) pstore_block<T, NT>(a, s, player0, mp, ldc, blk0);
+                    if (next1 == player1) pstore_block<T, NT>(a, s, player1, mp, ldc, blk1);
                     alive = false;
                     break;
                 }
             }
             if (next0 != player0) {
                 player0 = next0;
-                pload_block(a, s, player0, mp, ldc, blk0);
+                pload_block<T, NT>(a, s, player0, mp, ldc, blk0);
             }
             if (next1 != player1) {
                 player1 = next1;
-                pload_block(a, s, player1, mp, ldc, blk1);
+                pload_block<T, NT>(a, s, player1, mp, ldc, blk1);
             }
             __syncthreads();
             mark();
@@ -354,47 +402,49 @@ __global__ __launch_bounds__(kBlock) void jacobi_persistent_kernel(JacArgs<T> a,
     if (alive) {
         // sweep cap reached: every resident block goes home
         __syncthreads();
-        pstore_block(a, s, player0, mp, ldc, blk0);
-        pstore_block(a, s, player1, mp, ldc, blk1);
+        pstore_block<T, NT>(a, s, player0, mp, ldc, blk0);
+        pstore_block<T, NT>(a, s, player1, mp, ldc, blk1);
     }
     mark();
-    if (l16 == 0 && nrot_total) atomicAdd(a.rotations, (unsigned long long)nrot_total);
+    if (l == 0 && nrot_total) atomicAdd(a.rotations, (unsigned long long)nrot_total);
 }
 
 // ------------------------------------------------------------------ host
 
 namespace {
 
-// row groups of 16 per stacked column: slice rows and V rows each padded to 16
+constexpr int kPG = 32;   // lanes per pair: 512-thread workgroups, two waves per SIMD
+
+// row groups of PG per stacked column: slice rows and V rows each padded to PG
 int persist_rpt(int m, int n) {
-    const int need = (m + PG - 1) / PG + (n + PG - 1) / PG;
-    for (int r : {2, 4, 6, 8, 10, 12, 14, 16, 18, 20, 24})
+    const int need = (m + kPG - 1) / kPG + (n + kPG - 1) / kPG;
+    for (int r : {2, 3, 4, 5, 6, 7, 8, 9, 10, 12, 14, 16, 20})
         if (r >= need) return r;
     return -1;
 }
 
-size_t persist_lds(int rpt, int elem_bytes) { return 2 * (size_t)PBW * (PG * rpt + 1) * 2 * elem_bytes; }
-
-}  // namespace
-
-namespace {
+size_t persist_lds(int rpt, int elem_bytes) { return 2 * (size_t)PBW * (kPG * rpt + 1) * 2 * elem_bytes; }
 
 template <typename T, int RPT>
-hipError_t launch_persist_t(const JacArgs<T>& a, const PersistArgs& p, size_t lds, hipStream_t st,
-                            int max_wg_per_cu_check, int cus) {
-    auto* fn = jacobi_persistent_kernel<T, RPT>;
+hipError_t launch_persist_t(const JacArgs<T>& a, const PersistArgs& p, size_t lds, hipStream_t st, int cus) {
+    auto* fn = jacobi_persistent_kernel<T, kPG, RPT>;
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds);
     int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlock, lds);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, PBW * kPG, lds);
     if (e != hipSuccess) return e;
     const int grid = a.h * (a.nb / 2);
     if ((int64_t)per_cu * cus < grid) return hipErrorCooperativeLaunchTooLarge;
-    (void)max_wg_per_cu_check;
+    if (!p.cooperative) {
+        // ordinary launch (profiler runs): the grid still fits one workgroup
+        // per CU, and every barrier wait is bounded
+        hipLaunchKernelGGL(fn, dim3(grid), dim3(PBW * kPG), lds, st, a, p);
+        return hipGetLastError();
+    }
     JacArgs<T> aa = a;
     PersistArgs pp = p;
     void* args[] = {&aa, &pp};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(fn), dim3(grid), dim3(kBlock), args,
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(fn), dim3(grid), dim3(PBW * kPG), args,
                                       (unsigned)lds, st);
 }
 
@@ -405,9 +455,9 @@ int jacobi_persistent_blocks(int n) { return jacobi_num_blocks(n, PBW); }
 bool jacobi_persistent_fits(int m, int n, int h, int elem_bytes, int cus, size_t lds_cap) {
     const int rpt = persist_rpt(m, n);
     if (rpt < 0 || n < 2) return false;
-    if (persist_lds(rpt, elem_bytes) + 64 > lds_cap) return false;
+    if (persist_lds(rpt, elem_bytes) + 256 > lds_cap) return false;
     const int64_t grid = (int64_t)h * (jacobi_persistent_blocks(n) / 2);
-    return grid <= (int64_t)cus;   // one 256-thread workgroup per CU is always resident
+    return grid <= (int64_t)cus;   // one workgroup per CU is always resident
 }
 
 template <typename T>
@@ -415,23 +465,24 @@ hipError_t launch_jacobi_persistent(const JacArgs<T>& a, const PersistArgs& p, i
     const int rpt = persist_rpt(a.m, a.n);
     const size_t lds = persist_lds(rpt, sizeof(T));
     switch (rpt) {
-        case 2: return launch_persist_t<T, 2>(a, p, lds, st, 0, cus);
-        case 4: return launch_persist_t<T, 4>(a, p, lds, st, 0, cus);
-        case 6: return launch_persist_t<T, 6>(a, p, lds, st, 0, cus);
-        case 8: return launch_persist_t<T, 8>(a, p, lds, st, 0, cus);
-        case 10: return launch_persist_t<T, 10>(a, p, lds, st, 0, cus);
-        case 12: return launch_persist_t<T, 12>(a, p, lds, st, 0, cus);
-        case 14: return launch_persist_t<T, 14>(a, p, lds, st, 0, cus);
-        case 16: return launch_persist_t<T, 16>(a, p, lds, st, 0, cus);
-        case 18: return launch_persist_t<T, 18>(a, p, lds, st, 0, cus);
-        case 20: return launch_persist_t<T, 20>(a, p, lds, st, 0, cus);
-        default: return launch_persist_t<T, 24>(a, p, lds, st, 0, cus);
+        case 2: return launch_persist_t<T, 2>(a, p, lds, st, cus);
+        case 3: return launch_persist_t<T, 3>(a, p, lds, st, cus);
+        case 4: return launch_persist_t<T, 4>(a, p, lds, st, cus);
+        case 5: return launch_persist_t<T, 5>(a, p, lds, st, cus);
+        case 6: return launch_persist_t<T, 6>(a, p, lds, st, cus);
+        case 7: return launch_persist_t<T, 7>(a, p, lds, st, cus);
+        case 8: return launch_persist_t<T, 8>(a, p, lds, st, cus);
+        case 9: return launch_persist_t<T, 9>(a, p, lds, st, cus);
+        case 10: return launch_persist_t<T, 10>(a, p, lds, st, cus);
+        case 12: return launch_persist_t<T, 12>(a, p, lds, st, cus);
+        case 14: return launch_persist_t<T, 14>(a, p, lds, st, cus);
+        case 16: return launch_persist_t<T, 16>(a, p, lds, st, cus);
+        default: return launch_persist_t<T, 20>(a, p, lds, st, cus);
     }
 }
 
 template hipError_t launch_jacobi_persistent<double>(const JacArgs<double>&, const PersistArgs&, int,
                                                      hipStream_t);
-
 template hipError_t launch_jacobi_persistent<float>(const JacArgs<float>&, const PersistArgs&, int,
                                                     hipStream_t);
 

@@ -130,6 +130,7 @@ struct PersistArgs {
     int* err;        // set to 1 if a barrier wait ran out
     int max_sweeps;
     long long* trace;  // optional: 64 timestamps of workgroup 0 of slice 0
+    int cooperative;   // 1: cooperative launch (co-residency guaranteed by the runtime)
 };
 int jacobi_persistent_blocks(int n);
 bool jacobi_persistent_fits(int m, int n, int h, int elem_bytes, int cus, size_t lds_cap);
