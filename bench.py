@@ -41,12 +41,14 @@ PEAK_FP32_VALU_TFLOPS = 157.3  # MI355X FP32 vector
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_video_completion.json")
 
 
-def source_digest() -> str:
+def source_digest(files) -> str:
+    """Digest of the sources a traffic record was measured with (the kernel's
+    own file and the headers it includes): a record whose digest no longer
+    matches describes an older kernel and is not reported."""
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_1407_1785_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, name), "rb") as f:
-            h.update(name.encode())
+    for rel in files:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(os.path.basename(rel).encode())
             h.update(f.read())
     return h.hexdigest()[:16]
 
@@ -71,7 +73,7 @@ def roofline(stats: dict, steps: int, fp32: bool):
     try:
         with open(TRAFFIC_FILE) as f:
             tr = json.load(f)
-        if tr.get("source_digest") == source_digest() and tr.get("kernel") == name:
+        if tr.get("kernel") == name and tr.get("source_digest") == source_digest(tr["source_files"]):
             out["traffic"] = tr["bytes_per_launch"]
     except (OSError, ValueError, KeyError):
         pass
