@@ -155,8 +155,7 @@ struct SvtBuffers {
     cplx<T>* Z;       // second slice buffer
     cplx<T>* V[2];    // right singular vectors, ping-pong for re-orthonormalisation
     cplx<T>* G;       // n x n Gram scratch
-    T* d;
-    int* kept;
+    double* sigma;    // h x n singular values (FP64)
     int* rank;
     int* rot;
     int* sweeps;
@@ -181,7 +180,7 @@ size_t svt_bytes(const Geometry& g, int nparts) {
     size_t b = 0;
     b += 2 * slice * sizeof(cplx<T>) + 512;
     b += 3 * vv * sizeof(cplx<T>) + 768;
-    b += (int64_t)g.h * g.n * (sizeof(T) + sizeof(int)) + 512;
+    b += (int64_t)g.h * g.n * sizeof(double) + 256;
     b += (int64_t)g.h * 5 * sizeof(int) + 768;
     b += (int64_t)(4 * g.h + 1) * sizeof(int) + 256;
     b += (int64_t)nparts * kNumPartials * sizeof(double) + 256;
@@ -198,8 +197,7 @@ SvtBuffers<T> carve_svt(Carver& c, const Geometry& g, int nparts) {
     s.V[0] = c.take<cplx<T>>(vv);
     s.V[1] = c.take<cplx<T>>(vv);
     s.G = c.take<cplx<T>>(vv);
-    s.d = c.take<T>((int64_t)g.h * g.n);
-    s.kept = c.take<int>((int64_t)g.h * g.n);
+    s.sigma = c.take<double>((int64_t)g.h * g.n);
     s.rank = c.take<int>(g.h);
     s.rot = c.take<int>(3 * g.h);
     s.sweeps = c.take<int>(g.h);
@@ -259,9 +257,9 @@ enum Kind : int {
     K_CTRL, K_GEMM, K_JAC_PERSIST, K_OTHER, K_COUNT
 };
 const char* kKindName[K_COUNT] = {"dft_forward", "jacobi_init", "jacobi_self", "jacobi_cross",
-                                  "svt_weights", "svt_rebuild", "dft_inverse", "admm_ctrl",
+                                  "svt_sigma", "svt_rebuild", "dft_inverse", "admm_ctrl",
                                   "warm_gemm", "jacobi_persistent", "other"};
-const bool kKindBytes[K_COUNT] = {true, true, false, false, true, true, true, true, false, false, true};
+const bool kKindBytes[K_COUNT] = {true, true, false, false, true, false, true, true, false, false, true};
 
 hipEvent_t take_event(tsvd_handle h) {
     if (!h->ev_pool.empty()) {
@@ -347,7 +345,7 @@ struct SweepStats {
 // slice rows and n V rows of both columns).
 template <typename T>
 SweepStats run_svt(tsvd_handle h, const Geometry& g, const SvtBuffers<T>& sb, int max_sweeps,
-                   WarmState* warm = nullptr) {
+                   WarmState* warm = nullptr, bool want_rank = false) {
     hipStream_t st = h->stream;
     const bool use_warm = warm && warm->enabled && warm->valid;
     const int64_t nn = (int64_t)g.n * g.n, mn = (int64_t)g.m * g.n;
@@ -357,30 +355,30 @@ SweepStats run_svt(tsvd_handle h, const Geometry& g, const SvtBuffers<T>& sb, in
     if (use_warm) {
         if (warm->reorth_every > 0 && warm->iter % warm->reorth_every == 0) {
             // V <- 1.5 V - 0.5 V (V^H V): one Newton-Schulz step towards unitary
-            GemmArgs<T> gg{};
+            ZGemmArgs<T> gg{};
             gg.A = sb.V[vc]; gg.B = sb.V[vc]; gg.C = sb.G;
             gg.M = gg.N = gg.K = g.n;
             gg.lda = gg.ldb = gg.ldc = gg.ldd = g.n;
             gg.sA = gg.sB = gg.sC = gg.sD = nn;
-            gg.alpha = (T)1; gg.beta = (T)0; gg.opA_h = 1; gg.batch = g.h;
-            prof_launch(h, K_GEMM, 8.0 * g.n * g.n * g.n * g.h, [&] { launch_cgemm(gg, st); });
+            gg.alpha = (T)1; gg.beta = (T)0; gg.opA = 1; gg.opB = 0; gg.batch = g.h;
+            prof_launch(h, K_GEMM, 8.0 * g.n * g.n * g.n * g.h, [&] { launch_zgemm(gg, st); });
             launch_check("gemm gram");
-            GemmArgs<T> gn = gg;
+            ZGemmArgs<T> gn = gg;
             gn.A = sb.V[vc]; gn.B = sb.G; gn.D = sb.V[vc]; gn.C = sb.V[1 - vc];
-            gn.alpha = (T)-0.5; gn.beta = (T)1.5; gn.opA_h = 0;
-            prof_launch(h, K_GEMM, 8.0 * g.n * g.n * g.n * g.h, [&] { launch_cgemm(gn, st); });
+            gn.alpha = (T)-0.5; gn.beta = (T)1.5; gn.opA = 0;
+            prof_launch(h, K_GEMM, 8.0 * g.n * g.n * g.n * g.h, [&] { launch_zgemm(gn, st); });
             launch_check("gemm newton-schulz");
             vc = 1 - vc;
             warm->vcur = vc;
         }
         // pre-rotate: work = A V_prev
-        GemmArgs<T> ga{};
+        ZGemmArgs<T> ga{};
         ga.A = sb.A; ga.B = sb.V[vc]; ga.C = sb.Z;
         ga.M = g.m; ga.N = g.n; ga.K = g.n;
         ga.lda = g.m; ga.ldb = g.n; ga.ldc = g.m; ga.ldd = g.m;
         ga.sA = mn; ga.sB = nn; ga.sC = mn; ga.sD = mn;
-        ga.alpha = (T)1; ga.beta = (T)0; ga.opA_h = 0; ga.batch = g.h;
-        prof_launch(h, K_GEMM, 8.0 * g.m * g.n * g.n * g.h, [&] { launch_cgemm(ga, st); });
+        ga.alpha = (T)1; ga.beta = (T)0; ga.opA = 0; ga.opB = 0; ga.batch = g.h;
+        prof_launch(h, K_GEMM, 8.0 * g.m * g.n * g.n * g.h, [&] { launch_zgemm(ga, st); });
         launch_check("gemm prerotate");
         work = sb.Z;
         out = sb.A;
@@ -501,37 +499,34 @@ SweepStats run_svt(tsvd_handle h, const Geometry& g, const SvtBuffers<T>& sb, in
         }
     }
     }
-    SvtArgs<T> sa{};
-    sa.W = work;
-    sa.V = sb.V[vc];
-    sa.Z = out;
-    sa.d = sb.d;
-    sa.kept = sb.kept;
-    sa.rank = sb.rank;
-    sa.ctrl = h->ctrl;
-    sa.m = g.m;
-    sa.n = g.n;
-    sa.h = g.h;
+    // sigma_j = ||w_j||, then Zhat = W diag((1 - tau/sigma)_+) V^H on the matrix cores
     const int64_t slice_bytes = (int64_t)g.h * g.m * g.n * sizeof(cplx<T>);
-    prof_launch(h, K_SVT_W, (double)slice_bytes, [&] { launch_svt_weights(sa, st); });
-    launch_check("svt_weights");
-    const int ir = prof_launch(h, K_SVT_REBUILD, 0.0, [&] { launch_svt_rebuild(sa, st); });
+    prof_launch(h, K_SVT_W, (double)slice_bytes + (double)g.h * g.n * sizeof(double),
+                [&] { launch_svt_sigma(work, g.m, g.n, g.h, sb.sigma, st); });
+    launch_check("svt_sigma");
+    ZGemmArgs<T> gr{};
+    gr.A = work; gr.B = sb.V[vc]; gr.C = out;
+    gr.M = g.m; gr.N = g.n; gr.K = g.n;
+    gr.lda = g.m; gr.ldb = g.n; gr.ldc = g.m; gr.ldd = g.m;
+    gr.sA = mn; gr.sB = nn; gr.sC = mn; gr.sD = mn;
+    gr.alpha = (T)1; gr.beta = (T)0; gr.opA = 0; gr.opB = 1; gr.batch = g.h;
+    gr.sigma = sb.sigma; gr.ssig = g.n; gr.ctrl = h->ctrl;
+    gr.bf16x3 = env_int("TSVD_REBUILD_BF16", 0);
+    prof_launch(h, K_SVT_REBUILD, 8.0 * g.m * g.n * g.n * g.h, [&] { launch_zgemm(gr, st); });
     launch_check("svt_rebuild");
+    if (want_rank) {
+        launch_multirank(sb.sigma, g.n, g.n, g.h, h->ctrl, sb.rank, st);
+        launch_check("multirank");
+    }
     if (h->prof_on) {
-        // rotation work and the rebuild's bytes need device counts
+        // rotation work needs the device counts
         unsigned long long rots[2] = {0, 0};
         hip_check(hipMemcpyAsync(rots, h->rot_counter, sizeof(rots), hipMemcpyDeviceToHost, st),
                   "hipMemcpyAsync rotations");
-        ensure_host_ints(h, g.h);
-        hip_check(hipMemcpyAsync(h->host_ints, sb.rank, sizeof(int) * g.h, hipMemcpyDeviceToHost, st),
-                  "hipMemcpyAsync rank");
         hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
         hip_check(hipMemsetAsync(h->rot_counter, 0, 2 * sizeof(unsigned long long), st),
                   "hipMemsetAsync rotations");
-        int64_t kept = 0;
-        for (int s = 0; s < g.h; ++s) kept += h->host_ints[s];
         const double rot_flops = 16.0 * (g.m + g.n);
-        if (ir >= 0) h->pending[ir].work = (double)slice_bytes + (double)kept * (g.m + g.n) * sizeof(cplx<T>);
         prof_harvest(h);
         h->agg[K_JAC_SELF].work += rot_flops * (double)rots[0];
         h->agg[done_persist ? K_JAC_PERSIST : K_JAC_CROSS].work += rot_flops * (double)rots[1];
@@ -680,7 +675,7 @@ void do_tsvt(tsvd_handle h, const void* X, tsvd_shape shape, tsvd_dtype dtype, d
         prof_launch(h, K_DFT_FWD, slice_bytes + (double)g.numel * sizeof(T),
                     [&] { launch_dft_forward(PRO_COPY, fa, h->stream); });
         launch_check("dft_forward");
-        const SweepStats ss = run_svt<T>(h, g, sb, 30);
+        const SweepStats ss = run_svt<T>(h, g, sb, 30, nullptr, multirank_host != nullptr);
         InvArgs<T> ia{};
         ia.in = static_cast<const cplx<T>*>(ss.out);
         ia.tw = h->tw;

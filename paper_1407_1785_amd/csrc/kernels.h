@@ -72,36 +72,33 @@ struct JacArgs {
     int reset_v;    // jacobi_init: 1 = start from V = I, 0 = keep V (warm start)
 };
 
+// C[s] = alpha * op(A[s]) * diag(d[s]) * op(B[s]) + beta * D[s] over `batch`
+// slices, column-major complex, on the matrix cores (zgemm.hip).
+// op = 0: as stored; op = 1: conjugate transpose (A stored K x M, B N x K).
+// With sigma set, d_k = (1 - tau / sigma_k)_+ with tau = ctrl->tau; else d = 1.
 template <typename T>
-struct SvtArgs {
-    const cplx<T>* W;   // h slices m x n (Jacobi output)
-    const cplx<T>* V;   // h slices n x n
-    cplx<T>* Z;         // h slices m x n (rebuild output)
-    T* d;               // h x n shrink factors (1 - tau/sigma)_+ of kept columns
-    int* kept;          // h x n kept column indices
-    int* rank;          // h kept counts (multi-rank)
-    const Ctrl* ctrl;   // tau
-    int m, n, h;
-};
-
-// C[s] = alpha * op(A[s]) * B[s] + beta * D[s] over `batch` slices,
-// column-major complex; op(A) = A^H when opA_h (A stored K x M).
-template <typename T>
-struct GemmArgs {
+struct ZGemmArgs {
     const cplx<T>* A;
     const cplx<T>* B;
     const cplx<T>* D;   // may be null (beta ignored)
-    cplx<T>* C;         // must not alias A or B
-    int M, N, K;
-    int lda, ldb, ldc, ldd;
-    int64_t sA, sB, sC, sD;
+    cplx<T>* C;         // must not alias A, B or D's other tiles
+    int64_t sA, sB, sD, sC;
+    int lda, ldb, ldd, ldc;
+    int M, N, K, batch;
+    int opA, opB;
     T alpha, beta;
-    int opA_h;
-    int batch;
+    const double* sigma;   // optional, K per slice, stride ssig
+    int64_t ssig;
+    const Ctrl* ctrl;
+    int bf16x3;            // float only: 1 = bf16 split products, 0 = FP32 products
 };
 
 template <typename T>
-void launch_cgemm(const GemmArgs<T>& g, hipStream_t st);
+void launch_zgemm(const ZGemmArgs<T>& g, hipStream_t st);
+void launch_multirank(const double* sigma, int64_t ssig, int K, int h, const Ctrl* ctrl, int* rank,
+                      hipStream_t st);
+template <typename T>
+void launch_svt_sigma(const cplx<T>* W, int m, int n, int h, double* sigma, hipStream_t st);
 
 template <typename T>
 void launch_dft_forward(int prologue, const FwdArgs<T>& a, hipStream_t st);
@@ -136,11 +133,6 @@ int jacobi_persistent_blocks(int n);
 bool jacobi_persistent_fits(int m, int n, int h, int elem_bytes, int cus, size_t lds_cap);
 template <typename T>
 hipError_t launch_jacobi_persistent(const JacArgs<T>& a, const PersistArgs& p, int cus, hipStream_t st);
-
-template <typename T>
-void launch_svt_weights(const SvtArgs<T>& a, hipStream_t st);
-template <typename T>
-void launch_svt_rebuild(const SvtArgs<T>& a, hipStream_t st);
 
 void launch_admm_ctrl(Ctrl* c, const double* partials, int nparts, int rpca, hipStream_t st);
 template <typename T>

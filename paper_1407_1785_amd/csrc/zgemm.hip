@@ -1,0 +1,377 @@
+// Batched complex GEMM on the matrix cores, one problem per Fourier slice,
+// column-major complex operands:
+//
+//     C[s] = alpha * op(A[s]) * diag(d[s]) * op(B[s]) + beta * D[s],
+//     op(X) = X or X^H,  d optional (else 1).
+//
+// Users:
+//   * the rebuild of the shrinkage lemma (Sec. 4.1): Zhat = W diag(d) V^H
+//     with d_k = (1 - tau / sigma_k)_+ computed from the singular values
+//     while W is staged, so no compaction pass is needed (dropped columns
+//     get d = 0 exactly);
+//   * the warm start of the Jacobi SVD: the pre-rotation A V_prev and the
+//     Newton-Schulz step V <- 1.5 V - 0.5 V (V^H V).
+//
+// Arithmetic:
+//   double: v_mfma_f64_16x16x4f64, FP64 products and accumulation;
+//   float:  v_mfma_f32_16x16x4f32, FP32 products and accumulation (exact
+//           FP32 arithmetic), or with bf16x3 set, every FP32 operand x is
+//           split into bfloat16 parts hi = bf16(x), lo = bf16(x - hi) and each
+//           real product uses the three bf16 products hi*hi + hi*lo + lo*hi
+//           (v_mfma_f32_16x16x32_bf16) with FP32 accumulation; the dropped
+//           lo*lo term and the split residual leave about 2^-16 relative
+//           error per product.
+// A complex product takes four real MFMA products (re*re - im*im,
+// re*im + im*re).
+//
+// Tiling: one 256-thread workgroup per 64 x 64 tile of C; wave w owns the
+// 32 x 32 quadrant (w & 1, w >> 1), i.e. 2 x 2 MFMA tiles of 16 x 16.  K is
+// staged through LDS in chunks (16 for FP64, 32 for the bf16 split), with
+// the real and imaginary parts in separate arrays.  The MFMA operands are
+// given as (op(B) fragment, op(A) fragment), so the accumulator holds C
+// transposed: lane l owns 4 columns at row l % 16 of a 16 x 16 tile, and the
+// 16 lanes of a row group store 16 consecutive rows of a column-major C in
+// one coalesced access.
+
+#include "kernels.h"
+
+namespace tsvd {
+
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+constexpr int TM = 64, TN = 64;
+
+// Element (r, k) of an R x K operand view of X, zero outside [0,R) x [0,K).
+//   kcontig == false: X stored R x K column-major, (r, k) at k * ld + r;
+//   kcontig == true:  X stored K x R column-major, (r, k) at r * ld + k.
+template <typename T>
+__device__ __forceinline__ cplx<T> view_elem(const cplx<T>* X, int ld, bool kcontig, bool conj, int r, int k,
+                                             int R, int K) {
+    cplx<T> v{(T)0, (T)0};
+    if (r < R && k < K) {
+        v = kcontig ? X[(int64_t)r * ld + k] : X[(int64_t)k * ld + r];
+        if (conj) v.im = -v.im;
+    }
+    return v;
+}
+
+__device__ __forceinline__ double shrink_factor(const double* sigma, int k, int K, double tau) {
+    if (k >= K) return 0.0;
+    const double sg = sigma[k];
+    return sg > tau ? 1.0 - tau / sg : 0.0;
+}
+
+// ---- K = 4 per MFMA (FP64, or exact FP32), stage [k][r] -----------------
+
+constexpr int KC4 = 16, PAD4 = 1;
+
+template <typename T>
+struct Stage4 {
+    T ar[KC4][TM + PAD4], ai[KC4][TM + PAD4];
+    T br[KC4][TN + PAD4], bi[KC4][TN + PAD4];
+};
+
+// Stage a 64 x KC4 block of an operand view into re/im[k][r].
+template <typename T>
+__device__ __forceinline__ void stage4(const cplx<T>* X, int ld, bool kcontig, bool conj, int r0, int k0, int R,
+                                       int K, T (*re)[TM + PAD4], T (*im)[TM + PAD4], const double* sigma,
+                                       double tau) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        int rr, kk;
+        if (kcontig) {
+            kk = t % KC4;
+            rr = t / KC4 + 16 * q;
+        } else {
+            rr = t % TM;
+            kk = t / TM + 4 * q;
+        }
+        cplx<T> v = view_elem(X, ld, kcontig, conj, r0 + rr, k0 + kk, R, K);
+        if (sigma) {
+            const T dk = (T)shrink_factor(sigma, k0 + kk, K, tau);
+            v.re *= dk;
+            v.im *= dk;
+        }
+        re[kk][rr] = v.re;
+        im[kk][rr] = v.im;
+    }
+}
+
+template <typename T>
+struct Mfma4;
+
+template <>
+struct Mfma4<double> {
+    typedef v4d acc_t;
+    static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    // register v of lane l holds (row l % 16, column 4 v + l / 16) of the
+    // transposed 16 x 16 tile
+    static __device__ __forceinline__ int col(int lane, int v) { return 4 * v + (lane >> 4); }
+};
+
+template <>
+struct Mfma4<float> {
+    typedef v4f acc_t;
+    static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    // register v of lane l holds (row l % 16, column 4 (l / 16) + v)
+    static __device__ __forceinline__ int col(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void zgemm_k4_kernel(ZGemmArgs<T> g) {
+    typedef Mfma4<T> M;
+    typedef typename M::acc_t acc_t;
+    __shared__ Stage4<T> sm;
+    const int s = blockIdx.z;
+    const int row0 = blockIdx.x * TM, col0 = blockIdx.y * TN;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
+    const cplx<T>* A = g.A + (int64_t)s * g.sA;
+    const cplx<T>* B = g.B + (int64_t)s * g.sB;
+    const double* sigma = g.sigma ? g.sigma + (int64_t)s * g.ssig : nullptr;
+    const double tau = sigma ? g.ctrl->tau : 0.0;
+
+    acc_t cr[2][2], ci[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) cr[a][b] = ci[a][b] = acc_t{(T)0, (T)0, (T)0, (T)0};
+
+    for (int k0 = 0; k0 < g.K; k0 += KC4) {
+        // op(A): rows M, op N -> stored M x K (r-contiguous); op H -> stored K x M, conj
+        stage4<T>(A, g.lda, g.opA != 0, g.opA != 0, row0, k0, g.M, g.K, sm.ar, sm.ai, sigma, tau);
+        // op(B)^T as an N x K view: op N -> B stored K x N (k-contiguous); op H -> stored N x K, conj
+        stage4<T>(B, g.ldb, g.opB == 0, g.opB != 0, col0, k0, g.N, g.K, sm.br, sm.bi, nullptr, 0.0);
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < KC4; kk += 4) {
+            const int kq = kk + (lane >> 4), c16 = lane & 15;
+            T a_r[2], a_i[2], b_r[2], b_i[2];
+#pragma unroll
+            for (int x = 0; x < 2; ++x) {
+                a_r[x] = sm.ar[kq][wr + 16 * x + c16];
+                a_i[x] = sm.ai[kq][wr + 16 * x + c16];
+                b_r[x] = sm.br[kq][wc + 16 * x + c16];
+                b_i[x] = sm.bi[kq][wc + 16 * x + c16];
+            }
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+#pragma unroll
+                for (int y = 0; y < 2; ++y) {
+                    cr[x][y] = M::mma(b_r[y], a_r[x], cr[x][y]);
+                    cr[x][y] = M::mma(-b_i[y], a_i[x], cr[x][y]);
+                    ci[x][y] = M::mma(b_r[y], a_i[x], ci[x][y]);
+                    ci[x][y] = M::mma(b_i[y], a_r[x], ci[x][y]);
+                }
+        }
+        __syncthreads();
+    }
+
+    cplx<T>* C = g.C + (int64_t)s * g.sC;
+    const cplx<T>* D = g.D ? g.D + (int64_t)s * g.sD : nullptr;
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+        const int row = row0 + wr + 16 * x + (lane & 15);
+        if (row >= g.M) continue;
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int col = col0 + wc + 16 * y + M::col(lane, v);
+                if (col >= g.N) continue;
+                T re = g.alpha * cr[x][y][v], im = g.alpha * ci[x][y][v];
+                if (D) {
+                    const cplx<T> d = D[(int64_t)col * g.ldd + row];
+                    re += g.beta * d.re;
+                    im += g.beta * d.im;
+                }
+                C[(int64_t)col * g.ldc + row] = cplx<T>{re, im};
+            }
+    }
+}
+
+// ---- FP32 form: bf16 split, K = 32 per MFMA, stage [r][k] ----------------
+
+constexpr int KC16 = 32, PAD16 = 8;
+
+struct alignas(16) Stage16 {
+    // [part][r][k], part: 0 re hi, 1 re lo, 2 im hi, 3 im lo
+    __bf16 a[4][TM][KC16 + PAD16];
+    __bf16 b[4][TN][KC16 + PAD16];
+};
+
+__device__ __forceinline__ void split_store(__bf16 (*dst)[TM][KC16 + PAD16], int rr, int kk, float re, float im) {
+    const __bf16 rh = (__bf16)re, ih = (__bf16)im;
+    dst[0][rr][kk] = rh;
+    dst[1][rr][kk] = (__bf16)(re - (float)rh);
+    dst[2][rr][kk] = ih;
+    dst[3][rr][kk] = (__bf16)(im - (float)ih);
+}
+
+__device__ __forceinline__ void stage16(const cplx<float>* X, int ld, bool kcontig, bool conj, int r0, int k0,
+                                        int R, int K, __bf16 (*dst)[TM][KC16 + PAD16], const double* sigma,
+                                        double tau) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        int rr, kk;
+        if (kcontig) {
+            kk = t % KC16;
+            rr = t / KC16 + 8 * q;
+        } else {
+            rr = t % TM;
+            kk = t / TM + 4 * q;
+        }
+        cplx<float> v = view_elem(X, ld, kcontig, conj, r0 + rr, k0 + kk, R, K);
+        if (sigma) {
+            const float dk = (float)shrink_factor(sigma, k0 + kk, K, tau);
+            v.re *= dk;
+            v.im *= dk;
+        }
+        split_store(dst, rr, kk, v.re, v.im);
+    }
+}
+
+__device__ __forceinline__ v8bf frag16(const __bf16 (*part)[KC16 + PAD16], int r, int k) {
+    return *reinterpret_cast<const v8bf*>(&part[r][k]);
+}
+
+__device__ __forceinline__ v8bf neg8(v8bf x) {
+    typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+    v4u u = __builtin_bit_cast(v4u, x);
+    u ^= 0x80008000u;
+    return __builtin_bit_cast(v8bf, u);
+}
+
+#define MFMA_BF16(acc, x, y) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16((x), (y), (acc), 0, 0, 0)
+
+__global__ __launch_bounds__(256) void zgemm_bf16x3_kernel(ZGemmArgs<float> g) {
+    __shared__ Stage16 sm;
+    const int s = blockIdx.z;
+    const int row0 = blockIdx.x * TM, col0 = blockIdx.y * TN;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
+    const cplx<float>* A = g.A + (int64_t)s * g.sA;
+    const cplx<float>* B = g.B + (int64_t)s * g.sB;
+    const double* sigma = g.sigma ? g.sigma + (int64_t)s * g.ssig : nullptr;
+    const double tau = sigma ? g.ctrl->tau : 0.0;
+
+    v4f cr[2][2], ci[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) cr[a][b] = ci[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+
+    for (int k0 = 0; k0 < g.K; k0 += KC16) {
+        stage16(A, g.lda, g.opA != 0, g.opA != 0, row0, k0, g.M, g.K, sm.a, sigma, tau);
+        stage16(B, g.ldb, g.opB == 0, g.opB != 0, col0, k0, g.N, g.K, sm.b, nullptr, 0.0);
+        __syncthreads();
+        const int kq = 8 * (lane >> 4), c16 = lane & 15;
+        v8bf arh[2], arl[2], aih[2], ail[2];
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
+            const int r = wr + 16 * x + c16;
+            arh[x] = frag16(sm.a[0], r, kq);
+            arl[x] = frag16(sm.a[1], r, kq);
+            aih[x] = frag16(sm.a[2], r, kq);
+            ail[x] = frag16(sm.a[3], r, kq);
+        }
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+            const int r = wc + 16 * y + c16;
+            const v8bf brh = frag16(sm.b[0], r, kq), brl = frag16(sm.b[1], r, kq);
+            const v8bf bih = frag16(sm.b[2], r, kq), bil = frag16(sm.b[3], r, kq);
+            const v8bf nbih = neg8(bih), nbil = neg8(bil);
+#pragma unroll
+            for (int x = 0; x < 2; ++x) {
+                // re: br*ar - bi*ai
+                MFMA_BF16(cr[x][y], brh, arh[x]);
+                MFMA_BF16(cr[x][y], brh, arl[x]);
+                MFMA_BF16(cr[x][y], brl, arh[x]);
+                MFMA_BF16(cr[x][y], nbih, aih[x]);
+                MFMA_BF16(cr[x][y], nbih, ail[x]);
+                MFMA_BF16(cr[x][y], nbil, aih[x]);
+                // im: br*ai + bi*ar
+                MFMA_BF16(ci[x][y], brh, aih[x]);
+                MFMA_BF16(ci[x][y], brh, ail[x]);
+                MFMA_BF16(ci[x][y], brl, aih[x]);
+                MFMA_BF16(ci[x][y], bih, arh[x]);
+                MFMA_BF16(ci[x][y], bih, arl[x]);
+                MFMA_BF16(ci[x][y], bil, arh[x]);
+            }
+        }
+        __syncthreads();
+    }
+
+    cplx<float>* C = g.C + (int64_t)s * g.sC;
+    const cplx<float>* D = g.D ? g.D + (int64_t)s * g.sD : nullptr;
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+        const int row = row0 + wr + 16 * x + (lane & 15);
+        if (row >= g.M) continue;
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int col = col0 + wc + 16 * y + Mfma4<float>::col(lane, v);
+                if (col >= g.N) continue;
+                float re = g.alpha * cr[x][y][v], im = g.alpha * ci[x][y][v];
+                if (D) {
+                    const cplx<float> d = D[(int64_t)col * g.ldd + row];
+                    re += g.beta * d.re;
+                    im += g.beta * d.im;
+                }
+                C[(int64_t)col * g.ldc + row] = cplx<float>{re, im};
+            }
+    }
+}
+
+// The multi-rank (Sec. 2.4): rank[s] = #{k < K : sigma_k > tau}, one
+// workgroup per slice.
+__global__ __launch_bounds__(256) void multirank_kernel(const double* sigma, int64_t ssig, int K, const Ctrl* ctrl,
+                                                        int* rank) {
+    __shared__ int cnt;
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    const double tau = ctrl->tau;
+    const double* sg = sigma + (int64_t)blockIdx.x * ssig;
+    int c = 0;
+    for (int k = threadIdx.x; k < K; k += blockDim.x) c += sg[k] > tau ? 1 : 0;
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+    if ((threadIdx.x & 63) == 0) atomicAdd(&cnt, c);
+    __syncthreads();
+    if (threadIdx.x == 0) rank[blockIdx.x] = cnt;
+}
+
+}  // namespace
+
+template <>
+void launch_zgemm<double>(const ZGemmArgs<double>& g, hipStream_t st) {
+    dim3 grid((g.M + TM - 1) / TM, (g.N + TN - 1) / TN, g.batch);
+    hipLaunchKernelGGL(zgemm_k4_kernel<double>, grid, dim3(256), 0, st, g);
+}
+
+template <>
+void launch_zgemm<float>(const ZGemmArgs<float>& g, hipStream_t st) {
+    dim3 grid((g.M + TM - 1) / TM, (g.N + TN - 1) / TN, g.batch);
+    if (g.bf16x3)
+        hipLaunchKernelGGL(zgemm_bf16x3_kernel, grid, dim3(256), 0, st, g);
+    else
+        hipLaunchKernelGGL(zgemm_k4_kernel<float>, grid, dim3(256), 0, st, g);
+}
+
+void launch_multirank(const double* sigma, int64_t ssig, int K, int h, const Ctrl* ctrl, int* rank,
+                      hipStream_t st) {
+    hipLaunchKernelGGL(multirank_kernel, dim3(h), dim3(256), 0, st, sigma, ssig, K, ctrl, rank);
+}
+
+}  // namespace tsvd
