@@ -31,7 +31,9 @@
  * Precision. TSVD_PREC_FP64 computes every step in FP64 on FP64 data
  *           (dtype TSVD_F64 only).
  *
- * A handle is not thread safe: calls on one handle must not overlap.
+ * A handle is not thread safe: calls on one handle must not overlap, except
+ * tsvd_submit / tsvd_poll / tsvd_serve_stats_read, which may be called from
+ * any thread while the handle's serving worker runs.
  */
 #ifndef TSVD_H
 #define TSVD_H
@@ -52,7 +54,8 @@ typedef enum {
     TSVD_E_NOMEM = -3,     /* workspace does not fit the handle's budget    */
     TSVD_E_HIP = -4,       /* a HIP runtime call failed                     */
     TSVD_E_NONFINITE = -5, /* NaN or Inf met in the input or an iterate      */
-    TSVD_E_UNSUPPORTED = -6 /* valid request this build does not serve       */
+    TSVD_E_UNSUPPORTED = -6, /* valid request this build does not serve      */
+    TSVD_E_BUSY = -7       /* tsvd_poll: the problem has not finished yet   */
 } tsvd_status;
 
 typedef enum { TSVD_F64 = 0, TSVD_F32 = 1 } tsvd_dtype;
@@ -162,8 +165,9 @@ tsvd_status trpca(tsvd_handle h, const void* X, tsvd_shape shape, tsvd_dtype dty
 /* Per-kernel timing of the work a handle runs while profiling is on: a HIP
  * event pair around every launch on the handle's stream.  `work` is the
  * kernel's algorithmic work under the cost model stated in its source file:
- * bytes moved for the DFT, shrink and elementwise kernels (work_is_bytes =
- * 1), floating-point operations for the Jacobi kernels (work_is_bytes = 0).
+ * bytes moved for the DFT, singular-value and elementwise kernels
+ * (work_is_bytes = 1), floating-point operations for the Jacobi kernels and
+ * the matrix-core GEMMs of the rebuild and the warm start (work_is_bytes = 0).
  * Profiling adds a synchronisation after every launch group; it is for
  * measurement runs, not production runs. */
 typedef struct {
@@ -183,6 +187,91 @@ tsvd_status tsvd_profile(tsvd_handle h, int enable);
  * their number into *count_host.  Families never launched are omitted. */
 tsvd_status tsvd_profile_read(tsvd_handle h, tsvd_kernel_stat* out_host, int capacity,
                               int* count_host);
+
+/* ------------------------------------------------------------------------
+ * Batched and served solves
+ * ------------------------------------------------------------------------
+ * Many completion (Sec. 4) or tensor-RPCA (Sec. 5) problems of uneven shapes
+ * run together on one device: every phase of an ADMM iteration (forward
+ * DFT, warm-start GEMMs, Jacobi SVD, singular values, rebuild, inverse DFT,
+ * control) is one launch over all running problems, driven by per-problem
+ * argument tables; iterations are replayed from a captured HIP graph; the
+ * Jacobi block width of every shape is picked by timing the candidates on
+ * the device the first time the shape is seen.  Each problem computes
+ * exactly what tsvd_complete / trpca compute for it (same kernels, same
+ * order of operations; the Jacobi block width may differ, which changes
+ * results only by rounding).
+ *
+ * Device memory: the state of a running problem (iterates, Fourier slices,
+ * V, Gram scratch, residual partials) lives in one arena per handle, sized
+ * by the handle's hbm_budget_bytes (0: 90% of the device memory free when
+ * the arena is first needed).  A problem is admitted only while its state
+ * fits in the free part of the arena; the others wait in arrival order. */
+
+typedef enum { TSVD_KIND_COMPLETE = 0, TSVD_KIND_TRPCA = 1 } tsvd_kind;
+
+/* One problem: the arguments of tsvd_complete or trpca in one record.
+ * All tensor pointers are device pointers owned by the caller; inputs are
+ * read and outputs written while the problem runs (for tsvd_submit: until
+ * tsvd_poll has reported it finished). */
+typedef struct {
+    int32_t kind;          /* tsvd_kind                                         */
+    int32_t dtype;         /* tsvd_dtype                                        */
+    int32_t precision;     /* tsvd_precision, paired with dtype as for tsvt     */
+    int32_t shrink;        /* RPCA: tsvd_shrink                                 */
+    tsvd_shape shape;
+    const void* x;         /* completion: X_obs; RPCA: the data M               */
+    const uint8_t* mask;   /* completion: observation mask; RPCA: unused        */
+    double penalty;        /* initial rho (completion) or mu (RPCA), > 0        */
+    double lambda;         /* RPCA weight, > 0                                  */
+    double tol;            /* >= 0; 0 runs opts.max_iter iterations             */
+    tsvd_admm_opts opts;   /* growth, rho_max, max_iter, max_sweeps; its
+                              precision field is ignored                        */
+    void* out;             /* completion: X_out; RPCA: L_out                    */
+    void* out_s;           /* RPCA: S_out                                       */
+} tsvd_problem;
+
+/* Solve `count` problems together and return when all have stopped.
+ * infos_host: NULL or `count` host tsvd_info records (seconds = time from
+ * the call to the problem's completion).  status_host: NULL or `count` host
+ * int32 per-problem statuses (TSVD_OK, TSVD_E_NONFINITE, ...).  Problems of
+ * FP32 and FP64 data may be mixed; each dtype runs as its own batch.
+ * Errors: TSVD_E_INVALID / TSVD_E_SHAPE / TSVD_E_UNSUPPORTED for a bad record
+ * (nothing runs), TSVD_E_NOMEM if one problem alone does not fit the arena,
+ * TSVD_E_HIP; a problem that meets a non-finite value stops with
+ * TSVD_E_NONFINITE in status_host and does not fail the call. */
+tsvd_status tsvd_batch_run(tsvd_handle h, const tsvd_problem* probs, int32_t count, tsvd_info* infos_host,
+                           int32_t* status_host);
+
+/* Serving: queue one problem and return at once with its ticket.  A
+ * worker thread of the handle admits queued problems as arena space frees
+ * up (continuous batching: problems join and leave the running batch
+ * between iterations), runs them on a stream of its own, and writes each
+ * problem's outputs when it stops.  The record is copied; the tensors it
+ * points to must stay valid until tsvd_poll reports the ticket finished.
+ * Errors: as tsvd_batch_run for a bad record; TSVD_E_NOMEM if the problem
+ * can never fit the arena. */
+tsvd_status tsvd_submit(tsvd_handle h, const tsvd_problem* prob, uint64_t* ticket_host);
+
+/* TSVD_E_BUSY while the ticket is queued or running; otherwise the
+ * problem's final status (TSVD_OK, TSVD_E_NONFINITE, ...), with *info_host
+ * filled (seconds = time from submission to completion) when not NULL.  A
+ * finished ticket can be polled again; an unknown ticket is TSVD_E_INVALID. */
+tsvd_status tsvd_poll(tsvd_handle h, uint64_t ticket, tsvd_info* info_host);
+
+/* Serving counters (host struct). */
+typedef struct {
+    int64_t submitted;     /* tickets issued                                   */
+    int64_t finished;      /* tickets finished                                 */
+    int64_t queued;        /* waiting for arena space                          */
+    int64_t running;       /* in the running batch                             */
+    int64_t iterations;    /* batched ADMM iterations run by the worker        */
+    int64_t arena_bytes;   /* arena size                                       */
+    int64_t arena_used;    /* bytes held by running problems                   */
+    int64_t peak_running;  /* largest running batch                            */
+} tsvd_serve_stats;
+
+tsvd_status tsvd_serve_stats_read(tsvd_handle h, tsvd_serve_stats* out_host);
 
 /* Static string for a status code. */
 const char* tsvd_status_string(tsvd_status s);

@@ -8,6 +8,11 @@ arguments follow the C ABI in ``include/tsvd.h``:
     tsvt(X, tau)                          -> (Z, multirank)
     tsvd_complete(X_obs, mask, rho, tol)  -> (X, info)
     trpca(X, lam, mu, tol)                -> (L, S, info)
+    batch_run([problem, ...])             -> [(status, info), ...]
+    submit(problem) -> ticket;  poll(ticket) -> None | (status, info)
+
+Problems for the batched and served forms are built with
+``complete_problem`` / ``trpca_problem``, which allocate their outputs.
 
 There is no CPU fallback: if the library is missing, importing the module
 still works, but every call raises ``LibraryNotBuilt``.
@@ -22,6 +27,7 @@ import threading
 __all__ = [
     "LibraryNotBuilt", "TsvdError", "Info", "library_path", "load_library", "tsvt",
     "tsvd_complete", "trpca", "Handle", "PREC_FP64", "PREC_FP32", "SHRINK_L1", "SHRINK_L112",
+    "Problem", "complete_problem", "trpca_problem", "batch_run", "submit", "poll", "serve_stats",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -31,7 +37,9 @@ DTYPE_F64, DTYPE_F32 = 0, 1
 SHRINK_L1, SHRINK_L112 = 0, 1
 
 STATUS = {0: "TSVD_OK", -1: "TSVD_E_INVALID", -2: "TSVD_E_SHAPE", -3: "TSVD_E_NOMEM",
-          -4: "TSVD_E_HIP", -5: "TSVD_E_NONFINITE", -6: "TSVD_E_UNSUPPORTED"}
+          -4: "TSVD_E_HIP", -5: "TSVD_E_NONFINITE", -6: "TSVD_E_UNSUPPORTED", -7: "TSVD_E_BUSY"}
+E_BUSY = -7
+KIND_COMPLETE, KIND_TRPCA = 0, 1
 
 
 class LibraryNotBuilt(RuntimeError):
@@ -70,6 +78,24 @@ class KernelStat(ctypes.Structure):
                 ("work_is_bytes", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class ProblemRecord(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("dtype", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("shrink", ctypes.c_int32), ("shape", Shape), ("x", ctypes.c_void_p),
+                ("mask", ctypes.c_void_p), ("penalty", ctypes.c_double), ("lam", ctypes.c_double),
+                ("tol", ctypes.c_double), ("opts", AdmmOpts), ("out", ctypes.c_void_p),
+                ("out_s", ctypes.c_void_p)]
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("finished", ctypes.c_int64), ("queued", ctypes.c_int64),
+                ("running", ctypes.c_int64), ("iterations", ctypes.c_int64),
+                ("arena_bytes", ctypes.c_int64), ("arena_used", ctypes.c_int64),
+                ("peak_running", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 def library_path() -> str:
     return os.environ.get("TSVD_LIBRARY", os.path.join(HERE, "libtsvd.so"))
 
@@ -95,6 +121,12 @@ _SIGNATURES = {
     "tsvd_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "tsvd_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(KernelStat), ctypes.c_int,
                                          ctypes.POINTER(ctypes.c_int)]),
+    "tsvd_batch_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ProblemRecord), ctypes.c_int32,
+                                      ctypes.POINTER(Info), ctypes.POINTER(ctypes.c_int32)]),
+    "tsvd_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ProblemRecord),
+                                   ctypes.POINTER(ctypes.c_uint64)]),
+    "tsvd_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(Info)]),
+    "tsvd_serve_stats_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ServeStats)]),
     "tsvd_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "tsvd_last_error": (ctypes.c_char_p, []),
 }
@@ -134,6 +166,7 @@ class Handle:
         _check(lib.tsvd_create(int(device), int(hbm_budget_bytes), ctypes.byref(h)))
         self._h = h
         self.device = int(device)
+        self._served = {}   # ticket -> Problem, kept alive until finished
 
     @property
     def ptr(self):
@@ -158,6 +191,7 @@ class Handle:
         return out
 
     def close(self):
+        self._served = {}
         if self._h:
             load_library().tsvd_destroy(self._h)
             self._h = ctypes.c_void_p()
@@ -302,3 +336,118 @@ def trpca(X, lam: float, mu: float = 1e-3, tol: float = 1e-7, shrink: int = SHRI
                                 ctypes.byref(opts), ctypes.c_void_p(L.data_ptr()),
                                 ctypes.c_void_p(S.data_ptr()), ctypes.byref(info)))
     return L, S, info
+
+
+class Problem:
+    """One completion (Sec. 4) or tensor-RPCA (Sec. 5) problem for the
+    batched and served forms; owns its output tensors (``out`` = X or L,
+    ``out_s`` = S) and keeps its inputs alive."""
+
+    def __init__(self, kind, x, mask=None, penalty=1e-2, lam=0.0, tol=1e-8, shrink=SHRINK_L1,
+                 growth=0.0, rho_max=0.0, max_iter=0, precision=None, max_sweeps=0):
+        import torch
+
+        self.kind = int(kind)
+        self.x = _prepare(x, "x")
+        self.mask = None
+        if self.kind == KIND_COMPLETE:
+            m = _prepare(mask, "mask")
+            if m.dtype != torch.uint8:
+                m = m.to(torch.uint8)
+            if m.shape != self.x.shape or m.device != self.x.device:
+                raise ValueError("mask must match x in shape and device")
+            self.mask = m
+        self.out = torch.empty_like(self.x)
+        self.out_s = torch.empty_like(self.x) if self.kind == KIND_TRPCA else None
+        dt = _dtype_code(self.x)
+        if precision is None:
+            precision = PREC_FP32 if dt == DTYPE_F32 else PREC_FP64
+        rec = ProblemRecord()
+        rec.kind = self.kind
+        rec.dtype = dt
+        rec.precision = int(precision)
+        rec.shrink = int(shrink)
+        rec.shape = _shape(self.x)
+        rec.x = self.x.data_ptr()
+        rec.mask = self.mask.data_ptr() if self.mask is not None else None
+        rec.penalty = float(penalty)
+        rec.lam = float(lam)
+        rec.tol = float(tol)
+        rec.opts = _opts(growth, rho_max, max_iter, precision, max_sweeps)
+        rec.out = self.out.data_ptr()
+        rec.out_s = self.out_s.data_ptr() if self.out_s is not None else None
+        self.record = rec
+
+    @property
+    def device(self):
+        return self.x.device
+
+
+def complete_problem(X_obs, mask, rho=1e-2, tol=1e-8, growth=1.1, rho_max=1e3, max_iter=300,
+                     precision=None, max_sweeps=0) -> Problem:
+    return Problem(KIND_COMPLETE, X_obs, mask, rho, 0.0, tol, SHRINK_L1, growth, rho_max, max_iter,
+                   precision, max_sweeps)
+
+
+def trpca_problem(X, lam, mu=1e-3, tol=1e-7, shrink=SHRINK_L1, growth=1.2, mu_max=1e10, max_iter=500,
+                  precision=None, max_sweeps=0) -> Problem:
+    return Problem(KIND_TRPCA, X, None, mu, lam, tol, shrink, growth, mu_max, max_iter, precision,
+                   max_sweeps)
+
+
+def _sync_inputs(problems):
+    import torch
+
+    for dev in {p.device for p in problems}:
+        torch.cuda.current_stream(dev).synchronize()
+
+
+def batch_run(problems, handle: Handle | None = None):
+    """Solve the problems together (include/tsvd.h, ``tsvd_batch_run``).
+    Returns [(status, Info)] in order; outputs are in each problem's
+    ``out`` / ``out_s``."""
+    problems = list(problems)
+    if not problems:
+        return []
+    handle = handle or _handle_for(problems[0].x)
+    _sync_inputs(problems)
+    n = len(problems)
+    recs = (ProblemRecord * n)(*[p.record for p in problems])
+    infos = (Info * n)()
+    stats = (ctypes.c_int32 * n)()
+    _check(load_library().tsvd_batch_run(handle.ptr, recs, n, infos, stats))
+    return [(int(stats[i]), infos[i]) for i in range(n)]
+
+
+def submit(problem: Problem, handle: Handle | None = None) -> int:
+    """Queue a problem on the handle's serving worker (``tsvd_submit``)."""
+    handle = handle or _handle_for(problem.x)
+    _sync_inputs([problem])
+    ticket = ctypes.c_uint64()
+    _check(load_library().tsvd_submit(handle.ptr, ctypes.byref(problem.record), ctypes.byref(ticket)))
+    handle._served[ticket.value] = problem
+    return ticket.value
+
+
+def poll(ticket: int, handle: Handle | None = None, device: int = 0):
+    """None while the ticket runs; else (status, Info) (``tsvd_poll``)."""
+    handle = handle or _handles.get(device)
+    if handle is None:
+        raise TsvdError(-1, "no handle")
+    info = Info()
+    st = load_library().tsvd_poll(handle.ptr, ctypes.c_uint64(int(ticket)), ctypes.byref(info))
+    if st == E_BUSY:
+        return None
+    if st not in (0, -5):
+        _check(st)
+    handle._served.pop(int(ticket), None)
+    return st, info
+
+
+def serve_stats(handle: Handle | None = None, device: int = 0) -> dict:
+    handle = handle or _handles.get(device)
+    if handle is None:
+        return ServeStats().as_dict()
+    out = ServeStats()
+    _check(load_library().tsvd_serve_stats_read(handle.ptr, ctypes.byref(out)))
+    return out.as_dict()

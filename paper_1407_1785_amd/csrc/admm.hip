@@ -7,7 +7,8 @@
 //   max(sqrt(sum p1), sqrt(sum p2)) (RPCA);
 //   stop when max(primal, change) <= tol * ||data||_F;
 //   otherwise rho' = min(growth * rho, rho_max) and the stored dual is read
-//   as (rho / rho') times its value from then on (scaled-dual ADMM with a
+//   as (rho / rho') times its value from then on; a problem-table run also
+//   stops at its iteration cap (done = 2) (scaled-dual ADMM with a
 //   penalty schedule; the completion recursion of Sec. 4 and the RPCA
 //   recursion of Sec. 5 keep rho fixed, the growth is the workloads').
 // The partial sums are reduced in a fixed order, so a run is deterministic.
@@ -34,8 +35,7 @@ __device__ double block_sum_fixed(const double* p, int nparts, int stride, int c
 
 }  // namespace
 
-__global__ __launch_bounds__(kBlock) void admm_ctrl_kernel(Ctrl* c, const double* partials, int nparts,
-                                                          int rpca) {
+__device__ void admm_ctrl_body(Ctrl* c, const double* partials, int nparts, int rpca) {
     __shared__ double scratch[kBlock];
     const double p0 = block_sum_fixed(partials, nparts, kNumPartials, 0, scratch);
     const double p1 = block_sum_fixed(partials, nparts, kNumPartials, 1, scratch);
@@ -46,6 +46,9 @@ __global__ __launch_bounds__(kBlock) void admm_ctrl_kernel(Ctrl* c, const double
     c->primal = primal;
     c->change = change;
     c->iter += 1;
+    c->sweeps_total += c->sweep_max;
+    c->sweeps_last = c->sweep_max;
+    c->sweep_max = 0;
     c->rho_used = c->rho;
     c->dscale_used = c->dscale;
     if (!isfinite(primal) || !isfinite(change)) {
@@ -64,6 +67,20 @@ __global__ __launch_bounds__(kBlock) void admm_ctrl_kernel(Ctrl* c, const double
     c->rho = next;
     c->tau = 1.0 / next;
     c->shrink = c->lambda / next;
+    // iteration cap of a problem-table run (0: the host counts iterations)
+    if (c->max_iter > 0 && c->iter >= c->max_iter) c->done = 2;
+}
+
+__global__ __launch_bounds__(kBlock) void admm_ctrl_kernel(Ctrl* c, const double* partials, int nparts,
+                                                          int rpca) {
+    admm_ctrl_body(c, partials, nparts, rpca);
+}
+
+// One workgroup per problem; a problem that has stopped is left alone.
+__global__ __launch_bounds__(kBlock) void admm_ctrl_batched(const CtrlArgs* tab) {
+    const CtrlArgs& a = tab[blockIdx.x];
+    if (a.c->done) return;
+    admm_ctrl_body(a.c, a.partials, a.nparts, a.rpca);
 }
 
 template <typename T>
@@ -112,9 +129,44 @@ __global__ __launch_bounds__(kBlock) void fill_kernel(T* p, T v, int64_t n) {
         p[i] = v;
 }
 
+// Deterministic values in [-1, 1) from a 32-bit integer hash of the index
+// (test and tuning inputs; no statistical quality is needed).
+__device__ __forceinline__ float hash_unit(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x7feb352dU;
+    x ^= x >> 15;
+    x *= 0x846ca68bU;
+    x ^= x >> 16;
+    return (float)(x >> 8) * (2.0f / 16777216.0f) - 1.0f;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void fill_hash_kernel(cplx<T>* p, int64_t n, uint32_t seed) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t k = (uint32_t)i * 2u + seed * 0x9e3779b9U;
+        p[i] = cplx<T>{(T)hash_unit(k), (T)hash_unit(k + 1u)};
+    }
+}
+
+// h slices of the n x n identity
+template <typename T>
+__global__ __launch_bounds__(kBlock) void set_identity_kernel(cplx<T>* v, int n, int64_t total) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t e = i % ((int64_t)n * n);
+        const int64_t col = e / n, row = e - col * n;
+        v[i] = cplx<T>{row == col ? (T)1 : (T)0, (T)0};
+    }
+}
+
 static int grid_for(int64_t n) {
     const int64_t g = (n + kBlock - 1) / kBlock;
     return (int)(g < 2048 ? (g < 1 ? 1 : g) : 2048);
+}
+
+void launch_admm_ctrl_batched(const CtrlArgs* tab, int nprob, hipStream_t st) {
+    hipLaunchKernelGGL(admm_ctrl_batched, dim3(nprob), dim3(kBlock), 0, st, tab);
 }
 
 void launch_admm_ctrl(Ctrl* c, const double* partials, int nparts, int rpca, hipStream_t st) {
@@ -143,6 +195,21 @@ void launch_fill(T* p, T v, int64_t n, hipStream_t st) {
     hipLaunchKernelGGL((fill_kernel<T>), dim3(grid_for(n)), dim3(kBlock), 0, st, p, v, n);
 }
 
+template <typename T>
+void launch_fill_hash(cplx<T>* p, int64_t n, uint32_t seed, hipStream_t st) {
+    hipLaunchKernelGGL((fill_hash_kernel<T>), dim3(grid_for(n)), dim3(kBlock), 0, st, p, n, seed);
+}
+
+template <typename T>
+void launch_set_identity(cplx<T>* v, int n, int h, hipStream_t st) {
+    const int64_t total = (int64_t)h * n * n;
+    hipLaunchKernelGGL((set_identity_kernel<T>), dim3(grid_for(total)), dim3(kBlock), 0, st, v, n, total);
+}
+
+template void launch_fill_hash<double>(cplx<double>*, int64_t, uint32_t, hipStream_t);
+template void launch_fill_hash<float>(cplx<float>*, int64_t, uint32_t, hipStream_t);
+template void launch_set_identity<double>(cplx<double>*, int, int, hipStream_t);
+template void launch_set_identity<float>(cplx<float>*, int, int, hipStream_t);
 template void launch_sumsq<double>(const double*, const uint8_t*, int64_t, double*, int, hipStream_t);
 template void launch_complete_output<double>(const double*, const uint8_t*, const double*,
                                              const double*, const Ctrl*, double*, int64_t,

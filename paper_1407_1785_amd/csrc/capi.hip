@@ -19,122 +19,12 @@
 #include <string>
 #include <vector>
 
-#include "../../include/tsvd.h"
-#include "kernels.h"
+
+#include "host.h"
 
 using namespace tsvd;
 
 namespace {
-
-thread_local std::string g_last_error;
-
-struct Failure {
-    tsvd_status status;
-    std::string msg;
-};
-
-[[noreturn]] void fail(tsvd_status s, const std::string& msg) { throw Failure{s, msg}; }
-
-void hip_check(hipError_t e, const char* what) {
-    if (e != hipSuccess) fail(TSVD_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
-}
-
-void launch_check(const char* what) { hip_check(hipGetLastError(), what); }
-
-int env_int(const char* name, int dflt) {
-    const char* v = std::getenv(name);
-    return v && *v ? std::atoi(v) : dflt;
-}
-
-double env_double(const char* name, double dflt) {
-    const char* v = std::getenv(name);
-    return v && *v ? std::atof(v) : dflt;
-}
-
-// Largest supported sizes (LDS staging of the DFT tiles and Jacobi blocks).
-constexpr int kMaxTube = 512;
-constexpr int kMaxSlices = 300;
-
-}  // namespace
-
-struct tsvd_handle_s {
-    int device = 0;
-    size_t budget = 0;
-    hipStream_t stream = nullptr;
-    // workspace arena: one allocation, carved per call
-    void* ws = nullptr;
-    size_t ws_bytes = 0;
-    // small device objects
-    Ctrl* ctrl = nullptr;
-    int* flag = nullptr;            // non-finite flag
-    cplx<double>* tw = nullptr;     // twiddles of the current tube length
-    int tw_len = 0;
-    // pinned host staging
-    int* host_ints = nullptr;
-    int host_ints_len = 0;
-    Ctrl* host_ctrl = nullptr;
-    // profiling (tsvd_profile)
-    struct Pending {
-        int kind;
-        hipEvent_t a, b;
-        double work;
-    };
-    struct Agg {
-        int64_t launches = 0;
-        double ms = 0.0, work = 0.0;
-    };
-    bool prof_on = false;
-    std::vector<hipEvent_t> ev_pool;
-    std::vector<Pending> pending;
-    std::vector<Agg> agg;
-    unsigned long long* rot_counter = nullptr;   // [0] self, [1] cross
-    int cus = 0;
-    size_t lds_cap = 0;
-};
-
-namespace {
-
-struct Device {
-    explicit Device(int d) {
-        hip_check(hipGetDevice(&prev), "hipGetDevice");
-        if (prev != d) hip_check(hipSetDevice(d), "hipSetDevice");
-        target = d;
-    }
-    ~Device() {
-        if (prev != target) (void)hipSetDevice(prev);
-    }
-    int prev = 0, target = 0;
-};
-
-Geometry make_geometry(const tsvd_shape& s) {
-    if (s.ndim != 3 && s.ndim != 4) fail(TSVD_E_SHAPE, "ndim must be 3 or 4");
-    for (int k = 0; k < s.ndim; ++k)
-        if (s.n[k] < 1) fail(TSVD_E_SHAPE, "every dimension must be >= 1");
-    Geometry g{};
-    g.n1 = s.n[0];
-    g.n2 = s.n[1];
-    if (s.ndim == 3) {
-        g.P = 1;
-        g.Q = (int)s.n[2];
-        if (s.n[2] > kMaxTube) fail(TSVD_E_SHAPE, "tube length above the supported maximum");
-    } else {
-        if (s.n[2] * s.n[3] > kMaxTube) fail(TSVD_E_SHAPE, "tube length above the supported maximum");
-        g.P = (int)s.n[2];
-        g.Q = (int)s.n[3];
-    }
-    g.L = g.P * g.Q;
-    g.Qh = g.Q / 2 + 1;
-    g.h = g.P * g.Qh;
-    if (g.h > kMaxSlices) fail(TSVD_E_SHAPE, "too many Fourier slices");
-    g.trans = g.n1 < g.n2;
-    const int64_t m = std::max(g.n1, g.n2), n = std::min(g.n1, g.n2);
-    if (m > 4096) fail(TSVD_E_SHAPE, "matrix mode above the supported maximum");
-    g.m = (int)m;
-    g.n = (int)n;
-    g.ntubes = g.n1 * g.n2;
-    g.numel = g.ntubes * g.L;
-    return g;
-}
 
 // Bump allocator over the handle's workspace.
 struct Carver {
@@ -228,23 +118,12 @@ void ensure_host_ints(tsvd_handle h, int count) {
     h->host_ints_len = count;
 }
 
-// FP64 twiddles exp(-2 pi i u / L); the quarter points are exact.
 void ensure_twiddles(tsvd_handle h, int L) {
     if (h->tw_len == L) return;
     if (h->tw) hip_check(hipFree(h->tw), "hipFree");
     h->tw = nullptr;
     h->tw_len = 0;
-    std::vector<cplx<double>> tw(L);
-    for (int u = 0; u < L; ++u) {
-        if ((4 * u) % L == 0) {
-            const int q = (4 * u) / L;
-            const double c[4] = {1.0, 0.0, -1.0, 0.0}, s[4] = {0.0, -1.0, 0.0, 1.0};
-            tw[u] = cplx<double>{c[q], s[q]};
-        } else {
-            const double a = -2.0 * M_PI * (double)u / (double)L;
-            tw[u] = cplx<double>{std::cos(a), std::sin(a)};
-        }
-    }
+    const std::vector<cplx<double>> tw = twiddles_host(L);
     hip_check(hipMalloc(&h->tw, sizeof(cplx<double>) * L), "hipMalloc twiddles");
     hip_check(hipMemcpy(h->tw, tw.data(), sizeof(cplx<double>) * L, hipMemcpyHostToDevice),
               "hipMemcpy twiddles");
@@ -583,57 +462,6 @@ bool read_flag(tsvd_handle h) {
               "hipMemcpyAsync flag");
     hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
     return h->host_ints[0] != 0;
-}
-
-template <typename F>
-tsvd_status guarded(F&& f) {
-    try {
-        f();
-        g_last_error.clear();
-        return TSVD_OK;
-    } catch (const Failure& e) {
-        g_last_error = e.msg;
-        return e.status;
-    } catch (const std::bad_alloc&) {
-        g_last_error = "host allocation failed";
-        return TSVD_E_NOMEM;
-    } catch (...) {
-        g_last_error = "unexpected failure";
-        return TSVD_E_HIP;
-    }
-}
-
-void check_handle(tsvd_handle h) {
-    if (!h) fail(TSVD_E_INVALID, "null handle");
-}
-
-// true for the FP32 form (FP32 data), false for the plain FP64 path
-bool check_precision(int dtype, int precision) {
-    if (dtype != TSVD_F64 && dtype != TSVD_F32) fail(TSVD_E_INVALID, "unknown dtype");
-    if (precision != TSVD_PREC_FP64 && precision != TSVD_PREC_FP32)
-        fail(TSVD_E_INVALID, "unknown precision");
-    if (dtype == TSVD_F64 && precision == TSVD_PREC_FP64) return false;
-    if (dtype == TSVD_F32 && precision == TSVD_PREC_FP32) return true;
-    fail(TSVD_E_UNSUPPORTED, "FP64 data needs TSVD_PREC_FP64 and FP32 data TSVD_PREC_FP32");
-}
-
-struct AdmmSettings {
-    double growth, rho_max;
-    int max_iter, precision, max_sweeps;
-};
-
-AdmmSettings settings(const tsvd_admm_opts* o, double growth, double rho_max, int max_iter) {
-    AdmmSettings s{growth, rho_max, max_iter, TSVD_PREC_FP64, 30};
-    if (o) {
-        if (o->reserved != 0) fail(TSVD_E_INVALID, "opts.reserved must be 0");
-        if (o->growth > 0) s.growth = o->growth;
-        if (o->rho_max > 0) s.rho_max = o->rho_max;
-        if (o->max_iter > 0) s.max_iter = o->max_iter;
-        s.precision = o->precision;
-        if (o->max_sweeps > 0) s.max_sweeps = o->max_sweeps;
-    }
-    if (!(s.growth >= 1.0) || !std::isfinite(s.growth)) fail(TSVD_E_INVALID, "growth must be >= 1");
-    return s;
 }
 
 int elementwise_parts() { return 1024; }
@@ -986,6 +814,7 @@ tsvd_status tsvd_create(int device, size_t hbm_budget_bytes, tsvd_handle* out) {
 tsvd_status tsvd_destroy(tsvd_handle h) {
     if (!h) return TSVD_OK;
     return guarded([&] {
+        serve_shutdown(h);
         Device dev(h->device);
         if (h->stream) (void)hipStreamSynchronize(h->stream);
         else (void)hipDeviceSynchronize();
@@ -1088,6 +917,25 @@ tsvd_status tsvd_profile_read(tsvd_handle h, tsvd_kernel_stat* out_host, int cap
     });
 }
 
+tsvd_status tsvd_batch_run(tsvd_handle h, const tsvd_problem* probs, int32_t count, tsvd_info* infos_host,
+                           int32_t* status_host) {
+    return guarded([&] { batch_run(h, probs, count, infos_host, status_host); });
+}
+
+tsvd_status tsvd_submit(tsvd_handle h, const tsvd_problem* prob, uint64_t* ticket_host) {
+    return guarded([&] { serve_submit(h, prob, ticket_host); });
+}
+
+tsvd_status tsvd_poll(tsvd_handle h, uint64_t ticket, tsvd_info* info_host) {
+    tsvd_status st = TSVD_OK;
+    const tsvd_status g = guarded([&] { st = serve_poll(h, ticket, info_host); });
+    return g != TSVD_OK ? g : st;
+}
+
+tsvd_status tsvd_serve_stats_read(tsvd_handle h, tsvd_serve_stats* out_host) {
+    return guarded([&] { serve_stats(h, out_host); });
+}
+
 const char* tsvd_status_string(tsvd_status s) {
     switch (s) {
         case TSVD_OK: return "ok";
@@ -1097,6 +945,7 @@ const char* tsvd_status_string(tsvd_status s) {
         case TSVD_E_HIP: return "HIP runtime error";
         case TSVD_E_NONFINITE: return "non-finite value";
         case TSVD_E_UNSUPPORTED: return "unsupported request";
+        case TSVD_E_BUSY: return "not finished";
     }
     return "unknown status";
 }

@@ -51,8 +51,12 @@ struct Ctrl {
     double rho_used;   // penalty of the last finished iteration
     double dscale_used;  // dual scale of the last finished iteration
     int32_t iter;      // finished iterations
-    int32_t done;      // 1 once the stop test passed
+    int32_t done;      // 1 once the stop test passed, 2 at the iteration cap
     int32_t nonfinite; // 1 if a residual was not finite
+    int32_t max_iter;  // iteration cap of a problem-table run (0: none)
+    int32_t sweep_max;     // problem-table runs: largest sweep count of this iteration's SVDs
+    int32_t sweeps_total;  // problem-table runs: sum of sweep_max over finished iterations
+    int32_t sweeps_last;   // problem-table runs: sweep_max of the last finished iteration
     int32_t pad;
 };
 

@@ -38,8 +38,8 @@ __device__ __forceinline__ double warp_sum(double v) {
     return v;
 }
 
-// Block-wide sums of kNumPartials values into partials[blockIdx.x * kNumPartials + c].
-__device__ void block_partials(double (&v)[kNumPartials], double* partials, double* scratch) {
+// Block-wide sums of kNumPartials values into partials[slot * kNumPartials + c].
+__device__ void block_partials(double (&v)[kNumPartials], double* partials, double* scratch, int slot) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nwave = (blockDim.x + 63) >> 6;
 #pragma unroll
@@ -52,7 +52,7 @@ __device__ void block_partials(double (&v)[kNumPartials], double* partials, doub
     if (threadIdx.x < kNumPartials) {
         double s = 0.0;
         for (int w = 0; w < nwave; ++w) s += scratch[w * kNumPartials + threadIdx.x];
-        partials[(int64_t)blockIdx.x * kNumPartials + threadIdx.x] = s;
+        partials[(int64_t)slot * kNumPartials + threadIdx.x] = s;
     }
 }
 
@@ -62,8 +62,7 @@ __device__ __forceinline__ T sq(T v) { return v * v; }
 }  // namespace
 
 template <typename T, int PRO>
-__global__ __launch_bounds__(kBlock) void dft_forward_kernel(FwdArgs<T> a) {
-    extern __shared__ __align__(16) unsigned char smem[];
+__device__ __forceinline__ void dft_forward_body(const FwdArgs<T>& a, int bid, unsigned char* smem) {
     const Geometry& g = a.g;
     const int L = g.L, tile = a.tile, ldb = L + 1;
     cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem);
@@ -72,8 +71,8 @@ __global__ __launch_bounds__(kBlock) void dft_forward_kernel(FwdArgs<T> a) {
     for (int u = threadIdx.x; u < L; u += blockDim.x) tw[u] = cplx<T>{(T)a.tw[u].re, (T)a.tw[u].im};
 
     const int row_tiles = (g.m + tile - 1) / tile;
-    const int col = blockIdx.x / row_tiles;
-    const int row0 = (blockIdx.x - col * row_tiles) * tile;
+    const int col = bid / row_tiles;
+    const int row0 = (bid - col * row_tiles) * tile;
     const int nrow = min(tile, g.m - row0);
     const double ds = (PRO == PRO_COPY) ? 1.0 : a.ctrl->dscale;
 
@@ -126,8 +125,7 @@ __global__ __launch_bounds__(kBlock) void dft_forward_kernel(FwdArgs<T> a) {
 }
 
 template <typename T, int EPI>
-__global__ __launch_bounds__(kBlock) void dft_inverse_kernel(InvArgs<T> a) {
-    extern __shared__ __align__(16) unsigned char smem[];
+__device__ __forceinline__ void dft_inverse_body(const InvArgs<T>& a, int bid, unsigned char* smem) {
     const Geometry& g = a.g;
     const int L = g.L, tile = a.tile, h = g.h;
     cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem);
@@ -141,8 +139,8 @@ __global__ __launch_bounds__(kBlock) void dft_inverse_kernel(InvArgs<T> a) {
     for (int u = threadIdx.x; u < L; u += blockDim.x) tw[u] = cplx<T>{(T)a.tw[u].re, (T)a.tw[u].im};
 
     const int row_tiles = (g.m + tile - 1) / tile;
-    const int col = blockIdx.x / row_tiles;
-    const int row0 = (blockIdx.x - col * row_tiles) * tile;
+    const int col = bid / row_tiles;
+    const int row0 = (bid - col * row_tiles) * tile;
     const int nrow = min(tile, g.m - row0);
 
     for (int idx = threadIdx.x; idx < h * tile; idx += blockDim.x) {
@@ -251,7 +249,50 @@ __global__ __launch_bounds__(kBlock) void dft_inverse_kernel(InvArgs<T> a) {
     }
     if (EPI != EPI_STORE) {
         __syncthreads();
-        block_partials(part, a.partials, red);
+        block_partials(part, a.partials, red, bid);
+    }
+}
+
+template <typename T, int PRO>
+__global__ __launch_bounds__(kBlock) void dft_forward_kernel(FwdArgs<T> a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    dft_forward_body<T, PRO>(a, (int)blockIdx.x, smem);
+}
+
+template <typename T, int EPI>
+__global__ __launch_bounds__(kBlock) void dft_inverse_kernel(InvArgs<T> a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    dft_inverse_body<T, EPI>(a, (int)blockIdx.x, smem);
+}
+
+// Problem-table launches: the prologue / epilogue is a per-problem field;
+// a problem whose ADMM has stopped is skipped.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void dft_forward_batched(const FwdArgs<T>* tab, const int* wg_start, int nprob) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int p = batch_find(wg_start, nprob, (int)blockIdx.x);
+    const FwdArgs<T>& a = tab[p];
+    if (a.ctrl && a.ctrl->done) return;
+    const int bid = (int)blockIdx.x - wg_start[p];
+    switch (a.pro) {
+        case PRO_COPY: dft_forward_body<T, PRO_COPY>(a, bid, smem); break;
+        case PRO_COMPLETE: dft_forward_body<T, PRO_COMPLETE>(a, bid, smem); break;
+        default: dft_forward_body<T, PRO_RPCA>(a, bid, smem); break;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void dft_inverse_batched(const InvArgs<T>* tab, const int* wg_start, int nprob) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int p = batch_find(wg_start, nprob, (int)blockIdx.x);
+    const InvArgs<T>& a = tab[p];
+    if (a.ctrl && a.ctrl->done) return;
+    const int bid = (int)blockIdx.x - wg_start[p];
+    switch (a.epi) {
+        case EPI_STORE: dft_inverse_body<T, EPI_STORE>(a, bid, smem); break;
+        case EPI_COMPLETE: dft_inverse_body<T, EPI_COMPLETE>(a, bid, smem); break;
+        case EPI_RPCA_L1: dft_inverse_body<T, EPI_RPCA_L1>(a, bid, smem); break;
+        default: dft_inverse_body<T, EPI_RPCA_L112>(a, bid, smem); break;
     }
 }
 
@@ -278,9 +319,43 @@ int64_t dft_grid(const Geometry& g, int tile) {
 }
 
 template <typename T>
+size_t dft_forward_lds(const Geometry& g, int tile) {
+    return (size_t)g.L * sizeof(cplx<T>) + (size_t)tile * (g.L + 1) * sizeof(T);
+}
+
+template <typename T>
+size_t dft_inverse_lds(const Geometry& g, int tile, int epilogue) {
+    size_t lds = (size_t)g.L * sizeof(cplx<T>) + (size_t)g.h * tile * sizeof(cplx<T>);
+    if (epilogue == EPI_RPCA_L112) lds += 2 * (size_t)tile * g.L * sizeof(T);
+    return lds + 64 * sizeof(double) + (size_t)tile * sizeof(T) + 16;
+}
+
+template <typename T>
+void prepare_dft_batched(size_t lds_forward, size_t lds_inverse) {
+    if (lds_forward > 65536)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(dft_forward_batched<T>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_forward);
+    if (lds_inverse > 65536)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(dft_inverse_batched<T>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_inverse);
+}
+
+template <typename T>
+void launch_dft_forward_batched(const FwdArgs<T>* tab, const int* wg_start, int nprob, int nwg, size_t lds,
+                                hipStream_t st) {
+    hipLaunchKernelGGL((dft_forward_batched<T>), dim3(nwg), dim3(kBlock), lds, st, tab, wg_start, nprob);
+}
+
+template <typename T>
+void launch_dft_inverse_batched(const InvArgs<T>* tab, const int* wg_start, int nprob, int nwg, size_t lds,
+                                hipStream_t st) {
+    hipLaunchKernelGGL((dft_inverse_batched<T>), dim3(nwg), dim3(kBlock), lds, st, tab, wg_start, nprob);
+}
+
+template <typename T>
 void launch_dft_forward(int prologue, const FwdArgs<T>& a, hipStream_t st) {
     const int64_t grid = dft_grid(a.g, a.tile);
-    const size_t lds = (size_t)a.g.L * sizeof(cplx<T>) + (size_t)a.tile * (a.g.L + 1) * sizeof(T);
+    const size_t lds = dft_forward_lds<T>(a.g, a.tile);
     switch (prologue) {
         case PRO_COPY:
             hipLaunchKernelGGL((dft_forward_kernel<T, PRO_COPY>), dim3(grid), dim3(kBlock), lds, st, a);
@@ -297,9 +372,7 @@ void launch_dft_forward(int prologue, const FwdArgs<T>& a, hipStream_t st) {
 template <typename T>
 void launch_dft_inverse(int epilogue, const InvArgs<T>& a, hipStream_t st) {
     const int64_t grid = dft_grid(a.g, a.tile);
-    size_t lds = (size_t)a.g.L * sizeof(cplx<T>) + (size_t)a.g.h * a.tile * sizeof(cplx<T>);
-    if (epilogue == EPI_RPCA_L112) lds += 2 * (size_t)a.tile * a.g.L * sizeof(T);
-    lds += 64 * sizeof(double) + (size_t)a.tile * sizeof(T) + 16;
+    const size_t lds = dft_inverse_lds<T>(a.g, a.tile, epilogue);
     switch (epilogue) {
         case EPI_STORE:
             hipLaunchKernelGGL((dft_inverse_kernel<T, EPI_STORE>), dim3(grid), dim3(kBlock), lds, st, a);
@@ -316,6 +389,16 @@ void launch_dft_inverse(int epilogue, const InvArgs<T>& a, hipStream_t st) {
     }
 }
 
+template void prepare_dft_batched<double>(size_t, size_t);
+template void prepare_dft_batched<float>(size_t, size_t);
+template size_t dft_forward_lds<double>(const Geometry&, int);
+template size_t dft_inverse_lds<double>(const Geometry&, int, int);
+template size_t dft_forward_lds<float>(const Geometry&, int);
+template size_t dft_inverse_lds<float>(const Geometry&, int, int);
+template void launch_dft_forward_batched<double>(const FwdArgs<double>*, const int*, int, int, size_t, hipStream_t);
+template void launch_dft_inverse_batched<double>(const InvArgs<double>*, const int*, int, int, size_t, hipStream_t);
+template void launch_dft_forward_batched<float>(const FwdArgs<float>*, const int*, int, int, size_t, hipStream_t);
+template void launch_dft_inverse_batched<float>(const InvArgs<float>*, const int*, int, int, size_t, hipStream_t);
 template void launch_dft_forward<double>(int, const FwdArgs<double>&, hipStream_t);
 template void launch_dft_inverse<double>(int, const InvArgs<double>&, hipStream_t);
 template void launch_dft_forward<float>(int, const FwdArgs<float>&, hipStream_t);

@@ -1,0 +1,938 @@
+// Batched and served solves: many completion (Sec. 4) and tensor-RPCA
+// (Sec. 5) problems of uneven shapes advance together on one device.
+//
+// Every phase of an ADMM iteration is one launch over all running problems
+// of an element type, driven by per-problem argument tables (kernels.h,
+// "problem-table launches"):
+//   forward DFT + prologue -> Newton-Schulz V^H V -> Newton-Schulz V update
+//   -> pre-rotation A V -> Jacobi SVD (one launch per block-width / row-count
+//   class, one workgroup per slice) -> singular values -> rebuild
+//   -> inverse DFT + epilogue -> control step.
+// A problem runs exactly the arithmetic of the single-problem drivers in
+// capi.hip: the first iteration's pre-rotation by V = I is an exact copy, so
+// it equals their cold start.  Problems whose control step has stopped them
+// are skipped by every kernel, so a batch keeps running until the host,
+// which reads the control blocks after every two iterations, retires them.
+//
+// Buffers alternate between two parities (the iterates Z/Q, L/S/W and the
+// two V buffers), so two iterations -- one table set per parity -- form one
+// period; the period is captured once into a HIP graph and replayed until the
+// running set changes.  Problems join and leave only between periods.
+//
+// Device memory: each problem's state is one block of a per-engine arena
+// (first-fit allocator, host bookkeeping); admission waits until the block
+// fits.  The Jacobi block width of a shape is picked by the tuner below.
+
+#include "arena.h"
+#include "host.h"
+
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <tuple>
+#include <unordered_map>
+
+namespace tsvd {
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+// Jacobi block widths picked by the tuner, shared by every engine of the process.
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int>, int> g_tuned;
+
+// ------------------------------------------------------------------ problems
+
+struct Spec {
+    tsvd_problem p;
+    Geometry g;
+    AdmmSettings s;
+    bool fp32;
+};
+
+Spec validate(const tsvd_problem& p) {
+    Spec sp{};
+    sp.p = p;
+    if (p.kind != TSVD_KIND_COMPLETE && p.kind != TSVD_KIND_TRPCA) fail(TSVD_E_INVALID, "unknown problem kind");
+    sp.fp32 = check_precision(p.dtype, p.precision);
+    if (!p.x || !p.out) fail(TSVD_E_INVALID, "null tensor pointer");
+    if (!(p.penalty > 0.0) || !std::isfinite(p.penalty)) fail(TSVD_E_INVALID, "penalty must be > 0");
+    if (!(p.tol >= 0.0) || !std::isfinite(p.tol)) fail(TSVD_E_INVALID, "tol must be >= 0");
+    tsvd_admm_opts o = p.opts;
+    o.precision = p.precision;
+    if (p.kind == TSVD_KIND_COMPLETE) {
+        if (!p.mask) fail(TSVD_E_INVALID, "null mask");
+        sp.s = settings(&o, 1.1, 1e3, 300);
+    } else {
+        if (!p.out_s) fail(TSVD_E_INVALID, "null S output");
+        if (!(p.lambda > 0.0) || !std::isfinite(p.lambda)) fail(TSVD_E_INVALID, "lambda must be > 0");
+        if (p.shrink != TSVD_SHRINK_L1 && p.shrink != TSVD_SHRINK_L112) fail(TSVD_E_INVALID, "unknown shrink");
+        sp.s = settings(&o, 1.2, 1e10, 500);
+    }
+    if (sp.s.rho_max < p.penalty) fail(TSVD_E_INVALID, "rho_max must be >= the initial penalty");
+    sp.g = make_geometry(p.shape);
+    if (jacobi_slice_rpt(sp.g.m, sp.g.n) > jacobi_slice_max_rpt())
+        fail(TSVD_E_SHAPE, "slice too large for the batched Jacobi kernel");
+    if (sp.g.n < 2) fail(TSVD_E_SHAPE, "batched solves need min(n1, n2) >= 2");
+    return sp;
+}
+
+struct Result {
+    tsvd_status status = TSVD_E_BUSY;
+    tsvd_info info{};
+};
+
+template <typename T>
+struct Slot {
+    Spec sp;
+    uint64_t ticket = 0;
+    Clock::time_point t0;
+    size_t off = 0, bytes = 0;
+    T* it[3][2] = {};           // completion: Z, Q; RPCA: L, S, W (two parities each)
+    cplx<T>* A = nullptr;       // forward DFT output, rebuild output
+    cplx<T>* W = nullptr;       // pre-rotation output, Jacobi work array
+    cplx<T>* V[2] = {};
+    cplx<T>* G = nullptr;
+    double* sigma = nullptr;
+    int* sweeps = nullptr;
+    double* partials = nullptr;
+    Ctrl* ctrl = nullptr;
+    int* flag = nullptr;
+    cplx<double>* tw = nullptr;
+    int tile_f = 0, tile_i = 0, inv_parts = 0, pro = 0, epi = 0;
+    int bw = 0, rpt = 0, nb = 0;
+};
+
+template <typename T>
+size_t slot_layout(Slot<T>& sl, char* base) {
+    const Geometry& g = sl.sp.g;
+    const bool rpca = sl.sp.p.kind == TSVD_KIND_TRPCA;
+    sl.epi = rpca ? (sl.sp.p.shrink == TSVD_SHRINK_L1 ? EPI_RPCA_L1 : EPI_RPCA_L112) : EPI_COMPLETE;
+    sl.pro = rpca ? PRO_RPCA : PRO_COMPLETE;
+    sl.tile_f = dft_forward_tile(g);
+    sl.tile_i = dft_inverse_tile(g, sl.epi);
+    sl.inv_parts = (int)dft_grid(g, sl.tile_i);
+    const int nparts = std::max(sl.inv_parts, 1024);   // the data-norm pass uses 1024 partials
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char* {
+        off = Arena::round(off);
+        char* p = base ? base + off : nullptr;
+        off += bytes;
+        return p;
+    };
+    const int64_t N = g.numel, slice = (int64_t)g.h * g.m * g.n, vv = (int64_t)g.h * g.n * g.n;
+    const int nit = rpca ? 3 : 2;
+    for (int k = 0; k < nit; ++k)
+        for (int q = 0; q < 2; ++q) sl.it[k][q] = reinterpret_cast<T*>(take(N * sizeof(T)));
+    sl.A = reinterpret_cast<cplx<T>*>(take(slice * sizeof(cplx<T>)));
+    sl.W = reinterpret_cast<cplx<T>*>(take(slice * sizeof(cplx<T>)));
+    sl.V[0] = reinterpret_cast<cplx<T>*>(take(vv * sizeof(cplx<T>)));
+    sl.V[1] = reinterpret_cast<cplx<T>*>(take(vv * sizeof(cplx<T>)));
+    sl.G = reinterpret_cast<cplx<T>*>(take(vv * sizeof(cplx<T>)));
+    sl.sigma = reinterpret_cast<double*>(take((int64_t)g.h * g.n * sizeof(double)));
+    sl.sweeps = reinterpret_cast<int*>(take((int64_t)g.h * sizeof(int)));
+    sl.partials = reinterpret_cast<double*>(take((int64_t)nparts * kNumPartials * sizeof(double)));
+    sl.ctrl = reinterpret_cast<Ctrl*>(take(sizeof(Ctrl)));
+    sl.flag = reinterpret_cast<int*>(take(sizeof(int)));
+    sl.tw = reinterpret_cast<cplx<double>*>(take((int64_t)g.L * sizeof(cplx<double>)));
+    return Arena::round(off);
+}
+
+// ------------------------------------------------------------------ tables
+
+// Host images of the argument tables of one parity, packed into one device
+// buffer: [args of every phase][wg_start of every phase].
+template <typename T>
+struct Tables {
+    struct Phase {
+        size_t args_off = 0, ws_off = 0;
+        int nprob = 0, nwg = 0;
+        size_t lds = 0;
+        int bw = 0, rpt = 0;   // Jacobi classes
+    };
+    Phase fwd, gram, ns, pre, sig, reb, inv, ctl;
+    std::vector<Phase> jac;
+    std::vector<char> host;
+    char* dev = nullptr;
+    size_t dev_cap = 0;
+};
+
+template <typename A>
+size_t append(std::vector<char>& buf, const std::vector<A>& v) {
+    size_t off = (buf.size() + 255) & ~size_t(255);
+    buf.resize(off + v.size() * sizeof(A));
+    if (!v.empty()) std::memcpy(buf.data() + off, v.data(), v.size() * sizeof(A));
+    return off;
+}
+
+// ------------------------------------------------------------------ engine
+
+template <typename T>
+class Engine {
+public:
+    Engine(int device, int cus, size_t lds_cap) : device_(device), cus_(cus), lds_cap_(lds_cap) {}
+    ~Engine() { release(); }
+
+    void release() {
+        drop_graph();
+        for (int q = 0; q < 2; ++q)
+            if (tab_[q].dev) (void)hipFree(tab_[q].dev), tab_[q].dev = nullptr;
+        if (host_ctrl_) (void)hipHostFree(host_ctrl_), host_ctrl_ = nullptr;
+        if (stream_) (void)hipStreamDestroy(stream_), stream_ = nullptr;
+    }
+
+    void attach(Arena* arena) {
+        arena_ = arena;
+        if (!stream_) hip_check(hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking), "hipStreamCreate");
+    }
+
+    hipStream_t stream() const { return stream_; }
+    size_t running() const { return slots_.size(); }
+    int64_t iterations() const { return iterations_; }
+
+    static size_t footprint(const Spec& sp) {
+        Slot<T> sl;
+        sl.sp = sp;
+        return slot_layout(sl, nullptr);
+    }
+
+    // Try to admit; false if the arena has no room now.
+    bool admit(const Spec& sp, uint64_t ticket, Clock::time_point t0) {
+        Slot<T> sl;
+        sl.sp = sp;
+        sl.ticket = ticket;
+        sl.t0 = t0;
+        const size_t bytes = slot_layout(sl, nullptr);
+        size_t off = 0;
+        if (!arena_->take(bytes, &off)) return false;
+        sl.off = off;
+        sl.bytes = bytes;
+        slot_layout(sl, arena_->base() + off);
+        try {
+            setup(sl);
+        } catch (...) {
+            arena_->give(off, bytes);
+            throw;
+        }
+        slots_.push_back(sl);
+        dirty_ = true;
+        return true;
+    }
+
+    // Run one period (two iterations) over the running problems.
+    void period() {
+        if (slots_.empty()) return;
+        if (dirty_) rebuild();
+        if (graph_exec_) {
+            hip_check(hipGraphLaunch(graph_exec_, stream_), "hipGraphLaunch");
+        } else {
+            iteration(0);
+            iteration(1);
+        }
+        iterations_ += 2;
+    }
+
+    // Retire stopped problems: write their outputs and results.
+    template <typename F>
+    void harvest(F&& done_cb) {
+        if (slots_.empty()) return;
+        const size_t n = slots_.size();
+        ensure_host_ctrl(n);
+        for (size_t i = 0; i < n; ++i)
+            hip_check(hipMemcpyAsync(host_ctrl_ + i, slots_[i].ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, stream_),
+                      "hipMemcpyAsync ctrl");
+        hip_check(hipStreamSynchronize(stream_), "hipStreamSynchronize");
+        std::vector<size_t> stopped;
+        for (size_t i = 0; i < n; ++i)
+            if (host_ctrl_[i].done) stopped.push_back(i);
+        if (stopped.empty()) return;
+        std::vector<Ctrl> cs;
+        for (size_t i : stopped) cs.push_back(host_ctrl_[i]);
+        // outputs, sweep counts and non-finite flags of the stopped problems
+        std::vector<int> flags(stopped.size());
+        for (size_t k = 0; k < stopped.size(); ++k) {
+            Slot<T>& sl = slots_[stopped[k]];
+            write_outputs(sl, cs[k]);
+            hip_check(hipMemcpyAsync(&flags[k], sl.flag, sizeof(int), hipMemcpyDeviceToHost, stream_),
+                      "hipMemcpyAsync flag");
+        }
+        hip_check(hipStreamSynchronize(stream_), "hipStreamSynchronize");
+        const auto now = Clock::now();
+        for (size_t k = 0; k < stopped.size(); ++k) {
+            Slot<T>& sl = slots_[stopped[k]];
+            const Ctrl& c = cs[k];
+            Result r;
+            r.status = (c.nonfinite || flags[k]) ? TSVD_E_NONFINITE : TSVD_OK;
+            r.info.iters = c.iter;
+            r.info.converged = c.done == 1 && !c.nonfinite ? 1 : 0;
+            r.info.sweeps_total = c.sweeps_total;
+            r.info.sweeps_last = c.sweeps_last;
+            r.info.primal = c.primal;
+            r.info.change = c.change;
+            r.info.rho_final = c.rho_used;
+            r.info.seconds = std::chrono::duration<double>(now - sl.t0).count();
+            done_cb(sl.ticket, r);
+        }
+        // free in reverse index order so the remaining indices stay valid
+        for (auto it = stopped.rbegin(); it != stopped.rend(); ++it) {
+            arena_->give(slots_[*it].off, slots_[*it].bytes);
+            slots_.erase(slots_.begin() + (long)*it);
+        }
+        dirty_ = true;
+    }
+
+private:
+    void ensure_host_ctrl(size_t n) {
+        if (n <= host_ctrl_len_) return;
+        if (host_ctrl_) hip_check(hipHostFree(host_ctrl_), "hipHostFree");
+        host_ctrl_ = nullptr;
+        hip_check(hipHostMalloc(reinterpret_cast<void**>(&host_ctrl_), sizeof(Ctrl) * n, 0), "hipHostMalloc");
+        host_ctrl_len_ = n;
+    }
+
+    void setup(Slot<T>& sl) {
+        const Geometry& g = sl.sp.g;
+        const tsvd_problem& p = sl.sp.p;
+        const bool rpca = p.kind == TSVD_KIND_TRPCA;
+        const int64_t N = g.numel;
+        hipStream_t st = stream_;
+        // twiddles and the control block come from host memory: stage them
+        // through pinned buffers that outlive the copies (synchronised below)
+        const std::vector<cplx<double>> tw = twiddles_host(g.L);
+        Ctrl c{};
+        c.rho = p.penalty;
+        c.tau = 1.0 / p.penalty;
+        c.dscale = 1.0;
+        c.dscale_used = 1.0;
+        c.growth = sl.sp.s.growth;
+        c.rho_max = sl.sp.s.rho_max;
+        c.rho_used = p.penalty;
+        c.max_iter = sl.sp.s.max_iter;
+        if (rpca) {
+            c.lambda = p.lambda;
+            c.shrink = p.lambda / p.penalty;
+        }
+        void* staging = nullptr;
+        const size_t tw_bytes = tw.size() * sizeof(cplx<double>);
+        hip_check(hipHostMalloc(&staging, tw_bytes + sizeof(Ctrl), 0), "hipHostMalloc");
+        std::memcpy(staging, tw.data(), tw_bytes);
+        std::memcpy(static_cast<char*>(staging) + tw_bytes, &c, sizeof(Ctrl));
+        hip_check(hipMemcpyAsync(sl.tw, staging, tw_bytes, hipMemcpyHostToDevice, st), "hipMemcpyAsync twiddles");
+        hip_check(hipMemcpyAsync(sl.ctrl, static_cast<char*>(staging) + tw_bytes, sizeof(Ctrl),
+                                 hipMemcpyHostToDevice, st),
+                  "hipMemcpyAsync ctrl");
+        const int nit = rpca ? 3 : 2;
+        for (int k = 0; k < nit; ++k) launch_fill<T>(sl.it[k][0], (T)0, N, st);
+        launch_set_identity<T>(sl.V[0], g.n, g.h, st);
+        launch_fill<int>(sl.flag, 0, 1, st);
+        launch_sumsq<T>(static_cast<const T*>(p.x), rpca ? nullptr : p.mask, N, sl.partials, 1024, st);
+        launch_set_tol(sl.ctrl, sl.partials, 1024, p.tol, st);
+        launch_check("problem setup");
+        const hipError_t e = hipStreamSynchronize(st);
+        (void)hipHostFree(staging);
+        hip_check(e, "hipStreamSynchronize");
+        // Jacobi launch class
+        sl.rpt = jacobi_slice_rpt(g.m, g.n);
+        sl.bw = pick_bw(g.m, g.n, sl.rpt);
+        sl.nb = jacobi_num_blocks(g.n, sl.bw);
+    }
+
+    void write_outputs(Slot<T>& sl, const Ctrl& c) {
+        const Geometry& g = sl.sp.g;
+        const tsvd_problem& p = sl.sp.p;
+        const int64_t N = g.numel;
+        const int iters = std::max(c.iter, 1);
+        if (p.kind == TSVD_KIND_COMPLETE) {
+            // the X-update of the last iteration, from the iterates it started with
+            const int q = (iters - 1) % 2;
+            launch_complete_output<T>(static_cast<const T*>(p.x), p.mask, sl.it[0][q], sl.it[1][q], sl.ctrl,
+                                      static_cast<T*>(p.out), N, stream_);
+            launch_check("complete_output");
+        } else {
+            const int q = iters % 2;
+            hip_check(hipMemcpyAsync(p.out, sl.it[0][q], N * sizeof(T), hipMemcpyDeviceToDevice, stream_),
+                      "hipMemcpyAsync L");
+            hip_check(hipMemcpyAsync(p.out_s, sl.it[1][q], N * sizeof(T), hipMemcpyDeviceToDevice, stream_),
+                      "hipMemcpyAsync S");
+        }
+    }
+
+    // ---- Jacobi block-width tuner
+    int pick_bw(int m, int n, int rpt) {
+        std::vector<int> cand;
+        for (int bw : {16, 8, 4})
+            if (jacobi_slice_lds(bw, rpt, sizeof(T)) + 1024 <= lds_cap_) cand.push_back(bw);
+        if (cand.empty()) fail(TSVD_E_SHAPE, "slice too large for the batched Jacobi kernel");
+        const int forced = env_int("TSVD_BATCH_BW", 0);
+        for (int bw : cand)
+            if (bw == forced) return bw;
+        if (cand.size() == 1 || env_int("TSVD_TUNE", 1) == 0) return cand[0];
+        // one decision per device, element type, row class and 32-column class
+        const auto key = std::make_tuple(device_, (int)sizeof(T), rpt, (n + 31) / 32);
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            auto hit = g_tuned.find(key);
+            if (hit != g_tuned.end()) return hit->second;
+        }
+        const int bw = tune(m, n, rpt, cand);
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tuned[key] = bw;
+        return bw;
+    }
+
+    // Time every candidate block width on S synthetic slices of this shape
+    // (pseudo-random entries, V = I, one sweep) and keep the fastest.
+    int tune(int m, int n, int rpt, const std::vector<int>& cand) {
+        const int S = cus_;   // one slice per CU
+        const int64_t mn = (int64_t)m * n, nn = (int64_t)n * n;
+        cplx<T>* buf = nullptr;
+        hip_check(hipMalloc(&buf, sizeof(cplx<T>) * (size_t)S * (2 * mn + nn) + 1024), "hipMalloc tuner");
+        cplx<T>* A0 = buf;
+        cplx<T>* A = A0 + S * mn;
+        cplx<T>* V = A + S * mn;
+        JacSliceArgs<T>* dtab = nullptr;
+        int* dws = nullptr;
+        hip_check(hipMalloc(&dtab, sizeof(JacSliceArgs<T>)), "hipMalloc tuner");
+        hip_check(hipMalloc(&dws, 2 * sizeof(int)), "hipMalloc tuner");
+        hipEvent_t e0, e1;
+        hip_check(hipEventCreate(&e0), "hipEventCreate");
+        hip_check(hipEventCreate(&e1), "hipEventCreate");
+        int best = cand[0];
+        float best_ms = 1e30f;
+        try {
+            launch_fill_hash<T>(A0, S * mn, 12345u, stream_);
+            const int ws[2] = {0, S};
+            hip_check(hipMemcpyAsync(dws, ws, sizeof(ws), hipMemcpyHostToDevice, stream_), "hipMemcpyAsync");
+            for (int bw : cand) {
+                JacSliceArgs<T> ja{};
+                ja.A = A;
+                ja.V = V;
+                ja.m = m;
+                ja.n = n;
+                ja.h = S;
+                ja.nb = jacobi_num_blocks(n, bw);
+                ja.tol = (T)(std::sqrt((double)m) * (sizeof(T) == 4 ? 16.0 * 1.1920928955078125e-07 : 2.220446049250313e-16));
+                ja.max_sweeps = 1;
+                hip_check(hipMemcpyAsync(dtab, &ja, sizeof(ja), hipMemcpyHostToDevice, stream_), "hipMemcpyAsync");
+                hip_check(hipMemcpyAsync(A, A0, sizeof(cplx<T>) * S * mn, hipMemcpyDeviceToDevice, stream_),
+                          "hipMemcpyAsync");
+                launch_set_identity<T>(V, n, S, stream_);
+                hip_check(prepare_jacobi_slice<T>(bw, rpt), "jacobi tuner attribute");
+                hip_check(hipEventRecord(e0, stream_), "hipEventRecord");
+                hip_check(launch_jacobi_slice<T>(bw, rpt, dtab, dws, 1, S, 1, stream_), "jacobi tuner launch");
+                hip_check(hipEventRecord(e1, stream_), "hipEventRecord");
+                hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+                float ms = 0.f;
+                hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = bw;
+                }
+            }
+        } catch (...) {
+            (void)hipStreamSynchronize(stream_);
+            (void)hipFree(buf), (void)hipFree(dtab), (void)hipFree(dws);
+            (void)hipEventDestroy(e0), (void)hipEventDestroy(e1);
+            throw;
+        }
+        (void)hipFree(buf), (void)hipFree(dtab), (void)hipFree(dws);
+        (void)hipEventDestroy(e0), (void)hipEventDestroy(e1);
+        if (env_int("TSVD_TUNE_LOG", 0))
+            std::fprintf(stderr, "[tsvd tune] m=%d n=%d rpt=%d -> bw=%d (%.3f ms)\n", m, n, rpt, best, best_ms);
+        return best;
+    }
+
+    // ---- tables and graph
+    void rebuild() {
+        drop_graph();
+        for (int q = 0; q < 2; ++q) build_tables(q);
+        dirty_ = false;
+        if (env_int("TSVD_GRAPH", 1) == 0) return;
+        hipGraph_t graph = nullptr;
+        hip_check(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+        bool ok = true;
+        try {
+            iteration(0);
+            iteration(1);
+        } catch (...) {
+            ok = false;
+        }
+        const hipError_t e = hipStreamEndCapture(stream_, &graph);
+        if (!ok || e != hipSuccess || !graph) {
+            (void)hipGetLastError();
+            if (graph) (void)hipGraphDestroy(graph);
+            return;   // eager launches from now on for this running set
+        }
+        if (hipGraphInstantiate(&graph_exec_, graph, nullptr, nullptr, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            graph_exec_ = nullptr;
+        }
+        (void)hipGraphDestroy(graph);
+    }
+
+    void drop_graph() {
+        if (graph_exec_) (void)hipGraphExecDestroy(graph_exec_);
+        graph_exec_ = nullptr;
+    }
+
+    void build_tables(int par) {
+        Tables<T>& tb = tab_[par];
+        tb.host.clear();
+        tb.jac.clear();
+        const int P = par, Q = 1 - par;
+        std::vector<FwdArgs<T>> fwd;
+        std::vector<InvArgs<T>> inv;
+        std::vector<ZGemmArgs<T>> gram, ns, pre, reb;
+        std::vector<SigmaArgs<T>> sig;
+        std::vector<CtrlArgs> ctl;
+        std::vector<int> ws_fwd{0}, ws_inv{0}, ws_gram{0}, ws_ns{0}, ws_pre{0}, ws_reb{0}, ws_sig{0};
+        size_t lds_f = 0, lds_i = 0;
+        std::map<std::pair<int, int>, std::pair<std::vector<JacSliceArgs<T>>, std::vector<int>>> jc;
+        for (const Slot<T>& sl : slots_) {
+            const Geometry& g = sl.sp.g;
+            const tsvd_problem& p = sl.sp.p;
+            const bool rpca = p.kind == TSVD_KIND_TRPCA;
+            const int64_t mn = (int64_t)g.m * g.n, nn = (int64_t)g.n * g.n;
+            FwdArgs<T> fa{};
+            fa.x = static_cast<const T*>(p.x);
+            fa.mask = rpca ? nullptr : p.mask;
+            fa.ctrl = sl.ctrl;
+            fa.tw = sl.tw;
+            fa.out = sl.A;
+            fa.nonfinite = sl.flag;
+            fa.g = g;
+            fa.tile = sl.tile_f;
+            fa.pro = sl.pro;
+            if (rpca) {
+                fa.s = sl.it[1][P];
+                fa.dual = sl.it[2][P];
+            } else {
+                fa.z = sl.it[0][P];
+                fa.dual = sl.it[1][P];
+            }
+            fwd.push_back(fa);
+            ws_fwd.push_back(ws_fwd.back() + (int)dft_grid(g, sl.tile_f));
+            lds_f = std::max(lds_f, dft_forward_lds<T>(g, sl.tile_f));
+            // Newton-Schulz: G = V^H V, V' = 1.5 V - 0.5 V G
+            ZGemmArgs<T> gg{};
+            gg.A = sl.V[P];
+            gg.B = sl.V[P];
+            gg.C = sl.G;
+            gg.M = gg.N = gg.K = g.n;
+            gg.lda = gg.ldb = gg.ldc = gg.ldd = g.n;
+            gg.sA = gg.sB = gg.sC = gg.sD = nn;
+            gg.alpha = (T)1;
+            gg.beta = (T)0;
+            gg.opA = 1;
+            gg.opB = 0;
+            gg.batch = g.h;
+            gg.ctrl = sl.ctrl;
+            gram.push_back(gg);
+            ws_gram.push_back(ws_gram.back() + zgemm_workgroups(g.n, g.n, g.h));
+            ZGemmArgs<T> gn = gg;
+            gn.A = sl.V[P];
+            gn.B = sl.G;
+            gn.D = sl.V[P];
+            gn.C = sl.V[Q];
+            gn.alpha = (T)-0.5;
+            gn.beta = (T)1.5;
+            gn.opA = 0;
+            ns.push_back(gn);
+            ws_ns.push_back(ws_ns.back() + zgemm_workgroups(g.n, g.n, g.h));
+            // pre-rotation W = A V'
+            ZGemmArgs<T> ga{};
+            ga.A = sl.A;
+            ga.B = sl.V[Q];
+            ga.C = sl.W;
+            ga.M = g.m;
+            ga.N = g.n;
+            ga.K = g.n;
+            ga.lda = g.m;
+            ga.ldb = g.n;
+            ga.ldc = g.m;
+            ga.ldd = g.m;
+            ga.sA = mn;
+            ga.sB = nn;
+            ga.sC = mn;
+            ga.sD = mn;
+            ga.alpha = (T)1;
+            ga.beta = (T)0;
+            ga.batch = g.h;
+            ga.ctrl = sl.ctrl;
+            pre.push_back(ga);
+            ws_pre.push_back(ws_pre.back() + zgemm_workgroups(g.m, g.n, g.h));
+            // Jacobi on (W, V')
+            JacSliceArgs<T> ja{};
+            ja.A = sl.W;
+            ja.V = sl.V[Q];
+            ja.m = g.m;
+            ja.n = g.n;
+            ja.h = g.h;
+            ja.nb = sl.nb;
+            ja.tol = (T)(std::sqrt((double)g.m) *
+                         (sizeof(T) == 4 ? 16.0 * 1.1920928955078125e-07 : 2.220446049250313e-16));
+            ja.sweeps = sl.sweeps;
+            ja.ctrl = sl.ctrl;
+            ja.max_sweeps = sl.sp.s.max_sweeps;
+            auto& cls = jc[{sl.bw, sl.rpt}];
+            if (cls.second.empty()) cls.second.push_back(0);
+            cls.first.push_back(ja);
+            cls.second.push_back(cls.second.back() + g.h);
+            // singular values and rebuild A = W diag(d) V'^H
+            SigmaArgs<T> sa{sl.W, g.m, g.n, g.h, sl.sigma, sl.ctrl};
+            sig.push_back(sa);
+            ws_sig.push_back(ws_sig.back() + svt_sigma_workgroups(g.n, g.h));
+            ZGemmArgs<T> gr = ga;
+            gr.A = sl.W;
+            gr.B = sl.V[Q];
+            gr.C = sl.A;
+            gr.opB = 1;
+            gr.sigma = sl.sigma;
+            gr.ssig = g.n;
+            reb.push_back(gr);
+            ws_reb.push_back(ws_reb.back() + zgemm_workgroups(g.m, g.n, g.h));
+            // inverse DFT + epilogue
+            InvArgs<T> ia{};
+            ia.in = sl.A;
+            ia.tw = sl.tw;
+            ia.ctrl = sl.ctrl;
+            ia.g = g;
+            ia.tile = sl.tile_i;
+            ia.partials = sl.partials;
+            ia.epi = sl.epi;
+            ia.out = sl.it[0][Q];
+            if (rpca) {
+                ia.m = static_cast<const T*>(p.x);
+                ia.l_old = sl.it[0][P];
+                ia.s_old = sl.it[1][P];
+                ia.s_new = sl.it[1][Q];
+                ia.dual_old = sl.it[2][P];
+                ia.dual_new = sl.it[2][Q];
+            } else {
+                ia.y = static_cast<const T*>(p.x);
+                ia.mask = p.mask;
+                ia.z_old = sl.it[0][P];
+                ia.dual_old = sl.it[1][P];
+                ia.dual_new = sl.it[1][Q];
+            }
+            inv.push_back(ia);
+            ws_inv.push_back(ws_inv.back() + sl.inv_parts);
+            lds_i = std::max(lds_i, dft_inverse_lds<T>(g, sl.tile_i, sl.epi));
+            ctl.push_back(CtrlArgs{sl.ctrl, sl.partials, sl.inv_parts, rpca ? 1 : 0});
+        }
+        auto put = [&](typename Tables<T>::Phase& ph, auto& args, std::vector<int>& ws, size_t lds) {
+            ph.args_off = append(tb.host, args);
+            ph.ws_off = append(tb.host, ws);
+            ph.nprob = (int)args.size();
+            ph.nwg = ws.back();
+            ph.lds = lds;
+        };
+        put(tb.fwd, fwd, ws_fwd, lds_f);
+        put(tb.gram, gram, ws_gram, 0);
+        put(tb.ns, ns, ws_ns, 0);
+        put(tb.pre, pre, ws_pre, 0);
+        put(tb.sig, sig, ws_sig, 0);
+        put(tb.reb, reb, ws_reb, 0);
+        put(tb.inv, inv, ws_inv, lds_i);
+        std::vector<int> ws_ctl(ctl.size() + 1, 0);
+        put(tb.ctl, ctl, ws_ctl, 0);
+        tb.ctl.nwg = (int)ctl.size();
+        for (auto& kv : jc) {
+            typename Tables<T>::Phase ph;
+            put(ph, kv.second.first, kv.second.second, 0);
+            ph.bw = kv.first.first;
+            ph.rpt = kv.first.second;
+            hip_check(prepare_jacobi_slice<T>(ph.bw, ph.rpt), "jacobi attribute");
+            tb.jac.push_back(ph);
+        }
+        if (tb.host.size() > tb.dev_cap) {
+            if (tb.dev) hip_check(hipFree(tb.dev), "hipFree tables");
+            tb.dev = nullptr;
+            tb.dev_cap = std::max(tb.host.size() * 2, (size_t)1 << 16);
+            hip_check(hipMalloc(&tb.dev, tb.dev_cap), "hipMalloc tables");
+        }
+        hip_check(hipMemcpy(tb.dev, tb.host.data(), tb.host.size(), hipMemcpyHostToDevice), "hipMemcpy tables");
+        prepare_dft_batched<T>(lds_f, lds_i);
+    }
+
+    template <typename A>
+    const A* targs(const Tables<T>& tb, const typename Tables<T>::Phase& ph) const {
+        return reinterpret_cast<const A*>(tb.dev + ph.args_off);
+    }
+    const int* tws(const Tables<T>& tb, const typename Tables<T>::Phase& ph) const {
+        return reinterpret_cast<const int*>(tb.dev + ph.ws_off);
+    }
+
+    void iteration(int par) {
+        const Tables<T>& tb = tab_[par];
+        hipStream_t st = stream_;
+        launch_dft_forward_batched<T>(targs<FwdArgs<T>>(tb, tb.fwd), tws(tb, tb.fwd), tb.fwd.nprob, tb.fwd.nwg,
+                                      tb.fwd.lds, st);
+        launch_check("batched dft_forward");
+        launch_zgemm_batched<T>(targs<ZGemmArgs<T>>(tb, tb.gram), tws(tb, tb.gram), tb.gram.nprob, tb.gram.nwg, st);
+        launch_zgemm_batched<T>(targs<ZGemmArgs<T>>(tb, tb.ns), tws(tb, tb.ns), tb.ns.nprob, tb.ns.nwg, st);
+        launch_zgemm_batched<T>(targs<ZGemmArgs<T>>(tb, tb.pre), tws(tb, tb.pre), tb.pre.nprob, tb.pre.nwg, st);
+        launch_check("batched warm start");
+        for (const auto& ph : tb.jac)
+            hip_check(launch_jacobi_slice<T>(ph.bw, ph.rpt, targs<JacSliceArgs<T>>(tb, ph), tws(tb, ph), ph.nprob,
+                                             ph.nwg, 30, st),
+                      "batched jacobi");
+        launch_svt_sigma_batched<T>(targs<SigmaArgs<T>>(tb, tb.sig), tws(tb, tb.sig), tb.sig.nprob, tb.sig.nwg, st);
+        launch_zgemm_batched<T>(targs<ZGemmArgs<T>>(tb, tb.reb), tws(tb, tb.reb), tb.reb.nprob, tb.reb.nwg, st);
+        launch_check("batched rebuild");
+        launch_dft_inverse_batched<T>(targs<InvArgs<T>>(tb, tb.inv), tws(tb, tb.inv), tb.inv.nprob, tb.inv.nwg,
+                                      tb.inv.lds, st);
+        launch_admm_ctrl_batched(targs<CtrlArgs>(tb, tb.ctl), tb.ctl.nprob, st);
+        launch_check("batched control");
+    }
+
+    int device_, cus_;
+    size_t lds_cap_;
+    Arena* arena_ = nullptr;
+    hipStream_t stream_ = nullptr;
+    std::vector<Slot<T>> slots_;
+    Tables<T> tab_[2];
+    bool dirty_ = true;
+    hipGraphExec_t graph_exec_ = nullptr;
+    Ctrl* host_ctrl_ = nullptr;
+    size_t host_ctrl_len_ = 0;
+    int64_t iterations_ = 0;
+};
+
+size_t default_arena_bytes(size_t budget) {
+    if (budget) return budget;
+    size_t free_b = 0, total_b = 0;
+    hip_check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
+    return (size_t)(0.9 * (double)free_b);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ batch
+
+void batch_run(tsvd_handle h, const tsvd_problem* probs, int count, tsvd_info* infos, int32_t* status) {
+    check_handle(h);
+    if (count < 0 || (count > 0 && !probs)) fail(TSVD_E_INVALID, "bad problem array");
+    std::vector<Spec> specs;
+    specs.reserve(count);
+    for (int i = 0; i < count; ++i) specs.push_back(validate(probs[i]));
+    if (count == 0) return;
+    const auto t0 = Clock::now();
+    Device dev(h->device);
+    // arena: everything at once if it fits, else the budget
+    size_t need = 0, largest = 0;
+    for (const Spec& sp : specs) {
+        const size_t b = sp.fp32 ? Engine<float>::footprint(sp) : Engine<double>::footprint(sp);
+        need += Arena::round(b);
+        largest = std::max(largest, Arena::round(b));
+    }
+    const size_t cap = std::min(need, default_arena_bytes(h->budget));
+    if (largest > cap) fail(TSVD_E_NOMEM, "a problem does not fit the arena");
+    char* mem = nullptr;
+    hipError_t e = hipMalloc(&mem, cap);
+    if (e != hipSuccess) fail(TSVD_E_NOMEM, std::string("hipMalloc arena: ") + hipGetErrorString(e));
+    Arena arena;
+    arena.reset(mem, cap);
+    std::vector<Result> res(count);
+    try {
+        Engine<float> ef(h->device, h->cus, h->lds_cap);
+        Engine<double> ed(h->device, h->cus, h->lds_cap);
+        ef.attach(&arena);
+        ed.attach(&arena);
+        size_t next = 0;
+        auto record = [&](uint64_t ticket, const Result& r) { res[ticket] = r; };
+        for (;;) {
+            // admit in order while the arena has room
+            while (next < specs.size()) {
+                const Spec& sp = specs[next];
+                const bool ok = sp.fp32 ? ef.admit(sp, next, t0) : ed.admit(sp, next, t0);
+                if (!ok) break;
+                ++next;
+            }
+            if (ef.running() == 0 && ed.running() == 0) {
+                if (next >= specs.size()) break;
+                fail(TSVD_E_NOMEM, "arena too small for the next problem");
+            }
+            ef.period();
+            ed.period();
+            ef.harvest(record);
+            ed.harvest(record);
+        }
+    } catch (...) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(mem);
+        throw;
+    }
+    hip_check(hipFree(mem), "hipFree arena");
+    for (int i = 0; i < count; ++i) {
+        if (infos) infos[i] = res[i].info;
+        if (status) status[i] = res[i].status;
+    }
+}
+
+// ------------------------------------------------------------------ serving
+
+struct Server {
+    explicit Server(tsvd_handle h)
+        : handle(h), ef(h->device, h->cus, h->lds_cap), ed(h->device, h->cus, h->lds_cap) {}
+
+    tsvd_handle handle;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::thread worker;
+    bool stop = false;
+    bool started = false;
+    struct Queued {
+        uint64_t ticket;
+        Spec sp;
+        Clock::time_point t0;
+    };
+    std::deque<Queued> queue;
+    std::unordered_map<uint64_t, Result> results;
+    uint64_t next_ticket = 1;
+    tsvd_serve_stats stats{};
+    std::string worker_error;
+    // device side (worker thread only after start)
+    Arena arena;
+    char* mem = nullptr;
+    Engine<float> ef;
+    Engine<double> ed;
+
+    void start() {
+        if (started) return;
+        Device dev(handle->device);
+        const size_t cap = default_arena_bytes(handle->budget);
+        hipError_t e = hipMalloc(&mem, cap);
+        if (e != hipSuccess) fail(TSVD_E_NOMEM, std::string("hipMalloc arena: ") + hipGetErrorString(e));
+        arena.reset(mem, cap);
+        ef.attach(&arena);
+        ed.attach(&arena);
+        stats.arena_bytes = (int64_t)cap;
+        started = true;
+        worker = std::thread([this] { loop(); });
+    }
+
+    void shutdown() {
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            stop = true;
+        }
+        cv.notify_all();
+        if (worker.joinable()) worker.join();
+        if (started) {
+            Device dev(handle->device);
+            ef.release();
+            ed.release();
+            if (mem) (void)hipFree(mem);
+            mem = nullptr;
+        }
+    }
+
+    void finish(uint64_t ticket, const Result& r) {
+        std::lock_guard<std::mutex> lk(mu);
+        results[ticket] = r;
+        stats.finished += 1;
+    }
+
+    void loop() {
+        (void)hipSetDevice(handle->device);
+        for (;;) {
+            std::vector<Queued> take;
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                cv.wait(lk, [&] { return stop || !queue.empty() || ef.running() + ed.running() > 0; });
+                if (stop) return;
+            }
+            try {
+                // admit from the head of the queue while the arena has room
+                for (;;) {
+                    Queued q;
+                    {
+                        std::lock_guard<std::mutex> lk(mu);
+                        if (queue.empty()) break;
+                        q = queue.front();
+                    }
+                    const bool ok = q.sp.fp32 ? ef.admit(q.sp, q.ticket, q.t0) : ed.admit(q.sp, q.ticket, q.t0);
+                    if (!ok) break;
+                    std::lock_guard<std::mutex> lk(mu);
+                    queue.pop_front();
+                }
+                ef.period();
+                ed.period();
+                auto cb = [&](uint64_t t, const Result& r) { finish(t, r); };
+                ef.harvest(cb);
+                ed.harvest(cb);
+                std::lock_guard<std::mutex> lk(mu);
+                stats.iterations = ef.iterations() + ed.iterations();
+                stats.running = (int64_t)(ef.running() + ed.running());
+                stats.peak_running = std::max(stats.peak_running, stats.running);
+                stats.queued = (int64_t)queue.size();
+                stats.arena_used = (int64_t)arena.used();
+            } catch (const Failure& f) {
+                // a device failure ends serving: fail every open ticket
+                std::lock_guard<std::mutex> lk(mu);
+                worker_error = f.msg;
+                for (auto& q : queue) results[q.ticket].status = f.status;
+                queue.clear();
+                stop = true;
+                return;
+            }
+        }
+    }
+};
+
+void serve_submit(tsvd_handle h, const tsvd_problem* prob, uint64_t* ticket) {
+    check_handle(h);
+    if (!prob || !ticket) fail(TSVD_E_INVALID, "null argument");
+    const Spec sp = validate(*prob);
+    if (!h->server) h->server = new Server(h);
+    Server& s = *h->server;
+    s.start();
+    const size_t bytes = sp.fp32 ? Engine<float>::footprint(sp) : Engine<double>::footprint(sp);
+    if (Arena::round(bytes) > s.arena.cap()) fail(TSVD_E_NOMEM, "problem does not fit the serving arena");
+    {
+        std::lock_guard<std::mutex> lk(s.mu);
+        if (s.stop) fail(TSVD_E_HIP, "serving stopped after a device failure: " + s.worker_error);
+        *ticket = s.next_ticket++;
+        s.results[*ticket] = Result{};
+        s.queue.push_back(Server::Queued{*ticket, sp, Clock::now()});
+        s.stats.submitted += 1;
+    }
+    s.cv.notify_all();
+}
+
+tsvd_status serve_poll(tsvd_handle h, uint64_t ticket, tsvd_info* info) {
+    check_handle(h);
+    if (!h->server) fail(TSVD_E_INVALID, "unknown ticket");
+    Server& s = *h->server;
+    std::lock_guard<std::mutex> lk(s.mu);
+    auto it = s.results.find(ticket);
+    if (it == s.results.end()) fail(TSVD_E_INVALID, "unknown ticket");
+    if (it->second.status != TSVD_E_BUSY && info) *info = it->second.info;
+    return it->second.status;
+}
+
+void serve_stats(tsvd_handle h, tsvd_serve_stats* out) {
+    check_handle(h);
+    if (!out) fail(TSVD_E_INVALID, "null argument");
+    if (!h->server) {
+        *out = tsvd_serve_stats{};
+        return;
+    }
+    std::lock_guard<std::mutex> lk(h->server->mu);
+    *out = h->server->stats;
+}
+
+void serve_shutdown(tsvd_handle h) {
+    if (!h || !h->server) return;
+    h->server->shutdown();
+    delete h->server;
+    h->server = nullptr;
+}
+
+}  // namespace tsvd

@@ -1,0 +1,233 @@
+// One-sided Jacobi SVD with one workgroup per Fourier slice, for batches of
+// many problems (same rotation, block round-robin ordering and stopping
+// rule as jacobi.hip and jacobi_persist.hip).
+//
+// A batch of uneven problems has thousands of slices, many more than the
+// chip has CUs, so every slice gets a single workgroup and no workgroup
+// ever waits for another.  The workgroup runs all sweeps of its slice: in
+// every round of the block tournament it visits the round's nb/2 block
+// pairs one after the other, each time loading the two blocks (stacked
+// columns: m slice rows, then n rows of V) from global memory into LDS,
+// orthogonalising them against each other (and, in the first round of a
+// sweep, internally) and writing them back.  With nb = 2 the two blocks stay
+// in LDS for the whole SVD.  The slice stops after a sweep that rotated
+// nothing, or after max_sweeps.
+//
+// Work split as in jacobi_persist.hip: a column pair per group of PG = 32
+// lanes, BW pairs per step (BW = 4, 8 or 16 columns per block: the block
+// width is chosen per problem so that two blocks of its stacked height fit
+// in LDS), rotation parameters in FP64, norms exact at the start of a round
+// and tracked through it.
+//
+// Launch: a table of problems; workgroup b serves problem p when
+// wg_start[p] <= b < wg_start[p + 1], slice b - wg_start[p].  A problem
+// whose ADMM has stopped (ctrl->done) is skipped; each slice raises
+// ctrl->sweep_max to its sweep count.
+
+#include "jacobi_common.h"
+
+namespace tsvd {
+
+namespace {
+
+using namespace jac;
+
+constexpr int kPGs = 32;
+
+template <typename T, int BW, int RPT>
+__global__ __launch_bounds__(BW * kPGs) void jacobi_slice_kernel(const JacSliceArgs<T>* tab, const int* wg_start,
+                                                                  int nprob, int max_sweeps) {
+    constexpr int PG = kPGs, NT = BW * PG;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int rot_any;
+    __shared__ double jnorm[BW];
+    const int p = batch_find(wg_start, nprob, (int)blockIdx.x);
+    const JacSliceArgs<T>& a = tab[p];
+    if (a.ctrl && a.ctrl->done) return;
+    const int s = (int)blockIdx.x - wg_start[p];
+    const int m = a.m, n = a.n, nb = a.nb, G = nb / 2;
+    cplx<T>* const A = a.A + (int64_t)s * n * m;
+    cplx<T>* const V = a.V + (int64_t)s * n * n;
+    const int ka = (m + PG - 1) / PG;
+    const int mp = ka * PG;
+    const int ldc = PG * RPT + 1;
+    cplx<T>* const blk0 = reinterpret_cast<cplx<T>*>(smem);
+    cplx<T>* const blk1 = blk0 + (size_t)BW * ldc;
+    const int g = threadIdx.x / PG, l = threadIdx.x - g * PG;
+    const double tol = (double)a.tol;
+
+    for (int idx = threadIdx.x; idx < 2 * BW * ldc; idx += NT) blk0[idx] = cplx<T>{(T)0, (T)0};
+    __syncthreads();
+    if (G == 1) {
+        load_block<T, NT, BW>(A, V, m, n, nb, 0, mp, ldc, blk0);
+        load_block<T, NT, BW>(A, V, m, n, nb, 1, mp, ldc, blk1);
+    }
+
+    unsigned nrot = 0;
+    int sweeps = 0;
+    const int msw = a.max_sweeps > 0 ? a.max_sweeps : max_sweeps;
+    for (int sweep = 0; sweep < msw; ++sweep) {
+        if (threadIdx.x == 0) rot_any = 0;
+        unsigned nrot_sweep = 0;
+        for (int rd = 0; rd < nb - 1; ++rd) {
+            for (int gp = 0; gp < G; ++gp) {
+                const int player0 = ppos_player(gp, rd, nb), player1 = ppos_player(nb - 1 - gp, rd, nb);
+                if (G > 1) {
+                    __syncthreads();
+                    load_block<T, NT, BW>(A, V, m, n, nb, player0, mp, ldc, blk0);
+                    load_block<T, NT, BW>(A, V, m, n, nb, player1, mp, ldc, blk1);
+                }
+                __syncthreads();
+                const int wi = pblk_start(player0 + 1, n, nb) - pblk_start(player0, n, nb);
+                const int wj = pblk_start(player1 + 1, n, nb) - pblk_start(player1, n, nb);
+                if (rd == 0) {
+                    // internal pairs of both blocks: groups 0..BW/2-1 take block 0, the rest block 1
+                    const bool second = g >= BW / 2;
+                    const int gi = second ? g - BW / 2 : g;
+                    cplx<T>* const base = second ? blk1 : blk0;
+                    const int w = second ? wj : wi;
+                    const int wp = w + (w & 1);
+                    for (int st = 0; st < BW - 1; ++st) {
+                        if (st < wp - 1 && gi < wp / 2) {
+                            const int pp = ppos_player(gi, st, wp);
+                            const int qq = ppos_player(wp - 1 - gi, st, wp);
+                            if (pp < w && qq < w) {
+                                cplx<T>* cp = base + pp * ldc;
+                                cplx<T>* cq = base + qq * ldc;
+                                cplx<T> x[RPT], y[RPT];
+#pragma unroll
+                                for (int k = 0; k < RPT; ++k) {
+                                    x[k] = cp[l + PG * k];
+                                    y[k] = cq[l + PG * k];
+                                }
+                                double al = pnorm2<T, PG, RPT>(x, ka), be = pnorm2<T, PG, RPT>(y, ka);
+                                if (ppair<T, PG, RPT>(x, cq, al, be, ka, l, tol)) {
+                                    ++nrot_sweep;
+#pragma unroll
+                                    for (int k = 0; k < RPT; ++k) cp[l + PG * k] = x[k];
+                                }
+                            }
+                        }
+                        __syncthreads();
+                    }
+                }
+                // cross pairs: column g of block 0 (registers) meets every column of block 1
+                cplx<T> xi[RPT];
+#pragma unroll
+                for (int k = 0; k < RPT; ++k) xi[k] = blk0[g * ldc + l + PG * k];
+                double al = pnorm2<T, PG, RPT>(xi, ka);
+                {
+                    cplx<T> yj[RPT];
+#pragma unroll
+                    for (int k = 0; k < RPT; ++k) yj[k] = blk1[g * ldc + l + PG * k];
+                    const double bj = pnorm2<T, PG, RPT>(yj, ka);
+                    if (l == 0) jnorm[g] = bj;
+                }
+                __syncthreads();
+                for (int st = 0; st < BW; ++st) {
+                    const int jc = (g + st) & (BW - 1);
+                    if (g < wi && jc < wj) {
+                        double be = jnorm[jc];
+                        if (ppair<T, PG, RPT>(xi, blk1 + jc * ldc, al, be, ka, l, tol)) {
+                            ++nrot_sweep;
+                            if (l == 0) jnorm[jc] = be;
+                        }
+                    }
+                    __syncthreads();
+                }
+                if (g < wi) {
+#pragma unroll
+                    for (int k = 0; k < RPT; ++k) blk0[g * ldc + l + PG * k] = xi[k];
+                }
+                if (G > 1) {
+                    __syncthreads();
+                    store_block<T, NT, BW>(A, V, m, n, nb, player0, mp, ldc, blk0);
+                    store_block<T, NT, BW>(A, V, m, n, nb, player1, mp, ldc, blk1);
+                }
+            }
+        }
+        if (nrot_sweep && l == 0) rot_any = 1;
+        __syncthreads();
+        nrot += nrot_sweep;
+        sweeps = sweep + 1;
+        if (!rot_any) break;
+        __syncthreads();
+    }
+    if (G == 1) {
+        __syncthreads();
+        store_block<T, NT, BW>(A, V, m, n, nb, 0, mp, ldc, blk0);
+        store_block<T, NT, BW>(A, V, m, n, nb, 1, mp, ldc, blk1);
+    }
+    if (threadIdx.x == 0) {
+        if (a.sweeps) a.sweeps[s] = sweeps;
+        if (a.ctrl) atomicMax(&a.ctrl->sweep_max, sweeps);
+    }
+    if (l == 0 && nrot && a.rotations) atomicAdd(a.rotations, (unsigned long long)nrot);
+}
+
+template <typename T, int BW, int RPT>
+hipError_t launch_bw_rpt(bool prepare, const JacSliceArgs<T>* tab, const int* wg_start, int nprob, int nwg,
+                         int max_sweeps, hipStream_t st) {
+    auto* fn = jacobi_slice_kernel<T, BW, RPT>;
+    const size_t lds = jacobi_slice_lds(BW, RPT, sizeof(T));
+    if (prepare)
+        return hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)lds);
+    hipLaunchKernelGGL(fn, dim3(nwg), dim3(BW * kPGs), lds, st, tab, wg_start, nprob, max_sweeps);
+    return hipGetLastError();
+}
+
+template <typename T, int BW, int... R>
+hipError_t dispatch_rpt(int rpt, std::integer_sequence<int, R...>, bool prepare, const JacSliceArgs<T>* tab,
+                        const int* wg_start, int nprob, int nwg, int max_sweeps, hipStream_t st) {
+    hipError_t e = hipErrorInvalidValue;
+    ((rpt == R + 2 ? (e = launch_bw_rpt<T, BW, R + 2>(prepare, tab, wg_start, nprob, nwg, max_sweeps, st), 0) : 0),
+     ...);
+    return e;
+}
+
+template <typename T>
+hipError_t dispatch(bool prepare, int bw, int rpt, const JacSliceArgs<T>* tab, const int* wg_start, int nprob,
+                    int nwg, int max_sweeps, hipStream_t st) {
+    if (rpt < 2 || rpt > 20) return hipErrorInvalidValue;
+    auto seq = std::make_integer_sequence<int, 19>{};
+    switch (bw) {
+        case 4: return dispatch_rpt<T, 4>(rpt, seq, prepare, tab, wg_start, nprob, nwg, max_sweeps, st);
+        case 8: return dispatch_rpt<T, 8>(rpt, seq, prepare, tab, wg_start, nprob, nwg, max_sweeps, st);
+        case 16: return dispatch_rpt<T, 16>(rpt, seq, prepare, tab, wg_start, nprob, nwg, max_sweeps, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+int jacobi_slice_rpt(int m, int n) {
+    const int need = (m + kPGs - 1) / kPGs + (n + kPGs - 1) / kPGs;
+    return need < 2 ? 2 : need;
+}
+
+size_t jacobi_slice_lds(int bw, int rpt, int elem_bytes) {
+    return 2 * (size_t)bw * (kPGs * rpt + 1) * 2 * elem_bytes;
+}
+
+int jacobi_slice_max_rpt() { return 20; }
+
+template <typename T>
+hipError_t prepare_jacobi_slice(int bw, int rpt) {
+    return dispatch<T>(true, bw, rpt, nullptr, nullptr, 0, 0, 0, nullptr);
+}
+
+template <typename T>
+hipError_t launch_jacobi_slice(int bw, int rpt, const JacSliceArgs<T>* tab, const int* wg_start, int nprob,
+                               int nwg, int max_sweeps, hipStream_t st) {
+    return dispatch<T>(false, bw, rpt, tab, wg_start, nprob, nwg, max_sweeps, st);
+}
+
+template hipError_t prepare_jacobi_slice<double>(int, int);
+template hipError_t prepare_jacobi_slice<float>(int, int);
+template hipError_t launch_jacobi_slice<double>(int, int, const JacSliceArgs<double>*, const int*, int, int, int,
+                                                hipStream_t);
+template hipError_t launch_jacobi_slice<float>(int, int, const JacSliceArgs<float>*, const int*, int, int, int,
+                                               hipStream_t);
+
+}  // namespace tsvd

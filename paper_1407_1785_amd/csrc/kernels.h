@@ -3,7 +3,20 @@
 
 #include "common.h"
 
+#include <utility>
+
 namespace tsvd {
+
+// Problem-table launches: workgroup b serves problem p when
+// wg_start[p] <= b < wg_start[p + 1] (nprob + 1 ascending entries).
+__device__ __forceinline__ int batch_find(const int* wg_start, int nprob, int b) {
+    int lo = 0, hi = nprob - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (wg_start[mid] <= b) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
 
 // Fused prologues of the forward DFT: what tensor is transformed.
 enum Prologue : int {
@@ -33,6 +46,7 @@ struct FwdArgs {
     int* nonfinite;          // set to 1 if a transformed value is not finite
     Geometry g;
     int tile;                // tubes per workgroup
+    int pro;                 // prologue (problem-table launches)
 };
 
 template <typename T>
@@ -55,6 +69,7 @@ struct InvArgs {
     T* s_new;
     const T* l_old;
     double* partials;        // kNumPartials per workgroup
+    int epi;                 // epilogue (problem-table launches)
 };
 
 template <typename T>
@@ -89,14 +104,51 @@ struct ZGemmArgs {
     T alpha, beta;
     const double* sigma;   // optional, K per slice, stride ssig
     int64_t ssig;
-    const Ctrl* ctrl;
+    const Ctrl* ctrl;      // tau (with sigma); problem-table launches skip the problem once done
     int bf16x3;            // float only: 1 = bf16 split products, 0 = FP32 products
 };
 
 template <typename T>
 void launch_zgemm(const ZGemmArgs<T>& g, hipStream_t st);
+int zgemm_workgroups(int M, int N, int batch);
+template <typename T>
+void launch_zgemm_batched(const ZGemmArgs<T>* tab, const int* wg_start, int nprob, int nwg, hipStream_t st);
 void launch_multirank(const double* sigma, int64_t ssig, int K, int h, const Ctrl* ctrl, int* rank,
                       hipStream_t st);
+// One problem of a one-workgroup-per-slice Jacobi launch (jacobi_slice.hip).
+template <typename T>
+struct JacSliceArgs {
+    cplx<T>* A;          // h slices m x n, overwritten by W = A V
+    cplx<T>* V;          // h slices n x n (rotated in place; start value is the caller's)
+    int m, n, h, nb;     // nb: column blocks of width <= the launch's block width (even)
+    T tol;
+    int* sweeps;         // optional: sweeps run per slice
+    Ctrl* ctrl;          // optional: skip the problem once ctrl->done; sweep_max is raised
+    unsigned long long* rotations;  // optional running count
+    int max_sweeps;      // sweep cap (0: the launch's)
+};
+int jacobi_slice_rpt(int m, int n);
+size_t jacobi_slice_lds(int bw, int rpt, int elem_bytes);
+int jacobi_slice_max_rpt();
+// Sets the kernel's LDS limit; call once per (bw, rpt) before launches
+// (and before any stream capture).
+template <typename T>
+hipError_t prepare_jacobi_slice(int bw, int rpt);
+template <typename T>
+hipError_t launch_jacobi_slice(int bw, int rpt, const JacSliceArgs<T>* tab, const int* wg_start, int nprob,
+                               int nwg, int max_sweeps, hipStream_t st);
+
+template <typename T>
+struct SigmaArgs {
+    const cplx<T>* W;
+    int m, n, h;
+    double* sigma;
+    const Ctrl* ctrl;   // skip the problem once done
+};
+int svt_sigma_workgroups(int n, int h);
+template <typename T>
+void launch_svt_sigma_batched(const SigmaArgs<T>* tab, const int* wg_start, int nprob, int nwg, hipStream_t st);
+
 template <typename T>
 void launch_svt_sigma(const cplx<T>* W, int m, int n, int h, double* sigma, hipStream_t st);
 
@@ -104,6 +156,20 @@ template <typename T>
 void launch_dft_forward(int prologue, const FwdArgs<T>& a, hipStream_t st);
 template <typename T>
 void launch_dft_inverse(int epilogue, const InvArgs<T>& a, hipStream_t st);
+template <typename T>
+size_t dft_forward_lds(const Geometry& g, int tile);
+template <typename T>
+size_t dft_inverse_lds(const Geometry& g, int tile, int epilogue);
+// Raises the LDS limit of the problem-table DFT kernels when needed
+// (call outside stream capture).
+template <typename T>
+void prepare_dft_batched(size_t lds_forward, size_t lds_inverse);
+template <typename T>
+void launch_dft_forward_batched(const FwdArgs<T>* tab, const int* wg_start, int nprob, int nwg, size_t lds,
+                                hipStream_t st);
+template <typename T>
+void launch_dft_inverse_batched(const InvArgs<T>* tab, const int* wg_start, int nprob, int nwg, size_t lds,
+                                hipStream_t st);
 int dft_forward_tile(const Geometry& g);
 int dft_inverse_tile(const Geometry& g, int epilogue);
 int64_t dft_grid(const Geometry& g, int tile);
@@ -134,6 +200,12 @@ bool jacobi_persistent_fits(int m, int n, int h, int elem_bytes, int cus, size_t
 template <typename T>
 hipError_t launch_jacobi_persistent(const JacArgs<T>& a, const PersistArgs& p, int cus, hipStream_t st);
 
+struct CtrlArgs {
+    Ctrl* c;
+    const double* partials;
+    int nparts, rpca;
+};
+void launch_admm_ctrl_batched(const CtrlArgs* tab, int nprob, hipStream_t st);
 void launch_admm_ctrl(Ctrl* c, const double* partials, int nparts, int rpca, hipStream_t st);
 template <typename T>
 void launch_sumsq(const T* x, const uint8_t* mask, int64_t n, double* partials, int nparts,
@@ -144,5 +216,9 @@ void launch_complete_output(const T* y, const uint8_t* mask, const T* z, const T
                             const Ctrl* c, T* out, int64_t n, hipStream_t st);
 template <typename T>
 void launch_fill(T* p, T v, int64_t n, hipStream_t st);
+template <typename T>
+void launch_fill_hash(cplx<T>* p, int64_t n, uint32_t seed, hipStream_t st);
+template <typename T>
+void launch_set_identity(cplx<T>* v, int n, int h, hipStream_t st);
 
 }  // namespace tsvd

@@ -15,10 +15,9 @@
 namespace tsvd {
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void svt_sigma_kernel(const cplx<T>* W, int m, int n, int64_t cols,
-                                                          double* sigma) {
+__device__ __forceinline__ void svt_sigma_body(const cplx<T>* W, int m, int n, int64_t cols, double* sigma, int bid) {
     const int lane = threadIdx.x & 63;
-    const int64_t c = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const int64_t c = (int64_t)bid * (kBlock / 64) + (threadIdx.x >> 6);
     if (c >= cols) return;
     const int64_t s = c / n, j = c - s * n;
     const cplx<T>* w = W + (s * n + j) * (int64_t)m;
@@ -30,6 +29,31 @@ __global__ __launch_bounds__(kBlock) void svt_sigma_kernel(const cplx<T>* W, int
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
     if (lane == 0) sigma[c] = sqrt(acc);
 }
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void svt_sigma_kernel(const cplx<T>* W, int m, int n, int64_t cols,
+                                                          double* sigma) {
+    svt_sigma_body<T>(W, m, n, cols, sigma, (int)blockIdx.x);
+}
+
+// Problem-table launch; a problem whose ADMM has stopped is skipped.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void svt_sigma_batched(const SigmaArgs<T>* tab, const int* wg_start, int nprob) {
+    const int p = batch_find(wg_start, nprob, (int)blockIdx.x);
+    const SigmaArgs<T>& a = tab[p];
+    if (a.ctrl && a.ctrl->done) return;
+    svt_sigma_body<T>(a.W, a.m, a.n, (int64_t)a.h * a.n, a.sigma, (int)blockIdx.x - wg_start[p]);
+}
+
+int svt_sigma_workgroups(int n, int h) { return (int)(((int64_t)h * n + kBlock / 64 - 1) / (kBlock / 64)); }
+
+template <typename T>
+void launch_svt_sigma_batched(const SigmaArgs<T>* tab, const int* wg_start, int nprob, int nwg, hipStream_t st) {
+    hipLaunchKernelGGL((svt_sigma_batched<T>), dim3(nwg), dim3(kBlock), 0, st, tab, wg_start, nprob);
+}
+
+template void launch_svt_sigma_batched<double>(const SigmaArgs<double>*, const int*, int, int, hipStream_t);
+template void launch_svt_sigma_batched<float>(const SigmaArgs<float>*, const int*, int, int, hipStream_t);
 
 template <typename T>
 void launch_svt_sigma(const cplx<T>* W, int m, int n, int h, double* sigma, hipStream_t st) {

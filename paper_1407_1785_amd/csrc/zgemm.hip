@@ -26,8 +26,9 @@
 //
 // Tiling: one 256-thread workgroup per 64 x 64 tile of C; wave w owns the
 // 32 x 32 quadrant (w & 1, w >> 1), i.e. 2 x 2 MFMA tiles of 16 x 16.  K is
-// staged through LDS in chunks (16 for FP64, 32 for the bf16 split), with
-// the real and imaginary parts in separate arrays.  The MFMA operands are
+// staged through LDS in chunks of 32, with the real and imaginary parts in
+// separate arrays; the next chunk is loaded into registers while the
+// current one is multiplied.  The MFMA operands are
 // given as (op(B) fragment, op(A) fragment), so the accumulator holds C
 // transposed: lane l owns 4 columns at row l % 16 of a 16 x 16 tile, and the
 // 16 lanes of a row group store 16 consecutive rows of a column-major C in
@@ -67,7 +68,8 @@ __device__ __forceinline__ double shrink_factor(const double* sigma, int k, int 
 
 // ---- K = 4 per MFMA (FP64, or exact FP32), stage [k][r] -----------------
 
-constexpr int KC4 = 16, PAD4 = 1;
+constexpr int KC4 = 32, PAD4 = 1;
+constexpr int LD4 = TM * KC4 / 256;   // staged elements per thread and operand
 
 template <typename T>
 struct Stage4 {
@@ -75,30 +77,44 @@ struct Stage4 {
     T br[KC4][TN + PAD4], bi[KC4][TN + PAD4];
 };
 
-// Stage a 64 x KC4 block of an operand view into re/im[k][r].
-template <typename T>
-__device__ __forceinline__ void stage4(const cplx<T>* X, int ld, bool kcontig, bool conj, int r0, int k0, int R,
-                                       int K, T (*re)[TM + PAD4], T (*im)[TM + PAD4], const double* sigma,
-                                       double tau) {
+// Element q of this thread's share of a 64 x KC4 block of an operand view.
+__device__ __forceinline__ void slot4(bool kcontig, int q, int& rr, int& kk) {
     const int t = threadIdx.x;
+    if (kcontig) {
+        kk = t % KC4;
+        rr = t / KC4 + (256 / KC4) * q;
+    } else {
+        rr = t % TM;
+        kk = t / TM + 4 * q;
+    }
+}
+
+// Load this thread's share of a 64 x KC4 block (scaled by d_k when sigma is set).
+template <typename T>
+__device__ __forceinline__ void load4(const cplx<T>* X, int ld, bool kcontig, bool conj, int r0, int k0, int R,
+                                      int K, const double* sigma, double tau, cplx<T> (&v)[LD4]) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < LD4; ++q) {
         int rr, kk;
-        if (kcontig) {
-            kk = t % KC4;
-            rr = t / KC4 + 16 * q;
-        } else {
-            rr = t % TM;
-            kk = t / TM + 4 * q;
-        }
-        cplx<T> v = view_elem(X, ld, kcontig, conj, r0 + rr, k0 + kk, R, K);
+        slot4(kcontig, q, rr, kk);
+        v[q] = view_elem(X, ld, kcontig, conj, r0 + rr, k0 + kk, R, K);
         if (sigma) {
             const T dk = (T)shrink_factor(sigma, k0 + kk, K, tau);
-            v.re *= dk;
-            v.im *= dk;
+            v[q].re *= dk;
+            v[q].im *= dk;
         }
-        re[kk][rr] = v.re;
-        im[kk][rr] = v.im;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void store4(bool kcontig, const cplx<T> (&v)[LD4], T (*re)[TM + PAD4],
+                                       T (*im)[TM + PAD4]) {
+#pragma unroll
+    for (int q = 0; q < LD4; ++q) {
+        int rr, kk;
+        slot4(kcontig, q, rr, kk);
+        re[kk][rr] = v[q].re;
+        im[kk][rr] = v[q].im;
     }
 }
 
@@ -127,12 +143,11 @@ struct Mfma4<float> {
 };
 
 template <typename T>
-__global__ __launch_bounds__(256) void zgemm_k4_kernel(ZGemmArgs<T> g) {
+__device__ __forceinline__ void zgemm_k4_body(const ZGemmArgs<T>& g, int bx, int by, int s) {
     typedef Mfma4<T> M;
     typedef typename M::acc_t acc_t;
     __shared__ Stage4<T> sm;
-    const int s = blockIdx.z;
-    const int row0 = blockIdx.x * TM, col0 = blockIdx.y * TN;
+    const int row0 = bx * TM, col0 = by * TN;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
     const cplx<T>* A = g.A + (int64_t)s * g.sA;
@@ -146,12 +161,20 @@ __global__ __launch_bounds__(256) void zgemm_k4_kernel(ZGemmArgs<T> g) {
 #pragma unroll
         for (int b = 0; b < 2; ++b) cr[a][b] = ci[a][b] = acc_t{(T)0, (T)0, (T)0, (T)0};
 
+    // op(A): rows M, op N -> stored M x K (r-contiguous); op H -> stored K x M, conj.
+    // op(B)^T as an N x K view: op N -> B stored K x N (k-contiguous); op H -> stored N x K, conj.
+    const bool akc = g.opA != 0, bkc = g.opB == 0;
+    cplx<T> va[LD4], vb[LD4];
+    load4<T>(A, g.lda, akc, g.opA != 0, row0, 0, g.M, g.K, sigma, tau, va);
+    load4<T>(B, g.ldb, bkc, g.opB != 0, col0, 0, g.N, g.K, nullptr, 0.0, vb);
     for (int k0 = 0; k0 < g.K; k0 += KC4) {
-        // op(A): rows M, op N -> stored M x K (r-contiguous); op H -> stored K x M, conj
-        stage4<T>(A, g.lda, g.opA != 0, g.opA != 0, row0, k0, g.M, g.K, sm.ar, sm.ai, sigma, tau);
-        // op(B)^T as an N x K view: op N -> B stored K x N (k-contiguous); op H -> stored N x K, conj
-        stage4<T>(B, g.ldb, g.opB == 0, g.opB != 0, col0, k0, g.N, g.K, sm.br, sm.bi, nullptr, 0.0);
+        store4<T>(akc, va, sm.ar, sm.ai);
+        store4<T>(bkc, vb, sm.br, sm.bi);
         __syncthreads();
+        if (k0 + KC4 < g.K) {   // prefetch the next chunk while this one is multiplied
+            load4<T>(A, g.lda, akc, g.opA != 0, row0, k0 + KC4, g.M, g.K, sigma, tau, va);
+            load4<T>(B, g.ldb, bkc, g.opB != 0, col0, k0 + KC4, g.N, g.K, nullptr, 0.0, vb);
+        }
 #pragma unroll
         for (int kk = 0; kk < KC4; kk += 4) {
             const int kq = kk + (lane >> 4), c16 = lane & 15;
@@ -254,10 +277,9 @@ __device__ __forceinline__ v8bf neg8(v8bf x) {
 
 #define MFMA_BF16(acc, x, y) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16((x), (y), (acc), 0, 0, 0)
 
-__global__ __launch_bounds__(256) void zgemm_bf16x3_kernel(ZGemmArgs<float> g) {
+__device__ __forceinline__ void zgemm_bf16x3_body(const ZGemmArgs<float>& g, int bx, int by, int s) {
     __shared__ Stage16 sm;
-    const int s = blockIdx.z;
-    const int row0 = blockIdx.x * TM, col0 = blockIdx.y * TN;
+    const int row0 = bx * TM, col0 = by * TN;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
     const cplx<float>* A = g.A + (int64_t)s * g.sA;
@@ -335,6 +357,36 @@ __global__ __launch_bounds__(256) void zgemm_bf16x3_kernel(ZGemmArgs<float> g) {
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void zgemm_k4_kernel(ZGemmArgs<T> g) {
+    zgemm_k4_body<T>(g, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+__global__ __launch_bounds__(256) void zgemm_bf16x3_kernel(ZGemmArgs<float> g) {
+    zgemm_bf16x3_body(g, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// Problem-table launch: problem p owns tiles_m * tiles_n * batch workgroups;
+// a problem whose ADMM has stopped (ctrl->done) is skipped.
+template <typename T>
+__global__ __launch_bounds__(256) void zgemm_batched_kernel(const ZGemmArgs<T>* tab, const int* wg_start,
+                                                            int nprob) {
+    const int p = batch_find(wg_start, nprob, (int)blockIdx.x);
+    const ZGemmArgs<T>& g = tab[p];
+    if (g.ctrl && g.ctrl->done) return;
+    const int local = (int)blockIdx.x - wg_start[p];
+    const int tm = (g.M + TM - 1) / TM, tn = (g.N + TN - 1) / TN;
+    const int s = local / (tm * tn), rem = local - s * (tm * tn);
+    const int by = rem / tm, bx = rem - by * tm;
+    if constexpr (sizeof(T) == 4) {
+        if (g.bf16x3) {
+            zgemm_bf16x3_body(g, bx, by, s);
+            return;
+        }
+    }
+    zgemm_k4_body<T>(g, bx, by, s);
+}
+
 // The multi-rank (Sec. 2.4): rank[s] = #{k < K : sigma_k > tau}, one
 // workgroup per slice.
 __global__ __launch_bounds__(256) void multirank_kernel(const double* sigma, int64_t ssig, int K, const Ctrl* ctrl,
@@ -368,6 +420,16 @@ void launch_zgemm<float>(const ZGemmArgs<float>& g, hipStream_t st) {
     else
         hipLaunchKernelGGL(zgemm_k4_kernel<float>, grid, dim3(256), 0, st, g);
 }
+
+int zgemm_workgroups(int M, int N, int batch) { return ((M + TM - 1) / TM) * ((N + TN - 1) / TN) * batch; }
+
+template <typename T>
+void launch_zgemm_batched(const ZGemmArgs<T>* tab, const int* wg_start, int nprob, int nwg, hipStream_t st) {
+    hipLaunchKernelGGL((zgemm_batched_kernel<T>), dim3(nwg), dim3(256), 0, st, tab, wg_start, nprob);
+}
+
+template void launch_zgemm_batched<double>(const ZGemmArgs<double>*, const int*, int, int, hipStream_t);
+template void launch_zgemm_batched<float>(const ZGemmArgs<float>*, const int*, int, int, hipStream_t);
 
 void launch_multirank(const double* sigma, int64_t ssig, int K, int h, const Ctrl* ctrl, int* rank,
                       hipStream_t st) {

@@ -29,7 +29,8 @@ def declared_functions():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for fn in ("tsvt", "tsvd_complete", "trpca", "tsvd_create", "tsvd_destroy", "tsvd_set_stream",
-               "tsvd_status_string", "tsvd_last_error"):
+               "tsvd_status_string", "tsvd_last_error", "tsvd_batch_run", "tsvd_submit", "tsvd_poll",
+               "tsvd_serve_stats_read"):
         assert fn in names
 
 
@@ -64,6 +65,29 @@ def test_struct_layouts_match_c(tmp_path):
     want = [ctypes.sizeof(lib.Shape), ctypes.sizeof(lib.AdmmOpts), ctypes.sizeof(lib.Info),
             lib.Shape.n.offset, lib.Info.primal.offset, lib.AdmmOpts.max_sweeps.offset]
     assert got == want
+
+
+def test_batch_struct_layouts_match_c(tmp_path):
+    src = tmp_path / "layout2.c"
+    src.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "tsvd.h"\n'
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(tsvd_problem),"
+        " offsetof(tsvd_problem, shape), offsetof(tsvd_problem, x), offsetof(tsvd_problem, penalty),"
+        " offsetof(tsvd_problem, opts), offsetof(tsvd_problem, out_s), sizeof(tsvd_serve_stats),"
+        " offsetof(tsvd_serve_stats, peak_running));return 0;}\n")
+    exe = tmp_path / "layout2"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = list(map(int, subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()))
+    P = lib.ProblemRecord
+    want = [ctypes.sizeof(P), P.shape.offset, P.x.offset, P.penalty.offset, P.opts.offset, P.out_s.offset,
+            ctypes.sizeof(lib.ServeStats), lib.ServeStats.peak_running.offset]
+    assert got == want
+
+
+def test_busy_status_string():
+    if not os.path.exists(lib.library_path()):
+        pytest.skip("libtsvd.so not built")
+    assert lib.load_library().tsvd_status_string(-7) == b"not finished"
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):

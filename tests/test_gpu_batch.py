@@ -1,0 +1,180 @@
+"""Batched form (tsvd_batch_run): completion and tensor-RPCA problems of
+uneven shapes solved together with problem-table launches, against the FP64
+oracle and against the single-problem calls; HIP-graph replay against eager
+launches."""
+
+import os
+
+import numpy as np
+import pytest
+
+import paper_1407_1785_amd as lib
+from oracle import admm
+import workloads
+from tests.gpu_util import announce, rel_fro, to_gpu, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+ITERS = 12
+FP64_BAR = 1e-10
+FP32_BAR = 1e-4
+
+
+def _completion(shape, seed, p=0.5, rank=2):
+    rng = np.random.default_rng(seed)
+    if len(shape) == 3:
+        _, _, x = workloads.lowrank(rng, *shape, rank)
+    else:
+        x = rng.normal(size=shape)
+    mask = (rng.random(shape) < p).astype(np.uint8)
+    return x * mask, mask
+
+
+def _cases():
+    """(name, kind, data, mask, dtype, extra) -- shapes cover one and several
+    Jacobi blocks, n1 < n2, 4-D, n3 = 1, two columns, odd and even tubes."""
+    out = []
+    for name, shape in [("c32", (32, 32, 16)), ("c_ragged", (24, 17, 9)), ("c_trans", (13, 40, 6)),
+                        ("c_4d", (15, 26, 4, 3)), ("c_blocks", (70, 45, 5)), ("c_matrix", (30, 20, 1)),
+                        ("c_two_cols", (8, 2, 5))]:
+        y, m = _completion(shape, len(out) + 3)
+        out.append((name, "complete", y, m, np.float64, {}))
+    y, m = _completion((40, 50, 12), 99)
+    out.append(("c_fp32", "complete", y.astype(np.float32), m, np.float32, {}))
+    r = workloads.trpca_problem(0, shape=(20, 24, 10), rank=2)
+    out.append(("r_l1", "trpca", r["M"], None, np.float64, dict(lam=r["lam"], shrink="l1")))
+    t = workloads.tube_corruption(0, shape=(20, 24, 10), rank=2)
+    out.append(("r_l112", "trpca", t["M"], None, np.float64, dict(lam=t["lam"], shrink="l112")))
+    return out
+
+
+def _problem(torch, case, iters=ITERS, tol=0.0):
+    name, kind, x, mask, dt, extra = case
+    tdt = torch.float32 if dt == np.float32 else torch.float64
+    xg = to_gpu(torch, x, tdt)
+    if kind == "complete":
+        return lib.complete_problem(xg, to_gpu(torch, mask), rho=1e-2, tol=tol, max_iter=iters)
+    shrink = lib.SHRINK_L1 if extra["shrink"] == "l1" else lib.SHRINK_L112
+    return lib.trpca_problem(xg, extra["lam"], mu=1e-3, tol=tol, shrink=shrink, max_iter=iters)
+
+
+def _oracle(case, iters=ITERS):
+    name, kind, x, mask, dt, extra = case
+    x64 = np.asarray(x, dtype=np.float64)
+    if kind == "complete":
+        return [admm.complete(x64, mask, 1e-2, 1.1, 1e3, max_iter=iters, tol=0.0)["X"]]
+    r = admm.trpca(x64, extra["lam"], 1e-3, 1.2, 1e10, max_iter=iters, tol=0.0, shrink=extra["shrink"])
+    return [r["L"], r["S"]]
+
+
+def _outputs(p):
+    return [p.out.cpu().numpy()] + ([p.out_s.cpu().numpy()] if p.out_s is not None else [])
+
+
+@pytest.fixture(scope="module")
+def batch_result():
+    torch = torch_cuda()
+    cases = _cases()
+    probs = [_problem(torch, c) for c in cases]
+    announce("batch run", len(probs), "problems")
+    res = lib.batch_run(probs)
+    return cases, probs, res
+
+
+def test_batch_matches_oracle(batch_result):
+    cases, probs, res = batch_result
+    for case, p, (st, info) in zip(cases, probs, res):
+        assert st == 0, case[0]
+        assert info.iters == ITERS and info.converged == 0, case[0]
+        assert info.sweeps_total >= ITERS and info.sweeps_last >= 1, case[0]
+        bar = FP32_BAR if case[4] == np.float32 else FP64_BAR
+        for got, want in zip(_outputs(p), _oracle(case)):
+            err = rel_fro(got, want)
+            assert err <= bar, (case[0], err)
+
+
+def test_batch_matches_single_calls(batch_result):
+    torch = torch_cuda()
+    cases, probs, res = batch_result
+    for case, p in zip(cases, probs):
+        name, kind, x, mask, dt, extra = case
+        tdt = torch.float32 if dt == np.float32 else torch.float64
+        xg = to_gpu(torch, x, tdt)
+        prec = lib.PREC_FP32 if dt == np.float32 else lib.PREC_FP64
+        announce("single call", name)
+        if kind == "complete":
+            xs, _ = lib.tsvd_complete(xg, to_gpu(torch, mask), 1e-2, 0.0, max_iter=ITERS, precision=prec)
+            single = [xs.cpu().numpy()]
+        else:
+            shrink = lib.SHRINK_L1 if extra["shrink"] == "l1" else lib.SHRINK_L112
+            L, S, _ = lib.trpca(xg, extra["lam"], 1e-3, 0.0, shrink=shrink, max_iter=ITERS, precision=prec)
+            single = [L.cpu().numpy(), S.cpu().numpy()]
+        bar = 1e-5 if dt == np.float32 else 1e-12
+        for got, want in zip(_outputs(p), single):
+            assert rel_fro(got, want) <= bar, name
+
+
+def test_observed_entries_kept_exactly(batch_result):
+    cases, probs, res = batch_result
+    for case, p in zip(cases, probs):
+        if case[1] != "complete":
+            continue
+        omega = case[3].astype(bool)
+        got = p.out.cpu().numpy()
+        np.testing.assert_array_equal(got[omega], np.asarray(case[2])[omega])
+
+
+def test_graph_replay_equals_eager():
+    """Every replay of the captured two-iteration period must give the eager
+    result bit for bit (20 iterations = 10 replays, with host reads of the
+    control blocks between them)."""
+    torch = torch_cuda()
+    cases = _cases()[:5] + _cases()[-2:]
+    outs = {}
+    for mode in ("1", "0"):
+        os.environ["TSVD_GRAPH"] = mode
+        try:
+            probs = [_problem(torch, c, iters=20) for c in cases]
+            announce("graph mode", mode)
+            res = lib.batch_run(probs)
+        finally:
+            os.environ.pop("TSVD_GRAPH", None)
+        assert all(st == 0 for st, _ in res)
+        outs[mode] = [_outputs(p) for p in probs]
+    for a, b in zip(outs["1"], outs["0"]):
+        for x, y in zip(a, b):
+            np.testing.assert_array_equal(x, y)
+
+
+def test_problems_stop_at_their_own_iteration():
+    """With tol > 0 problems converge at different iterations; each stops
+    where its single call stops and keeps its output from then on."""
+    torch = torch_cuda()
+    w = workloads.completion_small(0)
+    cases = [("c_small", "complete", w["M_obs"], w["mask"], np.float64, {})] + _cases()[1:4]
+    probs = [_problem(torch, c, iters=300, tol=1e-6) for c in cases]
+    announce("batch convergence")
+    res = lib.batch_run(probs)
+    for case, p, (st, info) in zip(cases, probs, res):
+        name, kind, x, mask, dt, extra = case
+        xs, si = lib.tsvd_complete(to_gpu(torch, x), to_gpu(torch, mask), 1e-2, 1e-6, max_iter=300)
+        assert st == 0
+        assert info.converged == si.converged, name
+        assert abs(info.iters - si.iters) <= 1, (name, info.iters, si.iters)
+        if info.iters == si.iters:
+            assert rel_fro(p.out.cpu().numpy(), xs.cpu().numpy()) <= 1e-10, name
+
+
+def test_batch_rejects_bad_records():
+    torch = torch_cuda()
+    y, m = _completion((10, 10, 4), 1)
+    p = lib.complete_problem(to_gpu(torch, y), to_gpu(torch, m))
+    p.record.penalty = -1.0
+    with pytest.raises(lib.TsvdError) as e:
+        lib.batch_run([p])
+    assert e.value.status == -1
+    q = lib.complete_problem(to_gpu(torch, y), to_gpu(torch, m))
+    q.record.shape.ndim = 5
+    with pytest.raises(lib.TsvdError) as e:
+        lib.batch_run([q])
+    assert e.value.status == -2
