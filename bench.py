@@ -80,6 +80,112 @@ def roofline(stats: dict, steps: int, fp32: bool):
     return out
 
 
+def batched_leg(lib, torch, np, workloads, iters: int):
+    """64 uneven completion problems (n1, n2 ~ U{48..320}, n3 ~ U{8..128},
+    tubal rank ~ U{2..10}, Bernoulli(p ~ U[0.2, 0.6]) masks), FP32 form, a
+    fixed number of iterations each, solved together by tsvd_batch_run.
+    A short run over the same problems first lets the block-width tuner see
+    every shape class (its choices are cached for the process)."""
+    from oracle import admm
+
+    specs = workloads.batch_specs(0)
+    probs, data = [], []
+    for i, sp in enumerate(specs):
+        b = workloads.batch_problem(sp, i, iters=iters)
+        y = torch.from_numpy(b["M_obs"].astype(np.float32)).cuda()
+        m = torch.from_numpy(b["mask"]).cuda()
+        probs.append(lib.complete_problem(y, m, rho=b["rho"], tol=0.0, growth=b["growth"],
+                                          rho_max=b["rho_max"], max_iter=iters))
+        data.append(b)
+    print("[bench] batched leg: problems staged, tuning run", file=sys.stderr, flush=True)
+    lib.batch_run([lib.complete_problem(p.x, p.mask, 1e-2, 0.0, max_iter=2) for p in probs])
+    torch.cuda.synchronize()
+    print("[bench] batched leg: timed run", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    res = lib.batch_run(probs)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    elems = sum(int(np.prod(d["M_obs"].shape)) for d in data)
+    slices = sum(sp["n3"] // 2 + 1 for sp in specs)
+    out = {"workload": "64 uneven completion problems, n1,n2~U{48..320}, n3~U{8..128}, rank~U{2..10}, "
+                       "p~U[0.2,0.6], FP32 form", "problems": len(probs), "iters_per_solve": iters,
+           "elements": elems, "slices": slices, "seconds": dt, "solves_per_s": len(probs) / dt,
+           "iters_per_s": len(probs) * iters / dt,
+           "statuses_ok": all(st == 0 for st, _ in res),
+           "sweeps_per_iter_mean": float(np.mean([i.sweeps_total / max(1, i.iters) for _, i in res]))}
+    # checks: the observed entries are kept exactly; the smallest problem
+    # against the FP64 oracle at the same iteration count
+    out["observed_kept_exactly"] = all(
+        bool(np.array_equal(p.out.cpu().numpy()[d["mask"].astype(bool)],
+                            d["M_obs"].astype(np.float32)[d["mask"].astype(bool)])) for p, d in zip(probs, data))
+    k = int(np.argmin([d["M_obs"].size for d in data]))
+    ref = admm.complete(data[k]["M_obs"], data[k]["mask"], data[k]["rho"], data[k]["growth"],
+                        data[k]["rho_max"], max_iter=iters, tol=0.0)
+    got = probs[k].out.cpu().numpy().astype(np.float64)
+    out["sampled_rse_vs_oracle"] = float(np.linalg.norm(got - ref["X"]) / np.linalg.norm(ref["X"]))
+    out["sampled_shape"] = list(data[k]["M_obs"].shape)
+    return out
+
+
+def serving_leg(lib, torch, np, workloads, rate: float, window: float, budget_gb: float):
+    """The serving mix: Poisson arrivals at `rate` per second during `window`
+    seconds (70% completion / 30% tensor RPCA, 10% 4-D colour video, other
+    shapes as in the batched workload; FP32 form; at most 150 iterations,
+    tol 1e-7).  Every request is submitted at its arrival time to the
+    handle's serving worker; latency = completion - arrival."""
+    reqs = workloads.arrivals(0, rate, window)
+    staged = []
+    for r in reqs:
+        d = workloads.serve_request(r)
+        if d["kind"] == "complete":
+            y = torch.from_numpy(d["M_obs"].astype(np.float32)).cuda()
+            m = torch.from_numpy(d["mask"]).cuda()
+            p = lib.complete_problem(y, m, d["rho"], d["tol"], d["growth"], d["rho_max"], d["max_iter"])
+        else:
+            x = torch.from_numpy(d["M"].astype(np.float32)).cuda()
+            p = lib.trpca_problem(x, d["lam"], d["mu"], d["tol"], lib.SHRINK_L1, d["growth"], d["mu_max"],
+                                  d["max_iter"])
+        staged.append((r["t"], p))
+    torch.cuda.synchronize()
+    print(f"[bench] serving leg: {len(staged)} requests staged", file=sys.stderr, flush=True)
+    handle = lib.Handle(0, hbm_budget_bytes=int(budget_gb * (1 << 30)))
+    pending, lat, iters, statuses = {}, [], [], []
+    t0 = time.perf_counter()
+    nxt = 0
+    last_done = t0
+    try:
+        while nxt < len(staged) or pending:
+            now = time.perf_counter() - t0
+            while nxt < len(staged) and staged[nxt][0] <= now:
+                pending[lib.submit(staged[nxt][1], handle)] = staged[nxt][0]
+                nxt += 1
+            for t in list(pending):
+                r = lib.poll(t, handle)
+                if r is not None:
+                    st, info = r
+                    lat.append(info.seconds)
+                    iters.append(info.iters)
+                    statuses.append(st)
+                    del pending[t]
+                    last_done = time.perf_counter()
+                    if len(lat) % 20 == 0:
+                        print(f"[bench] serving leg: {len(lat)} done", file=sys.stderr, flush=True)
+            time.sleep(0.0005)
+        stats = lib.serve_stats(handle)
+    finally:
+        handle.close()
+    span = last_done - t0
+    lat = np.asarray(lat)
+    return {"workload": f"Poisson {rate:g} req/s for {window:g} s: 70% completion / 30% TRPCA, 10% 4-D "
+                        "96x128x3x48 colour video, else shapes as the batched workload; FP32 form, "
+                        "<=150 iterations, tol 1e-7",
+            "requests": len(staged), "solves_per_s": len(staged) / span, "span_s": span,
+            "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+            "max_s": float(lat.max()), "mean_iters": float(np.mean(iters)),
+            "statuses_ok": all(s == 0 for s in statuses), "peak_running": stats["peak_running"],
+            "arena_gb": stats["arena_bytes"] / (1 << 30)}
+
+
 def cpu_baseline(w, seconds: float):
     """The FP64 oracle on the same workload, timed for a bounded number of
     iterations (about `seconds` of CPU work)."""
@@ -115,6 +221,14 @@ def main() -> int:
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--only", choices=["fp32", "fp64"], default=None,
                     help="run one form only (for profiler runs); prints its timing line")
+    ap.add_argument("--batch-iters", type=int, default=150, help="iterations per batched problem")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-rate", type=float, default=50.0)
+    ap.add_argument("--serve-window", type=float, default=2.0,
+                    help="seconds of arrivals replayed (the full trace is 60 s)")
+    ap.add_argument("--serve-budget-gb", type=float, default=64.0)
+    ap.add_argument("--only-legs", action="store_true", help="run the batched and serving legs only")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain device copy of 1 GiB (reference for HBM byte counters) and exit")
     args = ap.parse_args()
@@ -141,6 +255,16 @@ def main() -> int:
         torch.cuda.synchronize()
         print(json.dumps({"calibration": "device copy", "bytes_read": src.numel() * 8,
                           "bytes_written": dst.numel() * 8}), flush=True)
+        return 0
+    if args.only_legs:
+        res = {}
+        if not args.no_batch:
+            res["batched"] = batched_leg(lib, torch, np, workloads, args.batch_iters)
+            print(json.dumps({"batched": res["batched"]}), flush=True)
+        if not args.no_serve:
+            res["serving"] = serving_leg(lib, torch, np, workloads, args.serve_rate, args.serve_window,
+                                         args.serve_budget_gb)
+            print(json.dumps({"serving": res["serving"]}), flush=True)
         return 0
     w = workloads.video_completion(0, shape=SHAPE)
     mask = torch.from_numpy(w["mask"]).to(dev)
@@ -221,6 +345,11 @@ def main() -> int:
                         "fp32_rel_err_vs_oracle": float(np.linalg.norm(
                             xp32.cpu().numpy().astype(np.float64) - ref["X"]) / den)}
 
+    if not args.no_batch:
+        result["batched"] = batched_leg(lib, torch, np, workloads, args.batch_iters)
+    if not args.no_serve:
+        result["serving"] = serving_leg(lib, torch, np, workloads, args.serve_rate, args.serve_window,
+                                        args.serve_budget_gb)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(result), flush=True)

@@ -6,7 +6,9 @@
 // "problem-table launches"):
 //   forward DFT + prologue -> Newton-Schulz V^H V -> Newton-Schulz V update
 //   -> pre-rotation A V -> Jacobi SVD (one launch per block-width / row-count
-//   class, one workgroup per slice) -> singular values -> rebuild
+//   class, one workgroup per slice; the classes run concurrently on side
+//   streams, forked from and joined back into the engine's stream)
+//   -> singular values -> rebuild
 //   -> inverse DFT + epilogue -> control step.
 // A problem runs exactly the arithmetic of the single-problem drivers in
 // capi.hip: the first iteration's pre-rotation by V = I is an exact copy, so
@@ -100,12 +102,14 @@ struct Slot {
     cplx<T>* G = nullptr;
     double* sigma = nullptr;
     int* sweeps = nullptr;
+    int* rot = nullptr;         // round-mode Jacobi: 3 x h rotation flags
     double* partials = nullptr;
     Ctrl* ctrl = nullptr;
     int* flag = nullptr;
     cplx<double>* tw = nullptr;
     int tile_f = 0, tile_i = 0, inv_parts = 0, pro = 0, epi = 0;
     int bw = 0, rpt = 0, nb = 0;
+    bool round = false;         // Jacobi in round mode (one launch per round)
 };
 
 template <typename T>
@@ -136,6 +140,7 @@ size_t slot_layout(Slot<T>& sl, char* base) {
     sl.G = reinterpret_cast<cplx<T>*>(take(vv * sizeof(cplx<T>)));
     sl.sigma = reinterpret_cast<double*>(take((int64_t)g.h * g.n * sizeof(double)));
     sl.sweeps = reinterpret_cast<int*>(take((int64_t)g.h * sizeof(int)));
+    sl.rot = reinterpret_cast<int*>(take((int64_t)3 * g.h * sizeof(int)));
     sl.partials = reinterpret_cast<double*>(take((int64_t)nparts * kNumPartials * sizeof(double)));
     sl.ctrl = reinterpret_cast<Ctrl*>(take(sizeof(Ctrl)));
     sl.flag = reinterpret_cast<int*>(take(sizeof(int)));
@@ -154,6 +159,10 @@ struct Tables {
         int nprob = 0, nwg = 0;
         size_t lds = 0;
         int bw = 0, rpt = 0;   // Jacobi classes
+        bool round = false;    // Jacobi classes: round mode
+        int nb_max = 0, sweeps_max = 0;   // round mode: launch schedule
+        double work = 0.0;     // Jacobi classes: sum over slices of n^2 (m + n)
+        int lane = 0;          // Jacobi classes: side stream
     };
     Phase fwd, gram, ns, pre, sig, reb, inv, ctl;
     std::vector<Phase> jac;
@@ -183,12 +192,23 @@ public:
         for (int q = 0; q < 2; ++q)
             if (tab_[q].dev) (void)hipFree(tab_[q].dev), tab_[q].dev = nullptr;
         if (host_ctrl_) (void)hipHostFree(host_ctrl_), host_ctrl_ = nullptr;
+        for (int k = 0; k < kLanes; ++k) {
+            if (side_[k]) (void)hipStreamDestroy(side_[k]), side_[k] = nullptr;
+            if (ev_join_[k]) (void)hipEventDestroy(ev_join_[k]), ev_join_[k] = nullptr;
+        }
+        if (ev_fork_) (void)hipEventDestroy(ev_fork_), ev_fork_ = nullptr;
         if (stream_) (void)hipStreamDestroy(stream_), stream_ = nullptr;
     }
 
     void attach(Arena* arena) {
         arena_ = arena;
-        if (!stream_) hip_check(hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking), "hipStreamCreate");
+        if (stream_) return;
+        hip_check(hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking), "hipStreamCreate");
+        for (int k = 0; k < kLanes; ++k) {
+            hip_check(hipStreamCreateWithFlags(&side_[k], hipStreamNonBlocking), "hipStreamCreate");
+            hip_check(hipEventCreateWithFlags(&ev_join_[k], hipEventDisableTiming), "hipEventCreate");
+        }
+        hip_check(hipEventCreateWithFlags(&ev_fork_, hipEventDisableTiming), "hipEventCreate");
     }
 
     hipStream_t stream() const { return stream_; }
@@ -330,6 +350,7 @@ private:
         for (int k = 0; k < nit; ++k) launch_fill<T>(sl.it[k][0], (T)0, N, st);
         launch_set_identity<T>(sl.V[0], g.n, g.h, st);
         launch_fill<int>(sl.flag, 0, 1, st);
+        launch_fill<int>(sl.rot, 0, 3 * g.h, st);
         launch_sumsq<T>(static_cast<const T*>(p.x), rpca ? nullptr : p.mask, N, sl.partials, 1024, st);
         launch_set_tol(sl.ctrl, sl.partials, 1024, p.tol, st);
         launch_check("problem setup");
@@ -340,6 +361,8 @@ private:
         sl.rpt = jacobi_slice_rpt(g.m, g.n);
         sl.bw = pick_bw(g.m, g.n, sl.rpt);
         sl.nb = jacobi_num_blocks(g.n, sl.bw);
+        // many block pairs per slice: one workgroup per pair and a launch per round
+        sl.round = sl.nb / 2 >= env_int("TSVD_ROUND_MIN_PAIRS", 4);
     }
 
     void write_outputs(Slot<T>& sl, const Ctrl& c) {
@@ -492,7 +515,10 @@ private:
         std::vector<CtrlArgs> ctl;
         std::vector<int> ws_fwd{0}, ws_inv{0}, ws_gram{0}, ws_ns{0}, ws_pre{0}, ws_reb{0}, ws_sig{0};
         size_t lds_f = 0, lds_i = 0;
-        std::map<std::pair<int, int>, std::pair<std::vector<JacSliceArgs<T>>, std::vector<int>>> jc;
+        using JKey = std::tuple<int, int, int>;   // (bw, rpt, round)
+        std::map<JKey, std::pair<std::vector<JacSliceArgs<T>>, std::vector<int>>> jc;
+        std::map<JKey, double> jwork;
+        std::map<JKey, std::pair<int, int>> jsched;   // round mode: (max nb, max sweeps)
         for (const Slot<T>& sl : slots_) {
             const Geometry& g = sl.sp.g;
             const tsvd_problem& p = sl.sp.p;
@@ -579,10 +605,16 @@ private:
             ja.sweeps = sl.sweeps;
             ja.ctrl = sl.ctrl;
             ja.max_sweeps = sl.sp.s.max_sweeps;
-            auto& cls = jc[{sl.bw, sl.rpt}];
+            ja.rot = sl.rot;
+            const JKey key{sl.bw, sl.rpt, sl.round ? 1 : 0};
+            auto& cls = jc[key];
             if (cls.second.empty()) cls.second.push_back(0);
             cls.first.push_back(ja);
-            cls.second.push_back(cls.second.back() + g.h);
+            cls.second.push_back(cls.second.back() + g.h * (sl.round ? sl.nb / 2 : 1));
+            jwork[key] += (double)g.h * g.n * g.n * (g.m + g.n);
+            auto& sc = jsched[key];
+            sc.first = std::max(sc.first, sl.nb);
+            sc.second = std::max(sc.second, sl.sp.s.max_sweeps);
             // singular values and rebuild A = W diag(d) V'^H
             SigmaArgs<T> sa{sl.W, g.m, g.n, g.h, sl.sigma, sl.ctrl};
             sig.push_back(sa);
@@ -623,7 +655,8 @@ private:
             inv.push_back(ia);
             ws_inv.push_back(ws_inv.back() + sl.inv_parts);
             lds_i = std::max(lds_i, dft_inverse_lds<T>(g, sl.tile_i, sl.epi));
-            ctl.push_back(CtrlArgs{sl.ctrl, sl.partials, sl.inv_parts, rpca ? 1 : 0});
+            ctl.push_back(CtrlArgs{sl.ctrl, sl.partials, sl.inv_parts, rpca ? 1 : 0, sl.round ? sl.rot : nullptr,
+                                   g.h});
         }
         auto put = [&](typename Tables<T>::Phase& ph, auto& args, std::vector<int>& ws, size_t lds) {
             ph.args_off = append(tb.host, args);
@@ -645,10 +678,25 @@ private:
         for (auto& kv : jc) {
             typename Tables<T>::Phase ph;
             put(ph, kv.second.first, kv.second.second, 0);
-            ph.bw = kv.first.first;
-            ph.rpt = kv.first.second;
+            ph.bw = std::get<0>(kv.first);
+            ph.rpt = std::get<1>(kv.first);
+            ph.round = std::get<2>(kv.first) != 0;
+            ph.nb_max = jsched[kv.first].first;
+            ph.sweeps_max = jsched[kv.first].second;
+            ph.work = jwork[kv.first];
             hip_check(prepare_jacobi_slice<T>(ph.bw, ph.rpt), "jacobi attribute");
             tb.jac.push_back(ph);
+        }
+        // the classes run concurrently on kLanes streams: largest work first,
+        // each to the least loaded stream
+        std::sort(tb.jac.begin(), tb.jac.end(), [](const auto& a, const auto& b) { return a.work > b.work; });
+        double load[kLanes] = {};
+        for (auto& ph : tb.jac) {
+            int best = 0;
+            for (int k = 1; k < kLanes; ++k)
+                if (load[k] < load[best]) best = k;
+            ph.lane = best;
+            load[best] += ph.work;
         }
         if (tb.host.size() > tb.dev_cap) {
             if (tb.dev) hip_check(hipFree(tb.dev), "hipFree tables");
@@ -678,10 +726,31 @@ private:
         launch_zgemm_batched<T>(targs<ZGemmArgs<T>>(tb, tb.ns), tws(tb, tb.ns), tb.ns.nprob, tb.ns.nwg, st);
         launch_zgemm_batched<T>(targs<ZGemmArgs<T>>(tb, tb.pre), tws(tb, tb.pre), tb.pre.nprob, tb.pre.nwg, st);
         launch_check("batched warm start");
-        for (const auto& ph : tb.jac)
-            hip_check(launch_jacobi_slice<T>(ph.bw, ph.rpt, targs<JacSliceArgs<T>>(tb, ph), tws(tb, ph), ph.nprob,
-                                             ph.nwg, 30, st),
-                      "batched jacobi");
+        // fork: the Jacobi classes on the side streams, then join
+        hip_check(hipEventRecord(ev_fork_, st), "hipEventRecord");
+        bool used[kLanes] = {};
+        for (const auto& ph : tb.jac) used[ph.lane] = true;
+        for (int k = 0; k < kLanes; ++k)
+            if (used[k]) hip_check(hipStreamWaitEvent(side_[k], ev_fork_, 0), "hipStreamWaitEvent");
+        for (const auto& ph : tb.jac) {
+            if (!ph.round) {
+                hip_check(launch_jacobi_slice<T>(ph.bw, ph.rpt, targs<JacSliceArgs<T>>(tb, ph), tws(tb, ph),
+                                                 ph.nprob, ph.nwg, 30, side_[ph.lane]),
+                          "batched jacobi");
+                continue;
+            }
+            // every sweep the cap allows, every round; converged slices return at once
+            for (int sw = 0; sw < ph.sweeps_max; ++sw)
+                for (int rd = 0; rd < ph.nb_max - 1; ++rd)
+                    hip_check(launch_jacobi_round<T>(ph.bw, ph.rpt, targs<JacSliceArgs<T>>(tb, ph), tws(tb, ph),
+                                                     ph.nprob, ph.nwg, sw, rd, side_[ph.lane]),
+                              "batched jacobi round");
+        }
+        for (int k = 0; k < kLanes; ++k)
+            if (used[k]) {
+                hip_check(hipEventRecord(ev_join_[k], side_[k]), "hipEventRecord");
+                hip_check(hipStreamWaitEvent(st, ev_join_[k], 0), "hipStreamWaitEvent");
+            }
         launch_svt_sigma_batched<T>(targs<SigmaArgs<T>>(tb, tb.sig), tws(tb, tb.sig), tb.sig.nprob, tb.sig.nwg, st);
         launch_zgemm_batched<T>(targs<ZGemmArgs<T>>(tb, tb.reb), tws(tb, tb.reb), tb.reb.nprob, tb.reb.nwg, st);
         launch_check("batched rebuild");
@@ -693,8 +762,11 @@ private:
 
     int device_, cus_;
     size_t lds_cap_;
+    static constexpr int kLanes = 3;   // side streams of the Jacobi phase
     Arena* arena_ = nullptr;
     hipStream_t stream_ = nullptr;
+    hipStream_t side_[kLanes] = {};
+    hipEvent_t ev_fork_ = nullptr, ev_join_[kLanes] = {};
     std::vector<Slot<T>> slots_;
     Tables<T> tab_[2];
     bool dirty_ = true;

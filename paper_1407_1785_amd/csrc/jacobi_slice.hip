@@ -19,6 +19,11 @@
 // in LDS), rotation parameters in FP64, norms exact at the start of a round
 // and tracked through it.
 //
+// Round mode (jacobi_round_kernel) for slices with many blocks: one launch
+// per (sweep, round) and one workgroup per block pair, so a large slice is
+// worked on by nb/2 workgroups at once; the launch boundaries order the
+// rounds.
+//
 // Launch: a table of problems; workgroup b serves problem p when
 // wg_start[p] <= b < wg_start[p + 1], slice b - wg_start[p].  A problem
 // whose ADMM has stopped (ctrl->done) is skipped; each slice raises
@@ -33,6 +38,79 @@ namespace {
 using namespace jac;
 
 constexpr int kPGs = 32;
+
+// One round of the block tournament on one block pair of a slice, with the
+// blocks in LDS (blk0 at tournament position gp, blk1 at nb - 1 - gp):
+// optionally the internal pairs of both blocks (first round of a sweep),
+// then every cross pair.  Returns the rotations applied (per thread: every
+// lane of a pair group counts its group's rotations).
+template <typename T, int BW, int RPT>
+__device__ __forceinline__ unsigned pair_round(cplx<T>* blk0, cplx<T>* blk1, int wi, int wj, bool self_phase,
+                                               int ka, int ldc, double tol, double* jnorm) {
+    constexpr int PG = kPGs;
+    const int g = threadIdx.x / PG, l = threadIdx.x - g * PG;
+    unsigned nrot = 0;
+    if (self_phase) {
+        // internal pairs of both blocks: groups 0..BW/2-1 take block 0, the rest block 1
+        const bool second = g >= BW / 2;
+        const int gi = second ? g - BW / 2 : g;
+        cplx<T>* const base = second ? blk1 : blk0;
+        const int w = second ? wj : wi;
+        const int wp = w + (w & 1);
+        for (int st = 0; st < BW - 1; ++st) {
+            if (st < wp - 1 && gi < wp / 2) {
+                const int pp = ppos_player(gi, st, wp);
+                const int qq = ppos_player(wp - 1 - gi, st, wp);
+                if (pp < w && qq < w) {
+                    cplx<T>* cp = base + pp * ldc;
+                    cplx<T>* cq = base + qq * ldc;
+                    cplx<T> x[RPT], y[RPT];
+#pragma unroll
+                    for (int k = 0; k < RPT; ++k) {
+                        x[k] = cp[l + PG * k];
+                        y[k] = cq[l + PG * k];
+                    }
+                    double al = pnorm2<T, PG, RPT>(x, ka), be = pnorm2<T, PG, RPT>(y, ka);
+                    if (ppair<T, PG, RPT>(x, cq, al, be, ka, l, tol)) {
+                        ++nrot;
+#pragma unroll
+                        for (int k = 0; k < RPT; ++k) cp[l + PG * k] = x[k];
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // cross pairs: column g of block 0 (registers) meets every column of block 1
+    cplx<T> xi[RPT];
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) xi[k] = blk0[g * ldc + l + PG * k];
+    double al = pnorm2<T, PG, RPT>(xi, ka);
+    {
+        cplx<T> yj[RPT];
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) yj[k] = blk1[g * ldc + l + PG * k];
+        const double bj = pnorm2<T, PG, RPT>(yj, ka);
+        if (l == 0) jnorm[g] = bj;
+    }
+    __syncthreads();
+    for (int st = 0; st < BW; ++st) {
+        const int jc = (g + st) & (BW - 1);
+        if (g < wi && jc < wj) {
+            double be = jnorm[jc];
+            if (ppair<T, PG, RPT>(xi, blk1 + jc * ldc, al, be, ka, l, tol)) {
+                ++nrot;
+                if (l == 0) jnorm[jc] = be;
+            }
+        }
+        __syncthreads();
+    }
+    if (g < wi) {
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) blk0[g * ldc + l + PG * k] = xi[k];
+    }
+    return nrot;
+}
 
 template <typename T, int BW, int RPT>
 __global__ __launch_bounds__(BW * kPGs) void jacobi_slice_kernel(const JacSliceArgs<T>* tab, const int* wg_start,
@@ -53,7 +131,7 @@ __global__ __launch_bounds__(BW * kPGs) void jacobi_slice_kernel(const JacSliceA
     const int ldc = PG * RPT + 1;
     cplx<T>* const blk0 = reinterpret_cast<cplx<T>*>(smem);
     cplx<T>* const blk1 = blk0 + (size_t)BW * ldc;
-    const int g = threadIdx.x / PG, l = threadIdx.x - g * PG;
+    const int l = threadIdx.x % PG;
     const double tol = (double)a.tol;
 
     for (int idx = threadIdx.x; idx < 2 * BW * ldc; idx += NT) blk0[idx] = cplx<T>{(T)0, (T)0};
@@ -80,65 +158,7 @@ __global__ __launch_bounds__(BW * kPGs) void jacobi_slice_kernel(const JacSliceA
                 __syncthreads();
                 const int wi = pblk_start(player0 + 1, n, nb) - pblk_start(player0, n, nb);
                 const int wj = pblk_start(player1 + 1, n, nb) - pblk_start(player1, n, nb);
-                if (rd == 0) {
-                    // internal pairs of both blocks: groups 0..BW/2-1 take block 0, the rest block 1
-                    const bool second = g >= BW / 2;
-                    const int gi = second ? g - BW / 2 : g;
-                    cplx<T>* const base = second ? blk1 : blk0;
-                    const int w = second ? wj : wi;
-                    const int wp = w + (w & 1);
-                    for (int st = 0; st < BW - 1; ++st) {
-                        if (st < wp - 1 && gi < wp / 2) {
-                            const int pp = ppos_player(gi, st, wp);
-                            const int qq = ppos_player(wp - 1 - gi, st, wp);
-                            if (pp < w && qq < w) {
-                                cplx<T>* cp = base + pp * ldc;
-                                cplx<T>* cq = base + qq * ldc;
-                                cplx<T> x[RPT], y[RPT];
-#pragma unroll
-                                for (int k = 0; k < RPT; ++k) {
-                                    x[k] = cp[l + PG * k];
-                                    y[k] = cq[l + PG * k];
-                                }
-                                double al = pnorm2<T, PG, RPT>(x, ka), be = pnorm2<T, PG, RPT>(y, ka);
-                                if (ppair<T, PG, RPT>(x, cq, al, be, ka, l, tol)) {
-                                    ++nrot_sweep;
-#pragma unroll
-                                    for (int k = 0; k < RPT; ++k) cp[l + PG * k] = x[k];
-                                }
-                            }
-                        }
-                        __syncthreads();
-                    }
-                }
-                // cross pairs: column g of block 0 (registers) meets every column of block 1
-                cplx<T> xi[RPT];
-#pragma unroll
-                for (int k = 0; k < RPT; ++k) xi[k] = blk0[g * ldc + l + PG * k];
-                double al = pnorm2<T, PG, RPT>(xi, ka);
-                {
-                    cplx<T> yj[RPT];
-#pragma unroll
-                    for (int k = 0; k < RPT; ++k) yj[k] = blk1[g * ldc + l + PG * k];
-                    const double bj = pnorm2<T, PG, RPT>(yj, ka);
-                    if (l == 0) jnorm[g] = bj;
-                }
-                __syncthreads();
-                for (int st = 0; st < BW; ++st) {
-                    const int jc = (g + st) & (BW - 1);
-                    if (g < wi && jc < wj) {
-                        double be = jnorm[jc];
-                        if (ppair<T, PG, RPT>(xi, blk1 + jc * ldc, al, be, ka, l, tol)) {
-                            ++nrot_sweep;
-                            if (l == 0) jnorm[jc] = be;
-                        }
-                    }
-                    __syncthreads();
-                }
-                if (g < wi) {
-#pragma unroll
-                    for (int k = 0; k < RPT; ++k) blk0[g * ldc + l + PG * k] = xi[k];
-                }
+                nrot_sweep += pair_round<T, BW, RPT>(blk0, blk1, wi, wj, rd == 0, ka, ldc, tol, jnorm);
                 if (G > 1) {
                     __syncthreads();
                     store_block<T, NT, BW>(A, V, m, n, nb, player0, mp, ldc, blk0);
@@ -165,36 +185,101 @@ __global__ __launch_bounds__(BW * kPGs) void jacobi_slice_kernel(const JacSliceA
     if (l == 0 && nrot && a.rotations) atomicAdd(a.rotations, (unsigned long long)nrot);
 }
 
+// Round mode: one launch per (sweep, round); workgroup b of problem p takes
+// slice (b - wg_start[p]) / G, block pair (b - wg_start[p]) % G.  A slice
+// whose previous sweep rotated nothing is skipped; sweep k records its
+// rotations in rot[(k % 3) h + s] and clears rot[((k + 1) % 3) h + s], the
+// entry that nobody reads or writes during sweep k (ring 0 is cleared by the
+// control step before every SVD).
 template <typename T, int BW, int RPT>
-hipError_t launch_bw_rpt(bool prepare, const JacSliceArgs<T>* tab, const int* wg_start, int nprob, int nwg,
-                         int max_sweeps, hipStream_t st) {
-    auto* fn = jacobi_slice_kernel<T, BW, RPT>;
+__global__ __launch_bounds__(BW * kPGs) void jacobi_round_kernel(const JacSliceArgs<T>* tab, const int* wg_start,
+                                                                  int nprob, int sweep, int rd) {
+    constexpr int PG = kPGs, NT = BW * PG;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int rot_any;
+    __shared__ double jnorm[BW];
+    const int p = batch_find(wg_start, nprob, (int)blockIdx.x);
+    const JacSliceArgs<T>& a = tab[p];
+    if (a.ctrl && a.ctrl->done) return;
+    const int m = a.m, n = a.n, nb = a.nb, G = nb / 2;
+    if (sweep >= (a.max_sweeps > 0 ? a.max_sweeps : 30) || rd >= nb - 1) return;
+    const int local = (int)blockIdx.x - wg_start[p];
+    const int s = local / G, gp = local - s * G;
+    int* const rot = a.rot;
+    if (rd == 0 && gp == 0 && threadIdx.x == 0) rot[((sweep + 1) % 3) * a.h + s] = 0;
+    if (sweep > 0 && rot[((sweep + 2) % 3) * a.h + s] == 0) return;   // converged in the previous sweep
+    cplx<T>* const A = a.A + (int64_t)s * n * m;
+    cplx<T>* const V = a.V + (int64_t)s * n * n;
+    const int ka = (m + PG - 1) / PG;
+    const int mp = ka * PG;
+    const int ldc = PG * RPT + 1;
+    cplx<T>* const blk0 = reinterpret_cast<cplx<T>*>(smem);
+    cplx<T>* const blk1 = blk0 + (size_t)BW * ldc;
+    const int l = threadIdx.x % PG;
+    for (int idx = threadIdx.x; idx < 2 * BW * ldc; idx += NT) blk0[idx] = cplx<T>{(T)0, (T)0};
+    if (threadIdx.x == 0) rot_any = 0;
+    __syncthreads();
+    const int player0 = ppos_player(gp, rd, nb), player1 = ppos_player(nb - 1 - gp, rd, nb);
+    load_block<T, NT, BW>(A, V, m, n, nb, player0, mp, ldc, blk0);
+    load_block<T, NT, BW>(A, V, m, n, nb, player1, mp, ldc, blk1);
+    __syncthreads();
+    const int wi = pblk_start(player0 + 1, n, nb) - pblk_start(player0, n, nb);
+    const int wj = pblk_start(player1 + 1, n, nb) - pblk_start(player1, n, nb);
+    const unsigned nrot = pair_round<T, BW, RPT>(blk0, blk1, wi, wj, rd == 0, ka, ldc, (double)a.tol, jnorm);
+    if (nrot && l == 0) rot_any = 1;
+    __syncthreads();
+    store_block<T, NT, BW>(A, V, m, n, nb, player0, mp, ldc, blk0);
+    store_block<T, NT, BW>(A, V, m, n, nb, player1, mp, ldc, blk1);
+    if (threadIdx.x == 0) {
+        if (rot_any) atomicOr(rot + (sweep % 3) * a.h + s, 1);
+        if (rd == 0 && gp == 0) {
+            if (a.sweeps) a.sweeps[s] = sweep + 1;
+            if (a.ctrl) atomicMax(&a.ctrl->sweep_max, sweep + 1);
+        }
+    }
+    if (l == 0 && nrot && a.rotations) atomicAdd(a.rotations, (unsigned long long)nrot);
+}
+
+// mode 0: slice kernel (x = max_sweeps); mode 1: round kernel (x = sweep, y = round);
+// prepare: set the LDS limit of both kernels.
+template <typename T, int BW, int RPT>
+hipError_t launch_bw_rpt(bool prepare, int mode, const JacSliceArgs<T>* tab, const int* wg_start, int nprob, int nwg,
+                         int x, int y, hipStream_t st) {
+    auto* fs = jacobi_slice_kernel<T, BW, RPT>;
+    auto* fr = jacobi_round_kernel<T, BW, RPT>;
     const size_t lds = jacobi_slice_lds(BW, RPT, sizeof(T));
-    if (prepare)
-        return hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
+    if (prepare) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fs),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        return hipFuncSetAttribute(reinterpret_cast<const void*>(fr), hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)lds);
-    hipLaunchKernelGGL(fn, dim3(nwg), dim3(BW * kPGs), lds, st, tab, wg_start, nprob, max_sweeps);
+    }
+    if (mode == 0)
+        hipLaunchKernelGGL(fs, dim3(nwg), dim3(BW * kPGs), lds, st, tab, wg_start, nprob, x);
+    else
+        hipLaunchKernelGGL(fr, dim3(nwg), dim3(BW * kPGs), lds, st, tab, wg_start, nprob, x, y);
     return hipGetLastError();
 }
 
 template <typename T, int BW, int... R>
-hipError_t dispatch_rpt(int rpt, std::integer_sequence<int, R...>, bool prepare, const JacSliceArgs<T>* tab,
-                        const int* wg_start, int nprob, int nwg, int max_sweeps, hipStream_t st) {
+hipError_t dispatch_rpt(int rpt, std::integer_sequence<int, R...>, bool prepare, int mode, const JacSliceArgs<T>* tab,
+                        const int* wg_start, int nprob, int nwg, int x, int y, hipStream_t st) {
     hipError_t e = hipErrorInvalidValue;
-    ((rpt == R + 2 ? (e = launch_bw_rpt<T, BW, R + 2>(prepare, tab, wg_start, nprob, nwg, max_sweeps, st), 0) : 0),
+    ((rpt == R + 2 ? (e = launch_bw_rpt<T, BW, R + 2>(prepare, mode, tab, wg_start, nprob, nwg, x, y, st), 0) : 0),
      ...);
     return e;
 }
 
 template <typename T>
-hipError_t dispatch(bool prepare, int bw, int rpt, const JacSliceArgs<T>* tab, const int* wg_start, int nprob,
-                    int nwg, int max_sweeps, hipStream_t st) {
+hipError_t dispatch(bool prepare, int mode, int bw, int rpt, const JacSliceArgs<T>* tab, const int* wg_start,
+                    int nprob, int nwg, int x, int y, hipStream_t st) {
     if (rpt < 2 || rpt > 20) return hipErrorInvalidValue;
     auto seq = std::make_integer_sequence<int, 19>{};
     switch (bw) {
-        case 4: return dispatch_rpt<T, 4>(rpt, seq, prepare, tab, wg_start, nprob, nwg, max_sweeps, st);
-        case 8: return dispatch_rpt<T, 8>(rpt, seq, prepare, tab, wg_start, nprob, nwg, max_sweeps, st);
-        case 16: return dispatch_rpt<T, 16>(rpt, seq, prepare, tab, wg_start, nprob, nwg, max_sweeps, st);
+        case 4: return dispatch_rpt<T, 4>(rpt, seq, prepare, mode, tab, wg_start, nprob, nwg, x, y, st);
+        case 8: return dispatch_rpt<T, 8>(rpt, seq, prepare, mode, tab, wg_start, nprob, nwg, x, y, st);
+        case 16: return dispatch_rpt<T, 16>(rpt, seq, prepare, mode, tab, wg_start, nprob, nwg, x, y, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -214,14 +299,25 @@ int jacobi_slice_max_rpt() { return 20; }
 
 template <typename T>
 hipError_t prepare_jacobi_slice(int bw, int rpt) {
-    return dispatch<T>(true, bw, rpt, nullptr, nullptr, 0, 0, 0, nullptr);
+    return dispatch<T>(true, 0, bw, rpt, nullptr, nullptr, 0, 0, 0, 0, nullptr);
 }
 
 template <typename T>
 hipError_t launch_jacobi_slice(int bw, int rpt, const JacSliceArgs<T>* tab, const int* wg_start, int nprob,
                                int nwg, int max_sweeps, hipStream_t st) {
-    return dispatch<T>(false, bw, rpt, tab, wg_start, nprob, nwg, max_sweeps, st);
+    return dispatch<T>(false, 0, bw, rpt, tab, wg_start, nprob, nwg, max_sweeps, 0, st);
 }
+
+template <typename T>
+hipError_t launch_jacobi_round(int bw, int rpt, const JacSliceArgs<T>* tab, const int* wg_start, int nprob,
+                               int nwg, int sweep, int round, hipStream_t st) {
+    return dispatch<T>(false, 1, bw, rpt, tab, wg_start, nprob, nwg, sweep, round, st);
+}
+
+template hipError_t launch_jacobi_round<double>(int, int, const JacSliceArgs<double>*, const int*, int, int, int,
+                                                int, hipStream_t);
+template hipError_t launch_jacobi_round<float>(int, int, const JacSliceArgs<float>*, const int*, int, int, int, int,
+                                               hipStream_t);
 
 template hipError_t prepare_jacobi_slice<double>(int, int);
 template hipError_t prepare_jacobi_slice<float>(int, int);

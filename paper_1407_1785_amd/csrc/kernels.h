@@ -126,10 +126,14 @@ struct JacSliceArgs {
     Ctrl* ctrl;          // optional: skip the problem once ctrl->done; sweep_max is raised
     unsigned long long* rotations;  // optional running count
     int max_sweeps;      // sweep cap (0: the launch's)
+    int* rot;            // round mode: 3 x h ring of per-sweep rotation flags (ring 0 clear before the SVD)
 };
 int jacobi_slice_rpt(int m, int n);
 size_t jacobi_slice_lds(int bw, int rpt, int elem_bytes);
 int jacobi_slice_max_rpt();
+template <typename T>
+hipError_t launch_jacobi_round(int bw, int rpt, const JacSliceArgs<T>* tab, const int* wg_start, int nprob,
+                               int nwg, int sweep, int round, hipStream_t st);
 // Sets the kernel's LDS limit; call once per (bw, rpt) before launches
 // (and before any stream capture).
 template <typename T>
@@ -204,6 +208,8 @@ struct CtrlArgs {
     Ctrl* c;
     const double* partials;
     int nparts, rpca;
+    int* rot_ring0;    // optional: h flags cleared after the step (round-mode Jacobi)
+    int h;
 };
 void launch_admm_ctrl_batched(const CtrlArgs* tab, int nprob, hipStream_t st);
 void launch_admm_ctrl(Ctrl* c, const double* partials, int nparts, int rpca, hipStream_t st);

@@ -178,3 +178,44 @@ def test_batch_rejects_bad_records():
     with pytest.raises(lib.TsvdError) as e:
         lib.batch_run([q])
     assert e.value.status == -2
+
+
+def test_round_mode_equals_slice_mode():
+    """The round-mode Jacobi (a launch per tournament round, one workgroup
+    per block pair) performs the same rotations in the same order as the
+    one-workgroup-per-slice kernel: outputs agree bit for bit."""
+    torch = torch_cuda()
+    cases = _cases()
+    outs = {}
+    for mode in ("1", "100000"):
+        os.environ["TSVD_ROUND_MIN_PAIRS"] = mode
+        try:
+            probs = [_problem(torch, c) for c in cases]
+            announce("round-mode threshold", mode)
+            res = lib.batch_run(probs)
+        finally:
+            os.environ.pop("TSVD_ROUND_MIN_PAIRS", None)
+        assert all(st == 0 for st, _ in res)
+        outs[mode] = [_outputs(p) for p in probs]
+    for a, b in zip(outs["1"], outs["100000"]):
+        for x, y in zip(a, b):
+            np.testing.assert_array_equal(x, y)
+
+
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+def test_large_slices_against_oracle(dt):
+    """Slices with many column blocks (150 x 140, several block pairs per
+    round) next to small ones, in one batch."""
+    torch = torch_cuda()
+    big = ("big", "complete", *_completion((150, 140, 4), 7, p=0.4, rank=3), dt, {})
+    big = (big[0], big[1], np.asarray(big[2], dtype=dt), big[3], dt, {})
+    small = _cases()[0]
+    cases = [big, small]
+    probs = [_problem(torch, c, iters=8) for c in cases]
+    announce("large slices", dt.__name__)
+    res = lib.batch_run(probs)
+    bar = FP32_BAR if dt == np.float32 else FP64_BAR
+    for case, p, (st, info) in zip(cases, probs, res):
+        assert st == 0
+        for got, want in zip(_outputs(p), _oracle(case, iters=8)):
+            assert rel_fro(got, want) <= bar, case[0]

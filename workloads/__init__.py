@@ -219,3 +219,39 @@ def arrivals(trial=0, rate=50.0, seconds=60.0):
         color = bool(g_kind.random() < 0.1)
         reqs.append(dict(id=i, t=float(ta), kind=kind, color=color))
     return reqs
+
+
+def serve_request(req, trial=0, iters=150, tol=1e-7):
+    """Data of one request of the serving mix (``arrivals``).
+
+    Shape: the 4-D colour video 96 x 128 x 3 x 48 when ``req["color"]``,
+    else n1, n2 ~ U{48..320}, n3 ~ U{8..128} as in workload 3.
+    Completion requests: tubal rank ~ U{2..10} with N(0, 1) factors (colour
+    requests: the video itself), Bernoulli(p) mask with p ~ U[0.2, 0.6],
+    rho0 = 1e-2 grown by 1.1 up to 1e3.  RPCA requests: the low-rank part as
+    in workload 2 (factors N(0, 1/n1); colour requests: the video), 10% of
+    the entries replaced by U[-1, 1] corruption added on top, lam =
+    1/sqrt(max(n1, n2) * L) with L the tube length, mu0 = 1e-3 grown by 1.2
+    up to 1e10.  At most ``iters`` iterations, stopping tolerance ``tol``."""
+    g_shape, g_fac, g_mask = streams(4, 100000 * (trial + 1) + int(req["id"]), 3)
+    rpca = req["kind"] == "trpca"
+    if req["color"]:
+        x = color_video(g_fac).astype(np.float64)
+    else:
+        n1, n2 = (int(v) for v in g_shape.integers(48, 321, size=2))
+        n3 = int(g_shape.integers(8, 129))
+        r = int(g_shape.integers(2, 11))
+        _, _, x = lowrank(g_fac, n1, n2, n3, r, std=(1.0 / math.sqrt(n1)) if rpca else 1.0)
+    shape = x.shape
+    if not rpca:
+        p = float(g_shape.uniform(0.2, 0.6))
+        mask = bernoulli_mask(g_mask, shape, p)
+        return dict(kind="complete", X=x, mask=mask, M_obs=x * mask, rho=1e-2, growth=1.1, rho_max=1e3,
+                    max_iter=iters, tol=tol)
+    supp = exact_mask(g_mask, shape, 0.1).astype(bool)
+    sp = np.zeros(shape)
+    sp[supp] = g_mask.uniform(-1.0, 1.0, size=int(supp.sum()))
+    tube = int(np.prod(shape[2:]))
+    lam = 1.0 / math.sqrt(max(shape[0], shape[1]) * tube)
+    return dict(kind="trpca", L=x, S=sp, M=x + sp, lam=lam, mu=1e-3, growth=1.2, mu_max=1e10,
+                max_iter=iters, tol=tol)
