@@ -17,40 +17,64 @@ __device__ __forceinline__ int ppos_player(int pos, int r, int nb) {
     return pos == 0 ? 0 : 1 + (pos - 1 + r) % (nb - 1);
 }
 
+// DPP lane exchange within a 16-lane row.  Every lane reads a valid source
+// for the controls used here; with bound_ctrl the exchange folds into the
+// consuming add as a DPP source operand.
+template <int CTRL>
+__device__ __forceinline__ float pdpp(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
+}
+
 template <int CTRL>
 __device__ __forceinline__ double pdpp(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
-    return __hiloint2double(hi, lo);
+    return __hiloint2double(__builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true),
+                            __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true));
 }
 
-__device__ __forceinline__ double preadlane(double v, int lane) {
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
-    return __hiloint2double(hi, lo);
+// Sum of the two 16-lane rows 2r and 2r + 1, in every lane of both.
+// v_permlane16_swap exchanges the odd rows of its first operand with the
+// even rows of its second; with both operands holding v, the two registers
+// then hold row 2r and row 2r + 1 of v in every lane of the row pair.  The
+// instruction is issued from a register-only asm block (no memory access)
+// because the compiler's builtin for it returns its first result for both
+// results; the s_nop pairs cover the VALU-write / cross-lane-read wait
+// states on both sides.
+__device__ __forceinline__ float rowpair_sum(float v) {
+    unsigned a = __builtin_bit_cast(unsigned, v), b = a;
+    asm volatile("s_nop 1\n\tv_permlane16_swap_b32 %0, %1\n\ts_nop 1" : "+v"(a), "+v"(b));
+    return __builtin_bit_cast(float, a) + __builtin_bit_cast(float, b);
 }
 
-// Sum over the PG lanes of a pair group; every lane of the group gets the
-// same value.  16 lanes = one DPP row; 32 lanes = two rows combined through
-// readlane in a fixed order.
-template <int PG>
-__device__ __forceinline__ double group_sum(double v) {
+__device__ __forceinline__ double rowpair_sum(double v) {
+    unsigned al = (unsigned)__double2loint(v), bl = al;
+    unsigned ah = (unsigned)__double2hiint(v), bh = ah;
+    asm volatile("s_nop 1\n\tv_permlane16_swap_b32 %0, %1\n\tv_permlane16_swap_b32 %2, %3\n\ts_nop 1"
+                 : "+v"(al), "+v"(bl), "+v"(ah), "+v"(bh));
+    return __hiloint2double((int)ah, (int)al) + __hiloint2double((int)bh, (int)bl);
+}
+
+// Sum over the PG lanes of a pair group, in the element type; every lane of
+// the group gets the same bits (each stage adds two equal-shaped partial
+// sums, and addition is commutative).  16 lanes = one DPP row; 32 lanes =
+// two rows.
+template <int PG, typename T>
+__device__ __forceinline__ T group_sum(T v) {
     v += pdpp<0xB1>(v);    // lane ^ 1
     v += pdpp<0x4E>(v);    // lane ^ 2
     v += pdpp<0x141>(v);   // other quad of the half row
     v += pdpp<0x140>(v);   // other half of the row
-    if (PG == 32) {
-        const double lo = preadlane(v, 0) + preadlane(v, 16);
-        const double hi = preadlane(v, 32) + preadlane(v, 48);
-        v = (__lane_id() < 32) ? lo : hi;
-    }
+    if (PG == 32) v = rowpair_sum(v);
     return v;
 }
 
+// 1/sqrt(x) and 1/x from the hardware estimates with Newton steps: NS = 2
+// reaches FP64 accuracy, NS = 1 about 2^-44 (enough when the results are
+// rounded to FP32).
+template <int NS>
 __device__ __forceinline__ double prsqrt(double x) {
     double y = __builtin_amdgcn_rsq(x);
-    y = y * (1.5 - 0.5 * x * y * y);
-    y = y * (1.5 - 0.5 * x * y * y);
+#pragma unroll
+    for (int i = 0; i < NS; ++i) y = y * (1.5 - 0.5 * x * y * y);
     return y;
 }
 
@@ -66,16 +90,18 @@ struct PRot {
     bool on;
 };
 
+template <typename T>
 __device__ __forceinline__ PRot prot(double al, double be, double gr, double gi, double tol) {
+    constexpr int NS = sizeof(T) == 4 ? 1 : 2;
     PRot r{1.0, 0.0, 0.0, 0.0, false};
     const double g2 = gr * gr + gi * gi;
     if (!(g2 > (tol * tol) * al * be) || !(g2 > 0.0)) return r;
-    const double rg = prsqrt(g2);
+    const double rg = prsqrt<NS>(g2);
     const double zeta = (be - al) * 0.5 * rg;
     const double q = 1.0 + zeta * zeta;
-    const double t = prcp(fabs(zeta) + q * prsqrt(q));
+    const double t = prcp(fabs(zeta) + q * prsqrt<NS>(q));
     const double ts = zeta >= 0.0 ? t : -t;
-    r.c = prsqrt(1.0 + ts * ts);
+    r.c = prsqrt<NS>(1.0 + ts * ts);
     const double s = r.c * ts;
     r.a = s * (gr * rg);
     r.b = s * (gi * rg);
@@ -94,34 +120,62 @@ __device__ __forceinline__ void prot_apply(const PRot& rd, cplx<T>& x, cplx<T>& 
     y = yn;
 }
 
-// Squared norm of the slice rows of a column held in registers.
-template <typename T, int PG, int RPT>
-__device__ __forceinline__ double pnorm2(const cplx<T> (&x)[RPT], int ka) {
+// Partial sums over the first K row groups (the slice rows; the V rows
+// below them take part in the rotations only).  The number of slice row
+// groups ka is a runtime value: a uniform branch picks the unrolled
+// instance, so no per-row select is needed.
+template <typename T, int RPT, int K>
+__device__ __forceinline__ void dot_first(const cplx<T> (&x)[RPT], const cplx<T> (&y)[RPT], T& gr, T& gi) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        gr += x[k].re * y[k].re + x[k].im * y[k].im;
+        gi += x[k].re * y[k].im - x[k].im * y[k].re;
+    }
+}
+
+template <typename T, int RPT, int... K>
+__device__ __forceinline__ void dot_rows(const cplx<T> (&x)[RPT], const cplx<T> (&y)[RPT], int ka, T& gr, T& gi,
+                                         std::integer_sequence<int, K...>) {
+    ((ka == K + 1 ? (dot_first<T, RPT, K + 1>(x, y, gr, gi), 0) : 0), ...);
+}
+
+template <typename T, int RPT, int K>
+__device__ __forceinline__ T norm_first(const cplx<T> (&x)[RPT]) {
     T acc = 0;
 #pragma unroll
-    for (int k = 0; k < RPT; ++k)
-        if (k < ka) acc += x[k].re * x[k].re + x[k].im * x[k].im;
-    return group_sum<PG>((double)acc);
+    for (int k = 0; k < K; ++k) acc += x[k].re * x[k].re + x[k].im * x[k].im;
+    return acc;
+}
+
+template <typename T, int RPT, int... K>
+__device__ __forceinline__ T norm_rows(const cplx<T> (&x)[RPT], int ka, std::integer_sequence<int, K...>) {
+    T acc = 0;
+    ((ka == K + 1 ? (acc = norm_first<T, RPT, K + 1>(x), 0) : 0), ...);
+    return acc;
+}
+
+// Squared norm of the slice rows of a column held in registers (group sum
+// in the element type, returned in FP64).
+template <typename T, int PG, int RPT>
+__device__ __forceinline__ double pnorm2(const cplx<T> (&x)[RPT], int ka) {
+    const T acc = norm_rows<T, RPT>(x, ka, std::make_integer_sequence<int, RPT - 1>{});
+    return (double)group_sum<PG>(acc);
 }
 
 // Orthogonalise column x (registers, squared norm al) against column y in
 // LDS (squared norm be).  Lane l of the pair group holds rows l + PG k; the
-// first ka row groups are slice rows, the rest V rows, padding rows are zero.
-// On a rotation the norms are updated in place (al -= t|gamma|, be += t|gamma|).
+// first ka row groups (1 <= ka < RPT) are slice rows, the rest V rows,
+// padding rows are zero.  On a rotation the norms are updated in place
+// (al -= t|gamma|, be += t|gamma|).
 template <typename T, int PG, int RPT>
 __device__ __forceinline__ bool ppair(cplx<T> (&x)[RPT], cplx<T>* y_lds, double& al, double& be, int ka,
                                       int l, double tol) {
     cplx<T> y[RPT];
-    T gr = 0, gi = 0;
 #pragma unroll
-    for (int k = 0; k < RPT; ++k) {
-        y[k] = y_lds[l + PG * k];
-        if (k < ka) {
-            gr += x[k].re * y[k].re + x[k].im * y[k].im;
-            gi += x[k].re * y[k].im - x[k].im * y[k].re;
-        }
-    }
-    const PRot rt = prot(al, be, group_sum<PG>((double)gr), group_sum<PG>((double)gi), tol);
+    for (int k = 0; k < RPT; ++k) y[k] = y_lds[l + PG * k];
+    T gr = 0, gi = 0;
+    dot_rows<T, RPT>(x, y, ka, gr, gi, std::make_integer_sequence<int, RPT - 1>{});
+    const PRot rt = prot<T>(al, be, (double)group_sum<PG>(gr), (double)group_sum<PG>(gi), tol);
     if (!rt.on) return false;
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
