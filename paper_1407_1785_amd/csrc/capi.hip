@@ -285,8 +285,9 @@ SweepStats run_svt(tsvd_handle h, const Geometry& g, const SvtBuffers<T>& sb, in
     ensure_host_ints(h, g.h);
     SweepStats stats;
     const double dot_flops = 16.0 * g.m;
+    const int xcds = env_int("TSVD_XCD", 0);
     const bool persist = env_int("TSVD_PERSIST", 1) != 0 &&
-                         jacobi_persistent_fits(g.m, g.n, g.h, sizeof(T), h->cus, h->lds_cap);
+                         jacobi_persistent_fits(g.m, g.n, g.h, sizeof(T), h->cus, h->lds_cap, xcds);
     bool done_persist = false;
     if (persist) {
         // one cooperative launch runs every sweep
@@ -298,7 +299,7 @@ SweepStats run_svt(tsvd_handle h, const Geometry& g, const SvtBuffers<T>& sb, in
         launch_fill<int>(sb.pbar, 0, 4 * g.h, st);   // the error word is cleared per call
         launch_check("fill");
         PersistArgs pa{sb.pbar, sb.pbar + g.h, sb.pbar + 4 * g.h, max_sweeps, nullptr,
-                       env_int("TSVD_COOP", 1) != 0 ? 1 : 0};
+                       env_int("TSVD_COOP", 1) != 0 ? 1 : 0, xcds, env_int("TSVD_SPREAD", 0)};
         static long long* trace_buf = nullptr;
         const bool tracing = env_int("TSVD_TRACE", 0) != 0;
         if (tracing) {

@@ -223,26 +223,91 @@ __device__ __forceinline__ void pcol_out(const cplx<T>* src_c, int len, cplx<T>*
     for (int r = threadIdx.x % TT; r < len; r += TT) dst[r] = src[r];
 }
 
-// Block blk of a slice (A: m x n, V: n x n, column-major) to / from LDS.
+// Device-coherent copies: relaxed agent-scope atomic loads and stores, which
+// the hardware serves at the device's coherence point (never from a stale
+// L2 line of another XCD).  Used by workgroups that exchange blocks through
+// global memory inside one launch, so that no L2 write-back or invalidation
+// is needed around the exchange.
+template <typename T>
+__device__ __forceinline__ void coh_copy_in(const cplx<T>* src, cplx<T>* dst);
+
+template <>
+__device__ __forceinline__ void coh_copy_in<float>(const cplx<float>* src, cplx<float>* dst) {
+    const unsigned long long u = __hip_atomic_load(reinterpret_cast<const unsigned long long*>(src),
+                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    *reinterpret_cast<unsigned long long*>(dst) = u;
+}
+
+template <>
+__device__ __forceinline__ void coh_copy_in<double>(const cplx<double>* src, cplx<double>* dst) {
+    const unsigned long long* s = reinterpret_cast<const unsigned long long*>(src);
+    unsigned long long* d = reinterpret_cast<unsigned long long*>(dst);
+    const unsigned long long a = __hip_atomic_load(s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long b = __hip_atomic_load(s + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    d[0] = a;
+    d[1] = b;
+}
+
+template <typename T>
+__device__ __forceinline__ void coh_copy_out(const cplx<T>* src, cplx<T>* dst);
+
+template <>
+__device__ __forceinline__ void coh_copy_out<float>(const cplx<float>* src, cplx<float>* dst) {
+    __hip_atomic_store(reinterpret_cast<unsigned long long*>(dst), *reinterpret_cast<const unsigned long long*>(src),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <>
+__device__ __forceinline__ void coh_copy_out<double>(const cplx<double>* src, cplx<double>* dst) {
+    const unsigned long long* s = reinterpret_cast<const unsigned long long*>(src);
+    unsigned long long* d = reinterpret_cast<unsigned long long*>(dst);
+    __hip_atomic_store(d, s[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(d + 1, s[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <typename T, int NT, int BW>
+__device__ __forceinline__ void ccol_in(const cplx<T>* src, int len, cplx<T>* dst) {
+    constexpr int TT = NT / BW;
+    for (int r = threadIdx.x % TT; r < len; r += TT) coh_copy_in<T>(src + r, dst + r);
+}
+
+template <typename T, int NT, int BW>
+__device__ __forceinline__ void ccol_out(const cplx<T>* src, int len, cplx<T>* dst) {
+    constexpr int TT = NT / BW;
+    for (int r = threadIdx.x % TT; r < len; r += TT) coh_copy_out<T>(src + r, dst + r);
+}
+
+// Block blk of a slice (A: m x n, V: n x n, column-major) to / from LDS;
+// COH selects the device-coherent copies.
+template <typename T, int NT, int BW, bool COH = false>
 __device__ __forceinline__ void load_block(const cplx<T>* A, const cplx<T>* V, int m, int n, int nb, int blk,
                                            int mp, int ldc, cplx<T>* lds) {
     const int c0 = pblk_start(blk, n, nb), w = pblk_start(blk + 1, n, nb) - c0;
     const int c = threadIdx.x / (NT / BW);
     if (c < w) {
-        pcol_in<T, NT, BW>(A + (int64_t)(c0 + c) * m, m, lds + c * ldc);
-        pcol_in<T, NT, BW>(V + (int64_t)(c0 + c) * n, n, lds + c * ldc + mp);
+        if (COH) {
+            ccol_in<T, NT, BW>(A + (int64_t)(c0 + c) * m, m, lds + c * ldc);
+            ccol_in<T, NT, BW>(V + (int64_t)(c0 + c) * n, n, lds + c * ldc + mp);
+        } else {
+            pcol_in<T, NT, BW>(A + (int64_t)(c0 + c) * m, m, lds + c * ldc);
+            pcol_in<T, NT, BW>(V + (int64_t)(c0 + c) * n, n, lds + c * ldc + mp);
+        }
     }
 }
 
-template <typename T, int NT, int BW>
+template <typename T, int NT, int BW, bool COH = false>
 __device__ __forceinline__ void store_block(cplx<T>* A, cplx<T>* V, int m, int n, int nb, int blk, int mp,
                                             int ldc, const cplx<T>* lds) {
     const int c0 = pblk_start(blk, n, nb), w = pblk_start(blk + 1, n, nb) - c0;
     const int c = threadIdx.x / (NT / BW);
     if (c < w) {
-        pcol_out<T, NT, BW>(lds + c * ldc, m, A + (int64_t)(c0 + c) * m);
-        pcol_out<T, NT, BW>(lds + c * ldc + mp, n, V + (int64_t)(c0 + c) * n);
+        if (COH) {
+            ccol_out<T, NT, BW>(lds + c * ldc, m, A + (int64_t)(c0 + c) * m);
+            ccol_out<T, NT, BW>(lds + c * ldc + mp, n, V + (int64_t)(c0 + c) * n);
+        } else {
+            pcol_out<T, NT, BW>(lds + c * ldc, m, A + (int64_t)(c0 + c) * m);
+            pcol_out<T, NT, BW>(lds + c * ldc + mp, n, V + (int64_t)(c0 + c) * n);
+        }
     }
 }
 

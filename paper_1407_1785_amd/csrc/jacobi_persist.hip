@@ -22,8 +22,9 @@
 // the round (a rotation moves t |gamma| from one squared norm to the other).
 //
 // Synchronisation.  The per-slice barrier is a counter in global memory:
-// each workgroup publishes its block writes (agent-scope release fence),
-// increments the counter and waits for G arrivals per round.  The launch is
+// each workgroup writes its moving blocks with device-coherent stores, waits
+// for their completion, increments the counter and waits for G arrivals per
+// round; blocks are read back with device-coherent loads.  The launch is
 // cooperative, so all workgroups are co-resident; the wait is also bounded
 // (a spin limit sets an error flag and lets the kernel finish, so a launch
 // can never hang).
@@ -47,36 +48,50 @@ constexpr long long kSpinLimit = 1LL << 21;   // about a second of polling
 
 template <typename T, int NT>
 __device__ void pload_block(const JacArgs<T>& a, int s, int blk, int mp, int ldc, cplx<T>* lds) {
-    load_block<T, NT, PBW>(a.A + (int64_t)s * a.n * a.m, a.V + (int64_t)s * a.n * a.n, a.m, a.n, a.nb, blk, mp,
-                           ldc, lds);
+    load_block<T, NT, PBW, true>(a.A + (int64_t)s * a.n * a.m, a.V + (int64_t)s * a.n * a.n, a.m, a.n, a.nb, blk,
+                                 mp, ldc, lds);
 }
 
 template <typename T, int NT>
 __device__ void pstore_block(const JacArgs<T>& a, int s, int blk, int mp, int ldc, const cplx<T>* lds) {
-    store_block<T, NT, PBW>(a.A + (int64_t)s * a.n * a.m, a.V + (int64_t)s * a.n * a.n, a.m, a.n, a.nb, blk, mp,
-                            ldc, lds);
+    store_block<T, NT, PBW, true>(a.A + (int64_t)s * a.n * a.m, a.V + (int64_t)s * a.n * a.n, a.m, a.n, a.nb, blk,
+                                  mp, ldc, lds);
 }
 
 // Slice barrier: returns false if the bounded wait ran out.
-__device__ bool slice_barrier(int* counter, int target, int* err) {
+//
+// The blocks travel through global memory with device-coherent (relaxed
+// agent-scope atomic) loads and stores, so the barrier needs no L2
+// write-back or invalidation: every wave waits until its own stores are
+// complete at the coherence point, the workgroup meets at s_barrier, and
+// thread 0 counts the arrival and waits for the other workgroups of the
+// slice; the next blocks are read only after that (loads are issued in
+// program order).  With tr set (thread 0 of the traced workgroup), three
+// timestamps: stores complete, counter incremented, wait over.
+__device__ bool slice_barrier(int* counter, int target, int* err, long long* tr = nullptr, int* nev = nullptr) {
     __shared__ int ok;
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) {
+        auto mark = [&]() {
+            if (tr && *nev < 64) tr[(*nev)++] = (long long)wall_clock64();
+        };
+        mark();
         ok = 1;
-        __threadfence();
-        atomicAdd(counter, 1);
+        __hip_atomic_fetch_add(counter, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        mark();
         long long spins = 0;
-        while (__hip_atomic_load(counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             __builtin_amdgcn_s_sleep(2);
             // another workgroup gave up: stop waiting at once
             if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
                 ++spins > kSpinLimit) {
-                atomicExch(err, 1);
+                __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 ok = 0;
                 break;
             }
         }
-        __threadfence();
+        mark();
     }
     __syncthreads();
     return ok != 0;
@@ -92,7 +107,17 @@ __global__ __launch_bounds__(PBW * PG) void jacobi_persistent_kernel(JacArgs<T> 
     __shared__ int stop;
     __shared__ double jnorm[PBW];
     const int G = a.nb / 2;
-    const int s = blockIdx.x / G, wg = blockIdx.x - s * G;
+    int s, wg;
+    if (p.xcds > 0) {
+        // workgroup b runs on XCD b mod X: the G workgroups of a slice get the
+        // same residue, so their block exchanges stay within one L2
+        const int X = p.xcds, b = (int)blockIdx.x, x = b % X, i = b / X;
+        s = x + X * (i / G);
+        wg = i % G;
+    } else {
+        s = (int)blockIdx.x / G;
+        wg = (int)blockIdx.x - s * G;
+    }
     if (s >= a.h) return;
     const int ka = (a.m + PG - 1) / PG;   // row groups holding slice rows
     const int mp = ka * PG;
@@ -127,7 +152,9 @@ __global__ __launch_bounds__(PBW * PG) void jacobi_persistent_kernel(JacArgs<T> 
     for (int sweep = 0; sweep < p.max_sweeps && alive; ++sweep) {
         if (threadIdx.x == 0) rot_any = 0;
         if (wg == 0 && threadIdx.x == 0) {
-            p.rotflag[((sweep + 1) % 3) * a.h + s] = 0;
+            // read by every workgroup of the slice: a device-coherent store
+            __hip_atomic_store(p.rotflag + ((sweep + 1) % 3) * a.h + s, 0, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
             a.sweeps[s] = sweep + 1;
         }
         __syncthreads();
@@ -203,7 +230,9 @@ __global__ __launch_bounds__(PBW * PG) void jacobi_persistent_kernel(JacArgs<T> 
             if (last) {
                 if (nrot && l == 0) rot_any = 1;
                 __syncthreads();
-                if (threadIdx.x == 0 && rot_any) atomicOr(p.rotflag + (sweep % 3) * a.h + s, 1);
+                if (threadIdx.x == 0 && rot_any)
+                    __hip_atomic_fetch_or(p.rotflag + (sweep % 3) * a.h + s, 1, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
             }
             // the next round's players (after the last round: round 0 of the next sweep)
             const int nr = (rd + 1) % (a.nb - 1);
@@ -214,7 +243,7 @@ __global__ __launch_bounds__(PBW * PG) void jacobi_persistent_kernel(JacArgs<T> 
             if (next1 != player1) pstore_block<T, NT>(a, s, player1, mp, ldc, blk1);
             mark();
             arrivals += G;
-            if (!slice_barrier(counter, arrivals, p.err)) {
+            if (!slice_barrier(counter, arrivals, p.err, trace, &nev)) {
                 alive = false;
                 break;
             }
@@ -270,6 +299,10 @@ int persist_rpt(int m, int n) {
 
 size_t persist_lds(int rpt, int elem_bytes) { return 2 * (size_t)PBW * (kPG * rpt + 1) * 2 * elem_bytes; }
 
+int persist_grid(int h, int G, int xcds) {
+    return xcds > 0 ? xcds * ((h + xcds - 1) / xcds) * G : h * G;
+}
+
 template <typename T, int RPT>
 hipError_t launch_persist_t(const JacArgs<T>& a, const PersistArgs& p, size_t lds, hipStream_t st, int cus) {
     auto* fn = jacobi_persistent_kernel<T, kPG, RPT>;
@@ -278,7 +311,7 @@ hipError_t launch_persist_t(const JacArgs<T>& a, const PersistArgs& p, size_t ld
     int per_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, PBW * kPG, lds);
     if (e != hipSuccess) return e;
-    const int grid = a.h * (a.nb / 2);
+    const int grid = persist_grid(a.h, a.nb / 2, p.xcds);
     if ((int64_t)per_cu * cus < grid) return hipErrorCooperativeLaunchTooLarge;
     if (!p.cooperative) {
         // ordinary launch (profiler runs): the grid still fits one workgroup
@@ -297,18 +330,25 @@ hipError_t launch_persist_t(const JacArgs<T>& a, const PersistArgs& p, size_t ld
 
 int jacobi_persistent_blocks(int n) { return jacobi_num_blocks(n, PBW); }
 
-bool jacobi_persistent_fits(int m, int n, int h, int elem_bytes, int cus, size_t lds_cap) {
+bool jacobi_persistent_fits(int m, int n, int h, int elem_bytes, int cus, size_t lds_cap, int xcds) {
     const int rpt = persist_rpt(m, n);
     if (rpt < 0 || n < 2) return false;
     if (persist_lds(rpt, elem_bytes) + 256 > lds_cap) return false;
-    const int64_t grid = (int64_t)h * (jacobi_persistent_blocks(n) / 2);
+    const int64_t grid = persist_grid(h, jacobi_persistent_blocks(n) / 2, xcds);
     return grid <= (int64_t)cus;   // one workgroup per CU is always resident
 }
 
 template <typename T>
 hipError_t launch_jacobi_persistent(const JacArgs<T>& a, const PersistArgs& p, int cus, hipStream_t st) {
     const int rpt = persist_rpt(a.m, a.n);
-    const size_t lds = persist_lds(rpt, sizeof(T));
+    size_t lds = persist_lds(rpt, sizeof(T));
+    if (p.spread) {
+        // more than half of a CU's LDS: the dispatcher cannot pair workgroups on a CU
+        int cap = 0, dev = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cap, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev);
+        if ((size_t)cap / 2 + 1024 <= (size_t)cap) lds = std::max(lds, (size_t)cap / 2 + 1024);
+    }
     switch (rpt) {
         case 2: return launch_persist_t<T, 2>(a, p, lds, st, cus);
         case 3: return launch_persist_t<T, 3>(a, p, lds, st, cus);

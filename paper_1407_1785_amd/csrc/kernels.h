@@ -198,9 +198,11 @@ struct PersistArgs {
     int max_sweeps;
     long long* trace;  // optional: 64 timestamps of workgroup 0 of slice 0
     int cooperative;   // 1: cooperative launch (co-residency guaranteed by the runtime)
+    int xcds;          // > 0: workgroups of a slice share one XCD (workgroup b runs on XCD b mod xcds)
+    int spread;        // 1: reserve over half a CU's LDS, so no two workgroups share a CU
 };
 int jacobi_persistent_blocks(int n);
-bool jacobi_persistent_fits(int m, int n, int h, int elem_bytes, int cus, size_t lds_cap);
+bool jacobi_persistent_fits(int m, int n, int h, int elem_bytes, int cus, size_t lds_cap, int xcds);
 template <typename T>
 hipError_t launch_jacobi_persistent(const JacArgs<T>& a, const PersistArgs& p, int cus, hipStream_t st);
 
