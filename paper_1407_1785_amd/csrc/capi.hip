@@ -49,7 +49,7 @@ struct SvtBuffers {
     int* rank;
     int* rot;
     int* sweeps;
-    int* pbar;        // persistent Jacobi: h barrier counters, 3h flags, 1 error word
+    int* pbar;        // persistent Jacobi: h barrier counters, 3h flags, 1 error word, h x nb block flags
     double* partials;
     int nparts;
 };
@@ -72,7 +72,7 @@ size_t svt_bytes(const Geometry& g, int nparts) {
     b += 3 * vv * sizeof(cplx<T>) + 768;
     b += (int64_t)g.h * g.n * sizeof(double) + 256;
     b += (int64_t)g.h * 5 * sizeof(int) + 768;
-    b += (int64_t)(4 * g.h + 1) * sizeof(int) + 256;
+    b += (int64_t)(4 * g.h + 1 + (int64_t)g.h * (g.n + 2)) * sizeof(int) + 256;
     b += (int64_t)nparts * kNumPartials * sizeof(double) + 256;
     return b;
 }
@@ -91,7 +91,7 @@ SvtBuffers<T> carve_svt(Carver& c, const Geometry& g, int nparts) {
     s.rank = c.take<int>(g.h);
     s.rot = c.take<int>(3 * g.h);
     s.sweeps = c.take<int>(g.h);
-    s.pbar = c.take<int>(4 * g.h + 1);
+    s.pbar = c.take<int>(4 * g.h + 1 + (int64_t)g.h * (g.n + 2));
     s.partials = c.take<double>((int64_t)nparts * kNumPartials);
     s.nparts = nparts;
     return s;
@@ -297,8 +297,9 @@ SweepStats run_svt(tsvd_handle h, const Geometry& g, const SvtBuffers<T>& sb, in
                     [&] { launch_jacobi_init(ja, st); });
         launch_check("jacobi_init");
         launch_fill<int>(sb.pbar, 0, 4 * g.h, st);   // the error word is cleared per call
+        launch_fill<int>(sb.pbar + 4 * g.h + 1, 0, (int64_t)g.h * ja.nb, st);
         launch_check("fill");
-        PersistArgs pa{sb.pbar, sb.pbar + g.h, sb.pbar + 4 * g.h, max_sweeps, nullptr,
+        PersistArgs pa{sb.pbar, sb.pbar + g.h, sb.pbar + 4 * g.h, sb.pbar + 4 * g.h + 1, max_sweeps, nullptr,
                        env_int("TSVD_COOP", 1) != 0 ? 1 : 0, xcds, env_int("TSVD_SPREAD", 0)};
         static long long* trace_buf = nullptr;
         const bool tracing = env_int("TSVD_TRACE", 0) != 0;

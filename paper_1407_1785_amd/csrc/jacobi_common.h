@@ -265,10 +265,28 @@ __device__ __forceinline__ void coh_copy_out<double>(const cplx<double>* src, cp
     __hip_atomic_store(d + 1, s[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+template <typename T>
+__device__ __forceinline__ cplx<T> coh_load(const cplx<T>* src) {
+    cplx<T> v;
+    coh_copy_in<T>(src, &v);
+    return v;
+}
+
+// Eight coherent loads in flight per thread (addresses clamped in range;
+// rows past the end rewrite the last row with its own value).
 template <typename T, int NT, int BW>
-__device__ __forceinline__ void ccol_in(const cplx<T>* src, int len, cplx<T>* dst) {
+__device__ __forceinline__ void ccol_in(const cplx<T>* src, int len, cplx<T>* dst_c) {
     constexpr int TT = NT / BW;
-    for (int r = threadIdx.x % TT; r < len; r += TT) coh_copy_in<T>(src + r, dst + r);
+    vec2<T>* dst = reinterpret_cast<vec2<T>*>(dst_c);
+    const int t = threadIdx.x % TT;
+    for (int base = t; base < len; base += 8 * TT) {
+#define TSVD_LD(u) const cplx<T> v##u = coh_load<T>(src + min(base + (u) * TT, len - 1))
+        TSVD_LD(0); TSVD_LD(1); TSVD_LD(2); TSVD_LD(3); TSVD_LD(4); TSVD_LD(5); TSVD_LD(6); TSVD_LD(7);
+#undef TSVD_LD
+#define TSVD_ST(u) dst[min(base + (u) * TT, len - 1)] = vec2<T>{v##u.re, v##u.im}
+        TSVD_ST(0); TSVD_ST(1); TSVD_ST(2); TSVD_ST(3); TSVD_ST(4); TSVD_ST(5); TSVD_ST(6); TSVD_ST(7);
+#undef TSVD_ST
+    }
 }
 
 template <typename T, int NT, int BW>

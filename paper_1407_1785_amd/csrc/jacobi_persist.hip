@@ -21,10 +21,13 @@
 // exactly at the start of every round and tracked through the rotations of
 // the round (a rotation moves t |gamma| from one squared norm to the other).
 //
-// Synchronisation.  The per-slice barrier is a counter in global memory:
-// each workgroup writes its moving blocks with device-coherent stores, waits
-// for their completion, increments the counter and waits for G arrivals per
-// round; blocks are read back with device-coherent loads.  The launch is
+// Synchronisation.  Blocks travel through global memory with device-
+// coherent stores and loads.  Within a sweep, a workgroup that has written a
+// block waits for the stores to complete and then sets the block's flag to
+// the index of the round that takes it next; a workgroup waits only on the
+// flags of the two blocks it takes next.  At the end of a sweep all
+// workgroups of the slice meet at a counter barrier (the stopping decision
+// needs every workgroup's rotation flag).  Every wait is bounded.  The launch is
 // cooperative, so all workgroups are co-resident; the wait is also bounded
 // (a spin limit sets an error flag and lets the kernel finish, so a launch
 // can never hang).
@@ -97,6 +100,20 @@ __device__ bool slice_barrier(int* counter, int target, int* err, long long* tr 
     return ok != 0;
 }
 
+// Bounded wait (thread 0) until a block flag reaches `value`; false if the
+// wait ran out or another workgroup gave up.
+__device__ bool wait_flag(int* flag, int value, int* err) {
+    long long spins = 0;
+    while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < value) {
+        __builtin_amdgcn_s_sleep(1);
+        if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 || ++spins > kSpinLimit) {
+            __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+    }
+    return true;
+}
+
 }  // namespace
 
 template <typename T, int PG, int RPT>
@@ -105,6 +122,7 @@ __global__ __launch_bounds__(PBW * PG) void jacobi_persistent_kernel(JacArgs<T> 
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int rot_any;
     __shared__ int stop;
+    __shared__ int ok_flag;
     __shared__ double jnorm[PBW];
     const int G = a.nb / 2;
     int s, wg;
@@ -242,13 +260,15 @@ __global__ __launch_bounds__(PBW * PG) void jacobi_persistent_kernel(JacArgs<T> 
             if (next0 != player0) pstore_block<T, NT>(a, s, player0, mp, ldc, blk0);
             if (next1 != player1) pstore_block<T, NT>(a, s, player1, mp, ldc, blk1);
             mark();
-            arrivals += G;
-            if (!slice_barrier(counter, arrivals, p.err, trace, &nev)) {
-                alive = false;
-                break;
-            }
-            mark();
             if (last) {
+                // end of the sweep: every workgroup of the slice meets, then all
+                // read the same rotation flag and stop together when it is clear
+                arrivals += G;
+                if (!slice_barrier(counter, arrivals, p.err, trace, &nev)) {
+                    alive = false;
+                    break;
+                }
+                mark();
                 if (threadIdx.x == 0) stop = __hip_atomic_load(p.rotflag + (sweep % 3) * a.h + s,
                                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
                 __syncthreads();
@@ -256,6 +276,28 @@ __global__ __launch_bounds__(PBW * PG) void jacobi_persistent_kernel(JacArgs<T> 
                     // converged: the blocks that did not move go home too
                     if (next0 == player0) pstore_block<T, NT>(a, s, player0, mp, ldc, blk0);
                     if (next1 == player1) pstore_block<T, NT>(a, s, player1, mp, ldc, blk1);
+                    alive = false;
+                    break;
+                }
+            } else {
+                // within a sweep: publish the blocks written (ready for round R + 1)
+                // and wait only for the two blocks this workgroup takes next
+                const int R = sweep * (a.nb - 1) + rd;
+                int* const bf = p.bflag + s * a.nb;
+                __builtin_amdgcn_s_waitcnt(0);
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    ok_flag = 1;
+                    if (next0 != player0) __hip_atomic_store(bf + player0, R + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (next1 != player1) __hip_atomic_store(bf + player1, R + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    mark();
+                    if ((next0 != player0 && !wait_flag(bf + next0, R + 1, p.err)) ||
+                        (next1 != player1 && !wait_flag(bf + next1, R + 1, p.err)))
+                        ok_flag = 0;
+                    mark();
+                }
+                __syncthreads();
+                if (!ok_flag) {
                     alive = false;
                     break;
                 }

@@ -195,6 +195,7 @@ struct PersistArgs {
     int* barrier;    // h arrival counters, zero before the launch
     int* rotflag;    // 3 x h sweep flags, zero before the launch
     int* err;        // set to 1 if a barrier wait ran out
+    int* bflag;      // h x nb block-ready flags, zero before the launch
     int max_sweeps;
     long long* trace;  // optional: 64 timestamps of workgroup 0 of slice 0
     int cooperative;   // 1: cooperative launch (co-residency guaranteed by the runtime)
