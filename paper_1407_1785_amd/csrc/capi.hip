@@ -46,6 +46,7 @@ struct SvtBuffers {
     cplx<T>* V[2];    // right singular vectors, ping-pong for re-orthonormalisation
     cplx<T>* G;       // n x n Gram scratch
     double* sigma;    // h x n singular values (FP64)
+    double* dk;       // h x n shrink factors
     int* rank;
     int* rot;
     int* sweeps;
@@ -70,7 +71,7 @@ size_t svt_bytes(const Geometry& g, int nparts) {
     size_t b = 0;
     b += 2 * slice * sizeof(cplx<T>) + 512;
     b += 3 * vv * sizeof(cplx<T>) + 768;
-    b += (int64_t)g.h * g.n * sizeof(double) + 256;
+    b += 2 * (int64_t)g.h * g.n * sizeof(double) + 512;
     b += (int64_t)g.h * 5 * sizeof(int) + 768;
     b += (int64_t)(4 * g.h + 1 + (int64_t)g.h * (g.n + 2)) * sizeof(int) + 256;
     b += (int64_t)nparts * kNumPartials * sizeof(double) + 256;
@@ -88,6 +89,7 @@ SvtBuffers<T> carve_svt(Carver& c, const Geometry& g, int nparts) {
     s.V[1] = c.take<cplx<T>>(vv);
     s.G = c.take<cplx<T>>(vv);
     s.sigma = c.take<double>((int64_t)g.h * g.n);
+    s.dk = c.take<double>((int64_t)g.h * g.n);
     s.rank = c.take<int>(g.h);
     s.rot = c.take<int>(3 * g.h);
     s.sweeps = c.take<int>(g.h);
@@ -383,7 +385,7 @@ SweepStats run_svt(tsvd_handle h, const Geometry& g, const SvtBuffers<T>& sb, in
     // sigma_j = ||w_j||, then Zhat = W diag((1 - tau/sigma)_+) V^H on the matrix cores
     const int64_t slice_bytes = (int64_t)g.h * g.m * g.n * sizeof(cplx<T>);
     prof_launch(h, K_SVT_W, (double)slice_bytes + (double)g.h * g.n * sizeof(double),
-                [&] { launch_svt_sigma(work, g.m, g.n, g.h, sb.sigma, st); });
+                [&] { launch_svt_sigma(work, g.m, g.n, g.h, sb.sigma, sb.dk, h->ctrl, st); });
     launch_check("svt_sigma");
     ZGemmArgs<T> gr{};
     gr.A = work; gr.B = sb.V[vc]; gr.C = out;
@@ -391,7 +393,7 @@ SweepStats run_svt(tsvd_handle h, const Geometry& g, const SvtBuffers<T>& sb, in
     gr.lda = g.m; gr.ldb = g.n; gr.ldc = g.m; gr.ldd = g.m;
     gr.sA = mn; gr.sB = nn; gr.sC = mn; gr.sD = mn;
     gr.alpha = (T)1; gr.beta = (T)0; gr.opA = 0; gr.opB = 1; gr.batch = g.h;
-    gr.sigma = sb.sigma; gr.ssig = g.n; gr.ctrl = h->ctrl;
+    gr.dk = sb.dk; gr.sdk = g.n; gr.ctrl = h->ctrl;
     gr.bf16x3 = env_int("TSVD_REBUILD_BF16", 0);
     prof_launch(h, K_SVT_REBUILD, 8.0 * g.m * g.n * g.n * g.h, [&] { launch_zgemm(gr, st); });
     launch_check("svt_rebuild");

@@ -101,6 +101,7 @@ struct Slot {
     cplx<T>* V[2] = {};
     cplx<T>* G = nullptr;
     double* sigma = nullptr;
+    double* dk = nullptr;       // shrink factors of the rebuild
     int* sweeps = nullptr;
     int* rot = nullptr;         // round-mode Jacobi: 3 x h rotation flags
     double* partials = nullptr;
@@ -139,6 +140,7 @@ size_t slot_layout(Slot<T>& sl, char* base) {
     sl.V[1] = reinterpret_cast<cplx<T>*>(take(vv * sizeof(cplx<T>)));
     sl.G = reinterpret_cast<cplx<T>*>(take(vv * sizeof(cplx<T>)));
     sl.sigma = reinterpret_cast<double*>(take((int64_t)g.h * g.n * sizeof(double)));
+    sl.dk = reinterpret_cast<double*>(take((int64_t)g.h * g.n * sizeof(double)));
     sl.sweeps = reinterpret_cast<int*>(take((int64_t)g.h * sizeof(int)));
     sl.rot = reinterpret_cast<int*>(take((int64_t)3 * g.h * sizeof(int)));
     sl.partials = reinterpret_cast<double*>(take((int64_t)nparts * kNumPartials * sizeof(double)));
@@ -616,7 +618,7 @@ private:
             sc.first = std::max(sc.first, sl.nb);
             sc.second = std::max(sc.second, sl.sp.s.max_sweeps);
             // singular values and rebuild A = W diag(d) V'^H
-            SigmaArgs<T> sa{sl.W, g.m, g.n, g.h, sl.sigma, sl.ctrl};
+            SigmaArgs<T> sa{sl.W, g.m, g.n, g.h, sl.sigma, sl.dk, sl.ctrl};
             sig.push_back(sa);
             ws_sig.push_back(ws_sig.back() + svt_sigma_workgroups(g.n, g.h));
             ZGemmArgs<T> gr = ga;
@@ -624,8 +626,8 @@ private:
             gr.B = sl.V[Q];
             gr.C = sl.A;
             gr.opB = 1;
-            gr.sigma = sl.sigma;
-            gr.ssig = g.n;
+            gr.dk = sl.dk;
+            gr.sdk = g.n;
             reb.push_back(gr);
             ws_reb.push_back(ws_reb.back() + zgemm_workgroups(g.m, g.n, g.h));
             // inverse DFT + epilogue

@@ -90,7 +90,7 @@ struct JacArgs {
 // C[s] = alpha * op(A[s]) * diag(d[s]) * op(B[s]) + beta * D[s] over `batch`
 // slices, column-major complex, on the matrix cores (zgemm.hip).
 // op = 0: as stored; op = 1: conjugate transpose (A stored K x M, B N x K).
-// With sigma set, d_k = (1 - tau / sigma_k)_+ with tau = ctrl->tau; else d = 1.
+// dk: optional per-slice factors d_k (K per slice, stride sdk); else d = 1.
 template <typename T>
 struct ZGemmArgs {
     const cplx<T>* A;
@@ -102,9 +102,9 @@ struct ZGemmArgs {
     int M, N, K, batch;
     int opA, opB;
     T alpha, beta;
-    const double* sigma;   // optional, K per slice, stride ssig
-    int64_t ssig;
-    const Ctrl* ctrl;      // tau (with sigma); problem-table launches skip the problem once done
+    const double* dk;      // optional column factors, K per slice, stride sdk
+    int64_t sdk;
+    const Ctrl* ctrl;      // problem-table launches skip the problem once ctrl->done
     int bf16x3;            // float only: 1 = bf16 split products, 0 = FP32 products
 };
 
@@ -147,14 +147,16 @@ struct SigmaArgs {
     const cplx<T>* W;
     int m, n, h;
     double* sigma;
-    const Ctrl* ctrl;   // skip the problem once done
+    double* dk;         // shrink factors (1 - tau/sigma)_+, tau = ctrl->tau
+    const Ctrl* ctrl;   // tau; skip the problem once done
 };
 int svt_sigma_workgroups(int n, int h);
 template <typename T>
 void launch_svt_sigma_batched(const SigmaArgs<T>* tab, const int* wg_start, int nprob, int nwg, hipStream_t st);
 
 template <typename T>
-void launch_svt_sigma(const cplx<T>* W, int m, int n, int h, double* sigma, hipStream_t st);
+void launch_svt_sigma(const cplx<T>* W, int m, int n, int h, double* sigma, double* dk, const Ctrl* ctrl,
+                      hipStream_t st);
 
 template <typename T>
 void launch_dft_forward(int prologue, const FwdArgs<T>& a, hipStream_t st);

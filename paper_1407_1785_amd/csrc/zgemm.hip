@@ -6,9 +6,9 @@
 //
 // Users:
 //   * the rebuild of the shrinkage lemma (Sec. 4.1): Zhat = W diag(d) V^H
-//     with d_k = (1 - tau / sigma_k)_+ computed from the singular values
-//     while W is staged, so no compaction pass is needed (dropped columns
-//     get d = 0 exactly);
+//     with the shrink factors d_k = (1 - tau / sigma_k)_+ (written by the
+//     singular-value kernel) applied while W is staged, so no compaction
+//     pass is needed (dropped columns get d = 0 exactly);
 //   * the warm start of the Jacobi SVD: the pre-rotation A V_prev and the
 //     Newton-Schulz step V <- 1.5 V - 0.5 V (V^H V).
 //
@@ -46,26 +46,11 @@ typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 constexpr int TM = 64, TN = 64;
 
-// Element (r, k) of an R x K operand view of X, zero outside [0,R) x [0,K).
-//   kcontig == false: X stored R x K column-major, (r, k) at k * ld + r;
-//   kcontig == true:  X stored K x R column-major, (r, k) at r * ld + k.
-template <typename T>
-__device__ __forceinline__ cplx<T> view_elem(const cplx<T>* X, int ld, bool kcontig, bool conj, int r, int k,
-                                             int R, int K) {
-    cplx<T> v{(T)0, (T)0};
-    if (r < R && k < K) {
-        v = kcontig ? X[(int64_t)r * ld + k] : X[(int64_t)k * ld + r];
-        if (conj) v.im = -v.im;
-    }
-    return v;
-}
-
-__device__ __forceinline__ double shrink_factor(const double* sigma, int k, int K, double tau) {
-    if (k >= K) return 0.0;
-    const double sg = sigma[k];
-    return sg > tau ? 1.0 - tau / sg : 0.0;
-}
-
+// Operand views: element (r, k) of an R x K view of X is at k * ld + r
+// (stored R x K column-major) or at r * ld + k (kcontig: stored K x R),
+// conjugated for the op = H operands, zero outside [0,R) x [0,K).  Staging
+// clamps the address into the matrix and masks the value afterwards, so all
+// loads of a pass are in flight together.
 // ---- K = 4 per MFMA (FP64, or exact FP32), stage [k][r] -----------------
 
 constexpr int KC4 = 32, PAD4 = 1;
@@ -89,32 +74,35 @@ __device__ __forceinline__ void slot4(bool kcontig, int q, int& rr, int& kk) {
     }
 }
 
-// Load this thread's share of a 64 x KC4 block (scaled by d_k when sigma is set).
+// Issue the loads of this thread's share of a 64 x KC4 block (and of the
+// column factors d_k when dk is set).  Nothing is done with the values
+// here, so the loads of the next chunk stay in flight while the current
+// chunk is multiplied; store4 masks, conjugates, scales and writes them.
 template <typename T>
-__device__ __forceinline__ void load4(const cplx<T>* X, int ld, bool kcontig, bool conj, int r0, int k0, int R,
-                                      int K, const double* sigma, double tau, cplx<T> (&v)[LD4]) {
+__device__ __forceinline__ void load4(const cplx<T>* X, int ld, bool kcontig, int r0, int k0, int R, int K,
+                                      const double* dk, cplx<T> (&v)[LD4], double (&dv)[LD4]) {
 #pragma unroll
     for (int q = 0; q < LD4; ++q) {
         int rr, kk;
         slot4(kcontig, q, rr, kk);
-        v[q] = view_elem(X, ld, kcontig, conj, r0 + rr, k0 + kk, R, K);
-        if (sigma) {
-            const T dk = (T)shrink_factor(sigma, k0 + kk, K, tau);
-            v[q].re *= dk;
-            v[q].im *= dk;
-        }
+        const int rc = min(r0 + rr, R - 1), kc = min(k0 + kk, K - 1);
+        v[q] = X[kcontig ? (int64_t)rc * ld + kc : (int64_t)kc * ld + rc];
+        if (dk) dv[q] = dk[kc];
     }
 }
 
 template <typename T>
-__device__ __forceinline__ void store4(bool kcontig, const cplx<T> (&v)[LD4], T (*re)[TM + PAD4],
+__device__ __forceinline__ void store4(bool kcontig, bool conj, int r0, int k0, int R, int K, bool scaled,
+                                       const cplx<T> (&v)[LD4], const double (&dv)[LD4], T (*re)[TM + PAD4],
                                        T (*im)[TM + PAD4]) {
 #pragma unroll
     for (int q = 0; q < LD4; ++q) {
         int rr, kk;
         slot4(kcontig, q, rr, kk);
-        re[kk][rr] = v[q].re;
-        im[kk][rr] = v[q].im;
+        const bool in = r0 + rr < R && k0 + kk < K;
+        const T f = in ? (scaled ? (T)dv[q] : (T)1) : (T)0;
+        re[kk][rr] = f * v[q].re;
+        im[kk][rr] = f * (conj ? -v[q].im : v[q].im);
     }
 }
 
@@ -152,8 +140,7 @@ __device__ __forceinline__ void zgemm_k4_body(const ZGemmArgs<T>& g, int bx, int
     const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
     const cplx<T>* A = g.A + (int64_t)s * g.sA;
     const cplx<T>* B = g.B + (int64_t)s * g.sB;
-    const double* sigma = g.sigma ? g.sigma + (int64_t)s * g.ssig : nullptr;
-    const double tau = sigma ? g.ctrl->tau : 0.0;
+    const double* dk = g.dk ? g.dk + (int64_t)s * g.sdk : nullptr;
 
     acc_t cr[2][2], ci[2][2];
 #pragma unroll
@@ -165,15 +152,16 @@ __device__ __forceinline__ void zgemm_k4_body(const ZGemmArgs<T>& g, int bx, int
     // op(B)^T as an N x K view: op N -> B stored K x N (k-contiguous); op H -> stored N x K, conj.
     const bool akc = g.opA != 0, bkc = g.opB == 0;
     cplx<T> va[LD4], vb[LD4];
-    load4<T>(A, g.lda, akc, g.opA != 0, row0, 0, g.M, g.K, sigma, tau, va);
-    load4<T>(B, g.ldb, bkc, g.opB != 0, col0, 0, g.N, g.K, nullptr, 0.0, vb);
+    double da[LD4], db[LD4];
+    load4<T>(A, g.lda, akc, row0, 0, g.M, g.K, dk, va, da);
+    load4<T>(B, g.ldb, bkc, col0, 0, g.N, g.K, nullptr, vb, db);
     for (int k0 = 0; k0 < g.K; k0 += KC4) {
-        store4<T>(akc, va, sm.ar, sm.ai);
-        store4<T>(bkc, vb, sm.br, sm.bi);
+        store4<T>(akc, g.opA != 0, row0, k0, g.M, g.K, dk != nullptr, va, da, sm.ar, sm.ai);
+        store4<T>(bkc, g.opB != 0, col0, k0, g.N, g.K, false, vb, db, sm.br, sm.bi);
         __syncthreads();
         if (k0 + KC4 < g.K) {   // prefetch the next chunk while this one is multiplied
-            load4<T>(A, g.lda, akc, g.opA != 0, row0, k0 + KC4, g.M, g.K, sigma, tau, va);
-            load4<T>(B, g.ldb, bkc, g.opB != 0, col0, k0 + KC4, g.N, g.K, nullptr, 0.0, vb);
+            load4<T>(A, g.lda, akc, row0, k0 + KC4, g.M, g.K, dk, va, da);
+            load4<T>(B, g.ldb, bkc, col0, k0 + KC4, g.N, g.K, nullptr, vb, db);
         }
 #pragma unroll
         for (int kk = 0; kk < KC4; kk += 4) {
@@ -186,13 +174,20 @@ __device__ __forceinline__ void zgemm_k4_body(const ZGemmArgs<T>& g, int bx, int
                 b_r[x] = sm.br[kq][wc + 16 * x + c16];
                 b_i[x] = sm.bi[kq][wc + 16 * x + c16];
             }
+            // four passes over the eight accumulators: consecutive MFMAs never
+            // depend on each other
 #pragma unroll
             for (int x = 0; x < 2; ++x)
 #pragma unroll
                 for (int y = 0; y < 2; ++y) {
                     cr[x][y] = M::mma(b_r[y], a_r[x], cr[x][y]);
-                    cr[x][y] = M::mma(-b_i[y], a_i[x], cr[x][y]);
                     ci[x][y] = M::mma(b_r[y], a_i[x], ci[x][y]);
+                }
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+#pragma unroll
+                for (int y = 0; y < 2; ++y) {
+                    cr[x][y] = M::mma(-b_i[y], a_i[x], cr[x][y]);
                     ci[x][y] = M::mma(b_i[y], a_r[x], ci[x][y]);
                 }
         }
@@ -201,23 +196,39 @@ __device__ __forceinline__ void zgemm_k4_body(const ZGemmArgs<T>& g, int bx, int
 
     cplx<T>* C = g.C + (int64_t)s * g.sC;
     const cplx<T>* D = g.D ? g.D + (int64_t)s * g.sD : nullptr;
+    // beta * D first, from clamped addresses (all loads in flight), then the
+    // guarded stores
+    cplx<T> dv[2][2][4];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) dv[x][y][v] = cplx<T>{(T)0, (T)0};
+    if (D) {
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
+            const int rowc = min(row0 + wr + 16 * x + (lane & 15), g.M - 1);
+#pragma unroll
+            for (int y = 0; y < 2; ++y)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int colc = min(col0 + wc + 16 * y + M::col(lane, v), g.N - 1);
+                    dv[x][y][v] = D[(int64_t)colc * g.ldd + rowc];
+                }
+        }
+    }
 #pragma unroll
     for (int x = 0; x < 2; ++x) {
         const int row = row0 + wr + 16 * x + (lane & 15);
-        if (row >= g.M) continue;
 #pragma unroll
         for (int y = 0; y < 2; ++y)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int col = col0 + wc + 16 * y + M::col(lane, v);
-                if (col >= g.N) continue;
-                T re = g.alpha * cr[x][y][v], im = g.alpha * ci[x][y][v];
-                if (D) {
-                    const cplx<T> d = D[(int64_t)col * g.ldd + row];
-                    re += g.beta * d.re;
-                    im += g.beta * d.im;
-                }
-                C[(int64_t)col * g.ldc + row] = cplx<T>{re, im};
+                const T re = g.alpha * cr[x][y][v] + g.beta * dv[x][y][v].re;
+                const T im = g.alpha * ci[x][y][v] + g.beta * dv[x][y][v].im;
+                if (row < g.M && col < g.N) C[(int64_t)col * g.ldc + row] = cplx<T>{re, im};
             }
     }
 }
@@ -241,26 +252,34 @@ __device__ __forceinline__ void split_store(__bf16 (*dst)[TM][KC16 + PAD16], int
 }
 
 __device__ __forceinline__ void stage16(const cplx<float>* X, int ld, bool kcontig, bool conj, int r0, int k0,
-                                        int R, int K, __bf16 (*dst)[TM][KC16 + PAD16], const double* sigma,
-                                        double tau) {
+                                        int R, int K, __bf16 (*dst)[TM][KC16 + PAD16], const double* dk) {
     const int t = threadIdx.x;
+    cplx<float> v[8];
+    double dv[8];
+    int rr[8], kk[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-        int rr, kk;
         if (kcontig) {
-            kk = t % KC16;
-            rr = t / KC16 + 8 * q;
+            kk[q] = t % KC16;
+            rr[q] = t / KC16 + 8 * q;
         } else {
-            rr = t % TM;
-            kk = t / TM + 4 * q;
+            rr[q] = t % TM;
+            kk[q] = t / TM + 4 * q;
         }
-        cplx<float> v = view_elem(X, ld, kcontig, conj, r0 + rr, k0 + kk, R, K);
-        if (sigma) {
-            const float dk = (float)shrink_factor(sigma, k0 + kk, K, tau);
-            v.re *= dk;
-            v.im *= dk;
+        const int rc = min(r0 + rr[q], R - 1), kc = min(k0 + kk[q], K - 1);
+        v[q] = X[kcontig ? (int64_t)rc * ld + kc : (int64_t)kc * ld + rc];
+        if (dk) dv[q] = dk[kc];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const bool in = r0 + rr[q] < R && k0 + kk[q] < K;
+        v[q].re = in ? v[q].re : 0.f;
+        v[q].im = in ? (conj ? -v[q].im : v[q].im) : 0.f;
+        if (dk) {
+            v[q].re *= (float)dv[q];
+            v[q].im *= (float)dv[q];
         }
-        split_store(dst, rr, kk, v.re, v.im);
+        split_store(dst, rr[q], kk[q], v[q].re, v[q].im);
     }
 }
 
@@ -284,8 +303,7 @@ __device__ __forceinline__ void zgemm_bf16x3_body(const ZGemmArgs<float>& g, int
     const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
     const cplx<float>* A = g.A + (int64_t)s * g.sA;
     const cplx<float>* B = g.B + (int64_t)s * g.sB;
-    const double* sigma = g.sigma ? g.sigma + (int64_t)s * g.ssig : nullptr;
-    const double tau = sigma ? g.ctrl->tau : 0.0;
+    const double* dk = g.dk ? g.dk + (int64_t)s * g.sdk : nullptr;
 
     v4f cr[2][2], ci[2][2];
 #pragma unroll
@@ -294,8 +312,8 @@ __device__ __forceinline__ void zgemm_bf16x3_body(const ZGemmArgs<float>& g, int
         for (int b = 0; b < 2; ++b) cr[a][b] = ci[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
 
     for (int k0 = 0; k0 < g.K; k0 += KC16) {
-        stage16(A, g.lda, g.opA != 0, g.opA != 0, row0, k0, g.M, g.K, sm.a, sigma, tau);
-        stage16(B, g.ldb, g.opB == 0, g.opB != 0, col0, k0, g.N, g.K, sm.b, nullptr, 0.0);
+        stage16(A, g.lda, g.opA != 0, g.opA != 0, row0, k0, g.M, g.K, sm.a, dk);
+        stage16(B, g.ldb, g.opB == 0, g.opB != 0, col0, k0, g.N, g.K, sm.b, nullptr);
         __syncthreads();
         const int kq = 8 * (lane >> 4), c16 = lane & 15;
         v8bf arh[2], arl[2], aih[2], ail[2];
@@ -336,23 +354,39 @@ __device__ __forceinline__ void zgemm_bf16x3_body(const ZGemmArgs<float>& g, int
 
     cplx<float>* C = g.C + (int64_t)s * g.sC;
     const cplx<float>* D = g.D ? g.D + (int64_t)s * g.sD : nullptr;
+    // beta * D first, from clamped addresses (all loads in flight), then the
+    // guarded stores
+    cplx<float> dv[2][2][4];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) dv[x][y][v] = cplx<float>{(float)0, (float)0};
+    if (D) {
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
+            const int rowc = min(row0 + wr + 16 * x + (lane & 15), g.M - 1);
+#pragma unroll
+            for (int y = 0; y < 2; ++y)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int colc = min(col0 + wc + 16 * y + Mfma4<float>::col(lane, v), g.N - 1);
+                    dv[x][y][v] = D[(int64_t)colc * g.ldd + rowc];
+                }
+        }
+    }
 #pragma unroll
     for (int x = 0; x < 2; ++x) {
         const int row = row0 + wr + 16 * x + (lane & 15);
-        if (row >= g.M) continue;
 #pragma unroll
         for (int y = 0; y < 2; ++y)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int col = col0 + wc + 16 * y + Mfma4<float>::col(lane, v);
-                if (col >= g.N) continue;
-                float re = g.alpha * cr[x][y][v], im = g.alpha * ci[x][y][v];
-                if (D) {
-                    const cplx<float> d = D[(int64_t)col * g.ldd + row];
-                    re += g.beta * d.re;
-                    im += g.beta * d.im;
-                }
-                C[(int64_t)col * g.ldc + row] = cplx<float>{re, im};
+                const float re = g.alpha * cr[x][y][v] + g.beta * dv[x][y][v].re;
+                const float im = g.alpha * ci[x][y][v] + g.beta * dv[x][y][v].im;
+                if (row < g.M && col < g.N) C[(int64_t)col * g.ldc + row] = cplx<float>{re, im};
             }
     }
 }
