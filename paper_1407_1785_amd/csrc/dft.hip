@@ -76,23 +76,49 @@ __device__ __forceinline__ void dft_forward_body(const FwdArgs<T>& a, int bid, u
     const int nrow = min(tile, g.m - row0);
     const double ds = (PRO == PRO_COPY) ? 1.0 : a.ctrl->dscale;
 
+    // the prox input of U elements per thread per pass: every load is issued
+    // (at clamped indices) before any value is used
+    constexpr int U = 8;
+    const int total = nrow * L;
     bool bad = false;
-    for (int idx = threadIdx.x; idx < nrow * L; idx += blockDim.x) {
-        const int r = idx / L, t = idx - r * L;
-        const int64_t e = tube_offset<T>(g, row0 + r, col) + t;
-        T v;
-        if (PRO == PRO_COPY) {
-            v = a.x[e];
-        } else if (PRO == PRO_COMPLETE) {
-            const T q = (T)(ds * (double)a.dual[e]);
-            const T x = a.mask[e] ? a.x[e] : (T)(a.z[e] - q);
-            v = x + q;
-        } else {
-            const T w = (T)(ds * (double)a.dual[e]);
-            v = (a.x[e] - a.s[e]) - w;
+    for (int base = threadIdx.x; base < total; base += U * (int)blockDim.x) {
+        T xv[U], zv[U], qv[U];
+        uint8_t mv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int idx = min(base + u * (int)blockDim.x, total - 1);
+            const int r = idx / L, t = idx - r * L;
+            const int64_t e = tube_offset<T>(g, row0 + r, col) + t;
+            xv[u] = a.x[e];
+            if (PRO == PRO_COMPLETE) {
+                zv[u] = a.z[e];
+                qv[u] = a.dual[e];
+                mv[u] = a.mask[e];
+            } else if (PRO == PRO_RPCA) {
+                zv[u] = a.s[e];
+                qv[u] = a.dual[e];
+            }
         }
-        bad |= !isfinite(v);
-        buf[r * ldb + t] = v;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int idx = base + u * (int)blockDim.x;
+            T v;
+            if (PRO == PRO_COPY) {
+                v = xv[u];
+            } else if (PRO == PRO_COMPLETE) {
+                const T q = (T)(ds * (double)qv[u]);
+                const T x = mv[u] ? xv[u] : (T)(zv[u] - q);
+                v = x + q;
+            } else {
+                const T w = (T)(ds * (double)qv[u]);
+                v = (xv[u] - zv[u]) - w;
+            }
+            if (idx < total) {
+                const int r = idx / L, t = idx - r * L;
+                bad |= !isfinite(v);
+                buf[r * ldb + t] = v;
+            }
+        }
     }
     if (bad) *a.nonfinite = 1;
     __syncthreads();
@@ -143,9 +169,11 @@ __device__ __forceinline__ void dft_inverse_body(const InvArgs<T>& a, int bid, u
     const int row0 = (bid - col * row_tiles) * tile;
     const int nrow = min(tile, g.m - row0);
 
+    // rows past nrow repeat the last row (never read): no branch around the loads
+#pragma unroll 4
     for (int idx = threadIdx.x; idx < h * tile; idx += blockDim.x) {
-        const int s = idx / tile, r = idx - s * tile;
-        if (r < nrow) zb[idx] = a.in[((int64_t)s * g.n + col) * g.m + row0 + r];
+        const int s = idx / tile, r = min(idx - s * tile, nrow - 1);
+        zb[idx] = a.in[((int64_t)s * g.n + col) * g.m + row0 + r];
     }
     __syncthreads();
 
@@ -180,15 +208,37 @@ __device__ __forceinline__ void dft_inverse_body(const InvArgs<T>& a, int bid, u
         return acc * inv_l;
     };
 
+    // U elements per thread per pass: the loads of a pass are issued (at
+    // clamped indices) before the DFT sums that consume them
+    constexpr int U = 4;
+    const int total = nrow * L;
+    auto elem = [&](int idx, int& r, int& t) -> int64_t {
+        r = idx / L;
+        t = idx - r * L;
+        return tube_offset<T>(g, row0 + r, col) + t;
+    };
     if (EPI == EPI_RPCA_L112) {
         // pass 1: prox output and D = M - W - L' into LDS
-        for (int idx = threadIdx.x; idx < nrow * L; idx += blockDim.x) {
-            const int r = idx / L, t = idx - r * L;
-            const int64_t e = tube_offset<T>(g, row0 + r, col) + t;
-            const T lv = synth(r, t);
-            const T w = (T)(ds * (double)a.dual_old[e]);
-            lb[idx] = lv;
-            db[idx] = (a.m[e] - w) - lv;
+        for (int base = threadIdx.x; base < total; base += U * (int)blockDim.x) {
+            T mv[U], wv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                int r, t;
+                const int64_t e = elem(min(base + u * (int)blockDim.x, total - 1), r, t);
+                mv[u] = a.m[e];
+                wv[u] = a.dual_old[e];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int idx = base + u * (int)blockDim.x;
+                if (idx >= total) continue;
+                int r, t;
+                (void)elem(idx, r, t);
+                const T lv = synth(r, t);
+                const T w = (T)(ds * (double)wv[u]);
+                lb[idx] = lv;
+                db[idx] = (mv[u] - w) - lv;
+            }
         }
         __syncthreads();
         // pass 2: per-tube shrink factor (1 - thr / ||D(i,j,:)||)_+, 0 for a zero tube
@@ -200,50 +250,87 @@ __device__ __forceinline__ void dft_inverse_body(const InvArgs<T>& a, int bid, u
             fac[r] = nrm > (T)0 ? (T)fmax((T)1 - (T)thr / nrm, (T)0) : (T)0;
         }
         __syncthreads();
-        for (int idx = threadIdx.x; idx < nrow * L; idx += blockDim.x) {
-            const int r = idx / L, t = idx - r * L;
-            const int64_t e = tube_offset<T>(g, row0 + r, col) + t;
-            const T lv = lb[idx];
-            const T sn = db[idx] * fac[r];
-            const T mv = a.m[e];
-            const T w = (T)(ds * (double)a.dual_old[e]);
-            const T wt = ((w + lv) + sn) - mv;
-            a.out[e] = lv;
-            a.s_new[e] = sn;
-            a.dual_new[e] = wt;
-            part[0] += (double)sq((lv + sn) - mv);
-            part[1] += (double)sq(lv - a.l_old[e]);
-            part[2] += (double)sq(sn - a.s_old[e]);
-        }
-    } else {
-        for (int idx = threadIdx.x; idx < nrow * L; idx += blockDim.x) {
-            const int r = idx / L, t = idx - r * L;
-            const int64_t e = tube_offset<T>(g, row0 + r, col) + t;
-            const T zv = synth(r, t);
-            if (EPI == EPI_STORE) {
-                a.out[e] = zv;
-            } else if (EPI == EPI_COMPLETE) {
-                const T zo = a.z_old[e];
-                const T q = (T)(ds * (double)a.dual_old[e]);
-                const T x = a.mask[e] ? a.y[e] : (T)(zo - q);
-                const T qt = (q + x) - zv;
-                a.out[e] = zv;
-                a.dual_new[e] = qt;
-                part[0] += (double)sq(x - zv);
-                part[1] += (double)sq(zv - zo);
-            } else {  // EPI_RPCA_L1
-                const T mv = a.m[e];
-                const T w = (T)(ds * (double)a.dual_old[e]);
-                const T d = (mv - w) - zv;
-                const T mag = (T)fmax(fabs(d) - (T)thr, (T)0);
-                const T sn = d > (T)0 ? mag : (d < (T)0 ? -mag : (T)0);
-                const T wt = ((w + zv) + sn) - mv;
-                a.out[e] = zv;
+        for (int base = threadIdx.x; base < total; base += U * (int)blockDim.x) {
+            T mv[U], wv[U], lo[U], so[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                int r, t;
+                const int64_t e = elem(min(base + u * (int)blockDim.x, total - 1), r, t);
+                mv[u] = a.m[e];
+                wv[u] = a.dual_old[e];
+                lo[u] = a.l_old[e];
+                so[u] = a.s_old[e];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int idx = base + u * (int)blockDim.x;
+                if (idx >= total) continue;
+                int r, t;
+                const int64_t e = elem(idx, r, t);
+                const T lv = lb[idx];
+                const T sn = db[idx] * fac[r];
+                const T w = (T)(ds * (double)wv[u]);
+                const T wt = ((w + lv) + sn) - mv[u];
+                a.out[e] = lv;
                 a.s_new[e] = sn;
                 a.dual_new[e] = wt;
-                part[0] += (double)sq((zv + sn) - mv);
-                part[1] += (double)sq(zv - a.l_old[e]);
-                part[2] += (double)sq(sn - a.s_old[e]);
+                part[0] += (double)sq((lv + sn) - mv[u]);
+                part[1] += (double)sq(lv - lo[u]);
+                part[2] += (double)sq(sn - so[u]);
+            }
+        }
+    } else {
+        for (int base = threadIdx.x; base < total; base += U * (int)blockDim.x) {
+            T v0[U], v1[U], v2[U], v3[U];
+            uint8_t mk[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                int r, t;
+                const int64_t e = elem(min(base + u * (int)blockDim.x, total - 1), r, t);
+                if (EPI == EPI_COMPLETE) {
+                    v0[u] = a.z_old[e];
+                    v1[u] = a.dual_old[e];
+                    v2[u] = a.y[e];
+                    mk[u] = a.mask[e];
+                } else if (EPI == EPI_RPCA_L1) {
+                    v0[u] = a.m[e];
+                    v1[u] = a.dual_old[e];
+                    v2[u] = a.l_old[e];
+                    v3[u] = a.s_old[e];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int idx = base + u * (int)blockDim.x;
+                if (idx >= total) continue;
+                int r, t;
+                const int64_t e = elem(idx, r, t);
+                const T zv = synth(r, t);
+                if (EPI == EPI_STORE) {
+                    a.out[e] = zv;
+                } else if (EPI == EPI_COMPLETE) {
+                    const T zo = v0[u];
+                    const T q = (T)(ds * (double)v1[u]);
+                    const T x = mk[u] ? v2[u] : (T)(zo - q);
+                    const T qt = (q + x) - zv;
+                    a.out[e] = zv;
+                    a.dual_new[e] = qt;
+                    part[0] += (double)sq(x - zv);
+                    part[1] += (double)sq(zv - zo);
+                } else {  // EPI_RPCA_L1
+                    const T mv = v0[u];
+                    const T w = (T)(ds * (double)v1[u]);
+                    const T d = (mv - w) - zv;
+                    const T mag = (T)fmax(fabs(d) - (T)thr, (T)0);
+                    const T sn = d > (T)0 ? mag : (d < (T)0 ? -mag : (T)0);
+                    const T wt = ((w + zv) + sn) - mv;
+                    a.out[e] = zv;
+                    a.s_new[e] = sn;
+                    a.dual_new[e] = wt;
+                    part[0] += (double)sq((zv + sn) - mv);
+                    part[1] += (double)sq(zv - v2[u]);
+                    part[2] += (double)sq(sn - v3[u]);
+                }
             }
         }
     }
