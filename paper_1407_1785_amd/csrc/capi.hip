@@ -120,16 +120,22 @@ void ensure_host_ints(tsvd_handle h, int count) {
     h->host_ints_len = count;
 }
 
-void ensure_twiddles(tsvd_handle h, int L) {
-    if (h->tw_len == L) return;
-    if (h->tw) hip_check(hipFree(h->tw), "hipFree");
-    h->tw = nullptr;
-    h->tw_len = 0;
-    const std::vector<cplx<double>> tw = twiddles_host(L);
-    hip_check(hipMalloc(&h->tw, sizeof(cplx<double>) * L), "hipMalloc twiddles");
-    hip_check(hipMemcpy(h->tw, tw.data(), sizeof(cplx<double>) * L, hipMemcpyHostToDevice),
-              "hipMemcpy twiddles");
-    h->tw_len = L;
+// The DFT matrices of the tube shape of g in the element type, cached on
+// the handle for consecutive calls on the same shape.
+template <typename T>
+const T* ensure_dft_matrices(tsvd_handle h, const Geometry& g) {
+    const int64_t key = ((int64_t)g.P << 32) | ((int64_t)g.Q << 8) | (int64_t)sizeof(T);
+    if (h->dmat_key == key) return static_cast<const T*>(h->dmat);
+    hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+    if (h->dmat) hip_check(hipFree(h->dmat), "hipFree");
+    h->dmat = nullptr;
+    h->dmat_key = -1;
+    const std::vector<T> m = dft_matrices_host<T>(g);
+    hip_check(hipMalloc(&h->dmat, sizeof(T) * m.size()), "hipMalloc DFT matrices");
+    hip_check(hipMemcpy(h->dmat, m.data(), sizeof(T) * m.size(), hipMemcpyHostToDevice),
+              "hipMemcpy DFT matrices");
+    h->dmat_key = key;
+    return static_cast<const T*>(h->dmat);
 }
 
 // Kernel families reported by tsvd_profile_read.
@@ -486,7 +492,7 @@ void do_tsvt(tsvd_handle h, const void* X, tsvd_shape shape, tsvd_dtype dtype, d
         ensure_workspace(h, svt_bytes<T>(g, nparts) + 4096);
         Carver cv{reinterpret_cast<char*>(h->ws)};
         SvtBuffers<T> sb = carve_svt<T>(cv, g, nparts);
-        ensure_twiddles(h, g.L);
+        const T* dmat = ensure_dft_matrices<T>(h, g);
         Ctrl c{};
         c.rho = tau > 0 ? 1.0 / tau : INFINITY;
         c.tau = tau;
@@ -498,7 +504,7 @@ void do_tsvt(tsvd_handle h, const void* X, tsvd_shape shape, tsvd_dtype dtype, d
         FwdArgs<T> fa{};
         fa.x = static_cast<const T*>(X);
         fa.ctrl = h->ctrl;
-        fa.tw = h->tw;
+        fa.mat = dmat;
         fa.out = sb.A;
         fa.nonfinite = h->flag;
         fa.g = g;
@@ -510,7 +516,7 @@ void do_tsvt(tsvd_handle h, const void* X, tsvd_shape shape, tsvd_dtype dtype, d
         const SweepStats ss = run_svt<T>(h, g, sb, 30, nullptr, multirank_host != nullptr);
         InvArgs<T> ia{};
         ia.in = static_cast<const cplx<T>*>(ss.out);
-        ia.tw = h->tw;
+        ia.mat = dmat + DftDims::of(g.h, g.L).fwd_size();
         ia.ctrl = h->ctrl;
         ia.g = g;
         ia.tile = dft_inverse_tile(g, EPI_STORE);
@@ -554,7 +560,7 @@ void do_complete(tsvd_handle h, const void* X_obs, const uint8_t* mask, tsvd_sha
         SvtBuffers<T> sb = carve_svt<T>(cv, g, nparts);
         T* Zb[2] = {cv.take<T>(N), cv.take<T>(N)};
         T* Qb[2] = {cv.take<T>(N), cv.take<T>(N)};
-        ensure_twiddles(h, g.L);
+        const T* dmat = ensure_dft_matrices<T>(h, g);
         hipStream_t st = h->stream;
         const T* Y = static_cast<const T*>(X_obs);
         launch_fill<T>(Zb[0], 0.0, N, st);
@@ -578,14 +584,14 @@ void do_complete(tsvd_handle h, const void* X_obs, const uint8_t* mask, tsvd_sha
         fa.x = Y;
         fa.mask = mask;
         fa.ctrl = h->ctrl;
-        fa.tw = h->tw;
+        fa.mat = dmat;
         fa.out = sb.A;
         fa.nonfinite = h->flag;
         fa.g = g;
         fa.tile = dft_forward_tile(g);
         InvArgs<T> ia{};
         ia.in = sb.Z;
-        ia.tw = h->tw;
+        ia.mat = dmat + DftDims::of(g.h, g.L).fwd_size();
         ia.ctrl = h->ctrl;
         ia.g = g;
         ia.tile = tile_i;
@@ -677,7 +683,7 @@ void do_trpca(tsvd_handle h, const void* X, tsvd_shape shape, tsvd_dtype dtype, 
         T* Lb[2] = {cv.take<T>(N), cv.take<T>(N)};
         T* Sb[2] = {cv.take<T>(N), cv.take<T>(N)};
         T* Wb[2] = {cv.take<T>(N), cv.take<T>(N)};
-        ensure_twiddles(h, g.L);
+        const T* dmat = ensure_dft_matrices<T>(h, g);
         hipStream_t st = h->stream;
         const T* M = static_cast<const T*>(X);
         launch_fill<T>(Lb[0], 0.0, N, st);
@@ -703,14 +709,14 @@ void do_trpca(tsvd_handle h, const void* X, tsvd_shape shape, tsvd_dtype dtype, 
         FwdArgs<T> fa{};
         fa.x = M;
         fa.ctrl = h->ctrl;
-        fa.tw = h->tw;
+        fa.mat = dmat;
         fa.out = sb.A;
         fa.nonfinite = h->flag;
         fa.g = g;
         fa.tile = dft_forward_tile(g);
         InvArgs<T> ia{};
         ia.in = sb.Z;
-        ia.tw = h->tw;
+        ia.mat = dmat + DftDims::of(g.h, g.L).fwd_size();
         ia.ctrl = h->ctrl;
         ia.g = g;
         ia.tile = tile_i;
@@ -823,7 +829,7 @@ tsvd_status tsvd_destroy(tsvd_handle h) {
         if (h->stream) (void)hipStreamSynchronize(h->stream);
         else (void)hipDeviceSynchronize();
         if (h->ws) (void)hipFree(h->ws);
-        if (h->tw) (void)hipFree(h->tw);
+        if (h->dmat) (void)hipFree(h->dmat);
         if (h->ctrl) (void)hipFree(h->ctrl);
         if (h->flag) (void)hipFree(h->flag);
         if (h->host_ints) (void)hipHostFree(h->host_ints);

@@ -13,12 +13,22 @@
 // tube-group shrink of eq. sparse2) and dual update of Sec. 5, plus FP64
 // partial sums of the residual norms.
 //
-// Work unit: one workgroup per tile of `tile` tubes that are consecutive
-// along the slice row mode, at one slice column.  The tile's tubes are
-// staged through LDS, so tube-contiguous HBM traffic on one side and
-// row-contiguous slice traffic on the other are both coalesced.
-// Transform: direct DFT against a twiddle table held in LDS (FP64 table,
-// rounded to the element type; L is at most a few hundred on this path).
+// Work unit: one workgroup per tile of `tile` tubes (a multiple of 16) that
+// are consecutive along the slice row mode, at one slice column.  The tile's
+// tubes are staged through LDS, so tube-contiguous HBM traffic on one side
+// and row-contiguous slice traffic on the other are both coalesced.
+// Transform: both DFTs are small dense products on the matrix cores against
+// the DFT matrices of the tube shape (built once in FP64 and rounded to the
+// element type; layout in kernels.h, DftDims), 16 x 16 x 4 MFMA steps with
+// the element type's own products and accumulation:
+//   forward  D (2hp x tile) = F^T X, X the tile's tubes as columns (LDS),
+//            rows s and hp + s of D the real and imaginary part of slice s;
+//   inverse  L (Lr x tile) = S^T Z, Z the tile's spectra as 2h real rows
+//            (real and imaginary part of each slice), L written to LDS and
+//            consumed by the epilogue.
+// The matrix fragments come from global memory (a few tens of KB, L2
+// resident); each wave owns a 16-row strip of D and sweeps every 16-column
+// block of the tile, so a fragment is loaded once per workgroup.
 
 #include "kernels.h"
 
@@ -59,16 +69,44 @@ __device__ void block_partials(double (&v)[kNumPartials], double* partials, doub
 template <typename T>
 __device__ __forceinline__ T sq(T v) { return v * v; }
 
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// 16 x 16 x 4 MFMA in the element type.  Operand lanes: lane l supplies
+// row l % 16 of the first operand and column l % 16 of the second, both at
+// k = l / 16.  Register v of lane l holds D(row(l, v), l % 16).
+template <typename T>
+struct Mma;
+
+template <>
+struct Mma<double> {
+    typedef v4d acc_t;
+    static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int v) { return 4 * v + (lane >> 4); }
+};
+
+template <>
+struct Mma<float> {
+    typedef v4f acc_t;
+    static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+
+constexpr int kMaxColBlocks = 4;   // tile <= 64
+constexpr int KU = 4;              // matrix fragments loaded ahead, in k steps
+
 }  // namespace
 
 template <typename T, int PRO>
 __device__ __forceinline__ void dft_forward_body(const FwdArgs<T>& a, int bid, unsigned char* smem) {
     const Geometry& g = a.g;
-    const int L = g.L, tile = a.tile, ldb = L + 1;
-    cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem);
-    T* buf = reinterpret_cast<T*>(tw + L);
-
-    for (int u = threadIdx.x; u < L; u += blockDim.x) tw[u] = cplx<T>{(T)a.tw[u].re, (T)a.tw[u].im};
+    const DftDims d = DftDims::of(g.h, g.L);
+    const int L = g.L, tile = a.tile, ldb = d.Lk + 1;
+    T* buf = reinterpret_cast<T*>(smem);   // tile x ldb, tube r at row r
 
     const int row_tiles = (g.m + tile - 1) / tile;
     const int col = bid / row_tiles;
@@ -121,32 +159,58 @@ __device__ __forceinline__ void dft_forward_body(const FwdArgs<T>& a, int bid, u
         }
     }
     if (bad) *a.nonfinite = 1;
+    // positions L..Lk-1 meet zero matrix rows but must be finite
+    for (int q = threadIdx.x; q < tile * (d.Lk - L); q += blockDim.x) {
+        const int r = q / (d.Lk - L);
+        buf[r * ldb + L + (q - r * (d.Lk - L))] = (T)0;
+    }
     __syncthreads();
 
-    const int P = g.P, Q = g.Q, Qh = g.Qh;
-    for (int o = threadIdx.x; o < g.h * tile; o += blockDim.x) {
-        const int s = o / tile, r = o - s * tile;
-        if (r >= nrow) continue;
-        const int k3 = s / Qh, k4 = s - k3 * Qh;
-        const int step3 = (k3 * Q) % L, step4 = (k4 * P) % L;
-        const T* xb = buf + r * ldb;
-        T re = 0, im = 0;
-        int u3 = 0;
-        for (int t3 = 0; t3 < P; ++t3) {
-            int u = u3;
-            const T* xr = xb + t3 * Q;
-            for (int t4 = 0; t4 < Q; ++t4) {
-                const T v = xr[t4];
-                re += v * tw[u].re;
-                im += v * tw[u].im;
-                u += step4;
-                if (u >= L) u -= L;
+    // D = F^T X.  Columns of X past nrow hold stale LDS; they only reach
+    // the columns of D that are not stored.
+    typedef Mma<T> M;
+    typedef typename M::acc_t acc_t;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+    const int c16 = lane & 15, kq = lane >> 4;
+    const int nj = (nrow + 15) >> 4;
+    const int64_t ldf = 2 * (int64_t)d.hp;
+    for (int i = wave; i < d.hp / 16; i += nwave) {
+        acc_t re[kMaxColBlocks], im[kMaxColBlocks];
+#pragma unroll
+        for (int j = 0; j < kMaxColBlocks; ++j) re[j] = im[j] = acc_t{(T)0, (T)0, (T)0, (T)0};
+        const T* fr = a.mat + i * 16 + c16;
+        for (int k0 = 0; k0 < d.Lk; k0 += 4 * KU) {
+            T ar[KU], ai[KU];
+#pragma unroll
+            for (int u = 0; u < KU; ++u) {
+                const int k = min(k0 + 4 * u + kq, d.Lk - 1);
+                ar[u] = fr[k * ldf];
+                ai[u] = fr[k * ldf + d.hp];
             }
-            u3 += step3;
-            if (u3 >= L) u3 -= L;
+#pragma unroll
+            for (int u = 0; u < KU; ++u) {
+                if (k0 + 4 * u >= d.Lk) break;
+                const T* xb = buf + c16 * ldb + k0 + 4 * u + kq;
+#pragma unroll
+                for (int j = 0; j < kMaxColBlocks; ++j) {
+                    if (j < nj) {
+                        const T b = xb[j * 16 * ldb];
+                        re[j] = M::mma(ar[u], b, re[j]);
+                        im[j] = M::mma(ai[u], b, im[j]);
+                    }
+                }
+            }
         }
-        const int64_t dst = ((int64_t)s * g.n + col) * g.m + row0 + r;
-        a.out[dst] = cplx<T>{re, im};
+#pragma unroll
+        for (int j = 0; j < kMaxColBlocks; ++j) {
+            if (j >= nj) break;
+            const int r = j * 16 + c16;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int s = i * 16 + M::row(lane, v);
+                if (s < g.h && r < nrow) a.out[((int64_t)s * g.n + col) * g.m + row0 + r] = cplx<T>{re[j][v], im[j][v]};
+            }
+        }
     }
 }
 
@@ -154,15 +218,14 @@ template <typename T, int EPI>
 __device__ __forceinline__ void dft_inverse_body(const InvArgs<T>& a, int bid, unsigned char* smem) {
     const Geometry& g = a.g;
     const int L = g.L, tile = a.tile, h = g.h;
-    cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem);
-    cplx<T>* zb = reinterpret_cast<cplx<T>*>(tw + L);               // h x tile
-    // L112 only: prox output and D of the tile, tile x L each
-    T* lb = reinterpret_cast<T*>(zb + (int64_t)h * tile);
-    T* db = lb + (EPI == EPI_RPCA_L112 ? (int64_t)tile * L : 0);
+    const DftDims d = DftDims::of(h, L);
+    const int ldl = d.Lr + 1;
+    cplx<T>* zb = reinterpret_cast<cplx<T>*>(smem);                  // h x tile spectra
+    T* lb = reinterpret_cast<T*>(zb + (int64_t)h * tile);           // tile x ldl prox output
+    // L112 only: D of the tile (tile x L), over the spectra once they are used
+    T* db = reinterpret_cast<T*>(zb);
     // reduction scratch (64 doubles) followed by the per-tube shrink factors
-    double* red = reinterpret_cast<double*>(db + (EPI == EPI_RPCA_L112 ? (int64_t)tile * L : 0));
-
-    for (int u = threadIdx.x; u < L; u += blockDim.x) tw[u] = cplx<T>{(T)a.tw[u].re, (T)a.tw[u].im};
+    double* red = reinterpret_cast<double*>(lb + (int64_t)tile * ldl);
 
     const int row_tiles = (g.m + tile - 1) / tile;
     const int col = bid / row_tiles;
@@ -177,8 +240,48 @@ __device__ __forceinline__ void dft_inverse_body(const InvArgs<T>& a, int bid, u
     }
     __syncthreads();
 
-    const int P = g.P, Q = g.Q, Qh = g.Qh;
-    const T inv_l = (T)1 / (T)L;
+    {
+        // L = S^T Z: row k of Z is the real (k even) or imaginary part of
+        // slice k / 2; rows past 2h meet zero matrix rows (clamped reads).
+        typedef Mma<T> M;
+        typedef typename M::acc_t acc_t;
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+        const int c16 = lane & 15, kq = lane >> 4;
+        const int nj = (nrow + 15) >> 4;
+        for (int i = wave; i < d.Lr / 16; i += nwave) {
+            acc_t acc[kMaxColBlocks];
+#pragma unroll
+            for (int j = 0; j < kMaxColBlocks; ++j) acc[j] = acc_t{(T)0, (T)0, (T)0, (T)0};
+            const T* sr = a.mat + i * 16 + c16;
+            for (int k0 = 0; k0 < d.Kr; k0 += 4 * KU) {
+                T av[KU];
+#pragma unroll
+                for (int u = 0; u < KU; ++u) av[u] = sr[(int64_t)min(k0 + 4 * u + kq, d.Kr - 1) * d.Lr];
+#pragma unroll
+                for (int u = 0; u < KU; ++u) {
+                    if (k0 + 4 * u >= d.Kr) break;
+                    const int k = k0 + 4 * u + kq;
+                    const cplx<T>* zr = zb + (int64_t)min(k >> 1, h - 1) * tile + c16;
+#pragma unroll
+                    for (int j = 0; j < kMaxColBlocks; ++j) {
+                        if (j < nj) {
+                            const cplx<T> z = zr[j * 16];
+                            acc[j] = M::mma(av[u], (k & 1) ? z.im : z.re, acc[j]);
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < kMaxColBlocks; ++j) {
+                if (j >= nj) break;
+                T* lr = lb + (j * 16 + c16) * ldl + i * 16;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) lr[M::row(lane, v)] = acc[j][v];
+            }
+        }
+    }
+    __syncthreads();
+
     double part[kNumPartials] = {0.0, 0.0, 0.0, 0.0};
     double ds = 1.0, thr = 0.0;
     if (EPI != EPI_STORE) {
@@ -186,30 +289,8 @@ __device__ __forceinline__ void dft_inverse_body(const InvArgs<T>& a, int bid, u
         thr = a.ctrl->shrink;
     }
 
-    // prox output of element (tube r, position t) of this tile
-    auto synth = [&](int r, int t) -> T {
-        const int t3 = t / Q, t4 = t - t3 * Q;
-        const int step3 = (t3 * Q) % L, step4 = (t4 * P) % L;
-        T acc = 0;
-        int u3 = 0;
-        for (int k3 = 0; k3 < P; ++k3) {
-            int u = u3;
-            const cplx<T>* zr = zb + (k3 * Qh) * tile + r;
-            for (int k4 = 0; k4 < Qh; ++k4) {
-                const cplx<T> z = zr[k4 * tile];
-                const T wgt = (k4 == 0 || 2 * k4 == Q) ? (T)1 : (T)2;
-                acc += wgt * (z.re * tw[u].re + z.im * tw[u].im);
-                u += step4;
-                if (u >= L) u -= L;
-            }
-            u3 += step3;
-            if (u3 >= L) u3 -= L;
-        }
-        return acc * inv_l;
-    };
-
-    // U elements per thread per pass: the loads of a pass are issued (at
-    // clamped indices) before the DFT sums that consume them
+    // U elements per thread per pass: the loads of a pass are all issued (at
+    // clamped indices) before any value is used
     constexpr int U = 4;
     const int total = nrow * L;
     auto elem = [&](int idx, int& r, int& t) -> int64_t {
@@ -218,7 +299,7 @@ __device__ __forceinline__ void dft_inverse_body(const InvArgs<T>& a, int bid, u
         return tube_offset<T>(g, row0 + r, col) + t;
     };
     if (EPI == EPI_RPCA_L112) {
-        // pass 1: prox output and D = M - W - L' into LDS
+        // pass 1: D = M - W - L' into LDS
         for (int base = threadIdx.x; base < total; base += U * (int)blockDim.x) {
             T mv[U], wv[U];
 #pragma unroll
@@ -234,9 +315,8 @@ __device__ __forceinline__ void dft_inverse_body(const InvArgs<T>& a, int bid, u
                 if (idx >= total) continue;
                 int r, t;
                 (void)elem(idx, r, t);
-                const T lv = synth(r, t);
+                const T lv = lb[r * ldl + t];
                 const T w = (T)(ds * (double)wv[u]);
-                lb[idx] = lv;
                 db[idx] = (mv[u] - w) - lv;
             }
         }
@@ -267,7 +347,7 @@ __device__ __forceinline__ void dft_inverse_body(const InvArgs<T>& a, int bid, u
                 if (idx >= total) continue;
                 int r, t;
                 const int64_t e = elem(idx, r, t);
-                const T lv = lb[idx];
+                const T lv = lb[r * ldl + t];
                 const T sn = db[idx] * fac[r];
                 const T w = (T)(ds * (double)wv[u]);
                 const T wt = ((w + lv) + sn) - mv[u];
@@ -305,7 +385,7 @@ __device__ __forceinline__ void dft_inverse_body(const InvArgs<T>& a, int bid, u
                 if (idx >= total) continue;
                 int r, t;
                 const int64_t e = elem(idx, r, t);
-                const T zv = synth(r, t);
+                const T zv = lb[r * ldl + t];
                 if (EPI == EPI_STORE) {
                     a.out[e] = zv;
                 } else if (EPI == EPI_COMPLETE) {
@@ -385,19 +465,18 @@ __global__ __launch_bounds__(kBlock) void dft_inverse_batched(const InvArgs<T>* 
 
 int dft_forward_tile(const Geometry& g) {
     // keep the LDS tile near 32 KB so several workgroups share a CU
+    const DftDims d = DftDims::of(g.h, g.L);
     int tile = 64;
-    while (tile > 8 && (int64_t)tile * (g.L + 1) * 8 > 32768) tile /= 2;
+    while (tile > 16 && (int64_t)tile * (d.Lk + 1) * 8 > 32768) tile /= 2;
     return tile;
 }
 
 int dft_inverse_tile(const Geometry& g, int epilogue) {
+    (void)epilogue;   // the L112 tile of D reuses the spectra's LDS
+    const DftDims d = DftDims::of(g.h, g.L);
     int tile = 64;
-    auto bytes = [&](int t) {
-        int64_t b = (int64_t)g.h * t * 16;
-        if (epilogue == EPI_RPCA_L112) b += 2LL * t * g.L * 8;
-        return b;
-    };
-    while (tile > 8 && bytes(tile) > 40960) tile /= 2;
+    auto bytes = [&](int t) { return (int64_t)g.h * t * 16 + (int64_t)t * (d.Lr + 1) * 8; };
+    while (tile > 16 && bytes(tile) > 49152) tile /= 2;
     return tile;
 }
 
@@ -407,24 +486,25 @@ int64_t dft_grid(const Geometry& g, int tile) {
 
 template <typename T>
 size_t dft_forward_lds(const Geometry& g, int tile) {
-    return (size_t)g.L * sizeof(cplx<T>) + (size_t)tile * (g.L + 1) * sizeof(T);
+    const DftDims d = DftDims::of(g.h, g.L);
+    return (size_t)tile * (d.Lk + 1) * sizeof(T);
 }
 
 template <typename T>
 size_t dft_inverse_lds(const Geometry& g, int tile, int epilogue) {
-    size_t lds = (size_t)g.L * sizeof(cplx<T>) + (size_t)g.h * tile * sizeof(cplx<T>);
-    if (epilogue == EPI_RPCA_L112) lds += 2 * (size_t)tile * g.L * sizeof(T);
+    (void)epilogue;
+    const DftDims d = DftDims::of(g.h, g.L);
+    const size_t lds = (size_t)g.h * tile * sizeof(cplx<T>) + (size_t)tile * (d.Lr + 1) * sizeof(T);
     return lds + 64 * sizeof(double) + (size_t)tile * sizeof(T) + 16;
 }
 
+template <typename K>
+void allow_lds(K kernel, size_t lds);
+
 template <typename T>
 void prepare_dft_batched(size_t lds_forward, size_t lds_inverse) {
-    if (lds_forward > 65536)
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(dft_forward_batched<T>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_forward);
-    if (lds_inverse > 65536)
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(dft_inverse_batched<T>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_inverse);
+    allow_lds(dft_forward_batched<T>, lds_forward);
+    allow_lds(dft_inverse_batched<T>, lds_inverse);
 }
 
 template <typename T>
@@ -439,40 +519,45 @@ void launch_dft_inverse_batched(const InvArgs<T>* tab, const int* wg_start, int 
     hipLaunchKernelGGL((dft_inverse_batched<T>), dim3(nwg), dim3(kBlock), lds, st, tab, wg_start, nprob);
 }
 
+// Dynamic LDS above the 64 KB default needs the kernel's opt-in (long
+// tubes in FP64).
+template <typename K>
+void allow_lds(K kernel, size_t lds) {
+    if (lds > 65536)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+template <typename T, int PRO>
+void launch_forward_as(const FwdArgs<T>& a, hipStream_t st) {
+    const size_t lds = dft_forward_lds<T>(a.g, a.tile);
+    allow_lds(dft_forward_kernel<T, PRO>, lds);
+    hipLaunchKernelGGL((dft_forward_kernel<T, PRO>), dim3(dft_grid(a.g, a.tile)), dim3(kBlock), lds, st, a);
+}
+
+template <typename T, int EPI>
+void launch_inverse_as(const InvArgs<T>& a, hipStream_t st) {
+    const size_t lds = dft_inverse_lds<T>(a.g, a.tile, EPI);
+    allow_lds(dft_inverse_kernel<T, EPI>, lds);
+    hipLaunchKernelGGL((dft_inverse_kernel<T, EPI>), dim3(dft_grid(a.g, a.tile)), dim3(kBlock), lds, st, a);
+}
+
 template <typename T>
 void launch_dft_forward(int prologue, const FwdArgs<T>& a, hipStream_t st) {
-    const int64_t grid = dft_grid(a.g, a.tile);
-    const size_t lds = dft_forward_lds<T>(a.g, a.tile);
     switch (prologue) {
-        case PRO_COPY:
-            hipLaunchKernelGGL((dft_forward_kernel<T, PRO_COPY>), dim3(grid), dim3(kBlock), lds, st, a);
-            break;
-        case PRO_COMPLETE:
-            hipLaunchKernelGGL((dft_forward_kernel<T, PRO_COMPLETE>), dim3(grid), dim3(kBlock), lds, st, a);
-            break;
-        default:
-            hipLaunchKernelGGL((dft_forward_kernel<T, PRO_RPCA>), dim3(grid), dim3(kBlock), lds, st, a);
-            break;
+        case PRO_COPY: launch_forward_as<T, PRO_COPY>(a, st); break;
+        case PRO_COMPLETE: launch_forward_as<T, PRO_COMPLETE>(a, st); break;
+        default: launch_forward_as<T, PRO_RPCA>(a, st); break;
     }
 }
 
 template <typename T>
 void launch_dft_inverse(int epilogue, const InvArgs<T>& a, hipStream_t st) {
-    const int64_t grid = dft_grid(a.g, a.tile);
-    const size_t lds = dft_inverse_lds<T>(a.g, a.tile, epilogue);
     switch (epilogue) {
-        case EPI_STORE:
-            hipLaunchKernelGGL((dft_inverse_kernel<T, EPI_STORE>), dim3(grid), dim3(kBlock), lds, st, a);
-            break;
-        case EPI_COMPLETE:
-            hipLaunchKernelGGL((dft_inverse_kernel<T, EPI_COMPLETE>), dim3(grid), dim3(kBlock), lds, st, a);
-            break;
-        case EPI_RPCA_L1:
-            hipLaunchKernelGGL((dft_inverse_kernel<T, EPI_RPCA_L1>), dim3(grid), dim3(kBlock), lds, st, a);
-            break;
-        default:
-            hipLaunchKernelGGL((dft_inverse_kernel<T, EPI_RPCA_L112>), dim3(grid), dim3(kBlock), lds, st, a);
-            break;
+        case EPI_STORE: launch_inverse_as<T, EPI_STORE>(a, st); break;
+        case EPI_COMPLETE: launch_inverse_as<T, EPI_COMPLETE>(a, st); break;
+        case EPI_RPCA_L1: launch_inverse_as<T, EPI_RPCA_L1>(a, st); break;
+        default: launch_inverse_as<T, EPI_RPCA_L112>(a, st); break;
     }
 }
 

@@ -107,7 +107,7 @@ struct Slot {
     double* partials = nullptr;
     Ctrl* ctrl = nullptr;
     int* flag = nullptr;
-    cplx<double>* tw = nullptr;
+    T* mat = nullptr;           // forward then inverse DFT matrix of the tube shape
     int tile_f = 0, tile_i = 0, inv_parts = 0, pro = 0, epi = 0;
     int bw = 0, rpt = 0, nb = 0;
     bool round = false;         // Jacobi in round mode (one launch per round)
@@ -146,7 +146,7 @@ size_t slot_layout(Slot<T>& sl, char* base) {
     sl.partials = reinterpret_cast<double*>(take((int64_t)nparts * kNumPartials * sizeof(double)));
     sl.ctrl = reinterpret_cast<Ctrl*>(take(sizeof(Ctrl)));
     sl.flag = reinterpret_cast<int*>(take(sizeof(int)));
-    sl.tw = reinterpret_cast<cplx<double>*>(take((int64_t)g.L * sizeof(cplx<double>)));
+    sl.mat = reinterpret_cast<T*>(take(DftDims::of(g.h, g.L).total() * sizeof(T)));
     return Arena::round(off);
 }
 
@@ -323,9 +323,9 @@ private:
         const bool rpca = p.kind == TSVD_KIND_TRPCA;
         const int64_t N = g.numel;
         hipStream_t st = stream_;
-        // twiddles and the control block come from host memory: stage them
-        // through pinned buffers that outlive the copies (synchronised below)
-        const std::vector<cplx<double>> tw = twiddles_host(g.L);
+        // the DFT matrices and the control block come from host memory: stage
+        // them through pinned buffers that outlive the copies (synchronised below)
+        const std::vector<T> mat = dft_matrices_host<T>(g);
         Ctrl c{};
         c.rho = p.penalty;
         c.tau = 1.0 / p.penalty;
@@ -340,12 +340,13 @@ private:
             c.shrink = p.lambda / p.penalty;
         }
         void* staging = nullptr;
-        const size_t tw_bytes = tw.size() * sizeof(cplx<double>);
-        hip_check(hipHostMalloc(&staging, tw_bytes + sizeof(Ctrl), 0), "hipHostMalloc");
-        std::memcpy(staging, tw.data(), tw_bytes);
-        std::memcpy(static_cast<char*>(staging) + tw_bytes, &c, sizeof(Ctrl));
-        hip_check(hipMemcpyAsync(sl.tw, staging, tw_bytes, hipMemcpyHostToDevice, st), "hipMemcpyAsync twiddles");
-        hip_check(hipMemcpyAsync(sl.ctrl, static_cast<char*>(staging) + tw_bytes, sizeof(Ctrl),
+        const size_t mat_bytes = Arena::round(mat.size() * sizeof(T));
+        hip_check(hipHostMalloc(&staging, mat_bytes + sizeof(Ctrl), 0), "hipHostMalloc");
+        std::memcpy(staging, mat.data(), mat.size() * sizeof(T));
+        std::memcpy(static_cast<char*>(staging) + mat_bytes, &c, sizeof(Ctrl));
+        hip_check(hipMemcpyAsync(sl.mat, staging, mat.size() * sizeof(T), hipMemcpyHostToDevice, st),
+                  "hipMemcpyAsync DFT matrices");
+        hip_check(hipMemcpyAsync(sl.ctrl, static_cast<char*>(staging) + mat_bytes, sizeof(Ctrl),
                                  hipMemcpyHostToDevice, st),
                   "hipMemcpyAsync ctrl");
         const int nit = rpca ? 3 : 2;
@@ -530,7 +531,7 @@ private:
             fa.x = static_cast<const T*>(p.x);
             fa.mask = rpca ? nullptr : p.mask;
             fa.ctrl = sl.ctrl;
-            fa.tw = sl.tw;
+            fa.mat = sl.mat;
             fa.out = sl.A;
             fa.nonfinite = sl.flag;
             fa.g = g;
@@ -633,7 +634,7 @@ private:
             // inverse DFT + epilogue
             InvArgs<T> ia{};
             ia.in = sl.A;
-            ia.tw = sl.tw;
+            ia.mat = sl.mat + DftDims::of(g.h, g.L).fwd_size();
             ia.ctrl = sl.ctrl;
             ia.g = g;
             ia.tile = sl.tile_i;

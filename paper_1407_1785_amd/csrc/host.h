@@ -66,8 +66,8 @@ struct tsvd_handle_s {
     // small device objects
     tsvd::Ctrl* ctrl = nullptr;
     int* flag = nullptr;            // non-finite flag
-    tsvd::cplx<double>* tw = nullptr;     // twiddles of the current tube length
-    int tw_len = 0;
+    void* dmat = nullptr;           // DFT matrices of the current tube shape
+    int64_t dmat_key = -1;          // (P, Q, element size) they were built for
     // pinned host staging
     int* host_ints = nullptr;
     int host_ints_len = 0;
@@ -138,6 +138,33 @@ inline Geometry make_geometry(const tsvd_shape& s) {
 
 
 // FP64 twiddles exp(-2 pi i u / L); the quarter points are exact.
+inline std::vector<cplx<double>> twiddles_host(int L);
+
+// The forward and inverse DFT matrices of a tube shape (layout in kernels.h,
+// DftDims), forward first, built in FP64 from the twiddles and rounded once
+// to the element type.
+template <typename T>
+inline std::vector<T> dft_matrices_host(const Geometry& g) {
+    const DftDims d = DftDims::of(g.h, g.L);
+    const std::vector<cplx<double>> tw = twiddles_host(g.L);
+    std::vector<T> m((size_t)d.total(), (T)0);
+    T* F = m.data();
+    T* S = m.data() + d.fwd_size();
+    for (int s = 0; s < g.h; ++s) {
+        const int k3 = s / g.Qh, k4 = s - k3 * g.Qh;
+        const double c = (k4 == 0 || 2 * k4 == g.Q) ? 1.0 : 2.0;
+        for (int t = 0; t < g.L; ++t) {
+            const int t3 = t / g.Q, t4 = t - t3 * g.Q;
+            const int64_t u = ((int64_t)t3 * k3 * g.Q + (int64_t)t4 * k4 * g.P) % g.L;
+            F[(int64_t)t * 2 * d.hp + s] = (T)tw[u].re;
+            F[(int64_t)t * 2 * d.hp + d.hp + s] = (T)tw[u].im;
+            S[(int64_t)(2 * s) * d.Lr + t] = (T)(c / g.L * tw[u].re);
+            S[(int64_t)(2 * s + 1) * d.Lr + t] = (T)(c / g.L * tw[u].im);
+        }
+    }
+    return m;
+}
+
 inline std::vector<cplx<double>> twiddles_host(int L) {
     std::vector<cplx<double>> tw(L);
     for (int u = 0; u < L; ++u) {

@@ -33,6 +33,27 @@ enum Epilogue : int {
     EPI_RPCA_L112 = 3,   // RPCA tube-group shrink + dual update + residuals
 };
 
+// Dimensions of the DFT matrices of one tube shape (dft.hip).  Forward:
+// F (Lk x 2hp, k-major): F[t][s] = Re w(s, t) and F[t][hp + s] = Im w(s, t)
+// with w(s, t) = exp(-2 pi i u(s, t) / L), u(s, t) = (t3 k3 Q + t4 k4 P)
+// mod L for slice s = k3 Qh + k4 and position t = t3 Q + t4; zero outside
+// s < h, t < L.  Inverse: S (Kr x Lr, k-major): S[2s + c][t] = (c_s / L)
+// (c ? Im : Re) w(s, t), c_s = 1 for the bins k4 = 0 and 2 k4 = Q, else 2.
+struct DftDims {
+    int hp, Lk, Lr, Kr;
+    __host__ __device__ static DftDims of(int h, int L) {
+        DftDims d;
+        d.hp = (h + 15) / 16 * 16;
+        d.Lk = (L + 3) / 4 * 4;
+        d.Lr = (L + 15) / 16 * 16;
+        d.Kr = (2 * h + 3) / 4 * 4;
+        return d;
+    }
+    __host__ __device__ int64_t fwd_size() const { return (int64_t)Lk * 2 * hp; }
+    __host__ __device__ int64_t inv_size() const { return (int64_t)Kr * Lr; }
+    __host__ __device__ int64_t total() const { return fwd_size() + inv_size(); }
+};
+
 template <typename T>
 struct FwdArgs {
     const T* x;              // COPY: X; COMPLETE: observed Y; RPCA: M
@@ -41,7 +62,7 @@ struct FwdArgs {
     const T* dual;           // COMPLETE: Q stored; RPCA: W stored (times ctrl->dscale)
     const T* s;              // RPCA: S_k
     const Ctrl* ctrl;
-    const cplx<double>* tw;  // L twiddles exp(-2 pi i u / L), u = 0..L-1
+    const T* mat;            // forward DFT matrix F (DftDims), element type
     cplx<T>* out;            // h slices, m x n column-major each
     int* nonfinite;          // set to 1 if a transformed value is not finite
     Geometry g;
@@ -52,7 +73,7 @@ struct FwdArgs {
 template <typename T>
 struct InvArgs {
     const cplx<T>* in;       // h slices of the prox output
-    const cplx<double>* tw;
+    const T* mat;            // inverse DFT matrix S (DftDims), element type
     const Ctrl* ctrl;
     Geometry g;
     int tile;
