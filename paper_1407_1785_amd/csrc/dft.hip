@@ -26,9 +26,12 @@
 //   inverse  L (Lr x tile) = S^T Z, Z the tile's spectra as 2h real rows
 //            (real and imaginary part of each slice), L written to LDS and
 //            consumed by the epilogue.
-// The matrix fragments come from global memory (a few tens of KB, L2
-// resident); each wave owns a 16-row strip of D and sweeps every 16-column
-// block of the tile, so a fragment is loaded once per workgroup.
+// The matrix fragments come from global memory (a few tens of KB, cache
+// resident); each wave owns 16-row strips of D and sweeps the 16-column
+// blocks of the tile, k in chunks of 16 with the next chunk's fragments in
+// flight while the current one is multiplied, four independent accumulator
+// chains per block.  The LDS row strides are 4 mod 16 words, so the 64 lanes
+// of an operand read (16 columns x 4 k) fall in distinct banks.
 
 #include "kernels.h"
 
@@ -96,8 +99,8 @@ struct Mma<float> {
     static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
 
-constexpr int kMaxColBlocks = 4;   // tile <= 64
-constexpr int KU = 4;              // matrix fragments loaded ahead, in k steps
+// LDS row stride for rows of n elements: n rounded up to 16, plus 4.
+__host__ __device__ constexpr int lds_stride(int n) { return (n + 15) / 16 * 16 + 4; }
 
 }  // namespace
 
@@ -105,7 +108,7 @@ template <typename T, int PRO>
 __device__ __forceinline__ void dft_forward_body(const FwdArgs<T>& a, int bid, unsigned char* smem) {
     const Geometry& g = a.g;
     const DftDims d = DftDims::of(g.h, g.L);
-    const int L = g.L, tile = a.tile, ldb = d.Lk + 1;
+    const int L = g.L, tile = a.tile, ldb = lds_stride(d.Lk);
     T* buf = reinterpret_cast<T*>(smem);   // tile x ldb, tube r at row r
 
     const int row_tiles = (g.m + tile - 1) / tile;
@@ -174,42 +177,48 @@ __device__ __forceinline__ void dft_forward_body(const FwdArgs<T>& a, int bid, u
     const int c16 = lane & 15, kq = lane >> 4;
     const int nj = (nrow + 15) >> 4;
     const int64_t ldf = 2 * (int64_t)d.hp;
-    for (int i = wave; i < d.hp / 16; i += nwave) {
-        acc_t re[kMaxColBlocks], im[kMaxColBlocks];
+    for (int item = wave; item < (d.hp / 16) * nj; item += nwave) {
+        const int i = item / nj, j = item - i * nj;
+        const T* fr = a.mat + kq * ldf + i * 16 + c16;
+        const T* xb = buf + (j * 16 + c16) * ldb + kq;
+        acc_t re0 = {0, 0, 0, 0}, im0 = re0, re1 = re0, im1 = re0;
+        T ar[4], ai[4], bx[4];
 #pragma unroll
-        for (int j = 0; j < kMaxColBlocks; ++j) re[j] = im[j] = acc_t{(T)0, (T)0, (T)0, (T)0};
-        const T* fr = a.mat + i * 16 + c16;
-        for (int k0 = 0; k0 < d.Lk; k0 += 4 * KU) {
-            T ar[KU], ai[KU];
+        for (int u = 0; u < 4; ++u) {
+            ar[u] = fr[4 * u * ldf];
+            ai[u] = fr[4 * u * ldf + d.hp];
+            bx[u] = xb[4 * u];
+        }
+        for (int k0 = 0; k0 < d.Lk; k0 += 16) {
+            const int kn = k0 + 16 < d.Lk ? k0 + 16 : k0;   // last chunk reloads itself
+            T nar[4], nai[4], nbx[4];
 #pragma unroll
-            for (int u = 0; u < KU; ++u) {
-                const int k = min(k0 + 4 * u + kq, d.Lk - 1);
-                ar[u] = fr[k * ldf];
-                ai[u] = fr[k * ldf + d.hp];
+            for (int u = 0; u < 4; ++u) {
+                nar[u] = fr[(kn + 4 * u) * ldf];
+                nai[u] = fr[(kn + 4 * u) * ldf + d.hp];
+                nbx[u] = xb[kn + 4 * u];
             }
+            re0 = M::mma(ar[0], bx[0], re0);
+            im0 = M::mma(ai[0], bx[0], im0);
+            re1 = M::mma(ar[1], bx[1], re1);
+            im1 = M::mma(ai[1], bx[1], im1);
+            re0 = M::mma(ar[2], bx[2], re0);
+            im0 = M::mma(ai[2], bx[2], im0);
+            re1 = M::mma(ar[3], bx[3], re1);
+            im1 = M::mma(ai[3], bx[3], im1);
 #pragma unroll
-            for (int u = 0; u < KU; ++u) {
-                if (k0 + 4 * u >= d.Lk) break;
-                const T* xb = buf + c16 * ldb + k0 + 4 * u + kq;
-#pragma unroll
-                for (int j = 0; j < kMaxColBlocks; ++j) {
-                    if (j < nj) {
-                        const T b = xb[j * 16 * ldb];
-                        re[j] = M::mma(ar[u], b, re[j]);
-                        im[j] = M::mma(ai[u], b, im[j]);
-                    }
-                }
+            for (int u = 0; u < 4; ++u) {
+                ar[u] = nar[u];
+                ai[u] = nai[u];
+                bx[u] = nbx[u];
             }
         }
+        const int r = j * 16 + c16;
 #pragma unroll
-        for (int j = 0; j < kMaxColBlocks; ++j) {
-            if (j >= nj) break;
-            const int r = j * 16 + c16;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int s = i * 16 + M::row(lane, v);
-                if (s < g.h && r < nrow) a.out[((int64_t)s * g.n + col) * g.m + row0 + r] = cplx<T>{re[j][v], im[j][v]};
-            }
+        for (int v = 0; v < 4; ++v) {
+            const int s = i * 16 + M::row(lane, v);
+            if (s < g.h && r < nrow)
+                a.out[((int64_t)s * g.n + col) * g.m + row0 + r] = cplx<T>{re0[v] + re1[v], im0[v] + im1[v]};
         }
     }
 }
@@ -219,7 +228,7 @@ __device__ __forceinline__ void dft_inverse_body(const InvArgs<T>& a, int bid, u
     const Geometry& g = a.g;
     const int L = g.L, tile = a.tile, h = g.h;
     const DftDims d = DftDims::of(h, L);
-    const int ldl = d.Lr + 1;
+    const int ldl = lds_stride(d.Lr);
     cplx<T>* zb = reinterpret_cast<cplx<T>*>(smem);                  // h x tile spectra
     T* lb = reinterpret_cast<T*>(zb + (int64_t)h * tile);           // tile x ldl prox output
     // L112 only: D of the tile (tile x L), over the spectra once they are used
@@ -243,41 +252,49 @@ __device__ __forceinline__ void dft_inverse_body(const InvArgs<T>& a, int bid, u
     {
         // L = S^T Z: row k of Z is the real (k even) or imaginary part of
         // slice k / 2; rows past 2h meet zero matrix rows (clamped reads).
+        // k = k0 + 4u + kq has the parity of kq.
         typedef Mma<T> M;
         typedef typename M::acc_t acc_t;
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
         const int c16 = lane & 15, kq = lane >> 4;
+        const bool odd = kq & 1;
         const int nj = (nrow + 15) >> 4;
-        for (int i = wave; i < d.Lr / 16; i += nwave) {
-            acc_t acc[kMaxColBlocks];
+        for (int item = wave; item < (d.Lr / 16) * nj; item += nwave) {
+            const int i = item / nj, j = item - i * nj;
+            const T* sr = a.mat + (int64_t)kq * d.Lr + i * 16 + c16;
+            const cplx<T>* zr = zb + j * 16 + c16;
+            acc_t c0 = {0, 0, 0, 0}, c1 = c0, c2 = c0, c3 = c0;
+            T av[4], bz[4];
+            auto zval = [&](int k) -> T {
+                const cplx<T> z = zr[min(k >> 1, h - 1) * tile];
+                return odd ? z.im : z.re;
+            };
 #pragma unroll
-            for (int j = 0; j < kMaxColBlocks; ++j) acc[j] = acc_t{(T)0, (T)0, (T)0, (T)0};
-            const T* sr = a.mat + i * 16 + c16;
-            for (int k0 = 0; k0 < d.Kr; k0 += 4 * KU) {
-                T av[KU];
+            for (int u = 0; u < 4; ++u) {
+                av[u] = sr[(int64_t)(4 * u) * d.Lr];
+                bz[u] = zval(4 * u + kq);
+            }
+            for (int k0 = 0; k0 < d.Kr; k0 += 16) {
+                const int kn = k0 + 16 < d.Kr ? k0 + 16 : k0;
+                T nav[4], nbz[4];
 #pragma unroll
-                for (int u = 0; u < KU; ++u) av[u] = sr[(int64_t)min(k0 + 4 * u + kq, d.Kr - 1) * d.Lr];
+                for (int u = 0; u < 4; ++u) {
+                    nav[u] = sr[(int64_t)(kn + 4 * u) * d.Lr];
+                    nbz[u] = zval(kn + 4 * u + kq);
+                }
+                c0 = M::mma(av[0], bz[0], c0);
+                c1 = M::mma(av[1], bz[1], c1);
+                c2 = M::mma(av[2], bz[2], c2);
+                c3 = M::mma(av[3], bz[3], c3);
 #pragma unroll
-                for (int u = 0; u < KU; ++u) {
-                    if (k0 + 4 * u >= d.Kr) break;
-                    const int k = k0 + 4 * u + kq;
-                    const cplx<T>* zr = zb + (int64_t)min(k >> 1, h - 1) * tile + c16;
-#pragma unroll
-                    for (int j = 0; j < kMaxColBlocks; ++j) {
-                        if (j < nj) {
-                            const cplx<T> z = zr[j * 16];
-                            acc[j] = M::mma(av[u], (k & 1) ? z.im : z.re, acc[j]);
-                        }
-                    }
+                for (int u = 0; u < 4; ++u) {
+                    av[u] = nav[u];
+                    bz[u] = nbz[u];
                 }
             }
+            T* lr = lb + (j * 16 + c16) * ldl + i * 16;
 #pragma unroll
-            for (int j = 0; j < kMaxColBlocks; ++j) {
-                if (j >= nj) break;
-                T* lr = lb + (j * 16 + c16) * ldl + i * 16;
-#pragma unroll
-                for (int v = 0; v < 4; ++v) lr[M::row(lane, v)] = acc[j][v];
-            }
+            for (int v = 0; v < 4; ++v) lr[M::row(lane, v)] = (c0[v] + c1[v]) + (c2[v] + c3[v]);
         }
     }
     __syncthreads();
@@ -467,7 +484,7 @@ int dft_forward_tile(const Geometry& g) {
     // keep the LDS tile near 32 KB so several workgroups share a CU
     const DftDims d = DftDims::of(g.h, g.L);
     int tile = 64;
-    while (tile > 16 && (int64_t)tile * (d.Lk + 1) * 8 > 32768) tile /= 2;
+    while (tile > 16 && (int64_t)tile * lds_stride(d.Lk) * 8 > 32768) tile /= 2;
     return tile;
 }
 
@@ -475,7 +492,7 @@ int dft_inverse_tile(const Geometry& g, int epilogue) {
     (void)epilogue;   // the L112 tile of D reuses the spectra's LDS
     const DftDims d = DftDims::of(g.h, g.L);
     int tile = 64;
-    auto bytes = [&](int t) { return (int64_t)g.h * t * 16 + (int64_t)t * (d.Lr + 1) * 8; };
+    auto bytes = [&](int t) { return (int64_t)g.h * t * 16 + (int64_t)t * lds_stride(d.Lr) * 8; };
     while (tile > 16 && bytes(tile) > 49152) tile /= 2;
     return tile;
 }
@@ -487,14 +504,14 @@ int64_t dft_grid(const Geometry& g, int tile) {
 template <typename T>
 size_t dft_forward_lds(const Geometry& g, int tile) {
     const DftDims d = DftDims::of(g.h, g.L);
-    return (size_t)tile * (d.Lk + 1) * sizeof(T);
+    return (size_t)tile * lds_stride(d.Lk) * sizeof(T);
 }
 
 template <typename T>
 size_t dft_inverse_lds(const Geometry& g, int tile, int epilogue) {
     (void)epilogue;
     const DftDims d = DftDims::of(g.h, g.L);
-    const size_t lds = (size_t)g.h * tile * sizeof(cplx<T>) + (size_t)tile * (d.Lr + 1) * sizeof(T);
+    const size_t lds = (size_t)g.h * tile * sizeof(cplx<T>) + (size_t)tile * lds_stride(d.Lr) * sizeof(T);
     return lds + 64 * sizeof(double) + (size_t)tile * sizeof(T) + 16;
 }
 

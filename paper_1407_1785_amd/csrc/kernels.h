@@ -38,15 +38,16 @@ enum Epilogue : int {
 // with w(s, t) = exp(-2 pi i u(s, t) / L), u(s, t) = (t3 k3 Q + t4 k4 P)
 // mod L for slice s = k3 Qh + k4 and position t = t3 Q + t4; zero outside
 // s < h, t < L.  Inverse: S (Kr x Lr, k-major): S[2s + c][t] = (c_s / L)
-// (c ? Im : Re) w(s, t), c_s = 1 for the bins k4 = 0 and 2 k4 = Q, else 2.
+// (c ? Im : Re) w(s, t), c_s = 1 for the bins k4 = 0 and 2 k4 = Q, else 2;
+// zero outside 2s + c < 2h, t < L.  Every dimension is a multiple of 16.
 struct DftDims {
     int hp, Lk, Lr, Kr;
     __host__ __device__ static DftDims of(int h, int L) {
         DftDims d;
         d.hp = (h + 15) / 16 * 16;
-        d.Lk = (L + 3) / 4 * 4;
-        d.Lr = (L + 15) / 16 * 16;
-        d.Kr = (2 * h + 3) / 4 * 4;
+        d.Lk = (L + 15) / 16 * 16;
+        d.Lr = d.Lk;
+        d.Kr = (2 * h + 15) / 16 * 16;
         return d;
     }
     __host__ __device__ int64_t fwd_size() const { return (int64_t)Lk * 2 * hp; }
