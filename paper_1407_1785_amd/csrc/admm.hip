@@ -71,9 +71,12 @@ __device__ void admm_ctrl_body(Ctrl* c, const double* partials, int nparts, int 
     if (c->max_iter > 0 && c->iter >= c->max_iter) c->done = 2;
 }
 
+// A stopped problem is left alone (iterations queued after the stop do
+// nothing); the mirror gets the control block either way.
 __global__ __launch_bounds__(kBlock) void admm_ctrl_kernel(Ctrl* c, const double* partials, int nparts,
-                                                          int rpca) {
-    admm_ctrl_body(c, partials, nparts, rpca);
+                                                          int rpca, Ctrl* mirror) {
+    if (!c->done) admm_ctrl_body(c, partials, nparts, rpca);
+    if (mirror && threadIdx.x == 0) *mirror = *c;
 }
 
 // One workgroup per problem; a problem that has stopped is left alone.
@@ -172,8 +175,8 @@ void launch_admm_ctrl_batched(const CtrlArgs* tab, int nprob, hipStream_t st) {
     hipLaunchKernelGGL(admm_ctrl_batched, dim3(nprob), dim3(kBlock), 0, st, tab);
 }
 
-void launch_admm_ctrl(Ctrl* c, const double* partials, int nparts, int rpca, hipStream_t st) {
-    hipLaunchKernelGGL(admm_ctrl_kernel, dim3(1), dim3(kBlock), 0, st, c, partials, nparts, rpca);
+void launch_admm_ctrl(Ctrl* c, const double* partials, int nparts, int rpca, Ctrl* mirror, hipStream_t st) {
+    hipLaunchKernelGGL(admm_ctrl_kernel, dim3(1), dim3(kBlock), 0, st, c, partials, nparts, rpca, mirror);
 }
 
 template <typename T>

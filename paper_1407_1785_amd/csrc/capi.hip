@@ -221,6 +221,7 @@ int64_t cross_pairs(int n, int nb, int round) {
 
 struct SweepStats {
     int sweeps = 0;
+    bool on_device = false;      // the sweeps were counted into ctrl->sweep_max
     const void* out = nullptr;   // slice buffer holding the prox output
 };
 
@@ -248,6 +249,7 @@ SweepStats run_svt(tsvd_handle h, const Geometry& g, const SvtBuffers<T>& sb, in
             gg.lda = gg.ldb = gg.ldc = gg.ldd = g.n;
             gg.sA = gg.sB = gg.sC = gg.sD = nn;
             gg.alpha = (T)1; gg.beta = (T)0; gg.opA = 1; gg.opB = 0; gg.batch = g.h;
+            gg.ctrl = h->ctrl;
             prof_launch(h, K_GEMM, 8.0 * g.n * g.n * g.n * g.h, [&] { launch_zgemm(gg, st); });
             launch_check("gemm gram");
             ZGemmArgs<T> gn = gg;
@@ -265,6 +267,7 @@ SweepStats run_svt(tsvd_handle h, const Geometry& g, const SvtBuffers<T>& sb, in
         ga.lda = g.m; ga.ldb = g.n; ga.ldc = g.m; ga.ldd = g.m;
         ga.sA = mn; ga.sB = nn; ga.sC = mn; ga.sD = mn;
         ga.alpha = (T)1; ga.beta = (T)0; ga.opA = 0; ga.opB = 0; ga.batch = g.h;
+        ga.ctrl = h->ctrl;
         prof_launch(h, K_GEMM, 8.0 * g.m * g.n * g.n * g.h, [&] { launch_zgemm(ga, st); });
         launch_check("gemm prerotate");
         work = sb.Z;
@@ -277,6 +280,7 @@ SweepStats run_svt(tsvd_handle h, const Geometry& g, const SvtBuffers<T>& sb, in
     ja.n = g.n;
     ja.h = g.h;
     ja.reset_v = use_warm ? 0 : 1;
+    ja.ctrl = h->ctrl;
     int bw = env_int("TSVD_JACOBI_BW", 0);
     if (bw != 4 && bw != 8 && bw != 16) bw = jacobi_block_width(g.m, g.n, sizeof(T), g.h);
     ja.nb = jacobi_num_blocks(g.n, bw);
@@ -301,12 +305,16 @@ SweepStats run_svt(tsvd_handle h, const Geometry& g, const SvtBuffers<T>& sb, in
         // one cooperative launch runs every sweep
         ja.nb = jacobi_persistent_blocks(g.n);
         ja.rotations = h->rot_counter + 1;
+        // the init also clears the barrier counters, rotation flags and block
+        // flags (the error word between them is cleared per call)
+        ja.clr[0] = sb.pbar;
+        ja.nclr[0] = 4 * g.h;
+        ja.clr[1] = sb.pbar + 4 * g.h + 1;
+        ja.nclr[1] = g.h * ja.nb;
         prof_launch(h, K_JAC_INIT, (double)g.h * g.n * g.n * sizeof(cplx<T>),
                     [&] { launch_jacobi_init(ja, st); });
         launch_check("jacobi_init");
-        launch_fill<int>(sb.pbar, 0, 4 * g.h, st);   // the error word is cleared per call
-        launch_fill<int>(sb.pbar + 4 * g.h + 1, 0, (int64_t)g.h * ja.nb, st);
-        launch_check("fill");
+        ja.clr[0] = ja.clr[1] = nullptr;
         PersistArgs pa{sb.pbar, sb.pbar + g.h, sb.pbar + 4 * g.h, sb.pbar + 4 * g.h + 1, max_sweeps, nullptr,
                        env_int("TSVD_COOP", 1) != 0 ? 1 : 0, xcds, env_int("TSVD_SPREAD", 0)};
         static long long* trace_buf = nullptr;
@@ -333,6 +341,7 @@ SweepStats run_svt(tsvd_handle h, const Geometry& g, const SvtBuffers<T>& sb, in
         if (e == hipSuccess) {
             done_persist = true;
             stats.sweeps = -1;   // known on the device only
+            stats.on_device = true;
             if (h->prof_on) {
                 // visited pairs: n(n-1)/2 per slice per sweep run
                 hip_check(hipMemcpyAsync(h->host_ints, sb.sweeps, sizeof(int) * g.h, hipMemcpyDeviceToHost, st),
@@ -442,6 +451,54 @@ Ctrl get_ctrl(tsvd_handle h) {
     return *h->host_ctrl;
 }
 
+void ensure_mirror(tsvd_handle h) {
+    if (h->mirror_host) return;
+    hip_check(hipHostMalloc(reinterpret_cast<void**>(&h->mirror_host), 2 * sizeof(Ctrl),
+                            hipHostMallocMapped | hipHostMallocCoherent),
+              "hipHostMalloc control mirror");
+    hip_check(hipHostGetDevicePointer(reinterpret_cast<void**>(&h->mirror_dev), h->mirror_host, 0),
+              "hipHostGetDevicePointer");
+    for (auto& e : h->mirror_ev) hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
+}
+
+struct LoopResult {
+    Ctrl c;   // the control block after the last iteration
+    int sweeps_total = 0, sweeps_last = 0;
+};
+
+// The ADMM loop of the single-problem calls.  iteration(k, mirror) queues
+// iteration k, its control kernel copying the control block to `mirror`,
+// and returns the largest sweep count of its SVDs when the host knows it,
+// else -1 (then the device counts them in the control block).  The host
+// stays one iteration behind the device: it reads the stop state of
+// iteration k - 1 only after queueing iteration k, so the device does not
+// wait for the host between iterations; every kernel of an iteration does
+// nothing once ctrl->done is set, so the iteration queued after the stop
+// changes nothing.
+template <typename F>
+LoopResult admm_loop(tsvd_handle h, int max_iter, F&& iteration) {
+    ensure_mirror(h);
+    std::vector<int> host_sweeps;
+    host_sweeps.reserve(std::max(max_iter, 0));
+    for (int k = 0; k < max_iter; ++k) {
+        host_sweeps.push_back(iteration(k, h->mirror_dev + (k & 1)));
+        hip_check(hipEventRecord(h->mirror_ev[k & 1], h->stream), "hipEventRecord");
+        if (k > 0) {
+            hip_check(hipEventSynchronize(h->mirror_ev[(k - 1) & 1]), "hipEventSynchronize");
+            if (h->mirror_host[(k - 1) & 1].done) break;
+        }
+    }
+    LoopResult r;
+    r.c = get_ctrl(h);
+    r.sweeps_total = r.c.sweeps_total;
+    r.sweeps_last = r.c.sweeps_last;
+    const int iters = std::min<int>(r.c.iter, (int)host_sweeps.size());
+    for (int k = 0; k < iters; ++k)
+        if (host_sweeps[k] >= 0) r.sweeps_total += host_sweeps[k];
+    if (iters > 0 && host_sweeps[iters - 1] >= 0) r.sweeps_last = host_sweeps[iters - 1];
+    return r;
+}
+
 void clear_flag(tsvd_handle h) { launch_fill<int>(h->flag, 0, 1, h->stream); }
 
 // error word of the persistent Jacobi barriers (last int of the pbar area)
@@ -460,12 +517,6 @@ void check_persist_err(tsvd_handle h, const Geometry& g, const SvtBuffers<T>& sb
 }
 
 // largest per-slice sweep count of the last SVD (read after a sync)
-int max_sweeps_of(tsvd_handle h, int nslices) {
-    int mx = 0;
-    for (int s = 0; s < nslices; ++s) mx = std::max(mx, h->host_ints[s]);
-    return mx;
-}
-
 bool read_flag(tsvd_handle h) {
     ensure_host_ints(h, 1);
     hip_check(hipMemcpyAsync(h->host_ints, h->flag, sizeof(int), hipMemcpyDeviceToHost, h->stream),
@@ -605,7 +656,7 @@ void do_complete(tsvd_handle h, const void* X_obs, const uint8_t* mask, tsvd_sha
         WarmState warm;
         warm.enabled = env_int("TSVD_WARM", 1) != 0;
         warm.reorth_every = env_int("TSVD_REORTH_EVERY", sizeof(T) == 4 ? 1 : 4);
-        for (int k = 0; k < s.max_iter; ++k) {
+        const LoopResult lr = admm_loop(h, s.max_iter, [&](int k, Ctrl* mirror) -> int {
             fa.z = Zb[k % 2];
             fa.dual = Qb[k % 2];
             // Y, mask, Z, Q in; slices out
@@ -613,11 +664,6 @@ void do_complete(tsvd_handle h, const void* X_obs, const uint8_t* mask, tsvd_sha
                         [&] { launch_dft_forward(PRO_COMPLETE, fa, st); });
             launch_check("dft_forward");
             const SweepStats ss = run_svt<T>(h, g, sb, s.max_sweeps, &warm);
-            if (ss.sweeps < 0) {
-                ensure_host_ints(h, g.h);
-                hip_check(hipMemcpyAsync(h->host_ints, sb.sweeps, sizeof(int) * g.h, hipMemcpyDeviceToHost, st),
-                          "hipMemcpyAsync sweeps");
-            }
             ia.in = static_cast<const cplx<T>*>(ss.out);
             ia.out = Zb[(k + 1) % 2];
             ia.z_old = Zb[k % 2];
@@ -628,14 +674,14 @@ void do_complete(tsvd_handle h, const void* X_obs, const uint8_t* mask, tsvd_sha
                         [&] { launch_dft_inverse(EPI_COMPLETE, ia, st); });
             launch_check("dft_inverse");
             prof_launch(h, K_CTRL, (double)inv_parts * kNumPartials * sizeof(double),
-                        [&] { launch_admm_ctrl(h->ctrl, sb.partials, inv_parts, 0, st); });
+                        [&] { launch_admm_ctrl(h->ctrl, sb.partials, inv_parts, 0, mirror, st); });
             launch_check("admm_ctrl");
-            hc = get_ctrl(h);
-            sweeps_last = ss.sweeps >= 0 ? ss.sweeps : max_sweeps_of(h, g.h);
-            sweeps_total += sweeps_last;
-            iters = k + 1;
-            if (hc.done) break;
-        }
+            return ss.on_device ? -1 : ss.sweeps;
+        });
+        hc = lr.c;
+        iters = hc.iter;
+        sweeps_total = lr.sweeps_total;
+        sweeps_last = lr.sweeps_last;
         launch_complete_output<T>(Y, mask, Zb[(iters - 1) % 2], Qb[(iters - 1) % 2], h->ctrl,
                                   static_cast<T*>(X_out), N, st);
         launch_check("complete_output");
@@ -729,7 +775,7 @@ void do_trpca(tsvd_handle h, const void* X, tsvd_shape shape, tsvd_dtype dtype, 
         WarmState warm;
         warm.enabled = env_int("TSVD_WARM", 1) != 0;
         warm.reorth_every = env_int("TSVD_REORTH_EVERY", sizeof(T) == 4 ? 1 : 4);
-        for (int k = 0; k < s.max_iter; ++k) {
+        const LoopResult lr = admm_loop(h, s.max_iter, [&](int k, Ctrl* mirror) -> int {
             fa.s = Sb[k % 2];
             fa.dual = Wb[k % 2];
             // M, S, W in; slices out
@@ -737,11 +783,6 @@ void do_trpca(tsvd_handle h, const void* X, tsvd_shape shape, tsvd_dtype dtype, 
                         [&] { launch_dft_forward(PRO_RPCA, fa, st); });
             launch_check("dft_forward");
             const SweepStats ss = run_svt<T>(h, g, sb, s.max_sweeps, &warm);
-            if (ss.sweeps < 0) {
-                ensure_host_ints(h, g.h);
-                hip_check(hipMemcpyAsync(h->host_ints, sb.sweeps, sizeof(int) * g.h, hipMemcpyDeviceToHost, st),
-                          "hipMemcpyAsync sweeps");
-            }
             ia.in = static_cast<const cplx<T>*>(ss.out);
             ia.out = Lb[(k + 1) % 2];
             ia.l_old = Lb[k % 2];
@@ -754,14 +795,14 @@ void do_trpca(tsvd_handle h, const void* X, tsvd_shape shape, tsvd_dtype dtype, 
                         [&] { launch_dft_inverse(epi, ia, st); });
             launch_check("dft_inverse");
             prof_launch(h, K_CTRL, (double)inv_parts * kNumPartials * sizeof(double),
-                        [&] { launch_admm_ctrl(h->ctrl, sb.partials, inv_parts, 1, st); });
+                        [&] { launch_admm_ctrl(h->ctrl, sb.partials, inv_parts, 1, mirror, st); });
             launch_check("admm_ctrl");
-            hc = get_ctrl(h);
-            sweeps_last = ss.sweeps >= 0 ? ss.sweeps : max_sweeps_of(h, g.h);
-            sweeps_total += sweeps_last;
-            iters = k + 1;
-            if (hc.done) break;
-        }
+            return ss.on_device ? -1 : ss.sweeps;
+        });
+        hc = lr.c;
+        iters = hc.iter;
+        sweeps_total = lr.sweeps_total;
+        sweeps_last = lr.sweeps_last;
         hip_check(hipMemcpyAsync(L_out, Lb[iters % 2], N * sizeof(T), hipMemcpyDeviceToDevice, st),
                   "hipMemcpyAsync L");
         hip_check(hipMemcpyAsync(S_out, Sb[iters % 2], N * sizeof(T), hipMemcpyDeviceToDevice, st),
@@ -834,6 +875,9 @@ tsvd_status tsvd_destroy(tsvd_handle h) {
         if (h->flag) (void)hipFree(h->flag);
         if (h->host_ints) (void)hipHostFree(h->host_ints);
         if (h->host_ctrl) (void)hipHostFree(h->host_ctrl);
+        if (h->mirror_host) (void)hipHostFree(h->mirror_host);
+        for (auto e : h->mirror_ev)
+            if (e) (void)hipEventDestroy(e);
         if (h->rot_counter) (void)hipFree(h->rot_counter);
         for (auto& p : h->pending) {
             (void)hipEventDestroy(p.a);

@@ -440,12 +440,14 @@ __device__ __forceinline__ void dft_inverse_body(const InvArgs<T>& a, int bid, u
 template <typename T, int PRO>
 __global__ __launch_bounds__(kBlock) void dft_forward_kernel(FwdArgs<T> a) {
     extern __shared__ __align__(16) unsigned char smem[];
+    if (a.ctrl && a.ctrl->done) return;
     dft_forward_body<T, PRO>(a, (int)blockIdx.x, smem);
 }
 
 template <typename T, int EPI>
 __global__ __launch_bounds__(kBlock) void dft_inverse_kernel(InvArgs<T> a) {
     extern __shared__ __align__(16) unsigned char smem[];
+    if (a.ctrl && a.ctrl->done) return;
     dft_inverse_body<T, EPI>(a, (int)blockIdx.x, smem);
 }
 

@@ -72,6 +72,12 @@ struct tsvd_handle_s {
     int* host_ints = nullptr;
     int host_ints_len = 0;
     tsvd::Ctrl* host_ctrl = nullptr;
+    // ADMM loop of the single-problem calls: the control kernel copies the
+    // control block into one of two slots of mapped pinned host memory, and
+    // an event per slot tells the host when it is complete
+    tsvd::Ctrl* mirror_host = nullptr;
+    tsvd::Ctrl* mirror_dev = nullptr;   // device address of mirror_host
+    hipEvent_t mirror_ev[2] = {nullptr, nullptr};
     // profiling (tsvd_profile)
     struct Pending {
         int kind;

@@ -220,8 +220,16 @@ __device__ __forceinline__ bool pair_step(cplx<T> (&x)[RPT], cplx<T>* y_lds, int
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void jacobi_init_kernel(JacArgs<T> a) {
+    if (a.ctrl && a.ctrl->done) return;
     const int s = blockIdx.y;
     const int64_t nn = (int64_t)a.n * a.n;
+    {
+        const int64_t t = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * blockDim.x + threadIdx.x;
+        const int64_t nt = (int64_t)gridDim.x * gridDim.y * blockDim.x;
+        for (int c = 0; c < 2; ++c)
+            if (a.clr[c])
+                for (int64_t i = t; i < a.nclr[c]; i += nt) a.clr[c][i] = 0;
+    }
     if (a.reset_v) {
         for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < nn;
              idx += (int64_t)gridDim.x * blockDim.x) {

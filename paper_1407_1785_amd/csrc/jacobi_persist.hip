@@ -124,6 +124,7 @@ __global__ __launch_bounds__(PBW * PG) void jacobi_persistent_kernel(JacArgs<T> 
     __shared__ int stop;
     __shared__ int ok_flag;
     __shared__ double jnorm[PBW];
+    if (a.ctrl && a.ctrl->done) return;
     const int G = a.nb / 2;
     int s, wg;
     if (p.xcds > 0) {
@@ -166,6 +167,7 @@ __global__ __launch_bounds__(PBW * PG) void jacobi_persistent_kernel(JacArgs<T> 
     __syncthreads();
 
     unsigned nrot_total = 0;
+    int swept = 0;   // sweeps started (kept by wg 0, thread 0)
     bool alive = true;
     for (int sweep = 0; sweep < p.max_sweeps && alive; ++sweep) {
         if (threadIdx.x == 0) rot_any = 0;
@@ -174,6 +176,7 @@ __global__ __launch_bounds__(PBW * PG) void jacobi_persistent_kernel(JacArgs<T> 
             __hip_atomic_store(p.rotflag + ((sweep + 1) % 3) * a.h + s, 0, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
             a.sweeps[s] = sweep + 1;
+            swept = sweep + 1;
         }
         __syncthreads();
         unsigned nrot = 0;
@@ -323,6 +326,7 @@ __global__ __launch_bounds__(PBW * PG) void jacobi_persistent_kernel(JacArgs<T> 
     }
     mark();
     if (l == 0 && nrot_total) atomicAdd(a.rotations, (unsigned long long)nrot_total);
+    if (a.ctrl && swept) atomicMax(&a.ctrl->sweep_max, swept);
 }
 
 // ------------------------------------------------------------------ host

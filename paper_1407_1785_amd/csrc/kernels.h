@@ -107,6 +107,12 @@ struct JacArgs {
     unsigned long long* rotations;  // running count of applied rotations
     T tol;          // rotate when |a_p^H a_q| > tol ||a_p|| ||a_q||
     int reset_v;    // jacobi_init: 1 = start from V = I, 0 = keep V (warm start)
+    // optional ADMM control block: jacobi_init and the persistent kernel do
+    // nothing once ctrl->done is set, and the persistent kernel raises
+    // ctrl->sweep_max to each slice's sweep count
+    Ctrl* ctrl;
+    int* clr[2];    // jacobi_init: optional int ranges zeroed before the sweeps
+    int nclr[2];
 };
 
 // C[s] = alpha * op(A[s]) * diag(d[s]) * op(B[s]) + beta * D[s] over `batch`
@@ -126,7 +132,7 @@ struct ZGemmArgs {
     T alpha, beta;
     const double* dk;      // optional column factors, K per slice, stride sdk
     int64_t sdk;
-    const Ctrl* ctrl;      // problem-table launches skip the problem once ctrl->done
+    const Ctrl* ctrl;      // optional: the product is skipped once ctrl->done
     int bf16x3;            // float only: 1 = bf16 split products, 0 = FP32 products
 };
 
@@ -239,7 +245,9 @@ struct CtrlArgs {
     int h;
 };
 void launch_admm_ctrl_batched(const CtrlArgs* tab, int nprob, hipStream_t st);
-void launch_admm_ctrl(Ctrl* c, const double* partials, int nparts, int rpca, hipStream_t st);
+// mirror (optional): a copy of the control block after the update, e.g. in
+// mapped pinned host memory; written also when the problem had already stopped
+void launch_admm_ctrl(Ctrl* c, const double* partials, int nparts, int rpca, Ctrl* mirror, hipStream_t st);
 template <typename T>
 void launch_sumsq(const T* x, const uint8_t* mask, int64_t n, double* partials, int nparts,
                   hipStream_t st);

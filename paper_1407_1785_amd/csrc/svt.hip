@@ -38,6 +38,7 @@ __device__ __forceinline__ void svt_sigma_body(const cplx<T>* W, int m, int n, i
 template <typename T>
 __global__ __launch_bounds__(kBlock) void svt_sigma_kernel(const cplx<T>* W, int m, int n, int64_t cols,
                                                           double* sigma, double* dk, const Ctrl* ctrl) {
+    if (ctrl->done) return;
     svt_sigma_body<T>(W, m, n, cols, sigma, dk, ctrl->tau, (int)blockIdx.x);
 }
 

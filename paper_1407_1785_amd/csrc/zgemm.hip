@@ -393,10 +393,12 @@ __device__ __forceinline__ void zgemm_bf16x3_body(const ZGemmArgs<float>& g, int
 
 template <typename T>
 __global__ __launch_bounds__(256) void zgemm_k4_kernel(ZGemmArgs<T> g) {
+    if (g.ctrl && g.ctrl->done) return;
     zgemm_k4_body<T>(g, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 __global__ __launch_bounds__(256) void zgemm_bf16x3_kernel(ZGemmArgs<float> g) {
+    if (g.ctrl && g.ctrl->done) return;
     zgemm_bf16x3_body(g, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
