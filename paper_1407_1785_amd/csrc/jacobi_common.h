@@ -53,6 +53,21 @@ __device__ __forceinline__ double rowpair_sum(double v) {
     return __hiloint2double((int)ah, (int)al) + __hiloint2double((int)bh, (int)bl);
 }
 
+// rowpair_sum of several independent values, their swaps in one block.
+__device__ __forceinline__ void rowpair_sum2(float& v, float& w) {
+    unsigned a = __builtin_bit_cast(unsigned, v), b = a;
+    unsigned c = __builtin_bit_cast(unsigned, w), d = c;
+    asm volatile("s_nop 1\n\tv_permlane16_swap_b32 %0, %1\n\tv_permlane16_swap_b32 %2, %3\n\ts_nop 1"
+                 : "+v"(a), "+v"(b), "+v"(c), "+v"(d));
+    v = __builtin_bit_cast(float, a) + __builtin_bit_cast(float, b);
+    w = __builtin_bit_cast(float, c) + __builtin_bit_cast(float, d);
+}
+
+__device__ __forceinline__ void rowpair_sum2(double& v, double& w) {
+    v = rowpair_sum(v);
+    w = rowpair_sum(w);
+}
+
 // Sum over the PG lanes of a pair group, in the element type; every lane of
 // the group gets the same bits (each stage adds two equal-shaped partial
 // sums, and addition is commutative).  16 lanes = one DPP row; 32 lanes =
@@ -65,6 +80,21 @@ __device__ __forceinline__ T group_sum(T v) {
     v += pdpp<0x140>(v);   // other half of the row
     if (PG == 32) v = rowpair_sum(v);
     return v;
+}
+
+// group_sum of two independent values, their exchange stages interleaved
+// (each value gets exactly the additions group_sum gives it).
+template <int PG, typename T>
+__device__ __forceinline__ void group_sum2(T& a, T& b) {
+    a += pdpp<0xB1>(a);
+    b += pdpp<0xB1>(b);
+    a += pdpp<0x4E>(a);
+    b += pdpp<0x4E>(b);
+    a += pdpp<0x141>(a);
+    b += pdpp<0x141>(b);
+    a += pdpp<0x140>(a);
+    b += pdpp<0x140>(b);
+    if (PG == 32) rowpair_sum2(a, b);
 }
 
 // 1/sqrt(x) and 1/x from the hardware estimates with Newton steps: NS = 2
@@ -90,12 +120,15 @@ struct PRot {
     bool on;
 };
 
+// The pair is rotated when |gamma|^2 > tol^2 alpha beta (and gamma != 0).
+__device__ __forceinline__ bool prot_needed(double al, double be, double g2, double tol) {
+    return g2 > (tol * tol) * al * be && g2 > 0.0;
+}
+
 template <typename T>
-__device__ __forceinline__ PRot prot(double al, double be, double gr, double gi, double tol) {
+__device__ __forceinline__ PRot prot_params(double al, double be, double gr, double gi, double g2) {
     constexpr int NS = sizeof(T) == 4 ? 1 : 2;
-    PRot r{1.0, 0.0, 0.0, 0.0, false};
-    const double g2 = gr * gr + gi * gi;
-    if (!(g2 > (tol * tol) * al * be) || !(g2 > 0.0)) return r;
+    PRot r;
     const double rg = prsqrt<NS>(g2);
     const double zeta = (be - al) * 0.5 * rg;
     const double q = 1.0 + zeta * zeta;
@@ -108,6 +141,13 @@ __device__ __forceinline__ PRot prot(double al, double be, double gr, double gi,
     r.tg = ts * (g2 * rg);
     r.on = true;
     return r;
+}
+
+template <typename T>
+__device__ __forceinline__ PRot prot(double al, double be, double gr, double gi, double tol) {
+    const double g2 = gr * gr + gi * gi;
+    if (!prot_needed(al, be, g2, tol)) return PRot{1.0, 0.0, 0.0, 0.0, false};
+    return prot_params<T>(al, be, gr, gi, g2);
 }
 
 // x <- c x - s conj(e) y,  y <- s e x + c y   with s e = a + i b
@@ -162,20 +202,34 @@ __device__ __forceinline__ double pnorm2(const cplx<T> (&x)[RPT], int ka) {
     return (double)group_sum<PG>(acc);
 }
 
-// Orthogonalise column x (registers, squared norm al) against column y in
-// LDS (squared norm be).  Lane l of the pair group holds rows l + PG k; the
-// first ka row groups (1 <= ka < RPT) are slice rows, the rest V rows,
-// padding rows are zero.  On a rotation the norms are updated in place
+// Orthogonalise column x against column y in LDS.  Lane l of the pair
+// group holds rows l + PG k; the first ka row groups (1 <= ka < RPT) are
+// slice rows, the rest V rows, padding rows are zero; only the slice rows
+// take part in the test.  With x_lds set, x is read from there first.
+// EXACT: al and be are computed here from the slice rows (their sums
+// reduced together with the inner product); otherwise they are the tracked
+// squared norms.  On a rotation the norms are updated in place
 // (al -= t|gamma|, be += t|gamma|).
-template <typename T, int PG, int RPT>
+template <typename T, int PG, int RPT, bool EXACT = false>
 __device__ __forceinline__ bool ppair(cplx<T> (&x)[RPT], cplx<T>* y_lds, double& al, double& be, int ka,
-                                      int l, double tol) {
+                                      int l, double tol, const cplx<T>* x_lds = nullptr) {
     cplx<T> y[RPT];
 #pragma unroll
-    for (int k = 0; k < RPT; ++k) y[k] = y_lds[l + PG * k];
+    for (int k = 0; k < RPT; ++k) {
+        if (x_lds) x[k] = x_lds[l + PG * k];
+        y[k] = y_lds[l + PG * k];
+    }
     T gr = 0, gi = 0;
     dot_rows<T, RPT>(x, y, ka, gr, gi, std::make_integer_sequence<int, RPT - 1>{});
-    const PRot rt = prot<T>(al, be, (double)group_sum<PG>(gr), (double)group_sum<PG>(gi), tol);
+    if (EXACT) {
+        T na = norm_rows<T, RPT>(x, ka, std::make_integer_sequence<int, RPT - 1>{});
+        T nb = norm_rows<T, RPT>(y, ka, std::make_integer_sequence<int, RPT - 1>{});
+        group_sum2<PG>(na, nb);
+        al = (double)na;
+        be = (double)nb;
+    }
+    group_sum2<PG>(gr, gi);
+    const PRot rt = prot<T>(al, be, (double)gr, (double)gi, tol);
     if (!rt.on) return false;
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {

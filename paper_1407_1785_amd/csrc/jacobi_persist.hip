@@ -114,6 +114,34 @@ __device__ bool wait_flag(int* flag, int value, int* err) {
     return true;
 }
 
+// Cross steps of a round, wave to wave: wave w finishes step st + 1 only
+// after reading what wave w + 1 (cyclically) wrote at step st, and nothing
+// else.  Each wave counts its finished steps in LDS (release after its LDS
+// writes); a wave waits for its successor's count (acquire) instead of a
+// workgroup barrier, so a step costs the waves' average rather than the
+// slowest pair.  Every wave finishes every step, so the waits end; the spin
+// cap only reports a fault through the error word.
+__device__ __forceinline__ void lds_publish(int* cnt, int value) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    if ((threadIdx.x & 63) == 0) __hip_atomic_store(cnt, value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+constexpr int kLdsSpinLimit = 1 << 18;   // far beyond any step of a workgroup's own waves
+
+__device__ __forceinline__ void lds_wait(const int* cnt, int value, int* err) {
+    int spins = 0;
+    while (__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < value) {
+        __builtin_amdgcn_s_sleep(1);
+        ++spins;
+        if (spins > kLdsSpinLimit) {
+            __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return;
+        }
+        // once the launch has failed, no wait spins to its cap again
+        if ((spins & 1023) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
+    }
+}
+
 }  // namespace
 
 template <typename T, int PG, int RPT>
@@ -124,6 +152,7 @@ __global__ __launch_bounds__(PBW * PG) void jacobi_persistent_kernel(JacArgs<T> 
     __shared__ int stop;
     __shared__ int ok_flag;
     __shared__ double jnorm[PBW];
+    __shared__ int wsteps[NT / 64];   // cross steps finished per wave, over the whole launch
     if (a.ctrl && a.ctrl->done) return;
     const int G = a.nb / 2;
     int s, wg;
@@ -159,6 +188,9 @@ __global__ __launch_bounds__(PBW * PG) void jacobi_persistent_kernel(JacArgs<T> 
 
     // zero both blocks once: padding rows stay zero under every rotation
     for (int idx = threadIdx.x; idx < 2 * PBW * ldc; idx += NT) blk0[idx] = cplx<T>{(T)0, (T)0};
+    const int wave = threadIdx.x >> 6, wave_next = (wave + 1) % (NT / 64);
+    if ((threadIdx.x & 63) == 0) wsteps[wave] = 0;
+    int steps = 0;   // cross steps finished by every wave before the current round
     __syncthreads();
     int player0 = ppos_player(pos0, 0, a.nb), player1 = ppos_player(pos1, 0, a.nb);
     pload_block<T, NT>(a, s, player0, mp, ldc, blk0);
@@ -196,14 +228,9 @@ __global__ __launch_bounds__(PBW * PG) void jacobi_persistent_kernel(JacArgs<T> 
                     if (pp < w && qq < w) {
                         cplx<T>* cp = base + pp * ldc;
                         cplx<T>* cq = base + qq * ldc;
-                        cplx<T> x[RPT], y[RPT];
-#pragma unroll
-                        for (int k = 0; k < RPT; ++k) {
-                            x[k] = cp[l + PG * k];
-                            y[k] = cq[l + PG * k];
-                        }
-                        double al = pnorm2<T, PG, RPT>(x, ka), be = pnorm2<T, PG, RPT>(y, ka);
-                        if (ppair<T, PG, RPT>(x, cq, al, be, ka, l, tol)) {
+                        cplx<T> x[RPT];
+                        double al, be;
+                        if (ppair<T, PG, RPT, true>(x, cq, al, be, ka, l, tol, cp)) {
                             ++nrot;
 #pragma unroll
                             for (int k = 0; k < RPT; ++k) cp[l + PG * k] = x[k];
@@ -231,7 +258,10 @@ __global__ __launch_bounds__(PBW * PG) void jacobi_persistent_kernel(JacArgs<T> 
                 if (l == 0) jnorm[g] = bj;
             }
             __syncthreads();
+            // step st: group g meets column (g + st) mod PBW of block 1, which
+            // group g + 1 met at step st - 1
             for (int st = 0; st < PBW; ++st) {
+                if (st > 0) lds_wait(wsteps + wave_next, steps + st, p.err);
                 const int jc = (g + st) & (PBW - 1);
                 if (g < wi && jc < wj) {
                     double be = jnorm[jc];
@@ -240,8 +270,10 @@ __global__ __launch_bounds__(PBW * PG) void jacobi_persistent_kernel(JacArgs<T> 
                         if (l == 0) jnorm[jc] = be;
                     }
                 }
-                __syncthreads();
+                lds_publish(wsteps + wave, steps + st + 1);
             }
+            steps += PBW;
+            __syncthreads();
             if (g < wi) {
 #pragma unroll
                 for (int k = 0; k < RPT; ++k) blk0[g * ldc + l + PG * k] = xi[k];

@@ -64,14 +64,9 @@ __device__ __forceinline__ unsigned pair_round(cplx<T>* blk0, cplx<T>* blk1, int
                 if (pp < w && qq < w) {
                     cplx<T>* cp = base + pp * ldc;
                     cplx<T>* cq = base + qq * ldc;
-                    cplx<T> x[RPT], y[RPT];
-#pragma unroll
-                    for (int k = 0; k < RPT; ++k) {
-                        x[k] = cp[l + PG * k];
-                        y[k] = cq[l + PG * k];
-                    }
-                    double al = pnorm2<T, PG, RPT>(x, ka), be = pnorm2<T, PG, RPT>(y, ka);
-                    if (ppair<T, PG, RPT>(x, cq, al, be, ka, l, tol)) {
+                    cplx<T> x[RPT];
+                    double al, be;
+                    if (ppair<T, PG, RPT, true>(x, cq, al, be, ka, l, tol, cp)) {
                         ++nrot;
 #pragma unroll
                         for (int k = 0; k < RPT; ++k) cp[l + PG * k] = x[k];
