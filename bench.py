@@ -228,6 +228,9 @@ def main() -> int:
     ap.add_argument("--serve-window", type=float, default=2.0,
                     help="seconds of arrivals replayed (the full trace is 60 s)")
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
+    ap.add_argument("--serve-sustained-rate", type=float, default=2.0,
+                    help="second serving window at a rate below capacity (0: skip)")
+    ap.add_argument("--serve-sustained-window", type=float, default=10.0)
     ap.add_argument("--only-legs", action="store_true", help="run the batched and serving legs only")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain device copy of 1 GiB (reference for HBM byte counters) and exit")
@@ -265,6 +268,10 @@ def main() -> int:
             res["serving"] = serving_leg(lib, torch, np, workloads, args.serve_rate, args.serve_window,
                                          args.serve_budget_gb)
             print(json.dumps({"serving": res["serving"]}), flush=True)
+            if args.serve_sustained_rate > 0:
+                res["serving_sustained"] = serving_leg(lib, torch, np, workloads, args.serve_sustained_rate,
+                                                       args.serve_sustained_window, args.serve_budget_gb)
+                print(json.dumps({"serving_sustained": res["serving_sustained"]}), flush=True)
         return 0
     w = workloads.video_completion(0, shape=SHAPE)
     mask = torch.from_numpy(w["mask"]).to(dev)
@@ -350,6 +357,10 @@ def main() -> int:
     if not args.no_serve:
         result["serving"] = serving_leg(lib, torch, np, workloads, args.serve_rate, args.serve_window,
                                         args.serve_budget_gb)
+        if args.serve_sustained_rate > 0:
+            # below capacity: latency is the service time in the mix, not queueing
+            result["serving_sustained"] = serving_leg(lib, torch, np, workloads, args.serve_sustained_rate,
+                                                      args.serve_sustained_window, args.serve_budget_gb)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(result), flush=True)

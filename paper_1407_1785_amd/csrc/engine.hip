@@ -215,6 +215,12 @@ public:
 
     hipStream_t stream() const { return stream_; }
     size_t running() const { return slots_.size(); }
+    // Fourier slices of the running problems (their share of the chip)
+    int64_t running_slices() const {
+        int64_t s = 0;
+        for (const Slot<T>& sl : slots_) s += sl.sp.g.h;
+        return s;
+    }
     int64_t iterations() const { return iterations_; }
 
     static size_t footprint(const Spec& sp) {
@@ -877,6 +883,9 @@ struct Server {
     char* mem = nullptr;
     Engine<float> ef;
     Engine<double> ed;
+    // admission stops at this many running Fourier slices (the batched form
+    // keeps the chip busy with about a thousand)
+    int64_t slice_cap = std::max(1, env_int("TSVD_SERVE_SLICES", 1024));
 
     void start() {
         if (started) return;
@@ -924,7 +933,10 @@ struct Server {
                 if (stop) return;
             }
             try {
-                // admit from the head of the queue while the arena has room
+                // admit from the head of the queue while the arena has room and
+                // the running problems do not yet fill the chip: past about
+                // slice_cap Fourier slices the GPU is saturated, and admitting
+                // more only makes every running request slower
                 for (;;) {
                     Queued q;
                     {
@@ -932,6 +944,8 @@ struct Server {
                         if (queue.empty()) break;
                         q = queue.front();
                     }
+                    const int64_t busy = ef.running_slices() + ed.running_slices();
+                    if (busy > 0 && busy + q.sp.g.h > slice_cap) break;
                     const bool ok = q.sp.fp32 ? ef.admit(q.sp, q.ticket, q.t0) : ed.admit(q.sp, q.ticket, q.t0);
                     if (!ok) break;
                     std::lock_guard<std::mutex> lk(mu);
