@@ -162,6 +162,44 @@ tsvd_status trpca(tsvd_handle h, const void* X, tsvd_shape shape, tsvd_dtype dty
                   double lambda, double mu, double tol, tsvd_shrink shrink,
                   const tsvd_admm_opts* opts, void* L_out, void* S_out, tsvd_info* info_host);
 
+/* The t-SVD M = U * S * V^T (Sec. 2.2, Algorithm 1): one SVD per Fourier
+ * slice (half spectrum; in 4-D the conjugate pairs inside it are solved once
+ * and mirrored), singular values of every slice in decreasing order, and the
+ * inverse transform of the factors along the trailing modes.  The factors
+ * are real; they are returned in economy form (n0 = min(n1, n2)): the
+ * columns of the paper's U and V beyond n0 multiply zero rows of S.
+ *
+ * M: device array of shape `shape` (n1 x n2 x trailing, C order), dtype.
+ * U_out: device array n1 x n0 x trailing (lateral slices U(:, i, :)).
+ * S_out: device array n0 x trailing: the singular tubes S(i, i, :) (the
+ *   f-diagonal of S; the rest of S is zero).
+ * V_out: device array n2 x n0 x trailing.  M = sum_i U(:, i, :) * S(i, i, :)
+ *   * V(:, i, :)^T.  A Fourier-domain singular value of 0 gets a zero
+ *   left singular vector.
+ * Errors: as tsvt (no tau). */
+tsvd_status tsvd_factors(tsvd_handle h, const void* M, tsvd_shape shape, tsvd_dtype dtype,
+                         tsvd_precision precision, void* U_out, void* S_out, void* V_out);
+
+typedef enum {
+    TSVD_COMPRESS_TSVD = 1,    /* Method 1: the k largest Fourier-domain singular values */
+    TSVD_COMPRESS_TUBAL = 2    /* Method 2: the first k singular tubes (Theorem 2.3.1)  */
+} tsvd_compress_method;
+
+/* Compression by truncated t-SVD (Sec. 3) of a third-order tensor M:
+ * Method 1 keeps the entries sigma >= t of the Fourier-domain S over the full
+ * spectrum, t the smallest threshold for which at most k of them (every
+ * entry of the full spectrum counted once) are kept -- conjugate pairs and
+ * exact ties at the cut are kept or dropped together, so fewer than k can be
+ * kept; 1 <= k <= n0 * n3.  Method 2 keeps the first k singular tubes,
+ * 1 <= k <= n0.  M_out receives the approximation; ratio_host (nullable)
+ * the compression ratio of Sec. 3: n1 n2 n3 / (k (n1 + n2 + 1)) for Method 1,
+ * n1 n2 / (k (n1 + n2 + 1)) for Method 2.
+ * Errors: TSVD_E_SHAPE for a tensor that is not third-order, TSVD_E_INVALID
+ * for k out of range or an unknown method; otherwise as tsvt. */
+tsvd_status tsvd_compress(tsvd_handle h, const void* M, tsvd_shape shape, tsvd_dtype dtype,
+                          tsvd_precision precision, int32_t method, int64_t k, void* M_out,
+                          double* ratio_host);
+
 /* Per-kernel timing of the work a handle runs while profiling is on: a HIP
  * event pair around every launch on the handle's stream.  `work` is the
  * kernel's algorithmic work under the cost model stated in its source file:

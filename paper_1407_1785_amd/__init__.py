@@ -28,6 +28,7 @@ __all__ = [
     "LibraryNotBuilt", "TsvdError", "Info", "library_path", "load_library", "tsvt",
     "tsvd_complete", "trpca", "Handle", "PREC_FP64", "PREC_FP32", "SHRINK_L1", "SHRINK_L112",
     "Problem", "complete_problem", "trpca_problem", "batch_run", "submit", "poll", "serve_stats",
+    "tsvd_factors", "compress", "COMPRESS_TSVD", "COMPRESS_TUBAL",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -35,6 +36,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 PREC_FP64, PREC_FP32 = 0, 1
 DTYPE_F64, DTYPE_F32 = 0, 1
 SHRINK_L1, SHRINK_L112 = 0, 1
+COMPRESS_TSVD, COMPRESS_TUBAL = 1, 2
 
 STATUS = {0: "TSVD_OK", -1: "TSVD_E_INVALID", -2: "TSVD_E_SHAPE", -3: "TSVD_E_NOMEM",
           -4: "TSVD_E_HIP", -5: "TSVD_E_NONFINITE", -6: "TSVD_E_UNSUPPORTED", -7: "TSVD_E_BUSY"}
@@ -118,6 +120,11 @@ _SIGNATURES = {
                              ctypes.c_double, ctypes.c_double, ctypes.c_int,
                              ctypes.POINTER(AdmmOpts), ctypes.c_void_p, ctypes.c_void_p,
                              ctypes.POINTER(Info)]),
+    "tsvd_factors": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, Shape, ctypes.c_int, ctypes.c_int,
+                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "tsvd_compress": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, Shape, ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p,
+                                     ctypes.POINTER(ctypes.c_double)]),
     "tsvd_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "tsvd_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(KernelStat), ctypes.c_int,
                                          ctypes.POINTER(ctypes.c_int)]),
@@ -291,6 +298,47 @@ def tsvt(X, tau: float, precision: int = PREC_FP64, handle: Handle | None = None
     _check(load_library().tsvt(handle.ptr, ctypes.c_void_p(X.data_ptr()), _shape(X), _dtype_code(X),
                                float(tau), int(precision), ctypes.c_void_p(Z.data_ptr()), ranks))
     return Z, list(ranks)
+
+
+def tsvd_factors(M, precision: int = PREC_FP64, handle: Handle | None = None):
+    """Real t-SVD factors of M (include/tsvd.h, ``tsvd_factors``).
+
+    Returns (U, S, V): U of shape (n1, n0) + trailing, S (n0,) + trailing
+    (the singular tubes S(i, i, :)), V (n2, n0) + trailing, n0 = min(n1, n2),
+    new tensors like M."""
+    import torch
+
+    M = _prepare(M, "M")
+    handle = handle or _handle_for(M)
+    _bind_stream(handle, M)
+    n1, n2 = M.shape[0], M.shape[1]
+    n0 = min(n1, n2)
+    trail = tuple(M.shape[2:])
+    U = torch.empty((n1, n0) + trail, dtype=M.dtype, device=M.device)
+    S = torch.empty((n0,) + trail, dtype=M.dtype, device=M.device)
+    V = torch.empty((n2, n0) + trail, dtype=M.dtype, device=M.device)
+    _check(load_library().tsvd_factors(handle.ptr, ctypes.c_void_p(M.data_ptr()), _shape(M), _dtype_code(M),
+                                       int(precision), ctypes.c_void_p(U.data_ptr()),
+                                       ctypes.c_void_p(S.data_ptr()), ctypes.c_void_p(V.data_ptr())))
+    return U, S, V
+
+
+def compress(M, method: int, k: int, precision: int = PREC_FP64, handle: Handle | None = None):
+    """Compression of a third-order M by Method 1 (COMPRESS_TSVD, the k
+    largest Fourier-domain singular values) or Method 2 (COMPRESS_TUBAL, the
+    first k singular tubes) (include/tsvd.h, ``tsvd_compress``).
+    Returns (M_k, ratio)."""
+    import torch
+
+    M = _prepare(M, "M")
+    handle = handle or _handle_for(M)
+    _bind_stream(handle, M)
+    out = torch.empty_like(M)
+    ratio = ctypes.c_double(0.0)
+    _check(load_library().tsvd_compress(handle.ptr, ctypes.c_void_p(M.data_ptr()), _shape(M), _dtype_code(M),
+                                        int(precision), int(method), int(k), ctypes.c_void_p(out.data_ptr()),
+                                        ctypes.byref(ratio)))
+    return out, ratio.value
 
 
 def tsvd_complete(X_obs, mask, rho: float = 1e-2, tol: float = 1e-8, growth: float = 1.1,

@@ -223,6 +223,8 @@ struct SweepStats {
     int sweeps = 0;
     bool on_device = false;      // the sweeps were counted into ctrl->sweep_max
     const void* out = nullptr;   // slice buffer holding the prox output
+    const void* w = nullptr;     // W = A V (orthogonal columns, sigma_j = ||w_j||)
+    const void* v = nullptr;     // V
 };
 
 // Jacobi sweeps + shrink + rebuild on the slices in sb.A; output in sb.Z.
@@ -233,7 +235,7 @@ struct SweepStats {
 // slice rows and n V rows of both columns).
 template <typename T>
 SweepStats run_svt(tsvd_handle h, const Geometry& g, const SvtBuffers<T>& sb, int max_sweeps,
-                   WarmState* warm = nullptr, bool want_rank = false) {
+                   WarmState* warm = nullptr, bool want_rank = false, bool rebuild = true) {
     hipStream_t st = h->stream;
     const bool use_warm = warm && warm->enabled && warm->valid;
     const int64_t nn = (int64_t)g.n * g.n, mn = (int64_t)g.m * g.n;
@@ -410,8 +412,10 @@ SweepStats run_svt(tsvd_handle h, const Geometry& g, const SvtBuffers<T>& sb, in
     gr.alpha = (T)1; gr.beta = (T)0; gr.opA = 0; gr.opB = 1; gr.batch = g.h;
     gr.dk = sb.dk; gr.sdk = g.n; gr.ctrl = h->ctrl;
     gr.bf16x3 = env_int("TSVD_REBUILD_BF16", 0);
-    prof_launch(h, K_SVT_REBUILD, 8.0 * g.m * g.n * g.n * g.h, [&] { launch_zgemm(gr, st); });
-    launch_check("svt_rebuild");
+    if (rebuild) {
+        prof_launch(h, K_SVT_REBUILD, 8.0 * g.m * g.n * g.n * g.h, [&] { launch_zgemm(gr, st); });
+        launch_check("svt_rebuild");
+    }
     if (want_rank) {
         launch_multirank(sb.sigma, g.n, g.n, g.h, h->ctrl, sb.rank, st);
         launch_check("multirank");
@@ -434,6 +438,8 @@ SweepStats run_svt(tsvd_handle h, const Geometry& g, const SvtBuffers<T>& sb, in
         warm->iter += 1;
     }
     stats.out = out;
+    stats.w = work;
+    stats.v = sb.V[vc];
     return stats;
 }
 
@@ -586,6 +592,157 @@ void do_tsvt(tsvd_handle h, const void* X, tsvd_shape shape, tsvd_dtype dtype, d
         prof_harvest(h);
         check_persist_err(h, g, sb);
         if (read_flag(h)) fail(TSVD_E_NONFINITE, "non-finite input");
+}
+
+// The slice SVDs of M with nothing thresholded (Sec. 2.2, Algorithm 1):
+// forward DFT, cold Jacobi (up to 30 sweeps), singular values, and in 4-D
+// the conjugate pairs inside the half spectrum mirrored.  `extra` bytes of
+// workspace stay free after the SVD buffers for the caller's carver.
+template <typename T>
+struct SvdStage {
+    SvtBuffers<T> sb;
+    SweepStats ss;
+    Carver cv{nullptr};
+    const T* dmat = nullptr;
+};
+
+template <typename T>
+SvdStage<T> svd_stage(tsvd_handle h, const Geometry& g, const void* X, size_t extra) {
+    const int nparts = (int)dft_grid(g, dft_inverse_tile(g, EPI_STORE));
+    ensure_workspace(h, svt_bytes<T>(g, nparts) + extra + 4096);
+    SvdStage<T> st;
+    st.cv = Carver{reinterpret_cast<char*>(h->ws)};
+    st.sb = carve_svt<T>(st.cv, g, nparts);
+    st.dmat = ensure_dft_matrices<T>(h, g);
+    Ctrl c{};
+    c.rho = INFINITY;
+    c.tau = 0.0;
+    c.dscale = 1.0;
+    put_ctrl(h, c);
+    clear_flag(h);
+    clear_persist_err(h, g, st.sb);
+    FwdArgs<T> fa{};
+    fa.x = static_cast<const T*>(X);
+    fa.ctrl = h->ctrl;
+    fa.mat = st.dmat;
+    fa.out = st.sb.A;
+    fa.nonfinite = h->flag;
+    fa.g = g;
+    fa.tile = dft_forward_tile(g);
+    const double slice_bytes = (double)g.h * g.m * g.n * sizeof(cplx<T>);
+    prof_launch(h, K_DFT_FWD, slice_bytes + (double)g.numel * sizeof(T),
+                [&] { launch_dft_forward(PRO_COPY, fa, h->stream); });
+    launch_check("dft_forward");
+    st.ss = run_svt<T>(h, g, st.sb, 30, nullptr, false, false);
+    launch_tsvd_mirror<T>(static_cast<cplx<T>*>(const_cast<void*>(st.ss.w)),
+                          static_cast<cplx<T>*>(const_cast<void*>(st.ss.v)), st.sb.sigma, g, h->stream);
+    launch_check("tsvd_mirror");
+    return st;
+}
+
+// Real inverse transform (EPI_STORE) of h slices of a tensor of geometry gf
+// that shares the trailing modes of the DFT matrices in dmat.
+template <typename T>
+void inverse_store(tsvd_handle h, const Geometry& gf, const T* dmat, const cplx<T>* in, T* out) {
+    InvArgs<T> ia{};
+    ia.in = in;
+    ia.mat = dmat + DftDims::of(gf.h, gf.L).fwd_size();
+    ia.ctrl = h->ctrl;
+    ia.g = gf;
+    ia.tile = dft_inverse_tile(gf, EPI_STORE);
+    ia.out = out;
+    prof_launch(h, K_DFT_INV, (double)gf.h * gf.m * gf.n * sizeof(cplx<T>) + (double)gf.numel * sizeof(T),
+                [&] { launch_dft_inverse(EPI_STORE, ia, h->stream); });
+    launch_check("dft_inverse");
+}
+
+// The geometry of a tensor with matrix modes a x b and the trailing modes of s.
+Geometry factor_geometry(const tsvd_shape& s, int64_t a, int64_t b) {
+    tsvd_shape f = s;
+    f.n[0] = a;
+    f.n[1] = b;
+    return make_geometry(f);
+}
+
+template <typename T>
+void finish_call(tsvd_handle h, const Geometry& g, const SvtBuffers<T>& sb) {
+    hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+    prof_harvest(h);
+    check_persist_err(h, g, sb);
+    if (read_flag(h)) fail(TSVD_E_NONFINITE, "non-finite input");
+}
+
+template <typename T>
+void do_factors(tsvd_handle h, const void* M, tsvd_shape shape, void* U_out, void* S_out, void* V_out) {
+    check_handle(h);
+    if (!M || !U_out || !S_out || !V_out) fail(TSVD_E_INVALID, "null tensor pointer");
+    const Geometry g = make_geometry(shape);
+    if (!jacobi_supported(g.m, g.n, sizeof(T))) fail(TSVD_E_SHAPE, "slice too large for the Jacobi kernels");
+    Device dev(h->device);
+    const int64_t n0 = g.n, n1 = g.n1, n2 = g.n2, hn = (int64_t)g.h * g.n;
+    const size_t extra = hn * sizeof(int) + (size_t)g.h * (n1 + n2 + 1) * n0 * sizeof(cplx<T>) + 4 * 256;
+    SvdStage<T> st = svd_stage<T>(h, g, M, extra);
+    Carver cv = st.cv;
+    int* rank = cv.take<int>(hn);
+    cplx<T>* Uh = cv.take<cplx<T>>((int64_t)g.h * n1 * n0);
+    cplx<T>* Vh = cv.take<cplx<T>>((int64_t)g.h * n2 * n0);
+    cplx<T>* Sh = cv.take<cplx<T>>((int64_t)g.h * n0);
+    launch_tsvd_rank(st.sb.sigma, g.n, g.h, rank, h->stream);
+    launch_tsvd_factors<T>(static_cast<const cplx<T>*>(st.ss.w), static_cast<const cplx<T>*>(st.ss.v), st.sb.sigma,
+                           rank, g, Uh, Vh, Sh, h->stream);
+    launch_check("tsvd_factors");
+    inverse_store<T>(h, factor_geometry(shape, n1, n0), st.dmat, Uh, static_cast<T*>(U_out));
+    inverse_store<T>(h, factor_geometry(shape, n2, n0), st.dmat, Vh, static_cast<T*>(V_out));
+    inverse_store<T>(h, factor_geometry(shape, n0, 1), st.dmat, Sh, static_cast<T*>(S_out));
+    finish_call<T>(h, g, st.sb);
+}
+
+template <typename T>
+void do_compress(tsvd_handle h, const void* M, tsvd_shape shape, int32_t method, int64_t k, void* M_out,
+                 double* ratio_host) {
+    check_handle(h);
+    if (!M || !M_out) fail(TSVD_E_INVALID, "null tensor pointer");
+    if (shape.ndim != 3) fail(TSVD_E_SHAPE, "the compression methods are stated for third-order tensors");
+    const Geometry g = make_geometry(shape);
+    if (!jacobi_supported(g.m, g.n, sizeof(T))) fail(TSVD_E_SHAPE, "slice too large for the Jacobi kernels");
+    const int64_t n0 = g.n, n1 = g.n1, n2 = g.n2, n3 = g.L;
+    if (method == TSVD_COMPRESS_TSVD) {
+        if (k < 1 || k > n0 * n3) fail(TSVD_E_INVALID, "Method 1 needs 1 <= k <= min(n1, n2) n3");
+    } else if (method == TSVD_COMPRESS_TUBAL) {
+        if (k < 1 || k > n0) fail(TSVD_E_INVALID, "Method 2 needs 1 <= k <= min(n1, n2)");
+    } else {
+        fail(TSVD_E_INVALID, "unknown compression method");
+    }
+    Device dev(h->device);
+    const int64_t hn = (int64_t)g.h * g.n;
+    SvdStage<T> st = svd_stage<T>(h, g, M, hn * sizeof(int) + 256);
+    if (method == TSVD_COMPRESS_TUBAL) {
+        Carver cv = st.cv;
+        int* rank = cv.take<int>(hn);
+        launch_tsvd_rank(st.sb.sigma, g.n, g.h, rank, h->stream);
+        launch_tubal_select(rank, hn, (int)k, st.sb.dk, h->stream);
+    } else {
+        launch_global_select(st.sb.sigma, g, k, st.sb.dk, h->stream);
+    }
+    launch_check("select");
+    // the kept triplets: W diag(d) V^H with d in {0, 1}
+    const cplx<T>* W = static_cast<const cplx<T>*>(st.ss.w);
+    cplx<T>* out = W == st.sb.A ? st.sb.Z : st.sb.A;
+    const int64_t mn = (int64_t)g.m * g.n, nn = (int64_t)g.n * g.n;
+    ZGemmArgs<T> gr{};
+    gr.A = W; gr.B = static_cast<const cplx<T>*>(st.ss.v); gr.C = out;
+    gr.M = g.m; gr.N = g.n; gr.K = g.n;
+    gr.lda = g.m; gr.ldb = g.n; gr.ldc = g.m; gr.ldd = g.m;
+    gr.sA = mn; gr.sB = nn; gr.sC = mn; gr.sD = mn;
+    gr.alpha = (T)1; gr.beta = (T)0; gr.opA = 0; gr.opB = 1; gr.batch = g.h;
+    gr.dk = st.sb.dk; gr.sdk = g.n; gr.ctrl = h->ctrl;
+    prof_launch(h, K_SVT_REBUILD, 8.0 * g.m * g.n * g.n * g.h, [&] { launch_zgemm(gr, h->stream); });
+    launch_check("compress_rebuild");
+    inverse_store<T>(h, g, st.dmat, out, static_cast<T*>(M_out));
+    finish_call<T>(h, g, st.sb);
+    if (ratio_host)
+        *ratio_host = method == TSVD_COMPRESS_TSVD ? (double)(n1 * n2 * n3) / ((double)k * (double)(n1 + n2 + 1))
+                                                   : (double)(n1 * n2) / ((double)k * (double)(n1 + n2 + 1));
 }
 
 template <typename T>
@@ -903,6 +1060,29 @@ tsvd_status tsvt(tsvd_handle h, const void* X, tsvd_shape shape, tsvd_dtype dtyp
             do_tsvt<float>(h, X, shape, dtype, tau, precision, Z, multirank_host);
         else
             do_tsvt<double>(h, X, shape, dtype, tau, precision, Z, multirank_host);
+    });
+}
+
+tsvd_status tsvd_factors(tsvd_handle h, const void* M, tsvd_shape shape, tsvd_dtype dtype,
+                         tsvd_precision precision, void* U_out, void* S_out, void* V_out) {
+    return guarded([&] {
+        check_handle(h);
+        if (check_precision(dtype, precision))
+            do_factors<float>(h, M, shape, U_out, S_out, V_out);
+        else
+            do_factors<double>(h, M, shape, U_out, S_out, V_out);
+    });
+}
+
+tsvd_status tsvd_compress(tsvd_handle h, const void* M, tsvd_shape shape, tsvd_dtype dtype,
+                          tsvd_precision precision, int32_t method, int64_t k, void* M_out,
+                          double* ratio_host) {
+    return guarded([&] {
+        check_handle(h);
+        if (check_precision(dtype, precision))
+            do_compress<float>(h, M, shape, method, k, M_out, ratio_host);
+        else
+            do_compress<double>(h, M, shape, method, k, M_out, ratio_host);
     });
 }
 

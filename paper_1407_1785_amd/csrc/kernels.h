@@ -141,6 +141,16 @@ void launch_zgemm(const ZGemmArgs<T>& g, hipStream_t st);
 int zgemm_workgroups(int M, int N, int batch);
 template <typename T>
 void launch_zgemm_batched(const ZGemmArgs<T>* tab, const int* wg_start, int nprob, int nwg, hipStream_t st);
+// t-SVD factors and compression (factors.hip)
+template <typename T>
+void launch_tsvd_mirror(cplx<T>* W, cplx<T>* V, double* sigma, const Geometry& g, hipStream_t st);
+void launch_tsvd_rank(const double* sigma, int n, int h, int* rank, hipStream_t st);
+template <typename T>
+void launch_tsvd_factors(const cplx<T>* W, const cplx<T>* V, const double* sigma, const int* rank, const Geometry& g,
+                         cplx<T>* Uh, cplx<T>* Vh, cplx<T>* Sh, hipStream_t st);
+void launch_tubal_select(const int* rank, int64_t count, int k3, double* dk, hipStream_t st);
+void launch_global_select(const double* sigma, const Geometry& g, int64_t k2, double* dk, hipStream_t st);
+
 void launch_multirank(const double* sigma, int64_t ssig, int K, int h, const Ctrl* ctrl, int* rank,
                       hipStream_t st);
 // One problem of a one-workgroup-per-slice Jacobi launch (jacobi_slice.hip).

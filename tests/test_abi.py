@@ -30,7 +30,7 @@ def test_header_declares_the_boundary():
     names = declared_functions()
     for fn in ("tsvt", "tsvd_complete", "trpca", "tsvd_create", "tsvd_destroy", "tsvd_set_stream",
                "tsvd_status_string", "tsvd_last_error", "tsvd_batch_run", "tsvd_submit", "tsvd_poll",
-               "tsvd_serve_stats_read"):
+               "tsvd_serve_stats_read", "tsvd_factors", "tsvd_compress"):
         assert fn in names
 
 
