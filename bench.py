@@ -85,9 +85,9 @@ def batched_leg(lib, torch, np, workloads, iters: int):
     tubal rank ~ U{2..10}, Bernoulli(p ~ U[0.2, 0.6]) masks), FP32 form, a
     fixed number of iterations each, solved together by tsvd_batch_run.
     A short run over the same problems first lets the block-width tuner see
-    every shape class (its choices are cached for the process)."""
-    from oracle import admm
-
+    every shape class (its choices are cached for the process).  Returns the
+    leg's figures and its smallest problem (inputs and GPU result) for the
+    oracle comparison of the CPU leg."""
     specs = workloads.batch_specs(0)
     probs, data = [], []
     for i, sp in enumerate(specs):
@@ -113,18 +113,59 @@ def batched_leg(lib, torch, np, workloads, iters: int):
            "iters_per_s": len(probs) * iters / dt,
            "statuses_ok": all(st == 0 for st, _ in res),
            "sweeps_per_iter_mean": float(np.mean([i.sweeps_total / max(1, i.iters) for _, i in res]))}
-    # checks: the observed entries are kept exactly; the smallest problem
-    # against the FP64 oracle at the same iteration count
+    # the observed entries are kept exactly; the smallest problem goes to the
+    # CPU leg for the oracle comparison at the same iteration count
     out["observed_kept_exactly"] = all(
         bool(np.array_equal(p.out.cpu().numpy()[d["mask"].astype(bool)],
                             d["M_obs"].astype(np.float32)[d["mask"].astype(bool)])) for p, d in zip(probs, data))
     k = int(np.argmin([d["M_obs"].size for d in data]))
-    ref = admm.complete(data[k]["M_obs"], data[k]["mask"], data[k]["rho"], data[k]["growth"],
-                        data[k]["rho_max"], max_iter=iters, tol=0.0)
-    got = probs[k].out.cpu().numpy().astype(np.float64)
-    out["sampled_rse_vs_oracle"] = float(np.linalg.norm(got - ref["X"]) / np.linalg.norm(ref["X"]))
     out["sampled_shape"] = list(data[k]["M_obs"].shape)
-    return out
+    case = {"data": data[k], "iters": iters, "got": probs[k].out.cpu().numpy().astype(np.float64)}
+    return out, case
+
+
+def compression_leg(lib, torch, np, workloads):
+    """Sec. 3 on the synthetic video (the completion workload's full
+    128 x 160 x 64 tensor): the explicit t-SVD factors (FP64 path and FP32
+    form) and Methods 1 and 2 at compression ratios near 5, 10, 20 and 40,
+    each timed on the GPU as the mean of 3 calls after one untimed call, with
+    RSE in dB (20 log10 of the relative Frobenius error, as Sec. 3 plots it).
+    Returns the figures and one Method 1 result for the CPU leg's oracle
+    comparison."""
+    x = np.asarray(workloads.video_completion(0, shape=SHAPE)["X"], dtype=np.float64)
+    n1, n2, n3 = x.shape
+    xg = torch.from_numpy(x).cuda()
+    xg32 = xg.float()
+
+    def timed(fn, reps=3):
+        r = fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r = fn()
+        torch.cuda.synchronize()
+        return r, (time.perf_counter() - t0) / reps
+
+    def rse_db(a):
+        a = a.cpu().numpy().astype(np.float64)
+        return float(20.0 * np.log10(np.linalg.norm(a - x) / np.linalg.norm(x)))
+
+    _, t64 = timed(lambda: lib.tsvd_factors(xg))
+    _, t32 = timed(lambda: lib.tsvd_factors(xg32, precision=lib.PREC_FP32))
+    curve = []
+    for target in (5, 10, 20, 40):
+        k2 = max(1, round(n1 * n2 * n3 / (target * (n1 + n2 + 1))))
+        k3 = max(1, round(n1 * n2 / (target * (n1 + n2 + 1))))
+        (m1, r1), t1 = timed(lambda: lib.compress(xg, lib.COMPRESS_TSVD, k2))
+        (m2, r2), t2 = timed(lambda: lib.compress(xg, lib.COMPRESS_TUBAL, k3))
+        curve.append({"target_ratio": target,
+                      "method1": {"k2": k2, "ratio": r1, "rse_db": rse_db(m1), "ms": t1 * 1e3},
+                      "method2": {"k3": k3, "ratio": r2, "rse_db": rse_db(m2), "ms": t2 * 1e3}})
+    k2 = curve[1]["method1"]["k2"]
+    got = lib.compress(xg, lib.COMPRESS_TSVD, k2)[0].cpu().numpy()
+    out = {"workload": "t-SVD factors and compression (Sec. 3) of the synthetic 128x160x64 video",
+           "factors_ms_fp64": t64 * 1e3, "factors_ms_fp32": t32 * 1e3, "curve": curve}
+    return out, {"x": x, "k2": k2, "got": got}
 
 
 def serving_leg(lib, torch, np, workloads, rate: float, window: float, budget_gb: float):
@@ -186,11 +227,40 @@ def serving_leg(lib, torch, np, workloads, rate: float, window: float, budget_gb
             "arena_gb": stats["arena_bytes"] / (1 << 30)}
 
 
-def cpu_baseline(w, seconds: float):
-    """The FP64 oracle on the same workload, timed for a bounded number of
-    iterations (about `seconds` of CPU work)."""
+def cpu_baseline(w, seconds: float, cases: dict):
+    """The FP64 oracle on the host: the same completion timed for a bounded
+    number of iterations (about `seconds` of CPU work), and the reference
+    results of the GPU legs' comparison cases (not timed, except the t-SVD of
+    the compression leg).  Returns (baseline, comparisons)."""
     import numpy as np
     from oracle import admm
+    from oracle import compress as ocompress
+    from oracle import tensor as otensor
+
+    cmp = {}
+    if "video" in cases:
+        c = cases["video"]
+        ref = admm.complete(np.asarray(w["M_obs"], dtype=np.float64), w["mask"], w["rho"], w["growth"],
+                            w["rho_max"], max_iter=c["iters"], tol=0.0)["X"]
+        den = np.linalg.norm(ref)
+        cmp["parity"] = {"iters": c["iters"],
+                         "fp64_rel_err_vs_oracle": float(np.linalg.norm(c["got64"] - ref) / den),
+                         "fp32_rel_err_vs_oracle": float(np.linalg.norm(c["got32"] - ref) / den)}
+    if "batched" in cases:
+        c = cases["batched"]
+        d = c["data"]
+        ref = admm.complete(d["M_obs"], d["mask"], d["rho"], d["growth"], d["rho_max"], max_iter=c["iters"],
+                            tol=0.0)["X"]
+        cmp["batched_sampled_rse_vs_oracle"] = float(np.linalg.norm(c["got"] - ref) / np.linalg.norm(ref))
+    if "compression" in cases:
+        c = cases["compression"]
+        t0 = time.perf_counter()
+        otensor.tsvd(c["x"])
+        t_tsvd = time.perf_counter() - t0
+        ref = ocompress.method1(c["x"], c["k2"])
+        cmp["compression"] = {"method1_k2": c["k2"],
+                              "method1_rel_err_vs_oracle": float(np.linalg.norm(c["got"] - ref) / np.linalg.norm(ref)),
+                              "oracle_tsvd_ms": t_tsvd * 1e3}
 
     try:
         from threadpoolctl import threadpool_info
@@ -206,9 +276,10 @@ def cpu_baseline(w, seconds: float):
     t0 = time.perf_counter()
     admm.complete(m_obs, w["mask"], w["rho"], w["growth"], w["rho_max"], max_iter=iters, tol=0.0)
     dt = time.perf_counter() - t0
-    return dict(value=iters / dt, unit="iters/s", cores=threads, kind="oracle",
+    base = dict(value=iters / dt, unit="iters/s", cores=threads, kind="oracle",
                 sample=f"first {iters} ADMM iterations of the same 128x160x64 completion "
                        f"({dt:.1f} s, NumPy FP64, BLAS threads={threads})")
+    return base, cmp
 
 
 def main() -> int:
@@ -224,6 +295,7 @@ def main() -> int:
     ap.add_argument("--batch-iters", type=int, default=150, help="iterations per batched problem")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-compress", action="store_true")
     ap.add_argument("--serve-rate", type=float, default=50.0)
     ap.add_argument("--serve-window", type=float, default=2.0,
                     help="seconds of arrivals replayed (the full trace is 60 s)")
@@ -262,7 +334,7 @@ def main() -> int:
     if args.only_legs:
         res = {}
         if not args.no_batch:
-            res["batched"] = batched_leg(lib, torch, np, workloads, args.batch_iters)
+            res["batched"], _ = batched_leg(lib, torch, np, workloads, args.batch_iters)
             print(json.dumps({"batched": res["batched"]}), flush=True)
         if not args.no_serve:
             res["serving"] = serving_leg(lib, torch, np, workloads, args.serve_rate, args.serve_window,
@@ -338,22 +410,17 @@ def main() -> int:
         result["roofline"] = roofline(stats, args.steps, fp32=True)
         result["kernels_ms_per_step"] = {k: v["total_ms"] / args.steps for k, v in stats.items()}
 
-    # parity on a short prefix of the same solve (oracle vs GPU, FP64)
-    from oracle import admm
-
+    # a short prefix of the same solve, compared with the oracle by the CPU leg
     n_par = 3
-    ref = admm.complete(np.asarray(w["M_obs"], dtype=np.float64), w["mask"], w["rho"],
-                        w["growth"], w["rho_max"], max_iter=n_par, tol=0.0)
-    den = np.linalg.norm(ref["X"])
     xp64, _ = lib.tsvd_complete(obs64, mask, max_iter=n_par, **kw)
     xp32, _ = lib.tsvd_complete(obs32, mask, max_iter=n_par, **kw, **fp32)
-    result["parity"] = {"iters": n_par,
-                        "fp64_rel_err_vs_oracle": float(np.linalg.norm(xp64.cpu().numpy() - ref["X"]) / den),
-                        "fp32_rel_err_vs_oracle": float(np.linalg.norm(
-                            xp32.cpu().numpy().astype(np.float64) - ref["X"]) / den)}
+    cases = {"video": {"iters": n_par, "got64": xp64.cpu().numpy(),
+                       "got32": xp32.cpu().numpy().astype(np.float64)}}
 
     if not args.no_batch:
-        result["batched"] = batched_leg(lib, torch, np, workloads, args.batch_iters)
+        result["batched"], cases["batched"] = batched_leg(lib, torch, np, workloads, args.batch_iters)
+    if not args.no_compress:
+        result["compression"], cases["compression"] = compression_leg(lib, torch, np, workloads)
     if not args.no_serve:
         result["serving"] = serving_leg(lib, torch, np, workloads, args.serve_rate, args.serve_window,
                                         args.serve_budget_gb)
@@ -362,7 +429,12 @@ def main() -> int:
             result["serving_sustained"] = serving_leg(lib, torch, np, workloads, args.serve_sustained_rate,
                                                       args.serve_sustained_window, args.serve_budget_gb)
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+        result["cpu_baseline"], cmp = cpu_baseline(w, args.cpu_seconds, cases)
+        result["parity"] = cmp.get("parity")
+        if "batched" in result:
+            result["batched"]["sampled_rse_vs_oracle"] = cmp.get("batched_sampled_rse_vs_oracle")
+        if "compression" in result:
+            result["compression"].update(cmp.get("compression", {}))
     print(json.dumps(result), flush=True)
     return 0
 
