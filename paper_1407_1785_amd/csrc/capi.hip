@@ -53,6 +53,7 @@ struct SvtBuffers {
     int* pbar;        // persistent Jacobi: h barrier counters, 3h flags, 1 error word, h x nb block flags
     double* partials;
     int nparts;
+    double* tall;     // tall slices: the Jacobi partial sums (jacobi_tall_plan)
 };
 
 // Warm-start state carried across the iterations of one solve.
@@ -75,6 +76,7 @@ size_t svt_bytes(const Geometry& g, int nparts) {
     b += (int64_t)g.h * 5 * sizeof(int) + 768;
     b += (int64_t)(4 * g.h + 1 + (int64_t)g.h * (g.n + 2)) * sizeof(int) + 256;
     b += (int64_t)nparts * kNumPartials * sizeof(double) + 256;
+    if (jacobi_tall(g.m, g.n, sizeof(T))) b += jacobi_tall_plan(g.m, g.n, g.h).part_doubles * sizeof(double) + 256;
     return b;
 }
 
@@ -96,6 +98,8 @@ SvtBuffers<T> carve_svt(Carver& c, const Geometry& g, int nparts) {
     s.pbar = c.take<int>(4 * g.h + 1 + (int64_t)g.h * (g.n + 2));
     s.partials = c.take<double>((int64_t)nparts * kNumPartials);
     s.nparts = nparts;
+    s.tall = jacobi_tall(g.m, g.n, sizeof(T)) ? c.take<double>(jacobi_tall_plan(g.m, g.n, g.h).part_doubles)
+                                              : nullptr;
     return s;
 }
 
@@ -367,6 +371,35 @@ SweepStats run_svt(tsvd_handle h, const Geometry& g, const SvtBuffers<T>& sb, in
                 h->pending.erase(h->pending.begin() + ip);
             }
         }
+    }
+    if (!done_persist && sb.tall) {
+        // tall slices: columns in global memory, two launches per round
+        const TallPlan tp = jacobi_tall_plan(g.m, g.n, g.h);
+        ja.nb = tp.players;
+        prof_launch(h, K_JAC_INIT, (double)g.h * g.n * g.n * sizeof(cplx<T>),
+                    [&] { launch_jacobi_init(ja, st); });
+        launch_check("jacobi_init");
+        ja.rotations = h->rot_counter + 1;
+        for (int sw = 0; sw < max_sweeps; ++sw) {
+            ja.sweep = sw;
+            for (int r = 0; r < tp.players - 1; ++r) {
+                ja.round = r;
+                prof_launch(h, K_JAC_CROSS, dot_flops * g.h * (tp.players / 2),
+                            [&] { launch_jacobi_tall_round(ja, tp, sb.tall, st); });
+                launch_check("jacobi_tall");
+            }
+            stats.sweeps = sw + 1;
+            if ((sw + 1) % check_every == 0 || sw + 1 == max_sweeps) {
+                hip_check(hipMemcpyAsync(h->host_ints, sb.rot + (sw % 3) * g.h, sizeof(int) * g.h,
+                                         hipMemcpyDeviceToHost, st),
+                          "hipMemcpyAsync rot");
+                hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+                int active = 0;
+                for (int s = 0; s < g.h; ++s) active += h->host_ints[s] != 0;
+                if (!active) break;
+            }
+        }
+        done_persist = true;
     }
     if (!done_persist) {
     ja.nb = jacobi_num_blocks(g.n, bw);

@@ -44,6 +44,7 @@ inline double env_double(const char* name, double dflt) {
 // Largest supported sizes (LDS staging of the DFT tiles and Jacobi blocks).
 constexpr int kMaxTube = 512;
 constexpr int kMaxSlices = 300;
+constexpr int64_t kMaxRows = 1 << 18;   // longer matrix mode of a slice (tall slices: global-memory Jacobi)
 
 struct Server;   // serving engine of a handle (engine.hip)
 
@@ -134,7 +135,7 @@ inline Geometry make_geometry(const tsvd_shape& s) {
     if (g.h > kMaxSlices) fail(TSVD_E_SHAPE, "too many Fourier slices");
     g.trans = g.n1 < g.n2;
     const int64_t m = std::max(g.n1, g.n2), n = std::min(g.n1, g.n2);
-    if (m > 4096) fail(TSVD_E_SHAPE, "matrix mode above the supported maximum");
+    if (m > kMaxRows) fail(TSVD_E_SHAPE, "matrix mode above the supported maximum");
     g.m = (int)m;
     g.n = (int)n;
     g.ntubes = g.n1 * g.n2;

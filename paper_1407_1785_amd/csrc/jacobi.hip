@@ -356,6 +356,94 @@ __global__ __launch_bounds__(64 * BW) void jacobi_cross_kernel(JacArgs<T> a) {
     if (threadIdx.x == 0 && any_rot) a.rot[(a.sweep % 3) * a.h + s] = 1;
 }
 
+// ---- tall slices
+// Slices whose stacked columns do not fit the LDS kernels (the unfoldings
+// of Sec. 3's vectorised baselines: n1 n2 rows) keep their columns in global
+// memory.  The rotations are the ones above and the pairs of a round are the
+// round-robin over single columns.  One round is two launches over
+// (column pairs x row chunks x slices):
+//   dots:   FP64 sums of ||a_p||^2, ||a_q||^2 and a_p^H a_q over the slice
+//           rows of one chunk of the stacked column;
+//   rotate: each workgroup adds its pair's chunk sums in chunk order (the
+//           same order in every workgroup, so all of them derive the same
+//           rotation) and applies the rotation to its chunk (slice rows and
+//           V rows).
+// part holds 4 doubles per (slice, pair, chunk).
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void jacobi_tall_dots_kernel(JacArgs<T> a, double* part, int chunks,
+                                                                 int rows_per) {
+    const int pair = blockIdx.x, c = blockIdx.y, s = blockIdx.z;
+    if (slice_done(a, s)) return;
+    const int p = rr_player(pair, a.round, a.nb), q = rr_player(a.nb - 1 - pair, a.round, a.nb);
+    if (p >= a.n || q >= a.n) return;
+    const cplx<T>* ap = a.A + ((int64_t)s * a.n + p) * a.m;
+    const cplx<T>* aq = a.A + ((int64_t)s * a.n + q) * a.m;
+    const int r0 = c * rows_per, r1 = min(r0 + rows_per, a.m);
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int r = r0 + (int)threadIdx.x; r < r1; r += blockDim.x) {
+        const cplx<T> x = ap[r], y = aq[r];
+        const double xr = x.re, xi = x.im, yr = y.re, yi = y.im;
+        v[0] += xr * xr + xi * xi;
+        v[1] += yr * yr + yi * yi;
+        v[2] += xr * yr + xi * yi;
+        v[3] += xr * yi - xi * yr;
+    }
+    __shared__ double red[4][kBlock / 64];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double t = v[k];
+        for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+        if ((threadIdx.x & 63) == 0) red[k][threadIdx.x >> 6] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        double t = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) t += red[threadIdx.x][w];
+        part[(((int64_t)s * (a.nb / 2) + pair) * chunks + c) * 4 + threadIdx.x] = t;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void jacobi_tall_rotate_kernel(JacArgs<T> a, const double* part, int chunks,
+                                                                   int rows_per) {
+    const int pair = blockIdx.x, c = blockIdx.y, s = blockIdx.z;
+    const bool lead = a.round == 0 && pair == 0 && c == 0 && threadIdx.x == 0;
+    // the ring entry of the next sweep is cleared for every slice, converged or not
+    if (lead) a.rot[((a.sweep + 1) % 3) * a.h + s] = 0;
+    if (slice_done(a, s)) return;
+    if (lead) a.sweeps[s] += 1;
+    const int p = rr_player(pair, a.round, a.nb), q = rr_player(a.nb - 1 - pair, a.round, a.nb);
+    if (p >= a.n || q >= a.n) return;
+    __shared__ double sum[4];
+    if (threadIdx.x < 4) {
+        const double* pp = part + ((int64_t)s * (a.nb / 2) + pair) * chunks * 4 + threadIdx.x;
+        double t = 0.0;
+        for (int k = 0; k < chunks; ++k) t += pp[(int64_t)k * 4];
+        sum[threadIdx.x] = t;
+    }
+    __syncthreads();
+    Rot rd;
+    if (!make_rotation(sum[0], sum[1], sum[2], sum[3], (double)a.tol, rd)) return;
+    if (c == 0 && threadIdx.x == 0) {
+        a.rot[(a.sweep % 3) * a.h + s] = 1;
+        if (a.rotations) atomicAdd(a.rotations, 1ull);
+    }
+    cplx<T>* ap = a.A + ((int64_t)s * a.n + p) * a.m;
+    cplx<T>* aq = a.A + ((int64_t)s * a.n + q) * a.m;
+    cplx<T>* vp = a.V + ((int64_t)s * a.n + p) * a.n;
+    cplx<T>* vq = a.V + ((int64_t)s * a.n + q) * a.n;
+    const int r0 = c * rows_per, r1 = min(r0 + rows_per, a.m + a.n);
+    for (int r = r0 + (int)threadIdx.x; r < r1; r += blockDim.x) {
+        cplx<T>* xp = r < a.m ? ap + r : vp + (r - a.m);
+        cplx<T>* xq = r < a.m ? aq + r : vq + (r - a.m);
+        cplx<T> x = *xp, y = *xq;
+        apply_rotation(rd, x, y);
+        *xp = x;
+        *xq = y;
+    }
+}
+
 // ------------------------------------------------------------------ host
 
 namespace {
@@ -397,7 +485,33 @@ int jacobi_block_width(int m, int n, int elem_bytes, int h) {
     return best;
 }
 
-bool jacobi_supported(int m, int n, int elem_bytes) { return jacobi_block_width(m, n, elem_bytes, 1) > 0; }
+bool jacobi_tall(int m, int n, int elem_bytes) {
+    return jacobi_block_width(m, n, elem_bytes, 1) < 0 && n >= 1 && n <= kMaxTallCols;
+}
+
+bool jacobi_supported(int m, int n, int elem_bytes) {
+    return jacobi_block_width(m, n, elem_bytes, 1) > 0 || jacobi_tall(m, n, elem_bytes);
+}
+
+TallPlan jacobi_tall_plan(int m, int n, int h) {
+    TallPlan t;
+    t.players = n + (n & 1);
+    const int pairs = t.players / 2;
+    const int rows = m + n;
+    // about a thousand workgroups per launch, chunks of at least 256 rows
+    const int64_t want = (1024 + (int64_t)pairs * h - 1) / ((int64_t)pairs * h);
+    t.chunks = (int)std::max<int64_t>(1, std::min<int64_t>(want, (rows + 255) / 256));
+    t.rows_per = (rows + t.chunks - 1) / t.chunks;
+    t.part_doubles = (int64_t)h * pairs * t.chunks * 4;
+    return t;
+}
+
+template <typename T>
+void launch_jacobi_tall_round(const JacArgs<T>& a, const TallPlan& t, double* part, hipStream_t st) {
+    const dim3 grid(t.players / 2, t.chunks, a.h);
+    hipLaunchKernelGGL((jacobi_tall_dots_kernel<T>), grid, dim3(kBlock), 0, st, a, part, t.chunks, t.rows_per);
+    hipLaunchKernelGGL((jacobi_tall_rotate_kernel<T>), grid, dim3(kBlock), 0, st, a, part, t.chunks, t.rows_per);
+}
 
 template <typename T>
 void launch_jacobi_init(const JacArgs<T>& a, hipStream_t st) {
@@ -464,10 +578,12 @@ void launch_jacobi_cross(const JacArgs<T>& a, int bw, hipStream_t st) {
 #undef TSVD_RPT_SWITCH
 
 template void launch_jacobi_init<double>(const JacArgs<double>&, hipStream_t);
+template void launch_jacobi_tall_round<double>(const JacArgs<double>&, const TallPlan&, double*, hipStream_t);
 template void launch_jacobi_self<double>(const JacArgs<double>&, int, hipStream_t);
 template void launch_jacobi_cross<double>(const JacArgs<double>&, int, hipStream_t);
 
 template void launch_jacobi_init<float>(const JacArgs<float>&, hipStream_t);
+template void launch_jacobi_tall_round<float>(const JacArgs<float>&, const TallPlan&, double*, hipStream_t);
 template void launch_jacobi_self<float>(const JacArgs<float>&, int, hipStream_t);
 template void launch_jacobi_cross<float>(const JacArgs<float>&, int, hipStream_t);
 

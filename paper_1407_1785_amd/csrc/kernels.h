@@ -227,6 +227,17 @@ void launch_jacobi_cross(const JacArgs<T>& a, int bw, hipStream_t st);
 int jacobi_block_width(int m, int n, int elem_bytes, int h);
 inline int jacobi_num_blocks(int n, int bw) { int nb = 2 * ((n + 2 * bw - 1) / (2 * bw)); return nb < 2 ? 2 : nb; }
 bool jacobi_supported(int m, int n, int elem_bytes);
+// Slices whose stacked columns fit no LDS kernel: columns in global memory,
+// one column pair per round-robin slot, rows split into chunks (jacobi.hip).
+constexpr int kMaxTallCols = 1024;
+bool jacobi_tall(int m, int n, int elem_bytes);
+struct TallPlan {
+    int players = 0, chunks = 0, rows_per = 0;
+    int64_t part_doubles = 0;   // partial sums: 4 per (slice, pair, chunk)
+};
+TallPlan jacobi_tall_plan(int m, int n, int h);
+template <typename T>
+void launch_jacobi_tall_round(const JacArgs<T>& a, const TallPlan& t, double* part, hipStream_t st);
 // LDS bytes one workgroup may use on the current device
 void jacobi_set_lds_limit(size_t bytes);
 
