@@ -168,6 +168,53 @@ def compression_leg(lib, torch, np, workloads):
     return out, {"x": x, "k2": k2, "got": got}
 
 
+def sweep_leg(lib, torch, np, workloads, iters: int):
+    """Sampling-rate sweep (the Sec. 6 completion experiment on synthetic
+    videos): RSE in dB of TNN completion (this solver on the tensor) and of
+    the vectorised matrix nuclear-norm baseline (the same solver with n3 = 1
+    on the n1 n2 x n3 unfolding, the frontal slices as columns), rates
+    10%..90%, 3-D video 128x160x64 and 4-D colour video 96x128x3x48, FP32
+    form, at most `iters` iterations with tol 1e-6.  Returns the figures and a
+    short FP64 prefix of the 3-D baseline at 50% for the CPU leg's oracle
+    comparison."""
+    sw = workloads.sampling_sweep(0)
+    kw = dict(rho=sw["rho"], growth=sw["growth"], rho_max=sw["rho_max"], tol=1e-6, max_iter=iters,
+              precision=lib.PREC_FP32)
+
+    def solve(x, mask, shape):
+        xs = torch.from_numpy(np.ascontiguousarray((x * mask).reshape(shape))).float().cuda()
+        ms = torch.from_numpy(np.ascontiguousarray(mask.reshape(shape))).cuda()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out, info = lib.tsvd_complete(xs, ms, **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        o = out.cpu().numpy().astype(np.float64).reshape(x.shape)
+        rse = np.linalg.norm(o - x) / np.linalg.norm(x)
+        return {"rse_db": float(20.0 * np.log10(rse)), "iters": int(info.iters), "seconds": dt}
+
+    rows = []
+    for p, (m3, m4) in sw["masks"].items():
+        v3, v4 = sw["video3"].astype(np.float64), sw["video4"].astype(np.float64)
+        rows.append({"rate": p,
+                     "video3_tnn": solve(v3, m3, v3.shape),
+                     "video3_matrix": solve(v3, m3, (128 * 160, 64, 1)),
+                     "video4_tnn": solve(v4, m4, v4.shape),
+                     "video4_matrix": solve(v4, m4, (96 * 128, 3 * 48, 1))})
+    print(f"[bench] sweep leg: {len(rows)} rates", file=sys.stderr, flush=True)
+    # FP64 prefix of the 3-D baseline at 50% for the oracle comparison
+    m3 = sw["masks"][0.5][0]
+    y = (sw["video3"].astype(np.float64) * m3).reshape(128 * 160, 64, 1)
+    mk = m3.reshape(128 * 160, 64, 1)
+    got, _ = lib.tsvd_complete(torch.from_numpy(y).cuda(), torch.from_numpy(mk).cuda(), rho=sw["rho"],
+                               growth=sw["growth"], rho_max=sw["rho_max"], tol=0.0, max_iter=5)
+    out = {"workload": "sampling sweep 10-90%: TNN vs vectorised matrix nuclear norm, synthetic 3-D and 4-D "
+                       "videos, FP32 form", "max_iter": iters, "rows": rows}
+    case = {"y": y, "mask": mk, "iters": 5, "rho": sw["rho"], "growth": sw["growth"], "rho_max": sw["rho_max"],
+            "got": got.cpu().numpy()}
+    return out, case
+
+
 def serving_leg(lib, torch, np, workloads, rate: float, window: float, budget_gb: float):
     """The serving mix: Poisson arrivals at `rate` per second during `window`
     seconds (70% completion / 30% tensor RPCA, 10% 4-D colour video, other
@@ -252,6 +299,11 @@ def cpu_baseline(w, seconds: float, cases: dict):
         ref = admm.complete(d["M_obs"], d["mask"], d["rho"], d["growth"], d["rho_max"], max_iter=c["iters"],
                             tol=0.0)["X"]
         cmp["batched_sampled_rse_vs_oracle"] = float(np.linalg.norm(c["got"] - ref) / np.linalg.norm(ref))
+    if "sweep" in cases:
+        c = cases["sweep"]
+        ref = admm.complete(c["y"], c["mask"], c["rho"], c["growth"], c["rho_max"], max_iter=c["iters"],
+                            tol=0.0)["X"]
+        cmp["sweep_matrix_baseline_rel_err_vs_oracle"] = float(np.linalg.norm(c["got"] - ref) / np.linalg.norm(ref))
     if "compression" in cases:
         c = cases["compression"]
         t0 = time.perf_counter()
@@ -296,6 +348,8 @@ def main() -> int:
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-compress", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--sweep-iters", type=int, default=150)
     ap.add_argument("--serve-rate", type=float, default=50.0)
     ap.add_argument("--serve-window", type=float, default=2.0,
                     help="seconds of arrivals replayed (the full trace is 60 s)")
@@ -421,6 +475,8 @@ def main() -> int:
         result["batched"], cases["batched"] = batched_leg(lib, torch, np, workloads, args.batch_iters)
     if not args.no_compress:
         result["compression"], cases["compression"] = compression_leg(lib, torch, np, workloads)
+    if not args.no_sweep:
+        result["sampling_sweep"], cases["sweep"] = sweep_leg(lib, torch, np, workloads, args.sweep_iters)
     if not args.no_serve:
         result["serving"] = serving_leg(lib, torch, np, workloads, args.serve_rate, args.serve_window,
                                         args.serve_budget_gb)
@@ -435,6 +491,9 @@ def main() -> int:
             result["batched"]["sampled_rse_vs_oracle"] = cmp.get("batched_sampled_rse_vs_oracle")
         if "compression" in result:
             result["compression"].update(cmp.get("compression", {}))
+        if "sampling_sweep" in result:
+            result["sampling_sweep"]["matrix_baseline_prefix_rel_err_vs_oracle"] = cmp.get(
+                "sweep_matrix_baseline_rel_err_vs_oracle")
     print(json.dumps(result), flush=True)
     return 0
 

@@ -17,6 +17,8 @@ Workloads (ids):
   2  tensor RPCA, 256x256x64 rank-5 plus 10% sparse U[-1,1] corruption
   3  batch of 64 uneven completion problems
   4  serving mix (Poisson arrivals, completion / RPCA / 4-D colour video)
+  5  tube-block corruption for the l1,1,2 RPCA (same pixels within blocks of frames)
+  6  sampling-rate sweep (3-D and 4-D synthetic videos, masks 10%..90%)
 """
 
 from __future__ import annotations
@@ -138,6 +140,18 @@ def color_video(rng, n1=96, n2=128, channels=3, frames=48):
     for c in range(channels):
         out[:, :, c, :] = video(rng, n1, n2, frames)
     return out
+
+
+def sampling_sweep(trial=0, rates=(0.1, 0.2, 0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9)):
+    """Sampling-rate sweep inputs (the Sec. 6 completion experiment, synthetic):
+    the grayscale video 128 x 160 x 64 and the colour video 96 x 128 x 3 x 48
+    (smoothed textures translated by (0.4, 0.7) px per frame), and for each
+    rate an exactly-sized uniform mask of each."""
+    g_v3, g_v4, g_mask = streams(6, trial, 3)
+    v3 = video(g_v3, 128, 160, 64)
+    v4 = color_video(g_v4)
+    masks = {p: (exact_mask(g_mask, v3.shape, p), exact_mask(g_mask, v4.shape, p)) for p in rates}
+    return dict(video3=v3, video4=v4, masks=masks, rho=1e-2, growth=1.1, rho_max=1e3)
 
 
 # ------------------------------------------------------------ workload 2
