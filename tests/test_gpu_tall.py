@@ -92,3 +92,23 @@ def test_tall_completion_of_an_unfolding():
         out, info = lib.tsvd_complete(to_gpu(torch, x * mask), to_gpu(torch, mask), tol=0.0, max_iter=iters, **kw)
         assert info.iters == iters
         assert rel_fro(out.cpu().numpy(), ref["X"]) <= TOL
+
+
+@pytest.mark.parametrize("shrink", ["l1", "l112"])
+def test_tall_rpca_of_an_unfolding(shrink):
+    """Matrix RPCA on an n1 n2 x n3 unfolding (the n3 = 1 case of the RPCA
+    solver, tall slice) against the oracle at fixed iteration counts."""
+    torch = torch_cuda()
+    rng = np.random.default_rng(5)
+    lo = rng.normal(size=(3200, 2)) @ rng.normal(size=(2, 24)) / 40.0
+    sp = np.where(rng.random(lo.shape) < 0.05, rng.uniform(-1, 1, size=lo.shape), 0.0)
+    x = (lo + sp)[:, :, None]
+    lam = 1.0 / np.sqrt(3200)
+    code = lib.SHRINK_L1 if shrink == "l1" else lib.SHRINK_L112
+    for iters in (1, 6):
+        ref = admm.trpca(x, lam, 1e-3, 1.2, 1e10, max_iter=iters, tol=0.0, shrink=shrink)
+        announce("tall rpca", shrink, iters)
+        lg, sg, info = lib.trpca(to_gpu(torch, x), lam, mu=1e-3, tol=0.0, shrink=code, max_iter=iters)
+        assert info.iters == iters
+        assert rel_fro(lg.cpu().numpy(), ref["L"]) <= TOL
+        assert rel_fro(sg.cpu().numpy(), ref["S"]) <= TOL

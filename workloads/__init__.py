@@ -19,6 +19,7 @@ Workloads (ids):
   4  serving mix (Poisson arrivals, completion / RPCA / 4-D colour video)
   5  tube-block corruption for the l1,1,2 RPCA (same pixels within blocks of frames)
   6  sampling-rate sweep (3-D and 4-D synthetic videos, masks 10%..90%)
+  7  tube-block video RPCA (Sec. 5 experiment shape 72x128x80, synthetic)
 """
 
 from __future__ import annotations
@@ -188,6 +189,28 @@ def tube_corruption(trial=0, shape=(36, 64, 40), rank=3, frac=0.05, block=10, am
         sp[pix, t0:t1] = g_sp.normal(0.0, amp, size=(int(pix.sum()), t1 - t0))
     lam = 1.0 / math.sqrt(max(n1, n2))
     return dict(L=lo, S=sp, M=lo + sp, lam=lam)
+
+
+def tube_block_video(trial=0, shape=(72, 128, 80), frac=0.02, block=10, amp=0.5):
+    """The Sec. 5 RPCA experiment, synthetic: a smoothed translated-texture
+    video (values in [0, 1]) as the low-rank part; in every block of `block`
+    frames a random fraction `frac` of the pixels gets i.i.d. N(0, amp^2)
+    noise on every frame of the block (the same pixels within a block).
+    lam_tensor = 1/sqrt(max(n1, n2)) (the paper's choice for tensor RPCA with
+    the tube shrink), lam_matrix = 1/sqrt(max(n1 n2, n3)) for matrix RPCA on
+    the n1 n2 x n3 unfolding; mu0 = 1e-3 grown by 1.2 up to 1e10, tol 1e-7,
+    at most 500 iterations."""
+    n1, n2, n3 = shape
+    g_v, g_sp = streams(7, trial, 2)
+    lo = video(g_v, n1, n2, n3).astype(np.float64)
+    sp = np.zeros(shape)
+    for t0 in range(0, n3, block):
+        pix = g_sp.random((n1, n2)) < frac
+        t1 = min(n3, t0 + block)
+        sp[pix, t0:t1] = g_sp.normal(0.0, amp, size=(int(pix.sum()), t1 - t0))
+    return dict(L=lo, S=sp, M=lo + sp, lam_tensor=1.0 / math.sqrt(max(n1, n2)),
+                lam_matrix=1.0 / math.sqrt(max(n1 * n2, n3)), mu=1e-3, growth=1.2, mu_max=1e10,
+                tol=1e-7, max_iter=500)
 
 
 # ------------------------------------------------------------ workload 3
