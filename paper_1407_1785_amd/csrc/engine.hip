@@ -194,6 +194,7 @@ public:
         for (int q = 0; q < 2; ++q)
             if (tab_[q].dev) (void)hipFree(tab_[q].dev), tab_[q].dev = nullptr;
         if (host_ctrl_) (void)hipHostFree(host_ctrl_), host_ctrl_ = nullptr;
+        if (flags_) (void)hipHostFree(flags_), flags_ = nullptr, flags_dev_ = nullptr;
         for (int k = 0; k < kLanes; ++k) {
             if (side_[k]) (void)hipStreamDestroy(side_[k]), side_[k] = nullptr;
             if (ev_join_[k]) (void)hipEventDestroy(ev_join_[k]), ev_join_[k] = nullptr;
@@ -211,6 +212,13 @@ public:
             hip_check(hipEventCreateWithFlags(&ev_join_[k], hipEventDisableTiming), "hipEventCreate");
         }
         hip_check(hipEventCreateWithFlags(&ev_fork_, hipEventDisableTiming), "hipEventCreate");
+        // round mode: one "still rotating" flag per Jacobi class, written by
+        // the device into mapped host memory and read after a stream sync
+        hip_check(hipHostMalloc(reinterpret_cast<void**>(&flags_), sizeof(int) * kMaxClasses,
+                                hipHostMallocMapped | hipHostMallocCoherent),
+                  "hipHostMalloc flags");
+        hip_check(hipHostGetDevicePointer(reinterpret_cast<void**>(&flags_dev_), flags_, 0),
+                  "hipHostGetDevicePointer");
     }
 
     hipStream_t stream() const { return stream_; }
@@ -485,6 +493,10 @@ private:
         for (int q = 0; q < 2; ++q) build_tables(q);
         dirty_ = false;
         if (env_int("TSVD_GRAPH", 1) == 0) return;
+        // round-mode classes size their sweep count from device flags read
+        // by the host mid-iteration: eager launches for such a running set
+        for (const auto& ph : tab_[0].jac)
+            if (ph.round) return;
         hipGraph_t graph = nullptr;
         hip_check(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
         bool ok = true;
@@ -725,6 +737,62 @@ private:
         return reinterpret_cast<const int*>(tb.dev + ph.ws_off);
     }
 
+    // One sweep of a round-mode class: nb - 1 launches, one per round;
+    // converged slices return at once.
+    void round_sweep(const Tables<T>& tb, const typename Tables<T>::Phase& ph, int sw) {
+        for (int rd = 0; rd < ph.nb_max - 1; ++rd)
+            hip_check(launch_jacobi_round<T>(ph.bw, ph.rpt, targs<JacSliceArgs<T>>(tb, ph), tws(tb, ph), ph.nprob,
+                                             ph.nwg, sw, rd, side_[ph.lane]),
+                      "batched jacobi round");
+    }
+
+    // Round-mode classes: launch an estimated number of sweeps per class,
+    // then one sweep at a time while some slice of the class still rotated
+    // in its last sweep (a device flag in mapped host memory, read after a
+    // sync of the side streams) and is below its cap.  The estimate follows
+    // the sweeps the class needed in the previous iteration.
+    void round_sweeps(const Tables<T>& tb) {
+        struct Run {
+            const typename Tables<T>::Phase* ph;
+            int sw, k, slot;
+            int* est;
+        };
+        std::vector<Run> runs;
+        for (const auto& ph : tb.jac) {
+            if (!ph.round) continue;
+            if ((int)runs.size() >= kMaxClasses) fail(TSVD_E_UNSUPPORTED, "too many Jacobi classes");
+            int& est = sweep_est_[{ph.bw, ph.rpt}];
+            if (est <= 0) est = kSweepEstimate0;
+            runs.push_back(Run{&ph, 0, std::min(est, ph.sweeps_max), (int)runs.size(), &est});
+        }
+        if (runs.empty()) return;
+        for (Run& r : runs) {
+            for (; r.sw < r.k; ++r.sw) round_sweep(tb, *r.ph, r.sw);
+            launch_jacobi_round_active<T>(targs<JacSliceArgs<T>>(tb, *r.ph), r.ph->nprob, r.sw - 1,
+                                          flags_dev_ + r.slot, side_[r.ph->lane]);
+        }
+        launch_check("batched jacobi rounds");
+        for (;;) {
+            bool lanes[kLanes] = {};
+            for (const Run& r : runs) lanes[r.ph->lane] = true;
+            for (int k = 0; k < kLanes; ++k)
+                if (lanes[k]) hip_check(hipStreamSynchronize(side_[k]), "hipStreamSynchronize");
+            bool more = false;
+            for (Run& r : runs) {
+                const bool active = reinterpret_cast<volatile int*>(flags_)[r.slot] != 0 && r.sw < r.ph->sweeps_max;
+                if (!active) continue;
+                round_sweep(tb, *r.ph, r.sw);
+                launch_jacobi_round_active<T>(targs<JacSliceArgs<T>>(tb, *r.ph), r.ph->nprob, r.sw,
+                                              flags_dev_ + r.slot, side_[r.ph->lane]);
+                ++r.sw;
+                more = true;
+            }
+            if (!more) break;
+            launch_check("batched jacobi rounds");
+        }
+        for (Run& r : runs) *r.est = r.sw > r.k ? r.sw : std::max(kSweepEstimateMin, r.k - 1);
+    }
+
     void iteration(int par) {
         const Tables<T>& tb = tab_[par];
         hipStream_t st = stream_;
@@ -748,13 +816,8 @@ private:
                           "batched jacobi");
                 continue;
             }
-            // every sweep the cap allows, every round; converged slices return at once
-            for (int sw = 0; sw < ph.sweeps_max; ++sw)
-                for (int rd = 0; rd < ph.nb_max - 1; ++rd)
-                    hip_check(launch_jacobi_round<T>(ph.bw, ph.rpt, targs<JacSliceArgs<T>>(tb, ph), tws(tb, ph),
-                                                     ph.nprob, ph.nwg, sw, rd, side_[ph.lane]),
-                              "batched jacobi round");
         }
+        round_sweeps(tb);
         for (int k = 0; k < kLanes; ++k)
             if (used[k]) {
                 hip_check(hipEventRecord(ev_join_[k], side_[k]), "hipEventRecord");
@@ -782,6 +845,12 @@ private:
     hipGraphExec_t graph_exec_ = nullptr;
     Ctrl* host_ctrl_ = nullptr;
     size_t host_ctrl_len_ = 0;
+    static constexpr int kMaxClasses = 64;       // round-mode flags
+    static constexpr int kSweepEstimate0 = 8;    // first sweep estimate of a class
+    static constexpr int kSweepEstimateMin = 2;
+    int* flags_ = nullptr;                        // mapped host memory
+    int* flags_dev_ = nullptr;                    // its device address
+    std::map<std::pair<int, int>, int> sweep_est_;   // (bw, rpt) -> sweeps
     int64_t iterations_ = 0;
 };
 

@@ -309,6 +309,34 @@ hipError_t launch_jacobi_round(int bw, int rpt, const JacSliceArgs<T>* tab, cons
     return dispatch<T>(false, 1, bw, rpt, tab, wg_start, nprob, nwg, sweep, round, st);
 }
 
+// Round mode: *flag = 1 when a slice of a running problem of the table
+// rotated in sweep `sweep` and may run another sweep (below its cap), else 0.
+// One workgroup; the flag is written once, after the scan.
+template <typename T>
+__global__ __launch_bounds__(256) void jacobi_round_active_kernel(const JacSliceArgs<T>* tab, int nprob, int sweep,
+                                                                 int* flag) {
+    __shared__ int any;
+    if (threadIdx.x == 0) any = 0;
+    __syncthreads();
+    for (int p = 0; p < nprob; ++p) {
+        const JacSliceArgs<T>& a = tab[p];
+        if (a.ctrl && a.ctrl->done) continue;
+        if (sweep + 1 >= (a.max_sweeps > 0 ? a.max_sweeps : 30)) continue;
+        for (int s = threadIdx.x; s < a.h; s += blockDim.x)
+            if (a.rot[(sweep % 3) * a.h + s]) atomicOr(&any, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) *flag = any;
+}
+
+template <typename T>
+void launch_jacobi_round_active(const JacSliceArgs<T>* tab, int nprob, int sweep, int* flag, hipStream_t st) {
+    hipLaunchKernelGGL((jacobi_round_active_kernel<T>), dim3(1), dim3(256), 0, st, tab, nprob, sweep, flag);
+}
+
+template void launch_jacobi_round_active<double>(const JacSliceArgs<double>*, int, int, int*, hipStream_t);
+template void launch_jacobi_round_active<float>(const JacSliceArgs<float>*, int, int, int*, hipStream_t);
+
 template hipError_t launch_jacobi_round<double>(int, int, const JacSliceArgs<double>*, const int*, int, int, int,
                                                 int, hipStream_t);
 template hipError_t launch_jacobi_round<float>(int, int, const JacSliceArgs<float>*, const int*, int, int, int, int,

@@ -172,6 +172,10 @@ int jacobi_slice_max_rpt();
 template <typename T>
 hipError_t launch_jacobi_round(int bw, int rpt, const JacSliceArgs<T>* tab, const int* wg_start, int nprob,
                                int nwg, int sweep, int round, hipStream_t st);
+// Round mode: *flag (e.g. mapped host memory) = 1 when some running slice of
+// the table rotated in `sweep` and is below its sweep cap.
+template <typename T>
+void launch_jacobi_round_active(const JacSliceArgs<T>* tab, int nprob, int sweep, int* flag, hipStream_t st);
 // Sets the kernel's LDS limit; call once per (bw, rpt) before launches
 // (and before any stream capture).
 template <typename T>
