@@ -34,9 +34,9 @@
 // three dot products are reduced across the wavefront with DPP row
 // operations and readlane, so the rotation parameters are wave-uniform.
 //
-// Convergence is tracked per slice: sweep k sets rot[k % 3][s] when any
-// pair of slice s was rotated; a slice whose previous sweep rotated nothing
-// is skipped.  Sweep k also clears ring entry (k+1) % 3 of every slice,
+// Convergence is tracked per slice: sweep k sets rot[k % 3][s] when a
+// rotation of slice s forces another sweep (rot_forces_sweep); a slice whose
+// previous sweep set nothing is skipped.  Sweep k also clears ring entry (k+1) % 3 of every slice,
 // skipped or not, which nobody reads or writes during sweep k.
 //
 // Work model (floating-point operations): a visited pair costs 16 m for the
@@ -100,6 +100,7 @@ __device__ __forceinline__ double rcp_close(double x) {
 
 struct Rot {
     double c, s, er, ei;
+    bool big;   // the rotation forces another sweep
 };
 
 // False when the pair is already orthogonal to tolerance (or a column is 0).
@@ -107,6 +108,7 @@ __device__ __forceinline__ bool make_rotation(double al, double be, double gr, d
                                               Rot& r) {
     const double g2 = gr * gr + gi * gi;
     if (!(g2 > (tol * tol) * al * be) || !(g2 > 0.0)) return false;
+    r.big = rot_forces_sweep(al, be, g2, tol);
     const double rg = rsqrt_acc(g2);
     const double zeta = (be - al) * 0.5 * rg;
     const double az = fabs(zeta);
@@ -191,9 +193,9 @@ __device__ __forceinline__ bool slice_done(const JacArgs<T>& a, int s) {
 }
 
 // One pair step for a wavefront: x (registers) against column y in LDS.
-// Returns true when a rotation was applied.
+// Returns 0 (not rotated), 1 (rotated) or 2 (rotated, forcing another sweep).
 template <typename T, int RPT>
-__device__ __forceinline__ bool pair_step(cplx<T> (&x)[RPT], cplx<T>* y_lds, int rows, int m, int lane,
+__device__ __forceinline__ unsigned pair_step(cplx<T> (&x)[RPT], cplx<T>* y_lds, int rows, int m, int lane,
                                           double tol) {
     cplx<T> y[RPT];
     T al = 0, be = 0, gr = 0, gi = 0;
@@ -206,14 +208,14 @@ __device__ __forceinline__ bool pair_step(cplx<T> (&x)[RPT], cplx<T>* y_lds, int
     const double sal = wave_sum((double)al), sbe = wave_sum((double)be);
     const double sgr = wave_sum((double)gr), sgi = wave_sum((double)gi);
     Rot rt;
-    if (!make_rotation(sal, sbe, sgr, sgi, tol, rt)) return false;
+    if (!make_rotation(sal, sbe, sgr, sgi, tol, rt)) return 0u;
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
         const int r = lane + 64 * k;
         apply_rotation(rt, x[k], y[k]);
         if (r < rows) y_lds[r] = y[k];
     }
-    return true;
+    return rt.big ? 2u : 1u;
 }
 
 }  // namespace
@@ -264,7 +266,7 @@ __global__ __launch_bounds__(32 * BW) void jacobi_self_kernel(JacArgs<T> a) {
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int wp = w + (w & 1);
-    unsigned nrot = 0;
+    unsigned nrot = 0, nbig = 0;
     for (int st = 0; st < wp - 1; ++st) {
         if (wave < wp / 2) {
             const int p = rr_player(wave, st, wp);
@@ -277,8 +279,9 @@ __global__ __launch_bounds__(32 * BW) void jacobi_self_kernel(JacArgs<T> a) {
                     const int r = lane + 64 * k;
                     x[k] = r < rows ? cp[r] : cplx<T>{(T)0, (T)0};
                 }
-                if (pair_step<T, RPT>(x, lds + q * rows, rows, a.m, lane, (double)a.tol)) {
+                if (const unsigned code = pair_step<T, RPT>(x, lds + q * rows, rows, a.m, lane, (double)a.tol)) {
                     ++nrot;
+                    nbig += code >> 1;
 #pragma unroll
                     for (int k = 0; k < RPT; ++k) {
                         const int r = lane + 64 * k;
@@ -289,9 +292,9 @@ __global__ __launch_bounds__(32 * BW) void jacobi_self_kernel(JacArgs<T> a) {
         }
         __syncthreads();
     }
-    if (nrot && lane == 0) {
-        any_rot = 1;
-        atomicAdd(a.rotations, (unsigned long long)nrot);
+    if (lane == 0) {
+        if (nbig) any_rot = 1;
+        if (nrot) atomicAdd(a.rotations, (unsigned long long)nrot);
     }
     __syncthreads();
     if (threadIdx.x == 0 && any_rot) a.rot[(a.sweep % 3) * a.h + s] = 1;
@@ -329,15 +332,19 @@ __global__ __launch_bounds__(64 * BW) void jacobi_cross_kernel(JacArgs<T> a) {
     block_to_lds(a, s, cj0, wj, rows, lds);
     __syncthreads();
 
-    unsigned nrot = 0;
+    unsigned nrot = 0, nbig = 0;
     for (int st = 0; st < BW; ++st) {
         const int jc = (g + st) % BW;
-        if (g < wi && jc < wj) nrot += pair_step<T, RPT>(xi, lds + jc * rows, rows, a.m, lane, (double)a.tol);
+        if (g < wi && jc < wj) {
+            const unsigned code = pair_step<T, RPT>(xi, lds + jc * rows, rows, a.m, lane, (double)a.tol);
+            nrot += code != 0;
+            nbig += code >> 1;
+        }
         __syncthreads();
     }
-    if (nrot && lane == 0) {
-        any_rot = 1;
-        atomicAdd(a.rotations, (unsigned long long)nrot);
+    if (lane == 0) {
+        if (nbig) any_rot = 1;
+        if (nrot) atomicAdd(a.rotations, (unsigned long long)nrot);
     }
     if (g < wi) {
         cplx<T>* colA = a.A + ((int64_t)s * a.n + ci0 + g) * a.m;
@@ -426,7 +433,7 @@ __global__ __launch_bounds__(kBlock) void jacobi_tall_rotate_kernel(JacArgs<T> a
     Rot rd;
     if (!make_rotation(sum[0], sum[1], sum[2], sum[3], (double)a.tol, rd)) return;
     if (c == 0 && threadIdx.x == 0) {
-        a.rot[(a.sweep % 3) * a.h + s] = 1;
+        if (rd.big) a.rot[(a.sweep % 3) * a.h + s] = 1;
         if (a.rotations) atomicAdd(a.rotations, 1ull);
     }
     cplx<T>* ap = a.A + ((int64_t)s * a.n + p) * a.m;

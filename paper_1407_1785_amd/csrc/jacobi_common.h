@@ -209,10 +209,11 @@ __device__ __forceinline__ double pnorm2(const cplx<T> (&x)[RPT], int ka) {
 // EXACT: al and be are computed here from the slice rows (their sums
 // reduced together with the inner product); otherwise they are the tracked
 // squared norms.  On a rotation the norms are updated in place
-// (al -= t|gamma|, be += t|gamma|).
+// (al -= t|gamma|, be += t|gamma|).  Returns 0 (not rotated), 1 (rotated)
+// or 2 (rotated, and the rotation forces another sweep: rot_forces_sweep).
 template <typename T, int PG, int RPT, bool EXACT = false>
-__device__ __forceinline__ bool ppair(cplx<T> (&x)[RPT], cplx<T>* y_lds, double& al, double& be, int ka,
-                                      int l, double tol, const cplx<T>* x_lds = nullptr) {
+__device__ __forceinline__ unsigned ppair(cplx<T> (&x)[RPT], cplx<T>* y_lds, double& al, double& be, int ka,
+                                          int l, double tol, const cplx<T>* x_lds = nullptr) {
     cplx<T> y[RPT];
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
@@ -229,8 +230,10 @@ __device__ __forceinline__ bool ppair(cplx<T> (&x)[RPT], cplx<T>* y_lds, double&
         be = (double)nb;
     }
     group_sum2<PG>(gr, gi);
-    const PRot rt = prot<T>(al, be, (double)gr, (double)gi, tol);
-    if (!rt.on) return false;
+    const double dgr = (double)gr, dgi = (double)gi;
+    const PRot rt = prot<T>(al, be, dgr, dgi, tol);
+    if (!rt.on) return 0u;
+    const unsigned code = rot_forces_sweep(al, be, dgr * dgr + dgi * dgi, tol) ? 2u : 1u;
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
         prot_apply(rt, x[k], y[k]);
@@ -238,7 +241,7 @@ __device__ __forceinline__ bool ppair(cplx<T> (&x)[RPT], cplx<T>* y_lds, double&
     }
     al -= rt.tg;
     be += rt.tg;
-    return true;
+    return code;
 }
 
 // LDS column of a block: slice rows 0..m-1 at 0..m-1, V rows at mp..mp+n-1

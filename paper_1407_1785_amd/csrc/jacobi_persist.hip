@@ -32,9 +32,10 @@
 // (a spin limit sets an error flag and lets the kernel finish, so a launch
 // can never hang).
 //
-// Convergence: workgroups OR a per-slice flag when they rotated during the
-// sweep; after the sweep's last barrier all workgroups of the slice read the
-// same flag and stop together when it is clear.
+// Convergence: workgroups OR a per-slice flag when a rotation of the sweep
+// forces another sweep (rot_forces_sweep); after the sweep's last barrier all
+// workgroups of the slice read the same flag and stop together when it is
+// clear.
 
 #include "jacobi_common.h"
 
@@ -211,7 +212,7 @@ __global__ __launch_bounds__(PBW * PG) void jacobi_persistent_kernel(JacArgs<T> 
             swept = sweep + 1;
         }
         __syncthreads();
-        unsigned nrot = 0;
+        unsigned nrot = 0, nbig = 0;   // rotations of the sweep; those that force another sweep
         {
             // internal pairs of both resident blocks: groups 0-7 take block 0,
             // groups 8-15 block 1
@@ -230,8 +231,9 @@ __global__ __launch_bounds__(PBW * PG) void jacobi_persistent_kernel(JacArgs<T> 
                         cplx<T>* cq = base + qq * ldc;
                         cplx<T> x[RPT];
                         double al, be;
-                        if (ppair<T, PG, RPT, true>(x, cq, al, be, ka, l, tol, cp)) {
+                        if (const unsigned code = ppair<T, PG, RPT, true>(x, cq, al, be, ka, l, tol, cp)) {
                             ++nrot;
+                            nbig += code >> 1;
 #pragma unroll
                             for (int k = 0; k < RPT; ++k) cp[l + PG * k] = x[k];
                         }
@@ -265,8 +267,9 @@ __global__ __launch_bounds__(PBW * PG) void jacobi_persistent_kernel(JacArgs<T> 
                 const int jc = (g + st) & (PBW - 1);
                 if (g < wi && jc < wj) {
                     double be = jnorm[jc];
-                    if (ppair<T, PG, RPT>(xi, blk1 + jc * ldc, al, be, ka, l, tol)) {
+                    if (const unsigned code = ppair<T, PG, RPT>(xi, blk1 + jc * ldc, al, be, ka, l, tol)) {
                         ++nrot;
+                        nbig += code >> 1;
                         if (l == 0) jnorm[jc] = be;
                     }
                 }
@@ -278,10 +281,10 @@ __global__ __launch_bounds__(PBW * PG) void jacobi_persistent_kernel(JacArgs<T> 
 #pragma unroll
                 for (int k = 0; k < RPT; ++k) blk0[g * ldc + l + PG * k] = xi[k];
             }
-            // end of the sweep: publish whether this workgroup rotated
+            // end of the sweep: publish whether this workgroup needs another sweep
             const bool last = rd == a.nb - 2;
             if (last) {
-                if (nrot && l == 0) rot_any = 1;
+                if (nbig && l == 0) rot_any = 1;
                 __syncthreads();
                 if (threadIdx.x == 0 && rot_any)
                     __hip_atomic_fetch_or(p.rotflag + (sweep % 3) * a.h + s, 1, __ATOMIC_RELAXED,

@@ -43,10 +43,11 @@ constexpr int kPGs = 32;
 // blocks in LDS (blk0 at tournament position gp, blk1 at nb - 1 - gp):
 // optionally the internal pairs of both blocks (first round of a sweep),
 // then every cross pair.  Returns the rotations applied (per thread: every
-// lane of a pair group counts its group's rotations).
+// lane of a pair group counts its group's rotations) and adds those that
+// force another sweep to nbig.
 template <typename T, int BW, int RPT>
 __device__ __forceinline__ unsigned pair_round(cplx<T>* blk0, cplx<T>* blk1, int wi, int wj, bool self_phase,
-                                               int ka, int ldc, double tol, double* jnorm) {
+                                               int ka, int ldc, double tol, double* jnorm, unsigned& nbig) {
     constexpr int PG = kPGs;
     const int g = threadIdx.x / PG, l = threadIdx.x - g * PG;
     unsigned nrot = 0;
@@ -66,8 +67,9 @@ __device__ __forceinline__ unsigned pair_round(cplx<T>* blk0, cplx<T>* blk1, int
                     cplx<T>* cq = base + qq * ldc;
                     cplx<T> x[RPT];
                     double al, be;
-                    if (ppair<T, PG, RPT, true>(x, cq, al, be, ka, l, tol, cp)) {
+                    if (const unsigned code = ppair<T, PG, RPT, true>(x, cq, al, be, ka, l, tol, cp)) {
                         ++nrot;
+                        nbig += code >> 1;
 #pragma unroll
                         for (int k = 0; k < RPT; ++k) cp[l + PG * k] = x[k];
                     }
@@ -93,8 +95,9 @@ __device__ __forceinline__ unsigned pair_round(cplx<T>* blk0, cplx<T>* blk1, int
         const int jc = (g + st) & (BW - 1);
         if (g < wi && jc < wj) {
             double be = jnorm[jc];
-            if (ppair<T, PG, RPT>(xi, blk1 + jc * ldc, al, be, ka, l, tol)) {
+            if (const unsigned code = ppair<T, PG, RPT>(xi, blk1 + jc * ldc, al, be, ka, l, tol)) {
                 ++nrot;
+                nbig += code >> 1;
                 if (l == 0) jnorm[jc] = be;
             }
         }
@@ -141,7 +144,7 @@ __global__ __launch_bounds__(BW * kPGs) void jacobi_slice_kernel(const JacSliceA
     const int msw = a.max_sweeps > 0 ? a.max_sweeps : max_sweeps;
     for (int sweep = 0; sweep < msw; ++sweep) {
         if (threadIdx.x == 0) rot_any = 0;
-        unsigned nrot_sweep = 0;
+        unsigned nrot_sweep = 0, nbig_sweep = 0;
         for (int rd = 0; rd < nb - 1; ++rd) {
             for (int gp = 0; gp < G; ++gp) {
                 const int player0 = ppos_player(gp, rd, nb), player1 = ppos_player(nb - 1 - gp, rd, nb);
@@ -153,7 +156,7 @@ __global__ __launch_bounds__(BW * kPGs) void jacobi_slice_kernel(const JacSliceA
                 __syncthreads();
                 const int wi = pblk_start(player0 + 1, n, nb) - pblk_start(player0, n, nb);
                 const int wj = pblk_start(player1 + 1, n, nb) - pblk_start(player1, n, nb);
-                nrot_sweep += pair_round<T, BW, RPT>(blk0, blk1, wi, wj, rd == 0, ka, ldc, tol, jnorm);
+                nrot_sweep += pair_round<T, BW, RPT>(blk0, blk1, wi, wj, rd == 0, ka, ldc, tol, jnorm, nbig_sweep);
                 if (G > 1) {
                     __syncthreads();
                     store_block<T, NT, BW>(A, V, m, n, nb, player0, mp, ldc, blk0);
@@ -161,7 +164,7 @@ __global__ __launch_bounds__(BW * kPGs) void jacobi_slice_kernel(const JacSliceA
                 }
             }
         }
-        if (nrot_sweep && l == 0) rot_any = 1;
+        if (nbig_sweep && l == 0) rot_any = 1;
         __syncthreads();
         nrot += nrot_sweep;
         sweeps = sweep + 1;
@@ -182,8 +185,9 @@ __global__ __launch_bounds__(BW * kPGs) void jacobi_slice_kernel(const JacSliceA
 
 // Round mode: one launch per (sweep, round); workgroup b of problem p takes
 // slice (b - wg_start[p]) / G, block pair (b - wg_start[p]) % G.  A slice
-// whose previous sweep rotated nothing is skipped; sweep k records its
-// rotations in rot[(k % 3) h + s] and clears rot[((k + 1) % 3) h + s], the
+// whose previous sweep forced no further sweep (rot_forces_sweep) is
+// skipped; sweep k records such rotations in rot[(k % 3) h + s] and clears
+// rot[((k + 1) % 3) h + s], the
 // entry that nobody reads or writes during sweep k (ring 0 is cleared by the
 // control step before every SVD).
 template <typename T, int BW, int RPT>
@@ -220,8 +224,9 @@ __global__ __launch_bounds__(BW * kPGs) void jacobi_round_kernel(const JacSliceA
     __syncthreads();
     const int wi = pblk_start(player0 + 1, n, nb) - pblk_start(player0, n, nb);
     const int wj = pblk_start(player1 + 1, n, nb) - pblk_start(player1, n, nb);
-    const unsigned nrot = pair_round<T, BW, RPT>(blk0, blk1, wi, wj, rd == 0, ka, ldc, (double)a.tol, jnorm);
-    if (nrot && l == 0) rot_any = 1;
+    unsigned nbig = 0;
+    const unsigned nrot = pair_round<T, BW, RPT>(blk0, blk1, wi, wj, rd == 0, ka, ldc, (double)a.tol, jnorm, nbig);
+    if (nbig && l == 0) rot_any = 1;
     __syncthreads();
     store_block<T, NT, BW>(A, V, m, n, nb, player0, mp, ldc, blk0);
     store_block<T, NT, BW>(A, V, m, n, nb, player1, mp, ldc, blk1);

@@ -94,6 +94,20 @@ struct InvArgs {
     int epi;                 // epilogue (problem-table launches)
 };
 
+// Stopping rule of every Jacobi variant.  A pair (alpha = ||x||^2,
+// beta = ||y||^2, gamma = x^H y) is rotated when |gamma|^2 > tol^2 alpha beta.
+// A slice runs another sweep only if some rotation of the sweep had
+// |gamma|^2 > kSweepMargin tol alpha beta, i.e. a relative off-diagonal
+// above sqrt(kSweepMargin tol).  Cyclic Jacobi converges quadratically, so
+// after a sweep whose rotations were all below that, the next sweep finds
+// every pair below tol and rotates nothing: the rule saves that confirming
+// sweep.  (Smaller rotations of the sweep are still applied.)
+constexpr double kSweepMargin = 1e-2;
+
+__device__ __forceinline__ bool rot_forces_sweep(double al, double be, double g2, double tol) {
+    return g2 > (kSweepMargin * tol) * al * be;
+}
+
 template <typename T>
 struct JacArgs {
     cplx<T>* A;     // h slices m x n; overwritten by W = A V
