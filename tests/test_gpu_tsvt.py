@@ -67,6 +67,48 @@ def test_tsvt_low_rank_input_and_extreme_thresholds():
         assert ranks == list(r_ref)
 
 
+def clustered_tensor(rng, m, n, n3, sig):
+    """A real m x n x n3 tensor whose Fourier slices all have the singular
+    values sig: each half-spectrum slice is U diag(sig) V^H with random
+    unitary U, V (real orthogonal for the self-conjugate slices), and the
+    inverse real DFT gives the tensor."""
+    h = n3 // 2 + 1
+    xh = np.zeros((m, n, h), dtype=np.complex128)
+    for k in range(h):
+        real = k == 0 or 2 * k == n3
+        def unitary(d):
+            g = rng.normal(size=(d, d)) + (0 if real else 1j * rng.normal(size=(d, d)))
+            return np.linalg.qr(g)[0]
+        u, v = unitary(m)[:, :len(sig)], unitary(n)[:, :len(sig)]
+        xh[:, :, k] = (u * sig) @ np.conj(v).T
+    return np.fft.irfft(xh, n=n3, axis=2)
+
+
+def test_tsvt_clustered_singular_values():
+    """Tight clusters of singular values (relative gaps down to 1e-12) are
+    where Jacobi converges slowest: the sweeps must still stop only once the
+    shrinkage is exact to the FP64 bar (and to the FP32 bar in that form)."""
+    torch = torch_cuda()
+    rng = np.random.default_rng(17)
+    sig = np.array([8.0, 8.0 * (1 + 1e-9), 8.0 * (1 + 2e-9), 8.0 * (1 + 3e-9), 3.0, 3.0 * (1 + 1e-7),
+                    1.0, 1.0 + 1e-12, 0.5, 0.5, 0.5, 0.25 * (1 + 1e-6), 0.25])
+    x = clustered_tensor(rng, 40, 24, 8, sig)
+    xg = to_gpu(torch, x)
+    xg32 = to_gpu(torch, x, torch.float32)
+    for tau, gap in ((2.0, True), (0.75, True), (8.0, False), (0.1, True)):
+        z_ref, r_ref = tsvt_oracle(x, tau)
+        # tau = 8 sits inside the top cluster: Z is ~1e-8 of X and the kept
+        # count depends on rounding, so the error is measured against X
+        scale = np.linalg.norm(z_ref) if gap else np.linalg.norm(x)
+        announce("tsvt clustered", tau)
+        z, ranks = lib.tsvt(xg, tau)
+        assert np.linalg.norm(z.cpu().numpy() - z_ref) <= TOL * scale
+        if gap:
+            assert ranks == list(r_ref)
+        z32, _ = lib.tsvt(xg32, tau, precision=lib.PREC_FP32)
+        assert np.linalg.norm(z32.cpu().numpy().astype(np.float64) - z_ref) <= 1e-4 * scale
+
+
 def test_tsvt_video_shape_sampled():
     """Full video-shaped slice size (128 x 160 x 64): whole-tensor parity."""
     torch = torch_cuda()
