@@ -292,12 +292,7 @@ SweepStats run_svt(tsvd_handle h, const Geometry& g, const SvtBuffers<T>& sb, in
     ja.nb = jacobi_num_blocks(g.n, bw);
     ja.rot = sb.rot;
     ja.sweeps = sb.sweeps;
-    // FP64: sqrt(m) eps.  FP32 form: 16 sqrt(m) eps32 -- the ADMM recovers the
-    // same tensor (measured relative difference to the FP64 path ~6e-6 on the
-    // video-shaped workload) with fewer sweeps than at the rounding floor.
-    const double eps = sizeof(T) == 4 ? 16.0 * 1.1920928955078125e-07 : 2.220446049250313e-16;
-    ja.tol = (T)env_double(sizeof(T) == 4 ? "TSVD_JACOBI_TOL32" : "TSVD_JACOBI_TOL",
-                           std::sqrt((double)g.m) * eps);
+    ja.tol = (T)jacobi_tol(g.m, sizeof(T));
     ja.rotations = h->rot_counter;
     const int check_every = std::max(1, env_int("TSVD_CHECK_EVERY", 1));
     ensure_host_ints(h, g.h);

@@ -456,7 +456,7 @@ private:
                 ja.n = n;
                 ja.h = S;
                 ja.nb = jacobi_num_blocks(n, bw);
-                ja.tol = (T)(std::sqrt((double)m) * (sizeof(T) == 4 ? 16.0 * 1.1920928955078125e-07 : 2.220446049250313e-16));
+                ja.tol = (T)jacobi_tol(m, sizeof(T));
                 ja.max_sweeps = 1;
                 hip_check(hipMemcpyAsync(dtab, &ja, sizeof(ja), hipMemcpyHostToDevice, stream_), "hipMemcpyAsync");
                 hip_check(hipMemcpyAsync(A, A0, sizeof(cplx<T>) * S * mn, hipMemcpyDeviceToDevice, stream_),
@@ -621,8 +621,7 @@ private:
             ja.n = g.n;
             ja.h = g.h;
             ja.nb = sl.nb;
-            ja.tol = (T)(std::sqrt((double)g.m) *
-                         (sizeof(T) == 4 ? 16.0 * 1.1920928955078125e-07 : 2.220446049250313e-16));
+            ja.tol = (T)jacobi_tol(g.m, sizeof(T));
             ja.sweeps = sl.sweeps;
             ja.ctrl = sl.ctrl;
             ja.max_sweeps = sl.sp.s.max_sweeps;
