@@ -127,12 +127,14 @@ __device__ __forceinline__ void lds_publish(int* cnt, int value) {
     if ((threadIdx.x & 63) == 0) __hip_atomic_store(cnt, value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-constexpr int kLdsSpinLimit = 1 << 18;   // far beyond any step of a workgroup's own waves
+// Polls back to back (a sleep between polls cost 0.7% of the iteration);
+// 2^18 LDS polls are milliseconds, far beyond any step of a workgroup's own
+// waves.
+constexpr int kLdsSpinLimit = 1 << 18;
 
 __device__ __forceinline__ void lds_wait(const int* cnt, int value, int* err) {
     int spins = 0;
     while (__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < value) {
-        __builtin_amdgcn_s_sleep(1);
         ++spins;
         if (spins > kLdsSpinLimit) {
             __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
