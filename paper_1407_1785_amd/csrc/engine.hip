@@ -378,8 +378,11 @@ private:
         sl.rpt = jacobi_slice_rpt(g.m, g.n);
         sl.bw = pick_bw(g.m, g.n, sl.rpt);
         sl.nb = jacobi_num_blocks(g.n, sl.bw);
-        // many block pairs per slice: one workgroup per pair and a launch per round
-        sl.round = sl.nb / 2 >= env_int("TSVD_ROUND_MIN_PAIRS", 4);
+        // two or more block pairs per slice: one workgroup per pair and a
+        // launch per round (on the 64-problem mix: 5.45 solves/s at a
+        // threshold of 1-3 pairs, 5.33 at 4, 5.15 at 8, 3.0 with every slice
+        // on one workgroup)
+        sl.round = sl.nb / 2 >= env_int("TSVD_ROUND_MIN_PAIRS", 2);
     }
 
     void write_outputs(Slot<T>& sl, const Ctrl& c) {
