@@ -244,6 +244,21 @@ __device__ __forceinline__ unsigned ppair(cplx<T> (&x)[RPT], cplx<T>* y_lds, dou
     return code;
 }
 
+// Cross steps wave to wave: a wave finishes step st + 1 only after its
+// successor wave (cyclically) has finished step st, whose column it reads
+// next; each wave counts its finished steps in LDS (release after its LDS
+// writes, acquire before its reads).  Every wave of the workgroup runs every
+// step, so the waits end; the bound only guards against a fault.
+__device__ __forceinline__ void ring_publish(int* cnt, int value) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    if ((threadIdx.x & 63) == 0) __hip_atomic_store(cnt, value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ void ring_wait(const int* cnt, int value) {
+    for (int spins = 0; spins < (1 << 20); ++spins)
+        if (__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) >= value) return;
+}
+
 // LDS column of a block: slice rows 0..m-1 at 0..m-1, V rows at mp..mp+n-1
 // (mp = m rounded up to PG), zeros elsewhere.  The NT threads split into
 // BW column teams of NT / BW threads; a team copies one column, striding

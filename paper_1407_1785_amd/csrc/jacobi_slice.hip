@@ -78,7 +78,11 @@ __device__ __forceinline__ unsigned pair_round(cplx<T>* blk0, cplx<T>* blk1, int
             __syncthreads();
         }
     }
-    // cross pairs: column g of block 0 (registers) meets every column of block 1
+    // cross pairs: column g of block 0 (registers) meets every column of block 1;
+    // step st of a wave waits only for its successor's step st - 1
+    __shared__ int wsteps[BW * PG / 64];
+    const int wave = threadIdx.x >> 6, wave_next = (wave + 1) % (BW * PG / 64);
+    if ((threadIdx.x & 63) == 0) wsteps[wave] = 0;
     cplx<T> xi[RPT];
 #pragma unroll
     for (int k = 0; k < RPT; ++k) xi[k] = blk0[g * ldc + l + PG * k];
@@ -92,6 +96,7 @@ __device__ __forceinline__ unsigned pair_round(cplx<T>* blk0, cplx<T>* blk1, int
     }
     __syncthreads();
     for (int st = 0; st < BW; ++st) {
+        if (st > 0) ring_wait(wsteps + wave_next, st);
         const int jc = (g + st) & (BW - 1);
         if (g < wi && jc < wj) {
             double be = jnorm[jc];
@@ -101,7 +106,7 @@ __device__ __forceinline__ unsigned pair_round(cplx<T>* blk0, cplx<T>* blk1, int
                 if (l == 0) jnorm[jc] = be;
             }
         }
-        __syncthreads();
+        ring_publish(wsteps + wave, st + 1);
     }
     if (g < wi) {
 #pragma unroll
