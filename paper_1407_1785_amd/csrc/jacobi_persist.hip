@@ -155,7 +155,8 @@ __global__ __launch_bounds__(PBW * PG) void jacobi_persistent_kernel(JacArgs<T> 
     __shared__ int stop;
     __shared__ int ok_flag;
     __shared__ double jnorm[PBW];
-    __shared__ int wsteps[NT / 64];   // cross steps finished per wave, over the whole launch
+    __shared__ double inorm[2 * PBW];   // internal phase: tracked norms of both blocks' columns
+    __shared__ int wsteps[NT / 64];   // pair steps finished per wave, over the whole launch
     if (a.ctrl && a.ctrl->done) return;
     const int G = a.nb / 2;
     int s, wg;
@@ -216,30 +217,56 @@ __global__ __launch_bounds__(PBW * PG) void jacobi_persistent_kernel(JacArgs<T> 
         __syncthreads();
         unsigned nrot = 0, nbig = 0;   // rotations of the sweep; those that force another sweep
         {
-            // internal pairs of both resident blocks: groups 0-7 take block 0,
-            // groups 8-15 block 1
+            // Internal pairs of both resident blocks (groups 0-7 take block 0,
+            // groups 8-15 block 1) by halving: the 8 x 8 cross pairs of the
+            // block's two halves, then the 4 x 4 cross pairs within each half,
+            // then 2 x 2, then the 8 adjacent pairs -- 15 steps, every pair once.
+            // Each level runs like a cross round: a group keeps its column of
+            // the first half of its subproblem in registers and meets the k
+            // columns of the second half, norms exact at the level's start and
+            // tracked through it, and a wave waits only for the wave whose
+            // previous step wrote the column it takes next.
             const bool second = g >= PBW / 2;
             const int gi = second ? g - PBW / 2 : g;
             const int pl = second ? player1 : player0;
             cplx<T>* const base = second ? blk1 : blk0;
+            double* const jn = inorm + (second ? PBW : 0);
             const int w = pblk_start(pl + 1, a.n, a.nb) - pblk_start(pl, a.n, a.nb);
-            const int wp = w + (w & 1);
-            for (int st = 0; st < PBW - 1; ++st) {
-                if (st < wp - 1 && gi < wp / 2) {
-                    const int pp = ppos_player(gi, st, wp);
-                    const int qq = ppos_player(wp - 1 - gi, st, wp);
-                    if (pp < w && qq < w) {
-                        cplx<T>* cp = base + pp * ldc;
-                        cplx<T>* cq = base + qq * ldc;
-                        cplx<T> x[RPT];
-                        double al, be;
-                        if (const unsigned code = ppair<T, PG, RPT, true>(x, cq, al, be, ka, l, tol, cp)) {
+            const int wl = wave & 3, wbase = wave & ~3;   // waves 0-3 hold block 0, 4-7 block 1
+            for (int k = PBW / 2; k >= 1; k /= 2) {
+                const int sp = gi / k, q = gi - sp * k;
+                const int xcol = 2 * k * sp + q, ybase = 2 * k * sp + k;
+                // the wave holding group (q + 1) mod k of this subproblem
+                const int wnext = k == 8 ? wbase + ((wl + 1) & 3) : (k == 4 ? wave ^ 1 : wave);
+                cplx<T> xr[RPT];
+#pragma unroll
+                for (int r = 0; r < RPT; ++r) xr[r] = base[xcol * ldc + l + PG * r];
+                double al = pnorm2<T, PG, RPT>(xr, ka);
+                {
+                    cplx<T> yr[RPT];
+#pragma unroll
+                    for (int r = 0; r < RPT; ++r) yr[r] = base[(ybase + q) * ldc + l + PG * r];
+                    const double bq = pnorm2<T, PG, RPT>(yr, ka);
+                    if (l == 0) jn[ybase + q] = bq;
+                }
+                __syncthreads();
+                for (int st = 0; st < k; ++st) {
+                    if (st > 0) lds_wait(wsteps + wnext, steps + st, p.err);
+                    const int ycol = ybase + ((q + st) & (k - 1));
+                    if (xcol < w && ycol < w) {
+                        double be = jn[ycol];
+                        if (const unsigned code = ppair<T, PG, RPT>(xr, base + ycol * ldc, al, be, ka, l, tol)) {
                             ++nrot;
                             nbig += code >> 1;
-#pragma unroll
-                            for (int k = 0; k < RPT; ++k) cp[l + PG * k] = x[k];
+                            if (l == 0) jn[ycol] = be;
                         }
                     }
+                    lds_publish(wsteps + wave, steps + st + 1);
+                }
+                steps += k;
+                if (xcol < w) {
+#pragma unroll
+                    for (int r = 0; r < RPT; ++r) base[xcol * ldc + l + PG * r] = xr[r];
                 }
                 __syncthreads();
             }
