@@ -202,33 +202,22 @@ __device__ __forceinline__ double pnorm2(const cplx<T> (&x)[RPT], int ka) {
     return (double)group_sum<PG>(acc);
 }
 
-// Orthogonalise column x against column y in LDS.  Lane l of the pair
-// group holds rows l + PG k; the first ka row groups (1 <= ka < RPT) are
-// slice rows, the rest V rows, padding rows are zero; only the slice rows
-// take part in the test.  With x_lds set, x is read from there first.
-// EXACT: al and be are computed here from the slice rows (their sums
-// reduced together with the inner product); otherwise they are the tracked
-// squared norms.  On a rotation the norms are updated in place
-// (al -= t|gamma|, be += t|gamma|).  Returns 0 (not rotated), 1 (rotated)
-// or 2 (rotated, and the rotation forces another sweep: rot_forces_sweep).
-template <typename T, int PG, int RPT, bool EXACT = false>
+// Orthogonalise column x (registers) against column y in LDS.  Lane l of
+// the pair group holds rows l + PG k; the first ka row groups (1 <= ka < RPT)
+// are slice rows, the rest V rows, padding rows are zero; only the slice rows
+// take part in the test.  al and be are the squared norms of the slice rows,
+// exact at the start of a round (or internal level) and tracked through it:
+// on a rotation they are updated in place (al -= t|gamma|, be += t|gamma|).
+// Returns 0 (not rotated), 1 (rotated) or 2 (rotated, and the rotation
+// forces another sweep: rot_forces_sweep).
+template <typename T, int PG, int RPT>
 __device__ __forceinline__ unsigned ppair(cplx<T> (&x)[RPT], cplx<T>* y_lds, double& al, double& be, int ka,
-                                          int l, double tol, const cplx<T>* x_lds = nullptr) {
+                                          int l, double tol) {
     cplx<T> y[RPT];
 #pragma unroll
-    for (int k = 0; k < RPT; ++k) {
-        if (x_lds) x[k] = x_lds[l + PG * k];
-        y[k] = y_lds[l + PG * k];
-    }
+    for (int k = 0; k < RPT; ++k) y[k] = y_lds[l + PG * k];
     T gr = 0, gi = 0;
     dot_rows<T, RPT>(x, y, ka, gr, gi, std::make_integer_sequence<int, RPT - 1>{});
-    if (EXACT) {
-        T na = norm_rows<T, RPT>(x, ka, std::make_integer_sequence<int, RPT - 1>{});
-        T nb = norm_rows<T, RPT>(y, ka, std::make_integer_sequence<int, RPT - 1>{});
-        group_sum2<PG>(na, nb);
-        al = (double)na;
-        be = (double)nb;
-    }
     group_sum2<PG>(gr, gi);
     const double dgr = (double)gr, dgi = (double)gi;
     const PRot rt = prot<T>(al, be, dgr, dgi, tol);

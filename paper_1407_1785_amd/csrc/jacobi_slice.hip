@@ -51,38 +51,66 @@ __device__ __forceinline__ unsigned pair_round(cplx<T>* blk0, cplx<T>* blk1, int
     constexpr int PG = kPGs;
     const int g = threadIdx.x / PG, l = threadIdx.x - g * PG;
     unsigned nrot = 0;
+    // pair steps finished per wave in this call; a wave waits only for the
+    // wave whose previous step wrote the column it takes next
+    __shared__ int wsteps[BW * PG / 64];
+    __shared__ double inorm[2 * BW];
+    const int wave = threadIdx.x >> 6, wave_next = (wave + 1) % (BW * PG / 64);
+    if ((threadIdx.x & 63) == 0) wsteps[wave] = 0;
+    int steps = 0;
     if (self_phase) {
-        // internal pairs of both blocks: groups 0..BW/2-1 take block 0, the rest block 1
+        // Internal pairs of both blocks (groups 0..BW/2-1 take block 0, the
+        // rest block 1) by halving: the cross pairs of the block's two halves,
+        // then of the halves of each half, down to adjacent pairs -- BW - 1
+        // steps, every pair once.  Each level runs like a cross round: a
+        // group keeps its column of the first half of its subproblem in
+        // registers and meets the k columns of the second half, norms exact
+        // at the level's start and tracked through it.
         const bool second = g >= BW / 2;
         const int gi = second ? g - BW / 2 : g;
         cplx<T>* const base = second ? blk1 : blk0;
+        double* const jn = inorm + (second ? BW : 0);
         const int w = second ? wj : wi;
-        const int wp = w + (w & 1);
-        for (int st = 0; st < BW - 1; ++st) {
-            if (st < wp - 1 && gi < wp / 2) {
-                const int pp = ppos_player(gi, st, wp);
-                const int qq = ppos_player(wp - 1 - gi, st, wp);
-                if (pp < w && qq < w) {
-                    cplx<T>* cp = base + pp * ldc;
-                    cplx<T>* cq = base + qq * ldc;
-                    cplx<T> x[RPT];
-                    double al, be;
-                    if (const unsigned code = ppair<T, PG, RPT, true>(x, cq, al, be, ka, l, tol, cp)) {
+        for (int k = BW / 2; k >= 1; k /= 2) {
+            const int sp = gi / k, q = gi - sp * k;
+            const int xcol = 2 * k * sp + q, ybase = 2 * k * sp + k;
+            // a subproblem of k groups spans k / 2 consecutive waves (one if k <= 2)
+            const int span = k >= 4 ? k / 2 : 1, wl = wave % span;
+            const int wnext = wave - wl + (wl + 1) % span;
+            cplx<T> xr[RPT];
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) xr[r] = base[xcol * ldc + l + PG * r];
+            double ax = pnorm2<T, PG, RPT>(xr, ka);
+            {
+                cplx<T> yr[RPT];
+#pragma unroll
+                for (int r = 0; r < RPT; ++r) yr[r] = base[(ybase + q) * ldc + l + PG * r];
+                const double bq = pnorm2<T, PG, RPT>(yr, ka);
+                if (l == 0) jn[ybase + q] = bq;
+            }
+            __syncthreads();
+            for (int st = 0; st < k; ++st) {
+                if (st > 0) ring_wait(wsteps + wnext, steps + st);
+                const int ycol = ybase + ((q + st) & (k - 1));
+                if (xcol < w && ycol < w) {
+                    double be = jn[ycol];
+                    if (const unsigned code = ppair<T, PG, RPT>(xr, base + ycol * ldc, ax, be, ka, l, tol)) {
                         ++nrot;
                         nbig += code >> 1;
-#pragma unroll
-                        for (int k = 0; k < RPT; ++k) cp[l + PG * k] = x[k];
+                        if (l == 0) jn[ycol] = be;
                     }
                 }
+                ring_publish(wsteps + wave, steps + st + 1);
+            }
+            steps += k;
+            if (xcol < w) {
+#pragma unroll
+                for (int r = 0; r < RPT; ++r) base[xcol * ldc + l + PG * r] = xr[r];
             }
             __syncthreads();
         }
     }
-    // cross pairs: column g of block 0 (registers) meets every column of block 1;
-    // step st of a wave waits only for its successor's step st - 1
-    __shared__ int wsteps[BW * PG / 64];
-    const int wave = threadIdx.x >> 6, wave_next = (wave + 1) % (BW * PG / 64);
-    if ((threadIdx.x & 63) == 0) wsteps[wave] = 0;
+    // cross pairs: column g of block 0 (registers) meets every column of block 1
     cplx<T> xi[RPT];
 #pragma unroll
     for (int k = 0; k < RPT; ++k) xi[k] = blk0[g * ldc + l + PG * k];
@@ -96,7 +124,7 @@ __device__ __forceinline__ unsigned pair_round(cplx<T>* blk0, cplx<T>* blk1, int
     }
     __syncthreads();
     for (int st = 0; st < BW; ++st) {
-        if (st > 0) ring_wait(wsteps + wave_next, st);
+        if (st > 0) ring_wait(wsteps + wave_next, steps + st);
         const int jc = (g + st) & (BW - 1);
         if (g < wi && jc < wj) {
             double be = jnorm[jc];
@@ -106,7 +134,7 @@ __device__ __forceinline__ unsigned pair_round(cplx<T>* blk0, cplx<T>* blk1, int
                 if (l == 0) jnorm[jc] = be;
             }
         }
-        ring_publish(wsteps + wave, st + 1);
+        ring_publish(wsteps + wave, steps + st + 1);
     }
     if (g < wi) {
 #pragma unroll
