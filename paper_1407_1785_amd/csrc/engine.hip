@@ -765,7 +765,8 @@ private:
             if ((int)runs.size() >= kMaxClasses) fail(TSVD_E_UNSUPPORTED, "too many Jacobi classes");
             int& est = sweep_est_[{ph.bw, ph.rpt}];
             if (est <= 0) est = kSweepEstimate0;
-            runs.push_back(Run{&ph, 0, std::min(est, ph.sweeps_max), (int)runs.size(), &est});
+            // at least one sweep, so the flag kernel reads the ring entry of sweep k - 1 >= 0
+            runs.push_back(Run{&ph, 0, std::max(1, std::min(est, ph.sweeps_max)), (int)runs.size(), &est});
         }
         if (runs.empty()) return;
         for (Run& r : runs) {
