@@ -303,7 +303,7 @@ SweepStats run_svt(tsvd_handle h, const Geometry& g, const SvtBuffers<T>& sb, in
                          jacobi_persistent_fits(g.m, g.n, g.h, sizeof(T), h->cus, h->lds_cap, xcds);
     bool done_persist = false;
     if (persist) {
-        // one cooperative launch runs every sweep
+        // one launch runs every sweep (TSVD_COOP=1: a cooperative launch)
         ja.nb = jacobi_persistent_blocks(g.n);
         ja.rotations = h->rot_counter + 1;
         // the init also clears the barrier counters, rotation flags and block
@@ -317,7 +317,7 @@ SweepStats run_svt(tsvd_handle h, const Geometry& g, const SvtBuffers<T>& sb, in
         launch_check("jacobi_init");
         ja.clr[0] = ja.clr[1] = nullptr;
         PersistArgs pa{sb.pbar, sb.pbar + g.h, sb.pbar + 4 * g.h, sb.pbar + 4 * g.h + 1, max_sweeps, nullptr,
-                       env_int("TSVD_COOP", 1) != 0 ? 1 : 0, xcds, env_int("TSVD_SPREAD", 0)};
+                       env_int("TSVD_COOP", 0) != 0 ? 1 : 0, xcds, env_int("TSVD_SPREAD", 0)};
         static long long* trace_buf = nullptr;
         const bool tracing = env_int("TSVD_TRACE", 0) != 0;
         if (tracing) {

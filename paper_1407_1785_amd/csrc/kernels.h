@@ -259,7 +259,7 @@ void launch_jacobi_tall_round(const JacArgs<T>& a, const TallPlan& t, double* pa
 // LDS bytes one workgroup may use on the current device
 void jacobi_set_lds_limit(size_t bytes);
 
-// Persistent Jacobi (jacobi_persist.hip): one cooperative launch per SVD.
+// Persistent Jacobi (jacobi_persist.hip): one launch per SVD.
 struct PersistArgs {
     int* barrier;    // h arrival counters, zero before the launch
     int* rotflag;    // 3 x h sweep flags, zero before the launch
@@ -267,7 +267,7 @@ struct PersistArgs {
     int* bflag;      // h x nb block-ready flags, zero before the launch
     int max_sweeps;
     long long* trace;  // optional: 64 timestamps of workgroup 0 of slice 0
-    int cooperative;   // 1: cooperative launch (co-residency guaranteed by the runtime)
+    int cooperative;   // 1: cooperative launch (co-residency guaranteed by the runtime; slower to launch)
     int xcds;          // > 0: workgroups of a slice share one XCD (workgroup b runs on XCD b mod xcds)
     int spread;        // 1: reserve over half a CU's LDS, so no two workgroups share a CU
 };
