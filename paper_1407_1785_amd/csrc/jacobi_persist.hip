@@ -60,6 +60,59 @@ __device__ void pload_block(const JacArgs<T>& a, int s, int blk, int mp, int ldc
                                  mp, ldc, lds);
 }
 
+// The blocks blk0 and blk1 (-1: none) into LDS.  FP64: every load in flight
+// before the first LDS store, one memory round trip for both blocks, slice
+// and V rows, instead of one per block and row segment (+2% iterations/s on
+// the video shape).  FP32 keeps the per-block loads: the combined loader
+// raised the kernel's scalar register spills and slowed its step loop by 5%.
+// Thread team c (PG lanes) takes column c of each block, lane t the stacked
+// rows t + PG r: slice rows below m, V rows from mp (the padding rows
+// between stay zero).
+template <typename T, int PG, int RPT>
+__device__ __forceinline__ void pload_pair(const JacArgs<T>& a, int s, int mp, int ldc, int blk0, cplx<T>* lds0,
+                                           int blk1, cplx<T>* lds1) {
+    if constexpr (sizeof(T) == 4) {
+        constexpr int NT = PBW * PG;
+        if (blk0 >= 0) pload_block<T, NT>(a, s, blk0, mp, ldc, lds0);
+        if (blk1 >= 0) pload_block<T, NT>(a, s, blk1, mp, ldc, lds1);
+        return;
+    }
+    const int c = threadIdx.x / PG, t = threadIdx.x - c * PG;
+    const cplx<T>* const A = a.A + (int64_t)s * a.n * a.m;
+    const cplx<T>* const V = a.V + (int64_t)s * a.n * a.n;
+    const int m = a.m, n = a.n;
+    auto col = [&](int blk) {
+        if (blk < 0) return -1;
+        const int c0 = pblk_start(blk, n, a.nb);
+        return c < pblk_start(blk + 1, n, a.nb) - c0 ? c0 + c : -1;
+    };
+    const int col0 = col(blk0), col1 = col(blk1);
+    cplx<T> v0[RPT], v1[RPT];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        const int R = t + PG * r;
+        if (col0 >= 0) {
+            if (R < m)
+                v0[r] = coh_load<T>(A + (int64_t)col0 * m + R);
+            else if (R >= mp && R - mp < n)
+                v0[r] = coh_load<T>(V + (int64_t)col0 * n + (R - mp));
+        }
+        if (col1 >= 0) {
+            if (R < m)
+                v1[r] = coh_load<T>(A + (int64_t)col1 * m + R);
+            else if (R >= mp && R - mp < n)
+                v1[r] = coh_load<T>(V + (int64_t)col1 * n + (R - mp));
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        const int R = t + PG * r;
+        const bool row = R < m || (R >= mp && R - mp < n);
+        if (col0 >= 0 && row) lds0[c * ldc + R] = v0[r];
+        if (col1 >= 0 && row) lds1[c * ldc + R] = v1[r];
+    }
+}
+
 template <typename T, int NT>
 __device__ void pstore_block(const JacArgs<T>& a, int s, int blk, int mp, int ldc, const cplx<T>* lds) {
     store_block<T, NT, PBW, true>(a.A + (int64_t)s * a.n * a.m, a.V + (int64_t)s * a.n * a.n, a.m, a.n, a.nb, blk,
@@ -201,8 +254,7 @@ __global__ __launch_bounds__(PBW * PG) void jacobi_persistent_kernel(JacArgs<T> 
     int steps = 0;   // cross steps finished by every wave before the current round
     __syncthreads();
     int player0 = ppos_player(pos0, 0, a.nb), player1 = ppos_player(pos1, 0, a.nb);
-    pload_block<T, NT>(a, s, player0, mp, ldc, blk0);
-    pload_block<T, NT>(a, s, player1, mp, ldc, blk1);
+    pload_pair<T, PG, RPT>(a, s, mp, ldc, player0, blk0, player1, blk1);
     if (wg == 0 && threadIdx.x == 0) a.sweeps[s] = 0;
     __syncthreads();
 
@@ -373,14 +425,10 @@ __global__ __launch_bounds__(PBW * PG) void jacobi_persistent_kernel(JacArgs<T> 
                     break;
                 }
             }
-            if (next0 != player0) {
-                player0 = next0;
-                pload_block<T, NT>(a, s, player0, mp, ldc, blk0);
-            }
-            if (next1 != player1) {
-                player1 = next1;
-                pload_block<T, NT>(a, s, player1, mp, ldc, blk1);
-            }
+            pload_pair<T, PG, RPT>(a, s, mp, ldc, next0 != player0 ? next0 : -1, blk0,
+                                   next1 != player1 ? next1 : -1, blk1);
+            player0 = next0;
+            player1 = next1;
             __syncthreads();
             mark();
         }
