@@ -178,3 +178,38 @@ def test_compression_errors():
                       (lib.COMPRESS_TSVD, 21), (7, 1)):
         with pytest.raises(lib.TsvdError, match="TSVD_E_INVALID"):
             lib.compress(m, method, k)
+
+
+# ------------------------------------------------------------ full size
+
+def test_factors_and_compression_at_video_size():
+    """The synthetic 128 x 160 x 64 video the bench compresses (Sec. 3's
+    experiment shape), at the bench's launch configuration: singular tubes
+    and reconstruction against the oracle's t-SVD, and Methods 1 and 2 at
+    compression ratio ~10 element by element."""
+    torch = torch_cuda()
+    import workloads
+
+    x = np.asarray(workloads.video_completion(0)["X"], dtype=np.float64)
+    n1, n2, n3 = x.shape
+    _, s_ref, _, _, _, _ = T.tsvd(x)
+    n0 = min(n1, n2)
+    tubes_ref = np.stack([s_ref[(i, i)] for i in range(n0)])
+    xg = to_gpu(torch, x)
+    announce("tsvd_factors video", x.shape)
+    u, s, v = (t.cpu().numpy() for t in lib.tsvd_factors(xg))
+    assert rel_fro(s, tubes_ref) <= TOL
+    assert rel_fro(reconstruct(u, s, v), x) <= TOL
+    k2 = round(n1 * n2 * n3 / (10 * (n1 + n2 + 1)))
+    k3 = round(n1 * n2 / (10 * (n1 + n2 + 1)))
+    out_ref, keep, t, _ = C.method1(x, k2, return_details=True)
+    srt = np.sort(np.unique(C.fourier_singular_values(T.tsvd(x)[4])))[::-1]
+    below = srt[srt < t]
+    assert below.size == 0 or (t - below[0]) / srt[0] > 1e-10   # a clear cut
+    announce("compress video", k2, k3)
+    m1, r1 = lib.compress(xg, lib.COMPRESS_TSVD, k2)
+    assert rel_fro(m1.cpu().numpy(), out_ref) <= TOL
+    assert r1 == pytest.approx(C.ratio_tsvd(n1, n2, n3, k2), rel=1e-14)
+    m2, r2 = lib.compress(xg, lib.COMPRESS_TUBAL, k3)
+    assert rel_fro(m2.cpu().numpy(), C.method2(x, k3)) <= TOL
+    assert r2 == pytest.approx(C.ratio_tubal(n1, n2, k3), rel=1e-14)
