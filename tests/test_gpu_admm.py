@@ -78,3 +78,29 @@ def test_trpca_recovers_planted():
     assert info.converged == 1 and abs(info.iters - ref["iters"]) <= 1
     assert metrics.rse(lo.cpu().numpy(), p["L"]) <= 1e-5
     assert metrics.support_f1(sp.cpu().numpy(), p["S"], p["M"]) >= 0.99
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_trpca_full_size_prefix(fp32):
+    """The 256 x 256 x 64 RPCA workload (rank 5, 10% sparse corruption,
+    entrywise l1) at its full size: the first 15 iterations against the
+    oracle.  mu grows by 1.2 from 1e-3, so the shrink threshold lambda / mu
+    drops below the corruption's magnitude after ~12 iterations: S is nonzero
+    by the end of the prefix."""
+    torch = torch_cuda()
+    p = workloads.trpca_problem(0)
+    ref = admm.trpca(p["M"], p["lam"], max_iter=15, tol=0.0, shrink="l1")
+    assert np.count_nonzero(ref["S"]) > 0
+    dt = torch.float32 if fp32 else torch.float64
+    prec = lib.PREC_FP32 if fp32 else lib.PREC_FP64
+    announce("trpca full size", "fp32" if fp32 else "fp64")
+    lo, sp, info = lib.trpca(to_gpu(torch, p["M"], dt), p["lam"], 1e-3, 0.0, shrink=lib.SHRINK_L1, max_iter=15,
+                             precision=prec)
+    assert info.iters == 15
+    lo, sp = lo.cpu().numpy().astype(np.float64), sp.cpu().numpy().astype(np.float64)
+    if fp32:
+        assert rel_fro(lo, ref["L"]) <= 1e-4
+        assert np.linalg.norm(sp - ref["S"]) <= 1e-4 * np.linalg.norm(p["M"])
+    else:
+        assert rel_fro(lo, ref["L"]) <= TOL
+        assert rel_fro(sp, ref["S"]) <= 1e-9
