@@ -124,6 +124,29 @@ def test_tsvt_video_shape_sampled():
     assert ranks == list(r_ref)
 
 
+def test_tsvt_colour_video_size():
+    """The 4-D colour video shape of the serving mix, 96 x 128 x 3 x 48 (DFT
+    along modes 3 and 4, 3 x 25 = 75 Fourier slices): whole-tensor parity,
+    FP64 and the FP32 form."""
+    torch = torch_cuda()
+    import workloads
+
+    x = np.asarray(workloads.color_video(workloads.streams(6, 0, 1)[0]), dtype=np.float64)
+    assert x.shape == (96, 128, 3, 48)
+    sv = np.sort(np.linalg.svd(np.moveaxis(T.fourier_half(x).reshape(96, 128, -1), 2, 0), compute_uv=False).ravel())
+    # tau at the midpoint of the widest relative gap among the largest 400
+    # singular values (the spectrum of the smooth video decays fast)
+    i = max(range(len(sv) - 400, len(sv) - 10), key=lambda k: (sv[k + 1] - sv[k]) / sv[k + 1])
+    tau = float(0.5 * (sv[i] + sv[i + 1]))
+    z_ref, r_ref = tsvt_oracle(x, tau)
+    announce("tsvt colour video", x.shape, tau)
+    z, ranks = lib.tsvt(to_gpu(torch, x), tau)
+    assert rel_fro(z.cpu().numpy(), z_ref) <= TOL
+    assert ranks == list(r_ref)
+    z32, _ = lib.tsvt(to_gpu(torch, x, torch.float32), tau, precision=lib.PREC_FP32)
+    assert rel_fro(z32.cpu().numpy().astype(np.float64), z_ref) <= 1e-4
+
+
 def test_tsvt_errors():
     torch = torch_cuda()
     x = torch.zeros((4, 5, 6), dtype=torch.float64, device="cuda")
