@@ -177,3 +177,27 @@ def test_shrinks_closed_form():
     t = np.array([[[3.0, 4.0]], [[0.0, 0.0]]])
     np.testing.assert_allclose(admm.shrink_tube(t, 2.5), [[[1.5, 2.0]], [[0.0, 0.0]]])
     np.testing.assert_allclose(admm.shrink_tube(t, 6.0), np.zeros_like(t))
+
+
+def test_metrics_closed_forms():
+    """The recovery metrics against hand-computed values: an error of a tenth
+    of the reference's norm is -20 dB, of a hundredth -40 dB; F1 from
+    counted true and false positives."""
+    x = np.zeros((4, 5, 3))
+    x[0, 0, 0] = 3.0
+    x[1, 2, 1] = 4.0                       # ||x|| = 5
+    e = np.zeros_like(x)
+    e[2, 2, 2] = 0.5                       # ||e|| = 0.5 = ||x|| / 10
+    assert metrics.rse(x + e, x) == pytest.approx(0.1, rel=1e-15)
+    assert metrics.rse_db(x + e, x) == pytest.approx(-20.0, rel=1e-14)
+    assert metrics.rse_db(x + e / 10, x) == pytest.approx(-40.0, rel=1e-14)
+    m = np.full((2, 2, 2), 10.0)           # threshold 1e-3 * 10 = 0.01
+    s_true = np.zeros((2, 2, 2))
+    s_true[0, 0, 0] = s_true[1, 1, 1] = 1.0
+    s_hat = np.zeros((2, 2, 2))
+    s_hat[0, 0, 0] = 0.5                   # true positive
+    s_hat[0, 1, 0] = 0.02                  # false positive (above 0.01)
+    s_hat[1, 0, 0] = 0.005                 # below the threshold: not predicted
+    # tp = 1, fp = 1, fn = 1 -> F1 = 2 / (2 + 1 + 1)
+    assert metrics.support_f1(s_hat, s_true, m) == pytest.approx(0.5, rel=1e-15)
+    assert metrics.support_f1(np.zeros_like(s_hat), s_true, m) == 0.0
