@@ -162,3 +162,30 @@ def test_tsvt_errors():
     with pytest.raises(lib.TsvdError) as e:
         lib.tsvt(x.float(), 1.0)   # FP32 data needs the FP32 form
     assert e.value.status == -6
+
+
+def test_tsvt_random_shapes():
+    """Seeded random shapes (either orientation, ragged Jacobi blocks, odd and
+    even tube lengths, 3-D and 4-D) with tau at a random point between two
+    adjacent singular values: every one against the oracle."""
+    torch = torch_cuda()
+    rng = np.random.default_rng(1407)
+    for case in range(16):
+        n1, n2 = (int(v) for v in rng.integers(1, 200, size=2))
+        trail = (int(rng.integers(1, 21)),) if case % 4 else (int(rng.integers(1, 5)), int(rng.integers(1, 9)))
+        shape = (n1, n2) + trail
+        x = rng.normal(size=shape) * rng.uniform(0.1, 10.0)
+        sv = np.sort(np.linalg.svd(np.moveaxis(T.fourier_half(x).reshape(n1, n2, -1), 2, 0),
+                                   compute_uv=False).ravel())
+        k = int(rng.integers(0, len(sv) - 1)) if len(sv) > 1 else 0
+        tau = float(0.5 * (sv[k] + sv[min(k + 1, len(sv) - 1)]))
+        z_ref, r_ref = tsvt_oracle(x, tau)
+        announce("tsvt random", shape, tau)
+        z, ranks = lib.tsvt(to_gpu(torch, x), tau)
+        z = z.cpu().numpy()
+        if np.linalg.norm(z_ref) > 0:
+            assert rel_fro(z, z_ref) <= TOL, shape
+        else:
+            assert np.abs(z).max() <= TOL * np.abs(x).max(), shape
+        if len(sv) > 1 and (sv[k + 1] - sv[k]) > 1e-9 * sv[-1]:
+            assert ranks == list(r_ref), shape
