@@ -104,3 +104,22 @@ def test_trpca_full_size_prefix(fp32):
     else:
         assert rel_fro(lo, ref["L"]) <= TOL
         assert rel_fro(sp, ref["S"]) <= 1e-9
+
+
+def test_completion_random_shapes():
+    """Seeded random shapes (either orientation, ragged Jacobi blocks, 3-D
+    and 4-D), random sampling rates, 6 warm-started iterations each against
+    the oracle."""
+    torch = torch_cuda()
+    rng = np.random.default_rng(4071)
+    for case in range(8):
+        n1, n2 = (int(v) for v in rng.integers(2, 150, size=2))
+        trail = (int(rng.integers(1, 17)),) if case % 3 else (int(rng.integers(1, 4)), int(rng.integers(2, 7)))
+        shape = (n1, n2) + trail
+        x = rng.normal(size=shape)
+        mask = (rng.random(shape) < rng.uniform(0.2, 0.8)).astype(np.uint8)
+        ref = admm.complete(x * mask, mask, 1e-2, 1.1, 1e3, max_iter=6, tol=0.0)
+        announce("completion random", shape)
+        out, info = lib.tsvd_complete(to_gpu(torch, x * mask), to_gpu(torch, mask), 1e-2, 0.0, max_iter=6)
+        assert info.iters == 6
+        assert rel_fro(out.cpu().numpy(), ref["X"]) <= TOL, shape
