@@ -36,6 +36,8 @@
 
 #include "kernels.h"
 
+#include <cstdlib>
+
 namespace tsvd {
 
 namespace {
@@ -391,15 +393,183 @@ __device__ __forceinline__ void zgemm_bf16x3_body(const ZGemmArgs<float>& g, int
     }
 }
 
+// ---- split-K form for products with few 64 x 64 tiles -------------------
+//
+// One 256-thread workgroup per 32 x 32 tile of C.  The four waves split the
+// K range into contiguous quarters; each wave computes the whole tile over
+// its quarter (2 x 2 MFMA tiles, the same accumulators and operand order as
+// the 64 x 64 form) with the fragments loaded straight from memory, no LDS
+// staging and no barrier.  The four partial tiles are then summed through LDS
+// in a fixed order (quarter 0 first), each wave finishing one 16 x 16 part.
+// A 128 x 128 product per slice has 16 such tiles instead of 4, so a batch of
+// a few dozen slices spreads over all compute units.
+
+constexpr int SKM = 32, SKN = 32;
+// MFMA k-steps (of 4) per load batch: 8 in FP32; 4 in FP64, which keeps the
+// kernel at two waves per SIMD (two workgroups per compute unit)
 template <typename T>
-__global__ __launch_bounds__(256) void zgemm_k4_kernel(ZGemmArgs<T> g) {
-    if (g.ctrl && g.ctrl->done) return;
-    zgemm_k4_body<T>(g, blockIdx.x, blockIdx.y, blockIdx.z);
+constexpr int sk_batch() { return sizeof(T) == 8 ? 4 : 8; }
+
+// Raw element (r, k) of an operand view (layout as for the staged form), from
+// an address clamped into the matrix, so the load is always in bounds; the
+// caller masks, conjugates and scales it.
+template <typename T>
+__device__ __forceinline__ cplx<T> view_load(const cplx<T>* X, int ld, bool kcontig, int r, int k, int R, int K) {
+    const int rc = min(r, R - 1), kc = min(k, K - 1);
+    return X[kcontig ? (int64_t)rc * ld + kc : (int64_t)kc * ld + rc];
 }
 
-__global__ __launch_bounds__(256) void zgemm_bf16x3_kernel(ZGemmArgs<float> g) {
+template <typename T>
+__device__ __forceinline__ void zgemm_sk_body(const ZGemmArgs<T>& g, int bx, int by, int s) {
+    typedef Mfma4<T> M;
+    typedef typename M::acc_t acc_t;
+    __shared__ T red[4][2][2][2][4][64];   // [wave][re, im][x][y][register][lane]
+    const int row0 = bx * SKM, col0 = by * SKN;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int l16 = lane & 15, lk = lane >> 4;
+    const cplx<T>* A = g.A + (int64_t)s * g.sA;
+    const cplx<T>* B = g.B + (int64_t)s * g.sB;
+    const double* dk = g.dk ? g.dk + (int64_t)s * g.sdk : nullptr;
+    const bool akc = g.opA != 0, bkc = g.opB == 0;
+    const bool aconj = g.opA != 0, bconj = g.opB != 0;
+
+    acc_t cr[2][2], ci[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) cr[a][b] = ci[a][b] = acc_t{(T)0, (T)0, (T)0, (T)0};
+
+    const int nks = (g.K + 3) / 4, per = (nks + 3) / 4;
+    const int ks0 = w * per, ks1 = min(ks0 + per, nks);
+    const int kend = min(4 * ks1, g.K);
+    constexpr int SKB = sk_batch<T>();
+    for (int kb = ks0; kb < ks1; kb += SKB) {
+        cplx<T> va[SKB][2], vb[SKB][2];
+        double dv[SKB];
+#pragma unroll
+        for (int j = 0; j < SKB; ++j) {
+            const int k = 4 * (kb + j) + lk;
+#pragma unroll
+            for (int x = 0; x < 2; ++x) {
+                va[j][x] = view_load<T>(A, g.lda, akc, row0 + 16 * x + l16, k, g.M, g.K);
+                vb[j][x] = view_load<T>(B, g.ldb, bkc, col0 + 16 * x + l16, k, g.N, g.K);
+            }
+            dv[j] = dk ? dk[min(k, g.K - 1)] : 1.0;
+        }
+#pragma unroll
+        for (int j = 0; j < SKB; ++j) {
+            const int k = 4 * (kb + j) + lk;
+            T a_r[2], a_i[2], b_r[2], b_i[2];
+#pragma unroll
+            for (int x = 0; x < 2; ++x) {
+                const bool ain = row0 + 16 * x + l16 < g.M && k < kend;
+                const bool bin = col0 + 16 * x + l16 < g.N && k < kend;
+                const T fa = ain ? (dk ? (T)dv[j] : (T)1) : (T)0;
+                const T fb = bin ? (T)1 : (T)0;
+                a_r[x] = fa * va[j][x].re;
+                a_i[x] = fa * (aconj ? -va[j][x].im : va[j][x].im);
+                b_r[x] = fb * vb[j][x].re;
+                b_i[x] = fb * (bconj ? -vb[j][x].im : vb[j][x].im);
+            }
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+#pragma unroll
+                for (int y = 0; y < 2; ++y) {
+                    cr[x][y] = M::mma(b_r[y], a_r[x], cr[x][y]);
+                    ci[x][y] = M::mma(b_r[y], a_i[x], ci[x][y]);
+                }
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+#pragma unroll
+                for (int y = 0; y < 2; ++y) {
+                    cr[x][y] = M::mma(-b_i[y], a_i[x], cr[x][y]);
+                    ci[x][y] = M::mma(b_i[y], a_r[x], ci[x][y]);
+                }
+        }
+    }
+
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                red[w][0][x][y][v][lane] = cr[x][y][v];
+                red[w][1][x][y][v][lane] = ci[x][y][v];
+            }
+    __syncthreads();
+    const int x = w & 1, y = w >> 1;
+    const int row = row0 + 16 * x + l16;
+    cplx<T>* C = g.C + (int64_t)s * g.sC;
+    const cplx<T>* D = g.D ? g.D + (int64_t)s * g.sD : nullptr;
+    cplx<T> dd[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        dd[v] = cplx<T>{(T)0, (T)0};
+        if (D) {
+            const int colc = min(col0 + 16 * y + M::col(lane, v), g.N - 1);
+            dd[v] = D[(int64_t)colc * g.ldd + min(row, g.M - 1)];
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        T sr = red[0][0][x][y][v][lane], si = red[0][1][x][y][v][lane];
+#pragma unroll
+        for (int q = 1; q < 4; ++q) {
+            sr += red[q][0][x][y][v][lane];
+            si += red[q][1][x][y][v][lane];
+        }
+        const int col = col0 + 16 * y + M::col(lane, v);
+        const T re = g.alpha * sr + g.beta * dd[v].re;
+        const T im = g.alpha * si + g.beta * dd[v].im;
+        if (row < g.M && col < g.N) C[(int64_t)col * g.ldc + row] = cplx<T>{re, im};
+    }
+}
+
+// Tile of this workgroup in a (gx, gy, batch) grid.  The device deals
+// workgroups to its 8 XCDs, each with its own L2, in turn by linear index;
+// with remap set the tiles are renumbered so that each XCD takes a contiguous
+// run of them (tile x fastest, then tile y, then slice), and a slice's
+// operands are fetched into one or two L2s instead of into all eight.
+__device__ __forceinline__ void grid_tile(int remap, int& bx, int& by, int& s) {
+    const int gx = gridDim.x, gy = gridDim.y;
+    if (!remap) {
+        bx = blockIdx.x;
+        by = blockIdx.y;
+        s = blockIdx.z;
+        return;
+    }
+    const int n = gx * gy * (int)gridDim.z;
+    const int lin = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    const int q = n / 8, r = n % 8, x = lin % 8;
+    const int id = x * q + min(x, r) + lin / 8;
+    s = id / (gx * gy);
+    const int rem = id - s * gx * gy;
+    by = rem / gx;
+    bx = rem - by * gx;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void zgemm_sk_kernel(ZGemmArgs<T> g, int remap) {
     if (g.ctrl && g.ctrl->done) return;
-    zgemm_bf16x3_body(g, blockIdx.x, blockIdx.y, blockIdx.z);
+    int bx, by, s;
+    grid_tile(remap, bx, by, s);
+    zgemm_sk_body<T>(g, bx, by, s);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void zgemm_k4_kernel(ZGemmArgs<T> g, int remap) {
+    if (g.ctrl && g.ctrl->done) return;
+    int bx, by, s;
+    grid_tile(remap, bx, by, s);
+    zgemm_k4_body<T>(g, bx, by, s);
+}
+
+__global__ __launch_bounds__(256) void zgemm_bf16x3_kernel(ZGemmArgs<float> g, int remap) {
+    if (g.ctrl && g.ctrl->done) return;
+    int bx, by, s;
+    grid_tile(remap, bx, by, s);
+    zgemm_bf16x3_body(g, bx, by, s);
 }
 
 // Problem-table launch: problem p owns tiles_m * tiles_n * batch workgroups;
@@ -442,19 +612,54 @@ __global__ __launch_bounds__(256) void multirank_kernel(const double* sigma, int
 
 }  // namespace
 
+namespace {
+
+// The split-K form when the 64 x 64 grid leaves compute units idle (fewer
+// than two tiles per unit of a 256-unit device).  TSVD_GEMM_SPLITK=0 / 1
+// forces the 64 x 64 / split-K form.
+int env_or(const char* name, int dflt) {
+    const char* v = std::getenv(name);
+    return v && *v ? std::atoi(v) : dflt;
+}
+
+int xcd_remap() {
+    static const int on = env_or("TSVD_GEMM_XCD", 1);
+    return on;
+}
+
+template <typename T>
+bool use_split_k_of(const ZGemmArgs<T>& g) {
+    static const int forced = env_or("TSVD_GEMM_SPLITK", -1);
+    if (forced >= 0) return forced != 0;
+    const int64_t tiles = (int64_t)((g.M + TM - 1) / TM) * ((g.N + TN - 1) / TN) * g.batch;
+    return tiles < 512;
+}
+
+}  // namespace
+
 template <>
 void launch_zgemm<double>(const ZGemmArgs<double>& g, hipStream_t st) {
+    if (use_split_k_of(g)) {
+        dim3 grid((g.M + SKM - 1) / SKM, (g.N + SKN - 1) / SKN, g.batch);
+        hipLaunchKernelGGL(zgemm_sk_kernel<double>, grid, dim3(256), 0, st, g, xcd_remap());
+        return;
+    }
     dim3 grid((g.M + TM - 1) / TM, (g.N + TN - 1) / TN, g.batch);
-    hipLaunchKernelGGL(zgemm_k4_kernel<double>, grid, dim3(256), 0, st, g);
+    hipLaunchKernelGGL(zgemm_k4_kernel<double>, grid, dim3(256), 0, st, g, xcd_remap());
 }
 
 template <>
 void launch_zgemm<float>(const ZGemmArgs<float>& g, hipStream_t st) {
+    if (!g.bf16x3 && use_split_k_of(g)) {
+        dim3 grid((g.M + SKM - 1) / SKM, (g.N + SKN - 1) / SKN, g.batch);
+        hipLaunchKernelGGL(zgemm_sk_kernel<float>, grid, dim3(256), 0, st, g, xcd_remap());
+        return;
+    }
     dim3 grid((g.M + TM - 1) / TM, (g.N + TN - 1) / TN, g.batch);
     if (g.bf16x3)
-        hipLaunchKernelGGL(zgemm_bf16x3_kernel, grid, dim3(256), 0, st, g);
+        hipLaunchKernelGGL(zgemm_bf16x3_kernel, grid, dim3(256), 0, st, g, xcd_remap());
     else
-        hipLaunchKernelGGL(zgemm_k4_kernel<float>, grid, dim3(256), 0, st, g);
+        hipLaunchKernelGGL(zgemm_k4_kernel<float>, grid, dim3(256), 0, st, g, xcd_remap());
 }
 
 int zgemm_workgroups(int M, int N, int batch) { return ((M + TM - 1) / TM) * ((N + TN - 1) / TN) * batch; }
