@@ -123,3 +123,20 @@ def test_completion_random_shapes():
         out, info = lib.tsvd_complete(to_gpu(torch, x * mask), to_gpu(torch, mask), 1e-2, 0.0, max_iter=6)
         assert info.iters == 6
         assert rel_fro(out.cpu().numpy(), ref["X"]) <= TOL, shape
+
+
+def test_completion_large_slices():
+    """256 x 200 slices, 33 of them: the warm-start and rebuild products have
+    528 tiles of 64 x 64 and take the tiled form (smaller products take the
+    split-K form), 4 warm-started iterations against the oracle."""
+    torch = torch_cuda()
+    rng = np.random.default_rng(256200)
+    a, b = rng.normal(size=(256, 6, 64)), rng.normal(size=(6, 200, 64))
+    x = np.fft.irfft(np.einsum("ikt,kjt->ijt", np.fft.rfft(a, axis=2), np.fft.rfft(b, axis=2)), n=64, axis=2)
+    x += 0.01 * rng.normal(size=x.shape)
+    mask = (rng.random(x.shape) < 0.4).astype(np.uint8)
+    ref = admm.complete(x * mask, mask, 1e-2, 1.1, 1e3, max_iter=4, tol=0.0)
+    announce("completion large slices", x.shape)
+    out, info = lib.tsvd_complete(to_gpu(torch, x * mask), to_gpu(torch, mask), 1e-2, 0.0, max_iter=4)
+    assert info.iters == 4
+    assert rel_fro(out.cpu().numpy(), ref["X"]) <= TOL
