@@ -419,7 +419,9 @@ __device__ __forceinline__ cplx<T> view_load(const cplx<T>* X, int ld, bool kcon
     return X[kcontig ? (int64_t)rc * ld + kc : (int64_t)kc * ld + rc];
 }
 
-template <typename T>
+// OPA, OPB: g.opA, g.opB as template arguments, so the operand layouts and
+// conjugations are fixed at compile time.
+template <typename T, int OPA, int OPB>
 __device__ __forceinline__ void zgemm_sk_body(const ZGemmArgs<T>& g, int bx, int by, int s) {
     typedef Mfma4<T> M;
     typedef typename M::acc_t acc_t;
@@ -430,8 +432,8 @@ __device__ __forceinline__ void zgemm_sk_body(const ZGemmArgs<T>& g, int bx, int
     const cplx<T>* A = g.A + (int64_t)s * g.sA;
     const cplx<T>* B = g.B + (int64_t)s * g.sB;
     const double* dk = g.dk ? g.dk + (int64_t)s * g.sdk : nullptr;
-    const bool akc = g.opA != 0, bkc = g.opB == 0;
-    const bool aconj = g.opA != 0, bconj = g.opB != 0;
+    constexpr bool akc = OPA != 0, bkc = OPB == 0;
+    constexpr bool aconj = OPA != 0, bconj = OPB != 0;
 
     acc_t cr[2][2], ci[2][2];
 #pragma unroll
@@ -551,12 +553,12 @@ __device__ __forceinline__ void grid_tile(int remap, int& bx, int& by, int& s) {
     bx = rem - by * gx;
 }
 
-template <typename T>
+template <typename T, int OPA, int OPB>
 __global__ __launch_bounds__(256) void zgemm_sk_kernel(ZGemmArgs<T> g, int remap) {
     if (g.ctrl && g.ctrl->done) return;
     int bx, by, s;
     grid_tile(remap, bx, by, s);
-    zgemm_sk_body<T>(g, bx, by, s);
+    zgemm_sk_body<T, OPA, OPB>(g, bx, by, s);
 }
 
 template <typename T>
@@ -632,6 +634,20 @@ int xcd_remap() {
 }
 
 template <typename T>
+void launch_split_k(const ZGemmArgs<T>& g, hipStream_t st) {
+    const dim3 grid((g.M + SKM - 1) / SKM, (g.N + SKN - 1) / SKN, g.batch);
+    const int r = xcd_remap();
+    if (g.opA == 0 && g.opB == 0)
+        hipLaunchKernelGGL((zgemm_sk_kernel<T, 0, 0>), grid, dim3(256), 0, st, g, r);
+    else if (g.opA == 0)
+        hipLaunchKernelGGL((zgemm_sk_kernel<T, 0, 1>), grid, dim3(256), 0, st, g, r);
+    else if (g.opB == 0)
+        hipLaunchKernelGGL((zgemm_sk_kernel<T, 1, 0>), grid, dim3(256), 0, st, g, r);
+    else
+        hipLaunchKernelGGL((zgemm_sk_kernel<T, 1, 1>), grid, dim3(256), 0, st, g, r);
+}
+
+template <typename T>
 bool use_split_k_of(const ZGemmArgs<T>& g) {
     static const int forced = env_or("TSVD_GEMM_SPLITK", -1);
     if (forced >= 0) return forced != 0;
@@ -644,8 +660,7 @@ bool use_split_k_of(const ZGemmArgs<T>& g) {
 template <>
 void launch_zgemm<double>(const ZGemmArgs<double>& g, hipStream_t st) {
     if (use_split_k_of(g)) {
-        dim3 grid((g.M + SKM - 1) / SKM, (g.N + SKN - 1) / SKN, g.batch);
-        hipLaunchKernelGGL(zgemm_sk_kernel<double>, grid, dim3(256), 0, st, g, xcd_remap());
+        launch_split_k(g, st);
         return;
     }
     dim3 grid((g.M + TM - 1) / TM, (g.N + TN - 1) / TN, g.batch);
@@ -655,8 +670,7 @@ void launch_zgemm<double>(const ZGemmArgs<double>& g, hipStream_t st) {
 template <>
 void launch_zgemm<float>(const ZGemmArgs<float>& g, hipStream_t st) {
     if (!g.bf16x3 && use_split_k_of(g)) {
-        dim3 grid((g.M + SKM - 1) / SKM, (g.N + SKN - 1) / SKN, g.batch);
-        hipLaunchKernelGGL(zgemm_sk_kernel<float>, grid, dim3(256), 0, st, g, xcd_remap());
+        launch_split_k(g, st);
         return;
     }
     dim3 grid((g.M + TM - 1) / TM, (g.N + TN - 1) / TN, g.batch);
