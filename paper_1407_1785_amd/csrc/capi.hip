@@ -256,9 +256,11 @@ SweepStats run_svt(tsvd_handle h, const Geometry& g, const SvtBuffers<T>& sb, in
             gg.sA = gg.sB = gg.sC = gg.sD = nn;
             gg.alpha = (T)1; gg.beta = (T)0; gg.opA = 1; gg.opB = 0; gg.batch = g.h;
             gg.ctrl = h->ctrl;
+            gg.herm = 1;
             prof_launch(h, K_GEMM, 8.0 * g.n * g.n * g.n * g.h, [&] { launch_zgemm(gg, st); });
             launch_check("gemm gram");
             ZGemmArgs<T> gn = gg;
+            gn.herm = 0;
             gn.A = sb.V[vc]; gn.B = sb.G; gn.D = sb.V[vc]; gn.C = sb.V[1 - vc];
             gn.alpha = (T)-0.5; gn.beta = (T)1.5; gn.opA = 0;
             prof_launch(h, K_GEMM, 8.0 * g.n * g.n * g.n * g.h, [&] { launch_zgemm(gn, st); });

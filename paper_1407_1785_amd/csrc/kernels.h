@@ -150,6 +150,9 @@ struct ZGemmArgs {
     int64_t sdk;
     const Ctrl* ctrl;      // optional: the product is skipped once ctrl->done
     int bf16x3;            // float only: 1 = bf16 split products, 0 = FP32 products
+    int herm;              // C = A^H A (B == A, opA = H, opB = N, no D): the split-K
+                           // form computes the tiles on and above the diagonal and
+                           // mirrors them; other forms compute every tile
 };
 
 template <typename T>

@@ -524,7 +524,10 @@ __device__ __forceinline__ void zgemm_sk_body(const ZGemmArgs<T>& g, int bx, int
         const int col = col0 + 16 * y + M::col(lane, v);
         const T re = g.alpha * sr + g.beta * dd[v].re;
         const T im = g.alpha * si + g.beta * dd[v].im;
-        if (row < g.M && col < g.N) C[(int64_t)col * g.ldc + row] = cplx<T>{re, im};
+        if (row < g.M && col < g.N) {
+            C[(int64_t)col * g.ldc + row] = cplx<T>{re, im};
+            if (g.herm && bx != by) C[(int64_t)row * g.ldc + col] = cplx<T>{re, -im};
+        }
     }
 }
 
@@ -553,11 +556,20 @@ __device__ __forceinline__ void grid_tile(int remap, int& bx, int& by, int& s) {
     bx = rem - by * gx;
 }
 
+// Tile (ti, tj), ti <= tj, of index t in the column-by-column enumeration of
+// the tiles on and above the diagonal: t = tj (tj + 1) / 2 + ti.
+__device__ __forceinline__ void upper_tile(int t, int& ti, int& tj) {
+    tj = 0;
+    while ((tj + 1) * (tj + 2) / 2 <= t) ++tj;
+    ti = t - tj * (tj + 1) / 2;
+}
+
 template <typename T, int OPA, int OPB>
 __global__ __launch_bounds__(256) void zgemm_sk_kernel(ZGemmArgs<T> g, int remap) {
     if (g.ctrl && g.ctrl->done) return;
     int bx, by, s;
     grid_tile(remap, bx, by, s);
+    if (g.herm) upper_tile(bx, bx, by);   // grid (tiles on and above the diagonal, 1, batch)
     zgemm_sk_body<T, OPA, OPB>(g, bx, by, s);
 }
 
@@ -634,8 +646,11 @@ int xcd_remap() {
 }
 
 template <typename T>
-void launch_split_k(const ZGemmArgs<T>& g, hipStream_t st) {
-    const dim3 grid((g.M + SKM - 1) / SKM, (g.N + SKN - 1) / SKN, g.batch);
+void launch_split_k(const ZGemmArgs<T>& gin, hipStream_t st) {
+    ZGemmArgs<T> g = gin;
+    g.herm = g.herm && g.M == g.N && g.A == g.B && g.opA != 0 && g.opB == 0 && !g.D && !g.dk ? 1 : 0;
+    const int tm = (g.M + SKM - 1) / SKM;
+    const dim3 grid = g.herm ? dim3(tm * (tm + 1) / 2, 1, g.batch) : dim3(tm, (g.N + SKN - 1) / SKN, g.batch);
     const int r = xcd_remap();
     if (g.opA == 0 && g.opB == 0)
         hipLaunchKernelGGL((zgemm_sk_kernel<T, 0, 0>), grid, dim3(256), 0, st, g, r);
