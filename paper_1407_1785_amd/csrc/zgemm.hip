@@ -405,8 +405,10 @@ __device__ __forceinline__ void zgemm_bf16x3_body(const ZGemmArgs<float>& g, int
 // a few dozen slices spreads over all compute units.
 
 constexpr int SKM = 32, SKN = 32;
-// MFMA k-steps (of 4) per load batch: 8 in FP32; 4 in FP64, which keeps the
-// kernel at two waves per SIMD (two workgroups per compute unit)
+// MFMA k-steps (of 4) per load batch: 8 in FP32, 4 in FP64.  With the
+// two-pass reduction (16 / 32 KB of LDS) and the launch bound below, both
+// fit three workgroups per compute unit, so the 528-660 workgroups of a batch
+// of 33 slices of up to 160 x 128 run in one round.
 template <typename T>
 constexpr int sk_batch() { return sizeof(T) == 8 ? 4 : 8; }
 
@@ -425,7 +427,7 @@ template <typename T, int OPA, int OPB>
 __device__ __forceinline__ void zgemm_sk_body(const ZGemmArgs<T>& g, int bx, int by, int s) {
     typedef Mfma4<T> M;
     typedef typename M::acc_t acc_t;
-    __shared__ T red[4][2][2][2][4][64];   // [wave][re, im][x][y][register][lane]
+    __shared__ T red[4][2][2][4][64];   // [wave][x][y][register][lane], one part at a time
     const int row0 = bx * SKM, col0 = by * SKN;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int l16 = lane & 15, lk = lane >> 4;
@@ -490,17 +492,28 @@ __device__ __forceinline__ void zgemm_sk_body(const ZGemmArgs<T>& g, int bx, int
         }
     }
 
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int y = 0; y < 2; ++y)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                red[w][0][x][y][v][lane] = cr[x][y][v];
-                red[w][1][x][y][v][lane] = ci[x][y][v];
-            }
-    __syncthreads();
+    // The four partial tiles are summed in a fixed order (quarter 0 first),
+    // the real parts first, then the imaginary parts through the same buffer.
     const int x = w & 1, y = w >> 1;
+    T sr[4], si[4];
+#pragma unroll
+    for (int part = 0; part < 2; ++part) {
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) red[w][a][b][v][lane] = part ? ci[a][b][v] : cr[a][b][v];
+        __syncthreads();
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            T t = red[0][x][y][v][lane];
+#pragma unroll
+            for (int q = 1; q < 4; ++q) t += red[q][x][y][v][lane];
+            (part ? si : sr)[v] = t;
+        }
+        if (part == 0) __syncthreads();
+    }
     const int row = row0 + 16 * x + l16;
     cplx<T>* C = g.C + (int64_t)s * g.sC;
     const cplx<T>* D = g.D ? g.D + (int64_t)s * g.sD : nullptr;
@@ -515,15 +528,9 @@ __device__ __forceinline__ void zgemm_sk_body(const ZGemmArgs<T>& g, int bx, int
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-        T sr = red[0][0][x][y][v][lane], si = red[0][1][x][y][v][lane];
-#pragma unroll
-        for (int q = 1; q < 4; ++q) {
-            sr += red[q][0][x][y][v][lane];
-            si += red[q][1][x][y][v][lane];
-        }
         const int col = col0 + 16 * y + M::col(lane, v);
-        const T re = g.alpha * sr + g.beta * dd[v].re;
-        const T im = g.alpha * si + g.beta * dd[v].im;
+        const T re = g.alpha * sr[v] + g.beta * dd[v].re;
+        const T im = g.alpha * si[v] + g.beta * dd[v].im;
         if (row < g.M && col < g.N) {
             C[(int64_t)col * g.ldc + row] = cplx<T>{re, im};
             if (g.herm && bx != by) C[(int64_t)row * g.ldc + col] = cplx<T>{re, -im};
@@ -565,7 +572,7 @@ __device__ __forceinline__ void upper_tile(int t, int& ti, int& tj) {
 }
 
 template <typename T, int OPA, int OPB>
-__global__ __launch_bounds__(256) void zgemm_sk_kernel(ZGemmArgs<T> g, int remap) {
+__global__ __launch_bounds__(256, 3) void zgemm_sk_kernel(ZGemmArgs<T> g, int remap) {
     if (g.ctrl && g.ctrl->done) return;
     int bx, by, s;
     grid_tile(remap, bx, by, s);
