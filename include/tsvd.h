@@ -32,8 +32,8 @@
  *           (dtype TSVD_F64 only).
  *
  * A handle is not thread safe: calls on one handle must not overlap, except
- * tsvd_submit / tsvd_poll / tsvd_serve_stats_read, which may be called from
- * any thread while the handle's serving worker runs.
+ * tsvd_submit / tsvd_poll / tsvd_cancel / tsvd_serve_stats_read, which may be
+ * called from any thread while the handle's serving worker runs.
  */
 #ifndef TSVD_H
 #define TSVD_H
@@ -55,7 +55,9 @@ typedef enum {
     TSVD_E_HIP = -4,       /* a HIP runtime call failed                     */
     TSVD_E_NONFINITE = -5, /* NaN or Inf met in the input or an iterate      */
     TSVD_E_UNSUPPORTED = -6, /* valid request this build does not serve      */
-    TSVD_E_BUSY = -7       /* tsvd_poll: the problem has not finished yet   */
+    TSVD_E_BUSY = -7,      /* tsvd_poll: the problem has not finished yet   */
+    TSVD_E_CANCELLED = -8, /* serving: the request was cancelled            */
+    TSVD_E_TIMEOUT = -9    /* serving: the request passed its deadline      */
 } tsvd_status;
 
 typedef enum { TSVD_F64 = 0, TSVD_F32 = 1 } tsvd_dtype;
@@ -71,6 +73,45 @@ typedef struct {
     int64_t n[4];  /* n1, n2, n3[, n4]; unused entries ignored */
 } tsvd_shape;
 
+/* Solver state, for checkpoint and resume of the single-problem solvers.
+ *
+ * The state after k iterations of the completion ADMM (Sec. 4) is the
+ * iterate pair (Z, Q) with Q the scaled dual, the penalty rho of the next
+ * iteration, and the factor by which the stored dual is still to be
+ * multiplied (the rescale rho_k / rho_{k+1} of the penalty schedule is
+ * applied lazily); for tensor RPCA (Sec. 5) it is (L, S, W) with mu.  The
+ * right singular vectors of every Fourier slice of the last prox are the
+ * Jacobi warm start of the next one: with them, k iterations plus N - k
+ * resumed iterations give bit for bit the N-iteration result; without them
+ * the first resumed SVDs start cold, which changes the iterates by rounding
+ * only.
+ *
+ * All pointers are DEVICE arrays owned by the caller.  z, dual, s: the
+ * tensor's shape and element type (z = Z or L; dual = Q or W, stored
+ * values; s = S, RPCA only, else NULL).  v: NULL, or h slices of n x n
+ * complex values (interleaved re, im) of the element type, column-major,
+ * n = min(n1, n2), h as in the file header.
+ * load = 1: the solve starts from this state (iter, penalty and dual_scale
+ *   included); load = 0: it starts from zero iterates, as Sec. 4 / Sec. 5
+ *   do, with the penalty argument of the call.
+ * save = 1: on return the buffers hold the state after the last iteration
+ *   run, penalty the next iteration's, dual_scale the pending dual factor,
+ *   iter the iterations run in total (this call's added to iter on load).
+ * Errors: TSVD_E_INVALID for a null z or dual (or s in RPCA), a penalty or
+ *   dual_scale that is not finite and > 0 on load, or iter < 0. */
+typedef struct {
+    void* z;
+    void* dual;
+    void* s;
+    void* v;
+    double penalty;
+    double dual_scale;
+    int32_t iter;
+    int32_t load;
+    int32_t save;
+    int32_t pad;
+} tsvd_state;
+
 /* ADMM options.  A NULL pointer means the defaults below. */
 typedef struct {
     double growth;        /* penalty growth per iteration (default 1.1 for
@@ -79,7 +120,10 @@ typedef struct {
     int32_t max_iter;     /* iteration cap (default 300 completion, 500 RPCA) */
     int32_t precision;    /* tsvd_precision (default TSVD_PREC_FP64)          */
     int32_t max_sweeps;   /* Jacobi sweep cap per SVD (default 30)            */
-    int32_t reserved;     /* must be 0                                        */
+    int32_t pad;          /* must be 0                                        */
+    tsvd_state* state;    /* NULL, or warm start / checkpoint of the solver
+                             (tsvd_complete and trpca only; the batched and
+                             served forms reject a non-NULL state)            */
 } tsvd_admm_opts;
 
 /* Per-solve report (host struct filled on return). */
@@ -209,12 +253,25 @@ tsvd_status tsvd_compress(tsvd_handle h, const void* M, tsvd_shape shape, tsvd_d
  * Profiling adds a synchronisation after every launch group; it is for
  * measurement runs, not production runs. */
 typedef struct {
-    char name[32];        /* kernel family, e.g. "jacobi_cross"            */
+    char name[32];        /* kernel family, e.g. "jacobi_persistent"       */
     int64_t launches;     /* launches timed                                */
     double total_ms;      /* summed event time                             */
     double work;          /* summed algorithmic bytes or flops             */
     int32_t work_is_bytes;
     int32_t reserved;
+    /* Jacobi families: summed over launches and slices, the sweeps run,
+     * the column pairs visited and the rotations applied (0 elsewhere).
+     * Their `work` is n (n - 1) / 2 (28 m + 20 n) flops per slice sweep
+     * (one complex dot product of the m slice rows plus two rotated columns
+     * of m + n stacked rows, per pair), whatever the rotations applied. */
+    double slice_sweeps;
+    double pairs_visited;
+    double rotations;
+    /* svt_rebuild: summed over launches and slices, the kept rank r_k (the
+     * singular values above tau, the multi-rank of Sec. 2.4); the product
+     * runs over all n columns with the dropped ones weighted by 0, and its
+     * `work` counts 8 m n^2 flops per slice (0 elsewhere). */
+    double kept_rank;
 } tsvd_kernel_stat;
 
 /* enable = 1 clears the statistics and starts timing; 0 stops timing
@@ -267,6 +324,11 @@ typedef struct {
                               precision field is ignored                        */
     void* out;             /* completion: X_out; RPCA: L_out                    */
     void* out_s;           /* RPCA: S_out                                       */
+    double deadline_s;     /* serving: seconds after tsvd_submit after which an
+                              unfinished request stops with TSVD_E_TIMEOUT and
+                              leaves its outputs unspecified (0: none); the
+                              worker checks it between iterations.  Ignored
+                              by tsvd_batch_run.  >= 0                          */
 } tsvd_problem;
 
 /* Solve `count` problems together and return when all have stopped.
@@ -292,10 +354,21 @@ tsvd_status tsvd_batch_run(tsvd_handle h, const tsvd_problem* probs, int32_t cou
 tsvd_status tsvd_submit(tsvd_handle h, const tsvd_problem* prob, uint64_t* ticket_host);
 
 /* TSVD_E_BUSY while the ticket is queued or running; otherwise the
- * problem's final status (TSVD_OK, TSVD_E_NONFINITE, ...), with *info_host
- * filled (seconds = time from submission to completion) when not NULL.  A
- * finished ticket can be polled again; an unknown ticket is TSVD_E_INVALID. */
+ * problem's final status (TSVD_OK, TSVD_E_NONFINITE, TSVD_E_CANCELLED,
+ * TSVD_E_TIMEOUT, ...), with *info_host filled (seconds = time from
+ * submission to completion) when not NULL.  A finished ticket can be polled
+ * again; an unknown ticket is TSVD_E_INVALID.  After a device failure ends
+ * the serving worker, every ticket it had not finished (queued or running)
+ * reports the failure's status (e.g. TSVD_E_HIP). */
 tsvd_status tsvd_poll(tsvd_handle h, uint64_t ticket, tsvd_info* info_host);
+
+/* Cancel a queued or running request.  Its status becomes TSVD_E_CANCELLED
+ * (a request that has already finished keeps its status); a running request
+ * leaves the batch at the worker's next period boundary, and its outputs are
+ * unspecified.  The caller must keep the request's tensors alive until
+ * tsvd_poll reports it finished.  Errors: TSVD_E_INVALID for an unknown
+ * ticket. */
+tsvd_status tsvd_cancel(tsvd_handle h, uint64_t ticket);
 
 /* Serving counters (host struct). */
 typedef struct {

@@ -10,6 +10,11 @@ arguments follow the C ABI in ``include/tsvd.h``:
     trpca(X, lam, mu, tol)                -> (L, S, info)
     batch_run([problem, ...])             -> [(status, info), ...]
     submit(problem) -> ticket;  poll(ticket) -> None | (status, info)
+    cancel(ticket)
+
+``SolverState`` holds the checkpoint of a solve (``tsvd_state``): pass it as
+``state=`` to ``tsvd_complete`` / ``trpca`` with ``save=True`` to keep the
+final iterates, and with ``load=True`` to resume from them.
 
 Problems for the batched and served forms are built with
 ``complete_problem`` / ``trpca_problem``, which allocate their outputs.
@@ -20,15 +25,18 @@ still works, but every call raises ``LibraryNotBuilt``.
 
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 import threading
+import weakref
 
 __all__ = [
     "LibraryNotBuilt", "TsvdError", "Info", "library_path", "load_library", "tsvt",
     "tsvd_complete", "trpca", "Handle", "PREC_FP64", "PREC_FP32", "SHRINK_L1", "SHRINK_L112",
     "Problem", "complete_problem", "trpca_problem", "batch_run", "submit", "poll", "serve_stats",
-    "tsvd_factors", "compress", "COMPRESS_TSVD", "COMPRESS_TUBAL",
+    "tsvd_factors", "compress", "COMPRESS_TSVD", "COMPRESS_TUBAL", "SolverState", "cancel",
+    "close_all",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -39,8 +47,9 @@ SHRINK_L1, SHRINK_L112 = 0, 1
 COMPRESS_TSVD, COMPRESS_TUBAL = 1, 2
 
 STATUS = {0: "TSVD_OK", -1: "TSVD_E_INVALID", -2: "TSVD_E_SHAPE", -3: "TSVD_E_NOMEM",
-          -4: "TSVD_E_HIP", -5: "TSVD_E_NONFINITE", -6: "TSVD_E_UNSUPPORTED", -7: "TSVD_E_BUSY"}
-E_BUSY = -7
+          -4: "TSVD_E_HIP", -5: "TSVD_E_NONFINITE", -6: "TSVD_E_UNSUPPORTED", -7: "TSVD_E_BUSY",
+          -8: "TSVD_E_CANCELLED", -9: "TSVD_E_TIMEOUT"}
+E_BUSY, E_CANCELLED, E_TIMEOUT = -7, -8, -9
 KIND_COMPLETE, KIND_TRPCA = 0, 1
 
 
@@ -58,10 +67,18 @@ class Shape(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_int32), ("n", ctypes.c_int64 * 4)]
 
 
+class StateRecord(ctypes.Structure):
+    _fields_ = [("z", ctypes.c_void_p), ("dual", ctypes.c_void_p), ("s", ctypes.c_void_p),
+                ("v", ctypes.c_void_p), ("penalty", ctypes.c_double), ("dual_scale", ctypes.c_double),
+                ("iter", ctypes.c_int32), ("load", ctypes.c_int32), ("save", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
+
+
 class AdmmOpts(ctypes.Structure):
     _fields_ = [("growth", ctypes.c_double), ("rho_max", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("max_sweeps", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("max_sweeps", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("state", ctypes.POINTER(StateRecord))]
 
 
 class Info(ctypes.Structure):
@@ -77,7 +94,9 @@ class Info(ctypes.Structure):
 class KernelStat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64),
                 ("total_ms", ctypes.c_double), ("work", ctypes.c_double),
-                ("work_is_bytes", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("work_is_bytes", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("slice_sweeps", ctypes.c_double), ("pairs_visited", ctypes.c_double),
+                ("rotations", ctypes.c_double), ("kept_rank", ctypes.c_double)]
 
 
 class ProblemRecord(ctypes.Structure):
@@ -85,7 +104,7 @@ class ProblemRecord(ctypes.Structure):
                 ("shrink", ctypes.c_int32), ("shape", Shape), ("x", ctypes.c_void_p),
                 ("mask", ctypes.c_void_p), ("penalty", ctypes.c_double), ("lam", ctypes.c_double),
                 ("tol", ctypes.c_double), ("opts", AdmmOpts), ("out", ctypes.c_void_p),
-                ("out_s", ctypes.c_void_p)]
+                ("out_s", ctypes.c_void_p), ("deadline_s", ctypes.c_double)]
 
 
 class ServeStats(ctypes.Structure):
@@ -133,6 +152,7 @@ _SIGNATURES = {
     "tsvd_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ProblemRecord),
                                    ctypes.POINTER(ctypes.c_uint64)]),
     "tsvd_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(Info)]),
+    "tsvd_cancel": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
     "tsvd_serve_stats_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ServeStats)]),
     "tsvd_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "tsvd_last_error": (ctypes.c_char_p, []),
@@ -174,6 +194,7 @@ class Handle:
         self._h = h
         self.device = int(device)
         self._served = {}   # ticket -> Problem, kept alive until finished
+        _all_handles.add(self)
 
     @property
     def ptr(self):
@@ -194,10 +215,14 @@ class Handle:
         for k in range(min(cnt.value, cap)):
             st = buf[k]
             out[st.name.decode()] = dict(launches=st.launches, total_ms=st.total_ms, work=st.work,
-                                         work_is_bytes=bool(st.work_is_bytes))
+                                         work_is_bytes=bool(st.work_is_bytes), slice_sweeps=st.slice_sweeps,
+                                         pairs_visited=st.pairs_visited, rotations=st.rotations,
+                                         kept_rank=st.kept_rank)
         return out
 
     def close(self):
+        """Destroy the library handle: stops its serving worker (joining the
+        thread) and frees its device memory.  Idempotent."""
         self._served = {}
         if self._h:
             load_library().tsvd_destroy(self._h)
@@ -211,6 +236,23 @@ class Handle:
 
 
 _handles: dict[int, Handle] = {}
+_all_handles = weakref.WeakSet()
+
+
+def close_all():
+    """Close every open handle (the module's shared ones and those made by
+    callers).  Registered with atexit, so the serving workers are joined and
+    the device memory freed while the HIP runtime is still loaded, not from
+    a finaliser at interpreter teardown."""
+    for h in list(_all_handles):
+        try:
+            h.close()
+        except Exception:
+            pass
+    _handles.clear()
+
+
+atexit.register(close_all)
 
 
 def handle_for(tensor) -> Handle:
@@ -265,15 +307,59 @@ def _bind_stream(handle: Handle, tensor):
     _check(load_library().tsvd_set_stream(handle.ptr, ctypes.c_void_p(stream.cuda_stream)))
 
 
-def _opts(growth, rho_max, max_iter, precision, max_sweeps):
+def _opts(growth, rho_max, max_iter, precision, max_sweeps, state=None):
     o = AdmmOpts()
     o.growth = float(growth or 0.0)
     o.rho_max = float(rho_max or 0.0)
     o.max_iter = int(max_iter or 0)
     o.precision = int(precision)
     o.max_sweeps = int(max_sweeps or 0)
-    o.reserved = 0
+    o.pad = 0
+    if state is not None:
+        o.state = ctypes.pointer(state.record)
     return o
+
+
+class SolverState:
+    """Checkpoint of a completion (Z, Q) or RPCA (L, S, W) solve, with the
+    Fourier-domain right singular vectors of the last prox (the Jacobi warm
+    start; ``with_v=False`` leaves them out, and a resumed solve then starts
+    its first SVDs cold).  Owns its device tensors (``z``, ``dual``, ``s``,
+    ``v``) and the ``tsvd_state`` record; ``penalty``, ``dual_scale`` and
+    ``iter`` mirror the record's fields."""
+
+    def __init__(self, like, rpca: bool = False, with_v: bool = True):
+        import torch
+
+        like = _prepare(like, "like")
+        self.z = torch.zeros_like(like)
+        self.dual = torch.zeros_like(like)
+        self.s = torch.zeros_like(like) if rpca else None
+        n = min(like.shape[0], like.shape[1])
+        self.v = (torch.zeros((_n_slices(like), n, n, 2), dtype=like.dtype, device=like.device)
+                  if with_v else None)
+        r = StateRecord()
+        r.z, r.dual = self.z.data_ptr(), self.dual.data_ptr()
+        r.s = self.s.data_ptr() if self.s is not None else None
+        r.v = self.v.data_ptr() if self.v is not None else None
+        r.penalty, r.dual_scale = 1.0, 1.0
+        self.record = r
+
+    def _arm(self, load: bool, save: bool):
+        self.record.load = 1 if load else 0
+        self.record.save = 1 if save else 0
+
+    @property
+    def penalty(self):
+        return self.record.penalty
+
+    @property
+    def dual_scale(self):
+        return self.record.dual_scale
+
+    @property
+    def iter(self):
+        return self.record.iter
 
 
 def _n_slices(tensor) -> int:
@@ -343,8 +429,11 @@ def compress(M, method: int, k: int, precision: int = PREC_FP64, handle: Handle 
 
 def tsvd_complete(X_obs, mask, rho: float = 1e-2, tol: float = 1e-8, growth: float = 1.1,
                   rho_max: float = 1e3, max_iter: int = 300, precision: int = PREC_FP64,
-                  max_sweeps: int = 0, handle: Handle | None = None):
-    """TNN completion (include/tsvd.h, ``tsvd_complete``).  Returns (X, info)."""
+                  max_sweeps: int = 0, handle: Handle | None = None, state: SolverState | None = None,
+                  load: bool = False, save: bool = True):
+    """TNN completion (include/tsvd.h, ``tsvd_complete``).  Returns (X, info).
+    With ``state``: start from it if ``load``, write the final state into it
+    if ``save``."""
     import torch
 
     X_obs = _prepare(X_obs, "X_obs")
@@ -357,7 +446,9 @@ def tsvd_complete(X_obs, mask, rho: float = 1e-2, tol: float = 1e-8, growth: flo
     _bind_stream(handle, X_obs)
     out = torch.empty_like(X_obs)
     info = Info()
-    opts = _opts(growth, rho_max, max_iter, precision, max_sweeps)
+    if state is not None:
+        state._arm(load, save)
+    opts = _opts(growth, rho_max, max_iter, precision, max_sweeps, state)
     _check(load_library().tsvd_complete(handle.ptr, ctypes.c_void_p(X_obs.data_ptr()),
                                         ctypes.c_void_p(mask.data_ptr()), _shape(X_obs),
                                         _dtype_code(X_obs), float(rho), float(tol),
@@ -368,8 +459,10 @@ def tsvd_complete(X_obs, mask, rho: float = 1e-2, tol: float = 1e-8, growth: flo
 
 def trpca(X, lam: float, mu: float = 1e-3, tol: float = 1e-7, shrink: int = SHRINK_L1,
           growth: float = 1.2, mu_max: float = 1e10, max_iter: int = 500,
-          precision: int = PREC_FP64, max_sweeps: int = 0, handle: Handle | None = None):
-    """Tensor robust PCA (include/tsvd.h, ``trpca``).  Returns (L, S, info)."""
+          precision: int = PREC_FP64, max_sweeps: int = 0, handle: Handle | None = None,
+          state: SolverState | None = None, load: bool = False, save: bool = True):
+    """Tensor robust PCA (include/tsvd.h, ``trpca``).  Returns (L, S, info).
+    ``state`` as for ``tsvd_complete``."""
     import torch
 
     X = _prepare(X, "X")
@@ -378,7 +471,9 @@ def trpca(X, lam: float, mu: float = 1e-3, tol: float = 1e-7, shrink: int = SHRI
     L = torch.empty_like(X)
     S = torch.empty_like(X)
     info = Info()
-    opts = _opts(growth, mu_max, max_iter, precision, max_sweeps)
+    if state is not None:
+        state._arm(load, save)
+    opts = _opts(growth, mu_max, max_iter, precision, max_sweeps, state)
     _check(load_library().trpca(handle.ptr, ctypes.c_void_p(X.data_ptr()), _shape(X),
                                 _dtype_code(X), float(lam), float(mu), float(tol), int(shrink),
                                 ctypes.byref(opts), ctypes.c_void_p(L.data_ptr()),
@@ -392,7 +487,7 @@ class Problem:
     ``out_s`` = S) and keeps its inputs alive."""
 
     def __init__(self, kind, x, mask=None, penalty=1e-2, lam=0.0, tol=1e-8, shrink=SHRINK_L1,
-                 growth=0.0, rho_max=0.0, max_iter=0, precision=None, max_sweeps=0):
+                 growth=0.0, rho_max=0.0, max_iter=0, precision=None, max_sweeps=0, deadline_s=0.0):
         import torch
 
         self.kind = int(kind)
@@ -424,6 +519,7 @@ class Problem:
         rec.opts = _opts(growth, rho_max, max_iter, precision, max_sweeps)
         rec.out = self.out.data_ptr()
         rec.out_s = self.out_s.data_ptr() if self.out_s is not None else None
+        rec.deadline_s = float(deadline_s)
         self.record = rec
 
     @property
@@ -432,15 +528,15 @@ class Problem:
 
 
 def complete_problem(X_obs, mask, rho=1e-2, tol=1e-8, growth=1.1, rho_max=1e3, max_iter=300,
-                     precision=None, max_sweeps=0) -> Problem:
+                     precision=None, max_sweeps=0, deadline_s=0.0) -> Problem:
     return Problem(KIND_COMPLETE, X_obs, mask, rho, 0.0, tol, SHRINK_L1, growth, rho_max, max_iter,
-                   precision, max_sweeps)
+                   precision, max_sweeps, deadline_s)
 
 
 def trpca_problem(X, lam, mu=1e-3, tol=1e-7, shrink=SHRINK_L1, growth=1.2, mu_max=1e10, max_iter=500,
-                  precision=None, max_sweeps=0) -> Problem:
+                  precision=None, max_sweeps=0, deadline_s=0.0) -> Problem:
     return Problem(KIND_TRPCA, X, None, mu, lam, tol, shrink, growth, mu_max, max_iter, precision,
-                   max_sweeps)
+                   max_sweeps, deadline_s)
 
 
 def _sync_inputs(problems):
@@ -486,10 +582,19 @@ def poll(ticket: int, handle: Handle | None = None, device: int = 0):
     st = load_library().tsvd_poll(handle.ptr, ctypes.c_uint64(int(ticket)), ctypes.byref(info))
     if st == E_BUSY:
         return None
-    if st not in (0, -5):
+    if st == -1:
         _check(st)
     handle._served.pop(int(ticket), None)
     return st, info
+
+
+def cancel(ticket: int, handle: Handle | None = None, device: int = 0):
+    """Cancel a queued or running request (``tsvd_cancel``); poll() then
+    reports E_CANCELLED unless it had already finished."""
+    handle = handle or _handles.get(device)
+    if handle is None:
+        raise TsvdError(-1, "no handle")
+    _check(load_library().tsvd_cancel(handle.ptr, ctypes.c_uint64(int(ticket))))
 
 
 def serve_stats(handle: Handle | None = None, device: int = 0) -> dict:

@@ -222,6 +222,7 @@ template void launch_complete_output<double>(const double*, const uint8_t*, cons
                                              hipStream_t);
 template void launch_fill<double>(double*, double, int64_t, hipStream_t);
 template void launch_fill<int>(int*, int, int64_t, hipStream_t);
+template void launch_fill<long long>(long long*, long long, int64_t, hipStream_t);
 
 template void launch_sumsq<float>(const float*, const uint8_t*, int64_t, double*, int, hipStream_t);
 template void launch_complete_output<float>(const float*, const uint8_t*, const float*,

@@ -50,11 +50,20 @@ struct SvtBuffers {
     int* rank;
     int* rot;
     int* sweeps;
-    int* pbar;        // persistent Jacobi: h barrier counters, 3h flags, 1 error word, h x nb block flags
+    int* pbar;        // persistent Jacobi: h barrier counters, 3h flags, the error word, the role
+                      // ticket, h x nb block flags
     double* partials;
     int nparts;
     double* tall;     // tall slices: the Jacobi partial sums (jacobi_tall_plan)
+    // after a persistent launch that gave up (error word set): the one-
+    // workgroup-per-slice kernel finishes the SVD; entry 2 (work == Z) + vc
+    // of the table, and the problem-table start {0, h}
+    JacSliceArgs<T>* ftab;
+    int* fws;
 };
+
+// pbar words of a geometry: barriers, rotation flags, error word, ticket, block flags
+inline int64_t pbar_words(const Geometry& g) { return 4 * (int64_t)g.h + 2 + (int64_t)g.h * (g.n + 2); }
 
 // Warm-start state carried across the iterations of one solve.
 struct WarmState {
@@ -74,8 +83,9 @@ size_t svt_bytes(const Geometry& g, int nparts) {
     b += 3 * vv * sizeof(cplx<T>) + 768;
     b += 2 * (int64_t)g.h * g.n * sizeof(double) + 512;
     b += (int64_t)g.h * 5 * sizeof(int) + 768;
-    b += (int64_t)(4 * g.h + 1 + (int64_t)g.h * (g.n + 2)) * sizeof(int) + 256;
+    b += pbar_words(g) * sizeof(int) + 256;
     b += (int64_t)nparts * kNumPartials * sizeof(double) + 256;
+    b += 4 * sizeof(JacSliceArgs<T>) + 2 * sizeof(int) + 512;
     if (jacobi_tall(g.m, g.n, sizeof(T))) b += jacobi_tall_plan(g.m, g.n, g.h).part_doubles * sizeof(double) + 256;
     return b;
 }
@@ -95,11 +105,13 @@ SvtBuffers<T> carve_svt(Carver& c, const Geometry& g, int nparts) {
     s.rank = c.take<int>(g.h);
     s.rot = c.take<int>(3 * g.h);
     s.sweeps = c.take<int>(g.h);
-    s.pbar = c.take<int>(4 * g.h + 1 + (int64_t)g.h * (g.n + 2));
+    s.pbar = c.take<int>(pbar_words(g));
     s.partials = c.take<double>((int64_t)nparts * kNumPartials);
     s.nparts = nparts;
     s.tall = jacobi_tall(g.m, g.n, sizeof(T)) ? c.take<double>(jacobi_tall_plan(g.m, g.n, g.h).part_doubles)
                                               : nullptr;
+    s.ftab = c.take<JacSliceArgs<T>>(4);
+    s.fws = c.take<int>(2);
     return s;
 }
 
@@ -122,6 +134,51 @@ void ensure_host_ints(tsvd_handle h, int count) {
     hip_check(hipHostMalloc(reinterpret_cast<void**>(&h->host_ints), sizeof(int) * count, 0),
               "hipHostMalloc");
     h->host_ints_len = count;
+}
+
+void* ensure_host_stage(tsvd_handle h, size_t bytes) {
+    if (bytes > h->host_stage_len) {
+        if (h->host_stage) hip_check(hipHostFree(h->host_stage), "hipHostFree");
+        h->host_stage = nullptr;
+        hip_check(hipHostMalloc(&h->host_stage, bytes, 0), "hipHostMalloc");
+        h->host_stage_len = bytes;
+    }
+    return h->host_stage;
+}
+
+// The argument table of the fallback after a persistent Jacobi launch that
+// gave up: the one-workgroup-per-slice kernel on the same slices (work
+// buffer A or Z, V buffer 0 or 1), gated on the persistent kernel's error
+// word.  Uploaded once per call; sets the kernel's LDS limit.
+template <typename T>
+void upload_fallback(tsvd_handle h, const Geometry& g, const SvtBuffers<T>& sb, int max_sweeps) {
+    if (!jacobi_persistent_fits(g.m, g.n, g.h, sizeof(T), h->cus, h->lds_cap)) return;
+    JacSliceArgs<T> tab[4];
+    for (int k = 0; k < 4; ++k) {
+        JacSliceArgs<T>& a = tab[k];
+        a = JacSliceArgs<T>{};
+        a.A = k >= 2 ? sb.Z : sb.A;
+        a.V = sb.V[k & 1];
+        a.m = g.m;
+        a.n = g.n;
+        a.h = g.h;
+        a.nb = jacobi_persistent_blocks(g.n);
+        a.tol = (T)jacobi_tol(g.m, sizeof(T));
+        a.sweeps = sb.sweeps;
+        a.ctrl = h->ctrl;
+        a.rotations = h->rot_counter + 1;
+        a.max_sweeps = max_sweeps;
+        a.only_if = sb.pbar + 4 * g.h;
+    }
+    const int ws[2] = {0, g.h};
+    char* stage = static_cast<char*>(ensure_host_stage(h, sizeof(tab) + sizeof(ws)));
+    std::memcpy(stage, tab, sizeof(tab));
+    std::memcpy(stage + sizeof(tab), ws, sizeof(ws));
+    hip_check(hipMemcpyAsync(sb.ftab, stage, sizeof(tab), hipMemcpyHostToDevice, h->stream), "hipMemcpyAsync");
+    hip_check(hipMemcpyAsync(sb.fws, stage + sizeof(tab), sizeof(ws), hipMemcpyHostToDevice, h->stream),
+              "hipMemcpyAsync");
+    hip_check(prepare_jacobi_slice<T>(16, jacobi_slice_rpt(g.m, g.n)), "jacobi fallback attribute");
+    hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
 }
 
 // The DFT matrices of the tube shape of g in the element type, cached on
@@ -173,6 +230,9 @@ void prof_harvest(tsvd_handle h) {
         g.launches += 1;
         g.ms += ms;
         g.work += p.work;
+        g.sweeps += p.sweeps;
+        g.pairs += p.pairs;
+        g.kept += p.kept;
         h->ev_pool.push_back(p.a);
         h->ev_pool.push_back(p.b);
     }
@@ -234,9 +294,11 @@ struct SweepStats {
 // Jacobi sweeps + shrink + rebuild on the slices in sb.A; output in sb.Z.
 //
 // Work model of the Jacobi kernels (FP operations): every visited column
-// pair costs 16 m (the three dot products over the m slice rows), and every
-// applied rotation another 16 (m + n) (the 2 x 2 complex update of the m
-// slice rows and n V rows of both columns).
+// pair costs 28 m + 20 n, one complex dot product over the m slice rows
+// (8 m) plus the 2 x 2 complex rotation of both columns' m slice rows and
+// n V rows (20 (m + n)), whether or not the rotation is applied; a slice
+// sweep visits n (n - 1) / 2 pairs.  Slice sweeps, visited pairs and applied
+// rotations are recorded beside it.
 template <typename T>
 SweepStats run_svt(tsvd_handle h, const Geometry& g, const SvtBuffers<T>& sb, int max_sweeps,
                    WarmState* warm = nullptr, bool want_rank = false, bool rebuild = true) {
@@ -299,54 +361,46 @@ SweepStats run_svt(tsvd_handle h, const Geometry& g, const SvtBuffers<T>& sb, in
     const int check_every = std::max(1, env_int("TSVD_CHECK_EVERY", 1));
     ensure_host_ints(h, g.h);
     SweepStats stats;
-    const double dot_flops = 16.0 * g.m;
-    const int xcds = env_int("TSVD_XCD", 0);
+    const double pair_flops = 28.0 * g.m + 20.0 * g.n;
+    const double slice_pairs = 0.5 * g.n * (g.n - 1.0);
     const bool persist = env_int("TSVD_PERSIST", 1) != 0 &&
-                         jacobi_persistent_fits(g.m, g.n, g.h, sizeof(T), h->cus, h->lds_cap, xcds);
+                         jacobi_persistent_fits(g.m, g.n, g.h, sizeof(T), h->cus, h->lds_cap);
     bool done_persist = false;
     if (persist) {
-        // one launch runs every sweep (TSVD_COOP=1: a cooperative launch)
+        // one launch runs every sweep
         ja.nb = jacobi_persistent_blocks(g.n);
         ja.rotations = h->rot_counter + 1;
-        // the init also clears the barrier counters, rotation flags and block
-        // flags (the error word between them is cleared per call)
+        // the init also clears the barrier counters, rotation flags, role
+        // ticket and block flags (the error word is cleared once per call)
         ja.clr[0] = sb.pbar;
         ja.nclr[0] = 4 * g.h;
         ja.clr[1] = sb.pbar + 4 * g.h + 1;
-        ja.nclr[1] = g.h * ja.nb;
+        ja.nclr[1] = 1 + g.h * ja.nb;
         prof_launch(h, K_JAC_INIT, (double)g.h * g.n * g.n * sizeof(cplx<T>),
                     [&] { launch_jacobi_init(ja, st); });
         launch_check("jacobi_init");
         ja.clr[0] = ja.clr[1] = nullptr;
-        PersistArgs pa{sb.pbar, sb.pbar + g.h, sb.pbar + 4 * g.h, sb.pbar + 4 * g.h + 1, max_sweeps, nullptr,
-                       env_int("TSVD_COOP", 0) != 0 ? 1 : 0, xcds, env_int("TSVD_SPREAD", 0)};
-        static long long* trace_buf = nullptr;
-        const bool tracing = env_int("TSVD_TRACE", 0) != 0;
-        if (tracing) {
-            if (!trace_buf) hip_check(hipMalloc(&trace_buf, 64 * sizeof(long long)), "hipMalloc trace");
-            hip_check(hipMemsetAsync(trace_buf, 0, 64 * sizeof(long long), st), "hipMemsetAsync trace");
-            pa.trace = trace_buf;
-        }
+        PersistArgs pa{};
+        pa.pbar = sb.pbar;
+        pa.max_sweeps = max_sweeps;
+        // about a second of polling; TSVD_PERSIST_SPIN lowers it (tests of the fallback)
+        pa.spin_limit = std::max(0, env_int("TSVD_PERSIST_SPIN", 1 << 21));
+        pa.spread = env_int("TSVD_SPREAD", 0);
         hipError_t e = hipSuccess;
         const int ip = prof_launch(h, K_JAC_PERSIST, 0.0,
                                    [&] { e = launch_jacobi_persistent(ja, pa, h->cus, st); });
-        if (e == hipSuccess && tracing) {
-            long long tb[64];
-            hip_check(hipMemcpyAsync(tb, trace_buf, sizeof(tb), hipMemcpyDeviceToHost, st), "trace copy");
-            hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
-            int rate_khz = 0;
-            (void)hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, h->device);
-            std::fprintf(stderr, "[tsvd trace] us since start:");
-            for (int i = 1; i < 64 && tb[i]; ++i)
-                std::fprintf(stderr, " %.1f", (double)(tb[i] - tb[0]) * 1e3 / (double)rate_khz);
-            std::fprintf(stderr, "\n");
+        if (e == hipSuccess) {
+            // finishes the SVD only if a wait of the persistent launch gave up
+            hip_check(launch_jacobi_slice<T>(16, jacobi_slice_rpt(g.m, g.n), sb.ftab + (work == sb.Z ? 2 : 0) + vc,
+                                             sb.fws, 1, g.h, max_sweeps, st),
+                      "jacobi fallback");
         }
         if (e == hipSuccess) {
             done_persist = true;
             stats.sweeps = -1;   // known on the device only
             stats.on_device = true;
             if (h->prof_on) {
-                // visited pairs: n(n-1)/2 per slice per sweep run
+                // n(n-1)/2 visited pairs per slice per sweep run
                 hip_check(hipMemcpyAsync(h->host_ints, sb.sweeps, sizeof(int) * g.h, hipMemcpyDeviceToHost, st),
                           "hipMemcpyAsync sweeps");
                 hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
@@ -356,7 +410,11 @@ SweepStats run_svt(tsvd_handle h, const Geometry& g, const SvtBuffers<T>& sb, in
                     sw += h->host_ints[s];
                     smax = std::max(smax, h->host_ints[s]);
                 }
-                if (ip >= 0) h->pending[ip].work = dot_flops * (double)sw * g.n * (g.n - 1) / 2.0;
+                if (ip >= 0) {
+                    h->pending[ip].work = pair_flops * slice_pairs * (double)sw;
+                    h->pending[ip].sweeps = (double)sw;
+                    h->pending[ip].pairs = slice_pairs * (double)sw;
+                }
                 stats.sweeps = smax;
             }
         } else {
@@ -381,8 +439,12 @@ SweepStats run_svt(tsvd_handle h, const Geometry& g, const SvtBuffers<T>& sb, in
             ja.sweep = sw;
             for (int r = 0; r < tp.players - 1; ++r) {
                 ja.round = r;
-                prof_launch(h, K_JAC_CROSS, dot_flops * g.h * (tp.players / 2),
-                            [&] { launch_jacobi_tall_round(ja, tp, sb.tall, st); });
+                const int ip = prof_launch(h, K_JAC_CROSS, pair_flops * g.h * (tp.players / 2),
+                                           [&] { launch_jacobi_tall_round(ja, tp, sb.tall, st); });
+                if (ip >= 0) {
+                    h->pending[ip].pairs = (double)g.h * (tp.players / 2);
+                    if (r == 0) h->pending[ip].sweeps = g.h;
+                }
                 launch_check("jacobi_tall");
             }
             stats.sweeps = sw + 1;
@@ -407,14 +469,19 @@ SweepStats run_svt(tsvd_handle h, const Geometry& g, const SvtBuffers<T>& sb, in
     for (int sw = 0; sw < max_sweeps; ++sw) {
         ja.sweep = sw;
         ja.rotations = h->rot_counter;
-        prof_launch(h, K_JAC_SELF, dot_flops * active * self_pairs(g.n, ja.nb),
-                    [&] { launch_jacobi_self(ja, bw, st); });
+        const double sp = (double)active * self_pairs(g.n, ja.nb);
+        const int ip = prof_launch(h, K_JAC_SELF, pair_flops * sp, [&] { launch_jacobi_self(ja, bw, st); });
+        if (ip >= 0) {
+            h->pending[ip].pairs = sp;
+            h->pending[ip].sweeps = active;
+        }
         launch_check("jacobi_self");
         ja.rotations = h->rot_counter + 1;
         for (int r = 0; r < ja.nb - 1; ++r) {
             ja.round = r;
-            prof_launch(h, K_JAC_CROSS, dot_flops * active * cross_pairs(g.n, ja.nb, r),
-                        [&] { launch_jacobi_cross(ja, bw, st); });
+            const double cp = (double)active * cross_pairs(g.n, ja.nb, r);
+            const int ic = prof_launch(h, K_JAC_CROSS, pair_flops * cp, [&] { launch_jacobi_cross(ja, bw, st); });
+            if (ic >= 0) h->pending[ic].pairs = cp;
             launch_check("jacobi_cross");
         }
         stats.sweeps = sw + 1;
@@ -443,8 +510,18 @@ SweepStats run_svt(tsvd_handle h, const Geometry& g, const SvtBuffers<T>& sb, in
     gr.dk = sb.dk; gr.sdk = g.n; gr.ctrl = h->ctrl;
     gr.bf16x3 = env_int("TSVD_REBUILD_BF16", 0);
     if (rebuild) {
-        prof_launch(h, K_SVT_REBUILD, 8.0 * g.m * g.n * g.n * g.h, [&] { launch_zgemm(gr, st); });
+        const int ip = prof_launch(h, K_SVT_REBUILD, 8.0 * g.m * g.n * g.n * g.h, [&] { launch_zgemm(gr, st); });
         launch_check("svt_rebuild");
+        if (ip >= 0 && !want_rank) {
+            // the kept rank of every slice, for the rebuild's useful work
+            launch_multirank(sb.sigma, g.n, g.n, g.h, h->ctrl, sb.rank, st);
+            hip_check(hipMemcpyAsync(h->host_ints, sb.rank, sizeof(int) * g.h, hipMemcpyDeviceToHost, st),
+                      "hipMemcpyAsync rank");
+            hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+            double kept = 0.0;
+            for (int s = 0; s < g.h; ++s) kept += h->host_ints[s];
+            h->pending[ip].kept = kept;
+        }
     }
     if (want_rank) {
         launch_multirank(sb.sigma, g.n, g.n, g.h, h->ctrl, sb.rank, st);
@@ -458,10 +535,9 @@ SweepStats run_svt(tsvd_handle h, const Geometry& g, const SvtBuffers<T>& sb, in
         hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
         hip_check(hipMemsetAsync(h->rot_counter, 0, 2 * sizeof(unsigned long long), st),
                   "hipMemsetAsync rotations");
-        const double rot_flops = 16.0 * (g.m + g.n);
         prof_harvest(h);
-        h->agg[K_JAC_SELF].work += rot_flops * (double)rots[0];
-        h->agg[done_persist ? K_JAC_PERSIST : K_JAC_CROSS].work += rot_flops * (double)rots[1];
+        h->agg[K_JAC_SELF].rotations += (double)rots[0];
+        h->agg[done_persist ? K_JAC_PERSIST : K_JAC_CROSS].rotations += (double)rots[1];
     }
     if (warm) {
         warm->valid = true;
@@ -537,7 +613,10 @@ LoopResult admm_loop(tsvd_handle h, int max_iter, F&& iteration) {
 
 void clear_flag(tsvd_handle h) { launch_fill<int>(h->flag, 0, 1, h->stream); }
 
-// error word of the persistent Jacobi barriers (last int of the pbar area)
+// Error word of the persistent Jacobi launches (pbar[4h]): cleared once per
+// call; bit 1 (a wait between workgroups gave up) only makes the fallback
+// kernel finish the SVDs, bit 2 (a wait inside a workgroup ran out: a fault)
+// fails the call.
 template <typename T>
 void clear_persist_err(tsvd_handle h, const Geometry& g, const SvtBuffers<T>& sb) {
     launch_fill<int>(sb.pbar + 4 * g.h, 0, 1, h->stream);
@@ -549,7 +628,7 @@ void check_persist_err(tsvd_handle h, const Geometry& g, const SvtBuffers<T>& sb
     hip_check(hipMemcpyAsync(h->host_ints, sb.pbar + 4 * g.h, sizeof(int), hipMemcpyDeviceToHost, h->stream),
               "hipMemcpyAsync err");
     hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
-    if (h->host_ints[0]) fail(TSVD_E_HIP, "Jacobi slice barrier wait ran out");
+    if (h->host_ints[0] & 2) fail(TSVD_E_HIP, "a Jacobi step wait inside a workgroup ran out");
 }
 
 // largest per-slice sweep count of the last SVD (read after a sync)
@@ -562,6 +641,20 @@ bool read_flag(tsvd_handle h) {
 }
 
 int elementwise_parts() { return 1024; }
+
+// Checks of a solver state (include/tsvd.h, tsvd_state).
+void check_state(const tsvd_state* st, bool rpca) {
+    if (!st) return;
+    if (!st->z || !st->dual || (rpca && !st->s)) fail(TSVD_E_INVALID, "state: null iterate pointer");
+    if (st->iter < 0) fail(TSVD_E_INVALID, "state: iter must be >= 0");
+    if (st->load && (!(st->penalty > 0.0) || !std::isfinite(st->penalty) || !(st->dual_scale > 0.0) ||
+                     !std::isfinite(st->dual_scale)))
+        fail(TSVD_E_INVALID, "state: penalty and dual_scale must be finite and > 0");
+}
+
+void copy_d2d(void* dst, const void* src, size_t bytes, hipStream_t st) {
+    hip_check(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st), "hipMemcpyAsync state");
+}
 
 }  // namespace
 
@@ -580,6 +673,7 @@ void do_tsvt(tsvd_handle h, const void* X, tsvd_shape shape, tsvd_dtype dtype, d
         Carver cv{reinterpret_cast<char*>(h->ws)};
         SvtBuffers<T> sb = carve_svt<T>(cv, g, nparts);
         const T* dmat = ensure_dft_matrices<T>(h, g);
+        upload_fallback<T>(h, g, sb, 30);
         Ctrl c{};
         c.rho = tau > 0 ? 1.0 / tau : INFINITY;
         c.tau = tau;
@@ -644,6 +738,7 @@ SvdStage<T> svd_stage(tsvd_handle h, const Geometry& g, const void* X, size_t ex
     st.cv = Carver{reinterpret_cast<char*>(h->ws)};
     st.sb = carve_svt<T>(st.cv, g, nparts);
     st.dmat = ensure_dft_matrices<T>(h, g);
+    upload_fallback<T>(h, g, st.sb, 30);
     Ctrl c{};
     c.rho = INFINITY;
     c.tau = 0.0;
@@ -801,16 +896,36 @@ void do_complete(tsvd_handle h, const void* X_obs, const uint8_t* mask, tsvd_sha
         const T* dmat = ensure_dft_matrices<T>(h, g);
         hipStream_t st = h->stream;
         const T* Y = static_cast<const T*>(X_obs);
-        launch_fill<T>(Zb[0], 0.0, N, st);
-        launch_fill<T>(Qb[0], 0.0, N, st);
+        const tsvd_state* state = s.state;
+        check_state(state, false);
+        const bool load = state && state->load;
+        const int64_t vv_bytes = (int64_t)g.h * g.n * g.n * sizeof(cplx<T>);
+        upload_fallback<T>(h, g, sb, s.max_sweeps);
+        WarmState warm;
+        warm.enabled = env_int("TSVD_WARM", 1) != 0;
+        warm.reorth_every = env_int("TSVD_REORTH_EVERY", sizeof(T) == 4 ? 1 : 4);
+        if (load) {
+            copy_d2d(Zb[0], state->z, N * sizeof(T), st);
+            copy_d2d(Qb[0], state->dual, N * sizeof(T), st);
+            warm.iter = state->iter;
+            if (state->v) {
+                copy_d2d(sb.V[0], state->v, vv_bytes, st);
+                warm.valid = true;
+            }
+        } else {
+            launch_fill<T>(Zb[0], 0.0, N, st);
+            launch_fill<T>(Qb[0], 0.0, N, st);
+        }
+        const double rho0 = load ? state->penalty : rho;
+        const double ds0 = load ? state->dual_scale : 1.0;
         Ctrl c{};
-        c.rho = rho;
-        c.tau = 1.0 / rho;
-        c.dscale = 1.0;
-        c.dscale_used = 1.0;
+        c.rho = rho0;
+        c.tau = 1.0 / rho0;
+        c.dscale = ds0;
+        c.dscale_used = ds0;
         c.growth = s.growth;
         c.rho_max = s.rho_max;
-        c.rho_used = rho;
+        c.rho_used = rho0;
         put_ctrl(h, c);
         launch_sumsq<T>(Y, mask, N, sb.partials, elementwise_parts(), st);
         launch_set_tol(h->ctrl, sb.partials, elementwise_parts(), tol, st);
@@ -840,9 +955,7 @@ void do_complete(tsvd_handle h, const void* X_obs, const uint8_t* mask, tsvd_sha
         const double slice_bytes = (double)g.h * g.m * g.n * sizeof(cplx<T>);
         int sweeps_total = 0, sweeps_last = 0, iters = 0;
         Ctrl hc{};
-        WarmState warm;
-        warm.enabled = env_int("TSVD_WARM", 1) != 0;
-        warm.reorth_every = env_int("TSVD_REORTH_EVERY", sizeof(T) == 4 ? 1 : 4);
+        std::vector<int> vcur_after;   // V buffer holding each queued iteration's V
         const LoopResult lr = admm_loop(h, s.max_iter, [&](int k, Ctrl* mirror) -> int {
             fa.z = Zb[k % 2];
             fa.dual = Qb[k % 2];
@@ -863,6 +976,7 @@ void do_complete(tsvd_handle h, const void* X_obs, const uint8_t* mask, tsvd_sha
             prof_launch(h, K_CTRL, (double)inv_parts * kNumPartials * sizeof(double),
                         [&] { launch_admm_ctrl(h->ctrl, sb.partials, inv_parts, 0, mirror, st); });
             launch_check("admm_ctrl");
+            vcur_after.push_back(warm.vcur);
             return ss.on_device ? -1 : ss.sweeps;
         });
         hc = lr.c;
@@ -872,10 +986,21 @@ void do_complete(tsvd_handle h, const void* X_obs, const uint8_t* mask, tsvd_sha
         launch_complete_output<T>(Y, mask, Zb[(iters - 1) % 2], Qb[(iters - 1) % 2], h->ctrl,
                                   static_cast<T*>(X_out), N, st);
         launch_check("complete_output");
+        if (state && state->save) {
+            copy_d2d(state->z, Zb[iters % 2], N * sizeof(T), st);
+            copy_d2d(state->dual, Qb[iters % 2], N * sizeof(T), st);
+            if (state->v) copy_d2d(state->v, sb.V[vcur_after[iters - 1]], vv_bytes, st);
+        }
         hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
         prof_harvest(h);
         check_persist_err(h, g, sb);
         if (hc.nonfinite || read_flag(h)) fail(TSVD_E_NONFINITE, "non-finite input or iterate");
+        if (state && state->save) {
+            tsvd_state* out = const_cast<tsvd_state*>(state);
+            out->penalty = hc.rho;
+            out->dual_scale = hc.dscale;
+            out->iter = (load ? state->iter : 0) + iters;
+        }
         if (info_host) {
             info_host->iters = iters;
             info_host->converged = hc.done ? 1 : 0;
@@ -919,19 +1044,40 @@ void do_trpca(tsvd_handle h, const void* X, tsvd_shape shape, tsvd_dtype dtype, 
         const T* dmat = ensure_dft_matrices<T>(h, g);
         hipStream_t st = h->stream;
         const T* M = static_cast<const T*>(X);
-        launch_fill<T>(Lb[0], 0.0, N, st);
-        launch_fill<T>(Sb[0], 0.0, N, st);
-        launch_fill<T>(Wb[0], 0.0, N, st);
+        const tsvd_state* state = s.state;
+        check_state(state, true);
+        const bool load = state && state->load;
+        const int64_t vv_bytes = (int64_t)g.h * g.n * g.n * sizeof(cplx<T>);
+        upload_fallback<T>(h, g, sb, s.max_sweeps);
+        WarmState warm;
+        warm.enabled = env_int("TSVD_WARM", 1) != 0;
+        warm.reorth_every = env_int("TSVD_REORTH_EVERY", sizeof(T) == 4 ? 1 : 4);
+        if (load) {
+            copy_d2d(Lb[0], state->z, N * sizeof(T), st);
+            copy_d2d(Sb[0], state->s, N * sizeof(T), st);
+            copy_d2d(Wb[0], state->dual, N * sizeof(T), st);
+            warm.iter = state->iter;
+            if (state->v) {
+                copy_d2d(sb.V[0], state->v, vv_bytes, st);
+                warm.valid = true;
+            }
+        } else {
+            launch_fill<T>(Lb[0], 0.0, N, st);
+            launch_fill<T>(Sb[0], 0.0, N, st);
+            launch_fill<T>(Wb[0], 0.0, N, st);
+        }
+        const double mu0 = load ? state->penalty : mu;
+        const double ds0 = load ? state->dual_scale : 1.0;
         Ctrl c{};
-        c.rho = mu;
-        c.tau = 1.0 / mu;
-        c.dscale = 1.0;
-        c.dscale_used = 1.0;
+        c.rho = mu0;
+        c.tau = 1.0 / mu0;
+        c.dscale = ds0;
+        c.dscale_used = ds0;
         c.growth = s.growth;
         c.rho_max = s.rho_max;
         c.lambda = lambda;
-        c.shrink = lambda / mu;
-        c.rho_used = mu;
+        c.shrink = lambda / mu0;
+        c.rho_used = mu0;
         put_ctrl(h, c);
         launch_sumsq<T>(M, nullptr, N, sb.partials, elementwise_parts(), st);
         launch_set_tol(h->ctrl, sb.partials, elementwise_parts(), tol, st);
@@ -959,9 +1105,7 @@ void do_trpca(tsvd_handle h, const void* X, tsvd_shape shape, tsvd_dtype dtype, 
         const double slice_bytes = (double)g.h * g.m * g.n * sizeof(cplx<T>);
         int sweeps_total = 0, sweeps_last = 0, iters = 0;
         Ctrl hc{};
-        WarmState warm;
-        warm.enabled = env_int("TSVD_WARM", 1) != 0;
-        warm.reorth_every = env_int("TSVD_REORTH_EVERY", sizeof(T) == 4 ? 1 : 4);
+        std::vector<int> vcur_after;   // V buffer holding each queued iteration's V
         const LoopResult lr = admm_loop(h, s.max_iter, [&](int k, Ctrl* mirror) -> int {
             fa.s = Sb[k % 2];
             fa.dual = Wb[k % 2];
@@ -984,6 +1128,7 @@ void do_trpca(tsvd_handle h, const void* X, tsvd_shape shape, tsvd_dtype dtype, 
             prof_launch(h, K_CTRL, (double)inv_parts * kNumPartials * sizeof(double),
                         [&] { launch_admm_ctrl(h->ctrl, sb.partials, inv_parts, 1, mirror, st); });
             launch_check("admm_ctrl");
+            vcur_after.push_back(warm.vcur);
             return ss.on_device ? -1 : ss.sweeps;
         });
         hc = lr.c;
@@ -994,10 +1139,22 @@ void do_trpca(tsvd_handle h, const void* X, tsvd_shape shape, tsvd_dtype dtype, 
                   "hipMemcpyAsync L");
         hip_check(hipMemcpyAsync(S_out, Sb[iters % 2], N * sizeof(T), hipMemcpyDeviceToDevice, st),
                   "hipMemcpyAsync S");
+        if (state && state->save) {
+            copy_d2d(state->z, Lb[iters % 2], N * sizeof(T), st);
+            copy_d2d(state->s, Sb[iters % 2], N * sizeof(T), st);
+            copy_d2d(state->dual, Wb[iters % 2], N * sizeof(T), st);
+            if (state->v) copy_d2d(state->v, sb.V[vcur_after[iters - 1]], vv_bytes, st);
+        }
         hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
         prof_harvest(h);
         check_persist_err(h, g, sb);
         if (hc.nonfinite || read_flag(h)) fail(TSVD_E_NONFINITE, "non-finite input or iterate");
+        if (state && state->save) {
+            tsvd_state* out = const_cast<tsvd_state*>(state);
+            out->penalty = hc.rho;
+            out->dual_scale = hc.dscale;
+            out->iter = (load ? state->iter : 0) + iters;
+        }
         if (info_host) {
             info_host->iters = iters;
             info_host->converged = hc.done ? 1 : 0;
@@ -1061,6 +1218,7 @@ tsvd_status tsvd_destroy(tsvd_handle h) {
         if (h->ctrl) (void)hipFree(h->ctrl);
         if (h->flag) (void)hipFree(h->flag);
         if (h->host_ints) (void)hipHostFree(h->host_ints);
+        if (h->host_stage) (void)hipHostFree(h->host_stage);
         if (h->host_ctrl) (void)hipHostFree(h->host_ctrl);
         if (h->mirror_host) (void)hipHostFree(h->mirror_host);
         for (auto e : h->mirror_ev)
@@ -1174,6 +1332,10 @@ tsvd_status tsvd_profile_read(tsvd_handle h, tsvd_kernel_stat* out_host, int cap
                 o.total_ms = g.ms;
                 o.work = g.work;
                 o.work_is_bytes = kKindBytes[k] ? 1 : 0;
+                o.slice_sweeps = g.sweeps;
+                o.pairs_visited = g.pairs;
+                o.rotations = g.rotations;
+                o.kept_rank = g.kept;
             }
             ++c;
         }
@@ -1196,6 +1358,10 @@ tsvd_status tsvd_poll(tsvd_handle h, uint64_t ticket, tsvd_info* info_host) {
     return g != TSVD_OK ? g : st;
 }
 
+tsvd_status tsvd_cancel(tsvd_handle h, uint64_t ticket) {
+    return guarded([&] { serve_cancel(h, ticket); });
+}
+
 tsvd_status tsvd_serve_stats_read(tsvd_handle h, tsvd_serve_stats* out_host) {
     return guarded([&] { serve_stats(h, out_host); });
 }
@@ -1210,6 +1376,8 @@ const char* tsvd_status_string(tsvd_status s) {
         case TSVD_E_NONFINITE: return "non-finite value";
         case TSVD_E_UNSUPPORTED: return "unsupported request";
         case TSVD_E_BUSY: return "not finished";
+        case TSVD_E_CANCELLED: return "cancelled";
+        case TSVD_E_TIMEOUT: return "deadline passed";
     }
     return "unknown status";
 }

@@ -37,6 +37,7 @@
 #include <thread>
 #include <tuple>
 #include <unordered_map>
+#include <unordered_set>
 
 namespace tsvd {
 
@@ -65,6 +66,8 @@ Spec validate(const tsvd_problem& p) {
     if (!p.x || !p.out) fail(TSVD_E_INVALID, "null tensor pointer");
     if (!(p.penalty > 0.0) || !std::isfinite(p.penalty)) fail(TSVD_E_INVALID, "penalty must be > 0");
     if (!(p.tol >= 0.0) || !std::isfinite(p.tol)) fail(TSVD_E_INVALID, "tol must be >= 0");
+    if (p.opts.state) fail(TSVD_E_UNSUPPORTED, "the batched and served forms take no solver state");
+    if (!(p.deadline_s >= 0.0) || !std::isfinite(p.deadline_s)) fail(TSVD_E_INVALID, "deadline_s must be >= 0");
     tsvd_admm_opts o = p.opts;
     o.precision = p.precision;
     if (p.kind == TSVD_KIND_COMPLETE) {
@@ -319,6 +322,44 @@ public:
             arena_->give(slots_[*it].off, slots_[*it].bytes);
             slots_.erase(slots_.begin() + (long)*it);
         }
+        dirty_ = true;
+    }
+
+    // Serving: drop the running problems that are cancelled or past their
+    // deadline (call between periods, after harvest, when the engine's
+    // stream is idle); each is reported with its status.
+    template <typename C, typename F>
+    void expire(C&& cancelled, Clock::time_point now, F&& done_cb) {
+        for (size_t i = slots_.size(); i-- > 0;) {
+            const Slot<T>& sl = slots_[i];
+            const double dl = sl.sp.p.deadline_s;
+            tsvd_status st = TSVD_OK;
+            if (cancelled(sl.ticket))
+                st = TSVD_E_CANCELLED;
+            else if (dl > 0.0 && std::chrono::duration<double>(now - sl.t0).count() > dl)
+                st = TSVD_E_TIMEOUT;
+            if (st == TSVD_OK) continue;
+            Result r;
+            r.status = st;
+            r.info.seconds = std::chrono::duration<double>(now - sl.t0).count();
+            done_cb(sl.ticket, r);
+            arena_->give(sl.off, sl.bytes);
+            slots_.erase(slots_.begin() + (long)i);
+            dirty_ = true;
+        }
+    }
+
+    // After a device failure: report every running problem with `status`
+    // and forget it (no device work is issued).
+    template <typename F>
+    void abandon(tsvd_status status, F&& done_cb) {
+        for (const Slot<T>& sl : slots_) {
+            Result r;
+            r.status = status;
+            done_cb(sl.ticket, r);
+            if (arena_) arena_->give(sl.off, sl.bytes);
+        }
+        slots_.clear();
         dirty_ = true;
     }
 
@@ -947,9 +988,11 @@ struct Server {
     };
     std::deque<Queued> queue;
     std::unordered_map<uint64_t, Result> results;
+    std::unordered_set<uint64_t> cancelled;   // running tickets to drop at the next period boundary
     uint64_t next_ticket = 1;
     tsvd_serve_stats stats{};
     std::string worker_error;
+    tsvd_status worker_status = TSVD_OK;
     // device side (worker thread only after start)
     Arena arena;
     char* mem = nullptr;
@@ -1009,6 +1052,23 @@ struct Server {
                 // the running problems do not yet fill the chip: past about
                 // slice_cap Fourier slices the GPU is saturated, and admitting
                 // more only makes every running request slower
+                {
+                    // queued requests past their deadline never start
+                    std::lock_guard<std::mutex> lk(mu);
+                    const auto now = Clock::now();
+                    for (auto it = queue.begin(); it != queue.end();) {
+                        const double dl = it->sp.p.deadline_s;
+                        if (dl > 0.0 && std::chrono::duration<double>(now - it->t0).count() > dl) {
+                            Result& r = results[it->ticket];
+                            r.status = TSVD_E_TIMEOUT;
+                            r.info.seconds = std::chrono::duration<double>(now - it->t0).count();
+                            stats.finished += 1;
+                            it = queue.erase(it);
+                        } else {
+                            ++it;
+                        }
+                    }
+                }
                 for (;;) {
                     Queued q;
                     {
@@ -1028,6 +1088,18 @@ struct Server {
                 auto cb = [&](uint64_t t, const Result& r) { finish(t, r); };
                 ef.harvest(cb);
                 ed.harvest(cb);
+                {
+                    // cancellations and deadlines of running requests
+                    std::unordered_set<uint64_t> drop;
+                    {
+                        std::lock_guard<std::mutex> lk(mu);
+                        drop.swap(cancelled);
+                    }
+                    auto is_cancelled = [&](uint64_t t) { return drop.count(t) != 0; };
+                    const auto now = Clock::now();
+                    ef.expire(is_cancelled, now, cb);
+                    ed.expire(is_cancelled, now, cb);
+                }
                 std::lock_guard<std::mutex> lk(mu);
                 stats.iterations = ef.iterations() + ed.iterations();
                 stats.running = (int64_t)(ef.running() + ed.running());
@@ -1035,11 +1107,19 @@ struct Server {
                 stats.queued = (int64_t)queue.size();
                 stats.arena_used = (int64_t)arena.used();
             } catch (const Failure& f) {
-                // a device failure ends serving: fail every open ticket
+                // a device failure ends serving: fail every open ticket,
+                // queued or running
                 std::lock_guard<std::mutex> lk(mu);
                 worker_error = f.msg;
+                worker_status = f.status;
                 for (auto& q : queue) results[q.ticket].status = f.status;
                 queue.clear();
+                auto fail_cb = [&](uint64_t t, const Result& r) {
+                    results[t] = r;
+                    stats.finished += 1;
+                };
+                ef.abandon(f.status, fail_cb);
+                ed.abandon(f.status, fail_cb);
                 stop = true;
                 return;
             }
@@ -1074,8 +1154,33 @@ tsvd_status serve_poll(tsvd_handle h, uint64_t ticket, tsvd_info* info) {
     std::lock_guard<std::mutex> lk(s.mu);
     auto it = s.results.find(ticket);
     if (it == s.results.end()) fail(TSVD_E_INVALID, "unknown ticket");
+    // a worker stopped by a device failure finishes no open ticket
+    if (it->second.status == TSVD_E_BUSY && s.stop && s.worker_status != TSVD_OK)
+        it->second.status = s.worker_status;
     if (it->second.status != TSVD_E_BUSY && info) *info = it->second.info;
     return it->second.status;
+}
+
+void serve_cancel(tsvd_handle h, uint64_t ticket) {
+    check_handle(h);
+    if (!h->server) fail(TSVD_E_INVALID, "unknown ticket");
+    Server& s = *h->server;
+    {
+        std::lock_guard<std::mutex> lk(s.mu);
+        auto it = s.results.find(ticket);
+        if (it == s.results.end()) fail(TSVD_E_INVALID, "unknown ticket");
+        if (it->second.status != TSVD_E_BUSY) return;   // already finished
+        for (auto q = s.queue.begin(); q != s.queue.end(); ++q) {
+            if (q->ticket != ticket) continue;
+            it->second.status = TSVD_E_CANCELLED;
+            it->second.info.seconds = std::chrono::duration<double>(Clock::now() - q->t0).count();
+            s.stats.finished += 1;
+            s.queue.erase(q);
+            return;
+        }
+        s.cancelled.insert(ticket);   // running: dropped at the next period boundary
+    }
+    s.cv.notify_all();
 }
 
 void serve_stats(tsvd_handle h, tsvd_serve_stats* out) {

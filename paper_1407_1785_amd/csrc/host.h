@@ -66,6 +66,7 @@ struct Server;   // serving engine of a handle (engine.hip)
 void batch_run(tsvd_handle h, const tsvd_problem* probs, int count, tsvd_info* infos, int32_t* status);
 void serve_submit(tsvd_handle h, const tsvd_problem* prob, uint64_t* ticket);
 tsvd_status serve_poll(tsvd_handle h, uint64_t ticket, tsvd_info* info);
+void serve_cancel(tsvd_handle h, uint64_t ticket);
 void serve_stats(tsvd_handle h, tsvd_serve_stats* out);
 void serve_shutdown(tsvd_handle h);
 
@@ -86,6 +87,8 @@ struct tsvd_handle_s {
     // pinned host staging
     int* host_ints = nullptr;
     int host_ints_len = 0;
+    void* host_stage = nullptr;     // argument tables uploaded once per call
+    size_t host_stage_len = 0;
     tsvd::Ctrl* host_ctrl = nullptr;
     // ADMM loop of the single-problem calls: the control kernel copies the
     // control block into one of two slots of mapped pinned host memory, and
@@ -98,10 +101,13 @@ struct tsvd_handle_s {
         int kind;
         hipEvent_t a, b;
         double work;
+        double sweeps = 0.0, pairs = 0.0;   // Jacobi families: slice sweeps and pairs visited
+        double kept = 0.0;                  // rebuild: summed kept rank
     };
     struct Agg {
         int64_t launches = 0;
         double ms = 0.0, work = 0.0;
+        double sweeps = 0.0, pairs = 0.0, rotations = 0.0, kept = 0.0;
     };
     bool prof_on = false;
     std::vector<hipEvent_t> ev_pool;
@@ -236,12 +242,14 @@ inline bool check_precision(int dtype, int precision) {
 struct AdmmSettings {
     double growth, rho_max;
     int max_iter, precision, max_sweeps;
+    const tsvd_state* state;
 };
 
 inline AdmmSettings settings(const tsvd_admm_opts* o, double growth, double rho_max, int max_iter) {
-    AdmmSettings s{growth, rho_max, max_iter, TSVD_PREC_FP64, 30};
+    AdmmSettings s{growth, rho_max, max_iter, TSVD_PREC_FP64, 30, nullptr};
     if (o) {
-        if (o->reserved != 0) fail(TSVD_E_INVALID, "opts.reserved must be 0");
+        if (o->pad != 0) fail(TSVD_E_INVALID, "opts.pad must be 0");
+        s.state = o->state;
         if (o->growth > 0) s.growth = o->growth;
         if (o->rho_max > 0) s.rho_max = o->rho_max;
         if (o->max_iter > 0) s.max_iter = o->max_iter;

@@ -27,14 +27,21 @@
 // the index of the round that takes it next; a workgroup waits only on the
 // flags of the two blocks it takes next.  At the end of a sweep all
 // workgroups of the slice meet at a counter barrier (the stopping decision
-// needs every workgroup's rotation flag).  The grid holds at most one
-// workgroup per CU, checked against the occupancy of the launch, so on a
-// device with nothing else running every workgroup is resident at once.
-// Every wait is bounded: a spin limit sets an error flag and lets the kernel
-// finish, so if other work keeps some workgroups from starting the call
-// fails instead of hanging.  A cooperative launch (the runtime guarantees
-// co-residency) is available; it costs ~25 us more per launch, 3% of a
-// video-shaped iteration.
+// needs every workgroup's rotation flag).
+//
+// Residency.  A workgroup takes its role (slice, block pair) from a ticket
+// counter when it starts, so the roles of the workgroups running at any time
+// are the lowest ones not yet finished: the workgroups of a slice wait only
+// for workgroups that are running or will start as soon as others finish.
+// The grid holds at most one workgroup per CU, so on an otherwise idle
+// device every workgroup is resident at once; under concurrent work the
+// slices finish in ticket order.  Every wait between workgroups is bounded
+// (PersistArgs.spin_limit polls): a wait that gives up sets bit 1 of the
+// error word, and every workgroup that meets the error word at its next wait
+// writes its resident blocks home and stops.  Each block is held by one workgroup at a
+// time and every rotation is applied to the slice rows and the V rows
+// together, so W = A V still holds for the partly rotated slices; the caller
+// then finishes the SVD with the one-workgroup-per-slice kernel.
 //
 // Convergence: workgroups OR a per-slice flag when a rotation of the sweep
 // forces another sweep (rot_forces_sweep); after the sweep's last barrier all
@@ -51,8 +58,7 @@ namespace {
 
 using namespace jac;
 
-constexpr int PBW = 16;                       // columns per block = pairs per step
-constexpr long long kSpinLimit = 1LL << 21;   // about a second of polling
+constexpr int PBW = 16;   // columns per block = pairs per step
 
 template <typename T, int NT>
 __device__ void pload_block(const JacArgs<T>& a, int s, int blk, int mp, int ldc, cplx<T>* lds) {
@@ -127,32 +133,25 @@ __device__ void pstore_block(const JacArgs<T>& a, int s, int blk, int mp, int ld
 // complete at the coherence point, the workgroup meets at s_barrier, and
 // thread 0 counts the arrival and waits for the other workgroups of the
 // slice; the next blocks are read only after that (loads are issued in
-// program order).  With tr set (thread 0 of the traced workgroup), three
-// timestamps: stores complete, counter incremented, wait over.
-__device__ bool slice_barrier(int* counter, int target, int* err, long long* tr = nullptr, int* nev = nullptr) {
+// program order).
+__device__ bool slice_barrier(int* counter, int target, int* err, int spin_limit) {
     __shared__ int ok;
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) {
-        auto mark = [&]() {
-            if (tr && *nev < 64) tr[(*nev)++] = (long long)wall_clock64();
-        };
-        mark();
         ok = 1;
         __hip_atomic_fetch_add(counter, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        mark();
-        long long spins = 0;
+        int spins = 0;
         while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             __builtin_amdgcn_s_sleep(2);
             // another workgroup gave up: stop waiting at once
             if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
-                ++spins > kSpinLimit) {
-                __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ++spins > spin_limit) {
+                __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 ok = 0;
                 break;
             }
         }
-        mark();
     }
     __syncthreads();
     return ok != 0;
@@ -160,12 +159,12 @@ __device__ bool slice_barrier(int* counter, int target, int* err, long long* tr 
 
 // Bounded wait (thread 0) until a block flag reaches `value`; false if the
 // wait ran out or another workgroup gave up.
-__device__ bool wait_flag(int* flag, int value, int* err) {
-    long long spins = 0;
+__device__ bool wait_flag(int* flag, int value, int* err, int spin_limit) {
+    int spins = 0;
     while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < value) {
         __builtin_amdgcn_s_sleep(1);
-        if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 || ++spins > kSpinLimit) {
-            __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 || ++spins > spin_limit) {
+            __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             return false;
         }
     }
@@ -177,8 +176,12 @@ __device__ bool wait_flag(int* flag, int value, int* err) {
 // else.  Each wave counts its finished steps in LDS (release after its LDS
 // writes); a wave waits for its successor's count (acquire) instead of a
 // workgroup barrier, so a step costs the waves' average rather than the
-// slowest pair.  Every wave finishes every step, so the waits end; the spin
-// cap only reports a fault through the error word.
+// slowest pair.  Every wave of the workgroup runs every step of a round
+// (giving up happens only between rounds), so a wait lasts at most a few
+// steps.  One that runs far longer means a fault: the wave stops waiting
+// and sets the error word to 2, which fails the call (the block data can no
+// longer be trusted); it checks the error word every 1024 polls, so after
+// such a fault no wait spins to its cap again.
 __device__ __forceinline__ void lds_publish(int* cnt, int value) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     if ((threadIdx.x & 63) == 0) __hip_atomic_store(cnt, value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -186,7 +189,7 @@ __device__ __forceinline__ void lds_publish(int* cnt, int value) {
 
 // Polls back to back (a sleep between polls cost 0.7% of the iteration);
 // 2^18 LDS polls are milliseconds, far beyond any step of a workgroup's own
-// waves.
+// waves, and 1024 polls tens of microseconds, tens of steps.
 constexpr int kLdsSpinLimit = 1 << 18;
 
 __device__ __forceinline__ void lds_wait(const int* cnt, int value, int* err) {
@@ -194,11 +197,13 @@ __device__ __forceinline__ void lds_wait(const int* cnt, int value, int* err) {
     while (__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < value) {
         ++spins;
         if (spins > kLdsSpinLimit) {
-            __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             return;
         }
-        // once the launch has failed, no wait spins to its cap again
-        if ((spins & 1023) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
+        if ((spins & 1023) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+            __hip_atomic_store(err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return;
+        }
     }
 }
 
@@ -214,19 +219,18 @@ __global__ __launch_bounds__(PBW * PG) void jacobi_persistent_kernel(JacArgs<T> 
     __shared__ double jnorm[PBW];
     __shared__ double inorm[2 * PBW];   // internal phase: tracked norms of both blocks' columns
     __shared__ int wsteps[NT / 64];   // pair steps finished per wave, over the whole launch
+    __shared__ int role;
     if (a.ctrl && a.ctrl->done) return;
     const int G = a.nb / 2;
-    int s, wg;
-    if (p.xcds > 0) {
-        // workgroup b runs on XCD b mod X: the G workgroups of a slice get the
-        // same residue, so their block exchanges stay within one L2
-        const int X = p.xcds, b = (int)blockIdx.x, x = b % X, i = b / X;
-        s = x + X * (i / G);
-        wg = i % G;
-    } else {
-        s = (int)blockIdx.x / G;
-        wg = (int)blockIdx.x - s * G;
-    }
+    // the int words of the launch: h barrier counters, 3h sweep flags, the
+    // error word, the role ticket, h x nb block flags
+    int* const rotflag = p.pbar + a.h;
+    int* const err = p.pbar + 4 * a.h;
+    if (threadIdx.x == 0) role = __hip_atomic_fetch_add(err + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    // uniform across the workgroup: keep it (and what derives from it) scalar
+    const int rl = __builtin_amdgcn_readfirstlane(role);
+    const int s = rl / G, wg = rl - s * G;
     if (s >= a.h) return;
     const int ka = (a.m + PG - 1) / PG;   // row groups holding slice rows
     const int mp = ka * PG;
@@ -235,16 +239,10 @@ __global__ __launch_bounds__(PBW * PG) void jacobi_persistent_kernel(JacArgs<T> 
     const int ldc = PG * RPT + 1;
     cplx<T>* const blk0 = reinterpret_cast<cplx<T>*>(smem);
     cplx<T>* const blk1 = blk0 + (size_t)PBW * ldc;
-    long long* trace = (p.trace && s == 0 && wg == 0 && threadIdx.x == 0) ? p.trace : nullptr;
-    int nev = 0;
-    auto mark = [&]() {
-        if (trace && nev < 64) trace[nev++] = (long long)wall_clock64();
-    };
-    mark();
     const int pos0 = wg, pos1 = a.nb - 1 - wg;
     const int g = threadIdx.x / PG, l = threadIdx.x - g * PG;
     const double tol = (double)a.tol;
-    int* counter = p.barrier + s;
+    int* counter = p.pbar + s;
     int arrivals = 0;
 
     // zero both blocks once: padding rows stay zero under every rotation
@@ -261,11 +259,15 @@ __global__ __launch_bounds__(PBW * PG) void jacobi_persistent_kernel(JacArgs<T> 
     unsigned nrot_total = 0;
     int swept = 0;   // sweeps started (kept by wg 0, thread 0)
     bool alive = true;
+    // resident blocks still to be written home when the sweeps end: both at
+    // the sweep cap; after a stop or a give-up, only those that did not move
+    // (the moving ones were written before the exchange)
+    bool home0 = true, home1 = true;
     for (int sweep = 0; sweep < p.max_sweeps && alive; ++sweep) {
         if (threadIdx.x == 0) rot_any = 0;
         if (wg == 0 && threadIdx.x == 0) {
             // read by every workgroup of the slice: a device-coherent store
-            __hip_atomic_store(p.rotflag + ((sweep + 1) % 3) * a.h + s, 0, __ATOMIC_RELAXED,
+            __hip_atomic_store(rotflag + ((sweep + 1) % 3) * a.h + s, 0, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
             a.sweeps[s] = sweep + 1;
             swept = sweep + 1;
@@ -307,7 +309,7 @@ __global__ __launch_bounds__(PBW * PG) void jacobi_persistent_kernel(JacArgs<T> 
                 }
                 __syncthreads();
                 for (int st = 0; st < k; ++st) {
-                    if (st > 0) lds_wait(wsteps + wnext, steps + st, p.err);
+                    if (st > 0) lds_wait(wsteps + wnext, steps + st, err);
                     const int ycol = ybase + ((q + st) & (k - 1));
                     if (xcol < w && ycol < w) {
                         double be = jn[ycol];
@@ -327,7 +329,6 @@ __global__ __launch_bounds__(PBW * PG) void jacobi_persistent_kernel(JacArgs<T> 
                 __syncthreads();
             }
         }
-        mark();
         for (int rd = 0; rd < a.nb - 1; ++rd) {
             // cross pairs: column g of block 0 (registers) meets every column of block 1
             const int wi = pblk_start(player0 + 1, a.n, a.nb) - pblk_start(player0, a.n, a.nb);
@@ -348,7 +349,7 @@ __global__ __launch_bounds__(PBW * PG) void jacobi_persistent_kernel(JacArgs<T> 
             // step st: group g meets column (g + st) mod PBW of block 1, which
             // group g + 1 met at step st - 1
             for (int st = 0; st < PBW; ++st) {
-                if (st > 0) lds_wait(wsteps + wave_next, steps + st, p.err);
+                if (st > 0) lds_wait(wsteps + wave_next, steps + st, err);
                 const int jc = (g + st) & (PBW - 1);
                 if (g < wi && jc < wj) {
                     double be = jnorm[jc];
@@ -372,33 +373,31 @@ __global__ __launch_bounds__(PBW * PG) void jacobi_persistent_kernel(JacArgs<T> 
                 if (nbig && l == 0) rot_any = 1;
                 __syncthreads();
                 if (threadIdx.x == 0 && rot_any)
-                    __hip_atomic_fetch_or(p.rotflag + (sweep % 3) * a.h + s, 1, __ATOMIC_RELAXED,
+                    __hip_atomic_fetch_or(rotflag + (sweep % 3) * a.h + s, 1, __ATOMIC_RELAXED,
                                           __HIP_MEMORY_SCOPE_AGENT);
             }
             // the next round's players (after the last round: round 0 of the next sweep)
             const int nr = (rd + 1) % (a.nb - 1);
             const int next0 = ppos_player(pos0, nr, a.nb), next1 = ppos_player(pos1, nr, a.nb);
             __syncthreads();
-            mark();
             if (next0 != player0) pstore_block<T, NT>(a, s, player0, mp, ldc, blk0);
             if (next1 != player1) pstore_block<T, NT>(a, s, player1, mp, ldc, blk1);
-            mark();
             if (last) {
                 // end of the sweep: every workgroup of the slice meets, then all
                 // read the same rotation flag and stop together when it is clear
                 arrivals += G;
-                if (!slice_barrier(counter, arrivals, p.err, trace, &nev)) {
+                if (!slice_barrier(counter, arrivals, err, p.spin_limit)) {
+                    home0 = next0 == player0;   // giving up
+                    home1 = next1 == player1;
                     alive = false;
                     break;
                 }
-                mark();
-                if (threadIdx.x == 0) stop = __hip_atomic_load(p.rotflag + (sweep % 3) * a.h + s,
+                if (threadIdx.x == 0) stop = __hip_atomic_load(rotflag + (sweep % 3) * a.h + s,
                                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
                 __syncthreads();
                 if (stop) {
-                    // converged: the blocks that did not move go home too
-                    if (next0 == player0) pstore_block<T, NT>(a, s, player0, mp, ldc, blk0);
-                    if (next1 == player1) pstore_block<T, NT>(a, s, player1, mp, ldc, blk1);
+                    home0 = next0 == player0;   // converged
+                    home1 = next1 == player1;
                     alive = false;
                     break;
                 }
@@ -406,21 +405,21 @@ __global__ __launch_bounds__(PBW * PG) void jacobi_persistent_kernel(JacArgs<T> 
                 // within a sweep: publish the blocks written (ready for round R + 1)
                 // and wait only for the two blocks this workgroup takes next
                 const int R = sweep * (a.nb - 1) + rd;
-                int* const bf = p.bflag + s * a.nb;
+                int* const bf = err + 2 + s * a.nb;
                 __builtin_amdgcn_s_waitcnt(0);
                 __syncthreads();
                 if (threadIdx.x == 0) {
                     ok_flag = 1;
                     if (next0 != player0) __hip_atomic_store(bf + player0, R + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     if (next1 != player1) __hip_atomic_store(bf + player1, R + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    mark();
-                    if ((next0 != player0 && !wait_flag(bf + next0, R + 1, p.err)) ||
-                        (next1 != player1 && !wait_flag(bf + next1, R + 1, p.err)))
+                    if ((next0 != player0 && !wait_flag(bf + next0, R + 1, err, p.spin_limit)) ||
+                        (next1 != player1 && !wait_flag(bf + next1, R + 1, err, p.spin_limit)))
                         ok_flag = 0;
-                    mark();
                 }
                 __syncthreads();
                 if (!ok_flag) {
+                    home0 = next0 == player0;   // giving up
+                    home1 = next1 == player1;
                     alive = false;
                     break;
                 }
@@ -430,17 +429,12 @@ __global__ __launch_bounds__(PBW * PG) void jacobi_persistent_kernel(JacArgs<T> 
             player0 = next0;
             player1 = next1;
             __syncthreads();
-            mark();
         }
         nrot_total += nrot;
     }
-    if (alive) {
-        // sweep cap reached: every resident block goes home
-        __syncthreads();
-        pstore_block<T, NT>(a, s, player0, mp, ldc, blk0);
-        pstore_block<T, NT>(a, s, player1, mp, ldc, blk1);
-    }
-    mark();
+    __syncthreads();
+    if (home0) pstore_block<T, NT>(a, s, player0, mp, ldc, blk0);
+    if (home1) pstore_block<T, NT>(a, s, player1, mp, ldc, blk1);
     if (l == 0 && nrot_total) atomicAdd(a.rotations, (unsigned long long)nrot_total);
     if (a.ctrl && swept) atomicMax(&a.ctrl->sweep_max, swept);
 }
@@ -461,10 +455,6 @@ int persist_rpt(int m, int n) {
 
 size_t persist_lds(int rpt, int elem_bytes) { return 2 * (size_t)PBW * (kPG * rpt + 1) * 2 * elem_bytes; }
 
-int persist_grid(int h, int G, int xcds) {
-    return xcds > 0 ? xcds * ((h + xcds - 1) / xcds) * G : h * G;
-}
-
 template <typename T, int RPT>
 hipError_t launch_persist_t(const JacArgs<T>& a, const PersistArgs& p, size_t lds, hipStream_t st, int cus) {
     auto* fn = jacobi_persistent_kernel<T, kPG, RPT>;
@@ -473,30 +463,21 @@ hipError_t launch_persist_t(const JacArgs<T>& a, const PersistArgs& p, size_t ld
     int per_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, PBW * kPG, lds);
     if (e != hipSuccess) return e;
-    const int grid = persist_grid(a.h, a.nb / 2, p.xcds);
-    if ((int64_t)per_cu * cus < grid) return hipErrorCooperativeLaunchTooLarge;
-    if (!p.cooperative) {
-        // ordinary launch: the grid fits one workgroup per CU, and every
-        // barrier wait is bounded
-        hipLaunchKernelGGL(fn, dim3(grid), dim3(PBW * kPG), lds, st, a, p);
-        return hipGetLastError();
-    }
-    JacArgs<T> aa = a;
-    PersistArgs pp = p;
-    void* args[] = {&aa, &pp};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(fn), dim3(grid), dim3(PBW * kPG), args,
-                                      (unsigned)lds, st);
+    const int grid = a.h * (a.nb / 2);
+    if ((int64_t)per_cu * cus < grid) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(PBW * kPG), lds, st, a, p);
+    return hipGetLastError();
 }
 
 }  // namespace
 
 int jacobi_persistent_blocks(int n) { return jacobi_num_blocks(n, PBW); }
 
-bool jacobi_persistent_fits(int m, int n, int h, int elem_bytes, int cus, size_t lds_cap, int xcds) {
+bool jacobi_persistent_fits(int m, int n, int h, int elem_bytes, int cus, size_t lds_cap) {
     const int rpt = persist_rpt(m, n);
     if (rpt < 0 || n < 2) return false;
     if (persist_lds(rpt, elem_bytes) + 256 > lds_cap) return false;
-    const int64_t grid = persist_grid(h, jacobi_persistent_blocks(n) / 2, xcds);
+    const int64_t grid = (int64_t)h * (jacobi_persistent_blocks(n) / 2);
     return grid <= (int64_t)cus;   // one workgroup per CU is always resident
 }
 

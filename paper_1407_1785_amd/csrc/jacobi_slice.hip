@@ -26,8 +26,10 @@
 //
 // Launch: a table of problems; workgroup b serves problem p when
 // wg_start[p] <= b < wg_start[p + 1], slice b - wg_start[p].  A problem
-// whose ADMM has stopped (ctrl->done) is skipped; each slice raises
-// ctrl->sweep_max to its sweep count.
+// whose ADMM has stopped (ctrl->done) is skipped, and so is one whose
+// optional only_if word is zero (the single-problem driver's fallback after
+// a persistent launch that gave up); each slice raises ctrl->sweep_max to
+// its sweep count.
 
 #include "jacobi_common.h"
 
@@ -153,6 +155,7 @@ __global__ __launch_bounds__(BW * kPGs) void jacobi_slice_kernel(const JacSliceA
     const int p = batch_find(wg_start, nprob, (int)blockIdx.x);
     const JacSliceArgs<T>& a = tab[p];
     if (a.ctrl && a.ctrl->done) return;
+    if (a.only_if && *a.only_if == 0) return;
     const int s = (int)blockIdx.x - wg_start[p];
     const int m = a.m, n = a.n, nb = a.nb, G = nb / 2;
     cplx<T>* const A = a.A + (int64_t)s * n * m;
@@ -233,6 +236,7 @@ __global__ __launch_bounds__(BW * kPGs) void jacobi_round_kernel(const JacSliceA
     const int p = batch_find(wg_start, nprob, (int)blockIdx.x);
     const JacSliceArgs<T>& a = tab[p];
     if (a.ctrl && a.ctrl->done) return;
+    if (a.only_if && *a.only_if == 0) return;
     const int m = a.m, n = a.n, nb = a.nb, G = nb / 2;
     if (sweep >= (a.max_sweeps > 0 ? a.max_sweeps : 30) || rd >= nb - 1) return;
     const int local = (int)blockIdx.x - wg_start[p];

@@ -184,6 +184,7 @@ struct JacSliceArgs {
     unsigned long long* rotations;  // optional running count
     int max_sweeps;      // sweep cap (0: the launch's)
     int* rot;            // round mode: 3 x h ring of per-sweep rotation flags (ring 0 clear before the SVD)
+    const int* only_if;  // optional: the problem is skipped unless *only_if != 0
 };
 int jacobi_slice_rpt(int m, int n);
 size_t jacobi_slice_lds(int bw, int rpt, int elem_bytes);
@@ -266,18 +267,17 @@ void jacobi_set_lds_limit(size_t bytes);
 
 // Persistent Jacobi (jacobi_persist.hip): one launch per SVD.
 struct PersistArgs {
-    int* barrier;    // h arrival counters, zero before the launch
-    int* rotflag;    // 3 x h sweep flags, zero before the launch
-    int* err;        // set to 1 if a barrier wait ran out
-    int* bflag;      // h x nb block-ready flags, zero before the launch
+    int* pbar;        // int words, zero before the launch except the error word (zero
+                      // before the first launch of a call): h barrier counters, 3 x h
+                      // sweep flags, the error word (bit 1: a wait between workgroups
+                      // gave up; bit 2: a wait inside one ran out), the role ticket,
+                      // h x nb block-ready flags
     int max_sweeps;
-    long long* trace;  // optional: 64 timestamps of workgroup 0 of slice 0
-    int cooperative;   // 1: cooperative launch (co-residency guaranteed by the runtime; slower to launch)
-    int xcds;          // > 0: workgroups of a slice share one XCD (workgroup b runs on XCD b mod xcds)
-    int spread;        // 1: reserve over half a CU's LDS, so no two workgroups share a CU
+    int spin_limit;   // polls of a wait between workgroups before it gives up
+    int spread;       // 1: reserve over half a CU's LDS, so no two workgroups share a CU
 };
 int jacobi_persistent_blocks(int n);
-bool jacobi_persistent_fits(int m, int n, int h, int elem_bytes, int cus, size_t lds_cap, int xcds);
+bool jacobi_persistent_fits(int m, int n, int h, int elem_bytes, int cus, size_t lds_cap);
 template <typename T>
 hipError_t launch_jacobi_persistent(const JacArgs<T>& a, const PersistArgs& p, int cus, hipStream_t st);
 

@@ -30,7 +30,7 @@ def test_header_declares_the_boundary():
     names = declared_functions()
     for fn in ("tsvt", "tsvd_complete", "trpca", "tsvd_create", "tsvd_destroy", "tsvd_set_stream",
                "tsvd_status_string", "tsvd_last_error", "tsvd_batch_run", "tsvd_submit", "tsvd_poll",
-               "tsvd_serve_stats_read", "tsvd_factors", "tsvd_compress"):
+               "tsvd_serve_stats_read", "tsvd_factors", "tsvd_compress", "tsvd_cancel"):
         assert fn in names
 
 
@@ -82,6 +82,31 @@ def test_batch_struct_layouts_match_c(tmp_path):
     want = [ctypes.sizeof(P), P.shape.offset, P.x.offset, P.penalty.offset, P.opts.offset, P.out_s.offset,
             ctypes.sizeof(lib.ServeStats), lib.ServeStats.peak_running.offset]
     assert got == want
+
+
+def test_state_and_stat_layouts_match_c(tmp_path):
+    src = tmp_path / "layout3.c"
+    src.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "tsvd.h"\n'
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(tsvd_state),"
+        " offsetof(tsvd_state, penalty), offsetof(tsvd_state, iter), offsetof(tsvd_state, save),"
+        " offsetof(tsvd_admm_opts, state), sizeof(tsvd_kernel_stat), offsetof(tsvd_kernel_stat, slice_sweeps),"
+        " offsetof(tsvd_kernel_stat, rotations), offsetof(tsvd_problem, deadline_s));return 0;}\n")
+    exe = tmp_path / "layout3"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = list(map(int, subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()))
+    S, K = lib.StateRecord, lib.KernelStat
+    want = [ctypes.sizeof(S), S.penalty.offset, S.iter.offset, S.save.offset, lib.AdmmOpts.state.offset,
+            ctypes.sizeof(K), K.slice_sweeps.offset, K.rotations.offset, lib.ProblemRecord.deadline_s.offset]
+    assert got == want
+
+
+def test_serving_status_strings():
+    if not os.path.exists(lib.library_path()):
+        pytest.skip("libtsvd.so not built")
+    so = lib.load_library()
+    assert so.tsvd_status_string(-8) == b"cancelled"
+    assert so.tsvd_status_string(-9) == b"deadline passed"
 
 
 def test_busy_status_string():

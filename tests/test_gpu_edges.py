@@ -11,6 +11,7 @@ import pytest
 import paper_1407_1785_amd as lib
 from oracle import admm
 from oracle.tsvt import tsvt as tsvt_oracle
+import workloads
 from tests.gpu_util import announce, rel_fro, to_gpu, torch_cuda
 
 pytestmark = pytest.mark.gpu
@@ -107,3 +108,23 @@ def test_completion_with_everything_observed():
     np.testing.assert_array_equal(out.cpu().numpy(), m)
     ref = admm.complete(m, mask, 1e-2, 1.1, 1e3, max_iter=5, tol=0.0)
     np.testing.assert_array_equal(ref["X"], m)
+
+
+def test_persistent_jacobi_fallback(monkeypatch):
+    """Every wait between the workgroups of the persistent Jacobi gives up at
+    its first poll (spin limit 0 from the host): the workgroups write their
+    blocks home and stop, and the one-workgroup-per-slice kernel finishes the
+    SVDs from there.  Results still match the oracle."""
+    torch = torch_cuda()
+    monkeypatch.setenv("TSVD_PERSIST_SPIN", "0")
+    rng = np.random.default_rng(77)
+    x = rng.normal(size=(96, 80, 12))
+    z_ref, r_ref = tsvt_oracle(x, 4.0)
+    announce("persistent fallback tsvt")
+    z, ranks = lib.tsvt(to_gpu(torch, x), 4.0)
+    assert rel_fro(z.cpu().numpy(), z_ref) <= 1e-10 and ranks == list(r_ref)
+    w = workloads.completion_small(0)
+    ref = admm.complete(w["M_obs"], w["mask"], max_iter=6, tol=0.0)
+    announce("persistent fallback completion")
+    xo, _ = lib.tsvd_complete(to_gpu(torch, w["M_obs"]), to_gpu(torch, w["mask"]), 1e-2, 0.0, max_iter=6)
+    assert rel_fro(xo.cpu().numpy(), ref["X"]) <= 1e-10

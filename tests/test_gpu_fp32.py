@@ -9,7 +9,7 @@ import paper_1407_1785_amd as lib
 from oracle import admm
 from oracle.tsvt import tsvt as tsvt_oracle
 import workloads
-from tests.gpu_util import announce, rel_fro, to_gpu, torch_cuda
+from tests.gpu_util import announce, assert_close_fp32, rel_fro, to_gpu, torch_cuda
 
 pytestmark = pytest.mark.gpu
 
@@ -26,7 +26,7 @@ def test_tsvt_fp32_form(shape):
     announce("tsvt fp32", shape)
     z, _ = lib.tsvt(to_gpu(torch, x), tau, precision=lib.PREC_FP32)
     assert z.dtype == torch.float32
-    assert rel_fro(z.cpu().numpy(), z_ref) <= BAR
+    assert_close_fp32(z.cpu().numpy(), z_ref, BAR, f"tsvt {shape}")
 
 
 def test_tsvt_fp32_video_shape():
@@ -35,7 +35,7 @@ def test_tsvt_fp32_video_shape():
     z_ref, _ = tsvt_oracle(w["X"].astype(np.float64), 5.0)
     announce("tsvt fp32 video")
     z, _ = lib.tsvt(to_gpu(torch, w["X"]), 5.0, precision=lib.PREC_FP32)
-    assert rel_fro(z.cpu().numpy(), z_ref) <= BAR
+    assert_close_fp32(z.cpu().numpy(), z_ref, BAR, "tsvt video")
 
 
 @pytest.mark.parametrize("iters", [5, 60])
@@ -47,7 +47,7 @@ def test_completion_fp32_form(iters):
     x, info = lib.tsvd_complete(to_gpu(torch, w["M_obs"].astype(np.float32)), to_gpu(torch, w["mask"]),
                                 1e-2, 0.0, max_iter=iters, precision=lib.PREC_FP32)
     assert info.iters == iters
-    assert rel_fro(x.cpu().numpy(), ref["X"]) <= BAR
+    assert_close_fp32(x.cpu().numpy(), ref["X"], BAR, f"completion {iters}")
 
 
 def test_completion_fp32_video_prefix():
@@ -59,7 +59,7 @@ def test_completion_fp32_video_prefix():
     announce("complete fp32 video prefix")
     x, _ = lib.tsvd_complete(to_gpu(torch, w["M_obs"]), to_gpu(torch, w["mask"]), w["rho"], 0.0,
                              max_iter=12, precision=lib.PREC_FP32)
-    assert rel_fro(x.cpu().numpy(), ref["X"]) <= BAR
+    assert_close_fp32(x.cpu().numpy(), ref["X"], BAR, "video prefix")
 
 
 def test_trpca_fp32_form():
@@ -69,7 +69,7 @@ def test_trpca_fp32_form():
     announce("trpca fp32")
     lo, sp, info = lib.trpca(to_gpu(torch, p["M"].astype(np.float32)), p["lam"], 1e-3, 0.0,
                              max_iter=40, precision=lib.PREC_FP32)
-    assert rel_fro(lo.cpu().numpy(), ref["L"]) <= BAR
+    assert_close_fp32(lo.cpu().numpy(), ref["L"], BAR, "trpca L")
 
 
 def test_precision_dtype_mismatch_is_rejected():

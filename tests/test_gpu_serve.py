@@ -113,3 +113,64 @@ def test_problem_larger_than_arena_is_refused():
         assert e.value.status == -3
     finally:
         handle.close()
+
+
+def _small_problem(torch, seed, iters=400, shape=(40, 44, 12), **kw):
+    rng = np.random.default_rng(seed)
+    _, _, xt = workloads.lowrank(rng, *shape, 2)
+    mask = (rng.random(shape) < 0.5).astype(np.uint8)
+    return lib.complete_problem(to_gpu(torch, xt * mask), to_gpu(torch, mask), 1e-2, 0.0, max_iter=iters, **kw)
+
+
+def test_cancel_queued_and_running(monkeypatch):
+    """A running request cancelled from the host leaves the batch at the next
+    period boundary with TSVD_E_CANCELLED; a queued one never starts; the
+    others finish normally, and cancelling a finished ticket changes
+    nothing."""
+    torch = torch_cuda()
+    probs = [_small_problem(torch, 60 + k) for k in range(3)]
+    # admission stops at 7 running Fourier slices, one problem's worth: the
+    # second and third wait in the queue
+    monkeypatch.setenv("TSVD_SERVE_SLICES", "7")
+    handle = lib.Handle(0, hbm_budget_bytes=64 << 20)
+    try:
+        announce("serve cancel")
+        tickets = [lib.submit(p, handle) for p in probs]
+        lib.cancel(tickets[2], handle)           # queued
+        time.sleep(0.05)
+        lib.cancel(tickets[0], handle)           # running (400 iterations take longer)
+        done = _wait(tickets, handle)
+        assert done[tickets[0]][0] == lib.E_CANCELLED
+        assert done[tickets[2]][0] == lib.E_CANCELLED
+        assert done[tickets[1]][0] == 0 and done[tickets[1]][1].iters == 400
+        lib.cancel(tickets[1], handle)
+        assert lib.poll(tickets[1], handle)[0] == 0
+        with pytest.raises(lib.TsvdError):
+            lib.cancel(987654, handle)
+        t0 = time.time()
+        while lib.serve_stats(handle)["running"] and time.time() - t0 < 5.0:
+            time.sleep(0.01)
+        stats = lib.serve_stats(handle)
+        assert stats["finished"] == 3 and stats["running"] == 0 and stats["queued"] == 0
+    finally:
+        handle.close()
+
+
+def test_deadline_stops_a_request():
+    """A request whose deadline passes stops with TSVD_E_TIMEOUT (the worker
+    checks deadlines between periods); one without a deadline beside it
+    finishes."""
+    torch = torch_cuda()
+    late = _small_problem(torch, 70, iters=100000, deadline_s=0.2)
+    ok = _small_problem(torch, 71, iters=20)
+    handle = lib.Handle(0, hbm_budget_bytes=64 << 20)
+    try:
+        announce("serve deadline")
+        t_late = lib.submit(late, handle)
+        t_ok = lib.submit(ok, handle)
+        done = _wait([t_late, t_ok], handle)
+        assert done[t_ok][0] == 0 and done[t_ok][1].iters == 20
+        st, info = done[t_late]
+        assert st == lib.E_TIMEOUT and info.seconds >= 0.2
+    finally:
+        handle.close()

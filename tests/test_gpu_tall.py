@@ -7,7 +7,7 @@ import pytest
 import paper_1407_1785_amd as lib
 from oracle import admm
 from oracle.tsvt import tsvt as tsvt_oracle
-from tests.gpu_util import announce, rel_fro, to_gpu, torch_cuda
+from tests.gpu_util import announce, assert_close_fp32, rel_fro, to_gpu, torch_cuda
 
 pytestmark = pytest.mark.gpu
 
@@ -54,7 +54,7 @@ def test_tall_tsvt_fp32_form():
     z_ref, _ = tsvt_oracle(x, tau)
     announce("tall tsvt fp32")
     z, _ = lib.tsvt(to_gpu(torch, x, torch.float32), tau, precision=lib.PREC_FP32)
-    assert rel_fro(z.cpu().numpy().astype(np.float64), z_ref) <= 1e-4
+    assert_close_fp32(z.cpu().numpy(), z_ref, 1e-4, "tall tsvt")
 
 
 def test_tall_low_rank_and_zero_columns():

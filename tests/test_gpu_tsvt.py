@@ -6,7 +6,7 @@ import pytest
 import paper_1407_1785_amd as lib
 from oracle.tsvt import tsvt as tsvt_oracle
 from oracle import tensor as T
-from tests.gpu_util import announce, rel_fro, to_gpu, torch_cuda
+from tests.gpu_util import announce, assert_close_fp32, rel_fro, to_gpu, torch_cuda
 
 pytestmark = pytest.mark.gpu
 
@@ -144,7 +144,7 @@ def test_tsvt_colour_video_size():
     assert rel_fro(z.cpu().numpy(), z_ref) <= TOL
     assert ranks == list(r_ref)
     z32, _ = lib.tsvt(to_gpu(torch, x, torch.float32), tau, precision=lib.PREC_FP32)
-    assert rel_fro(z32.cpu().numpy().astype(np.float64), z_ref) <= 1e-4
+    assert_close_fp32(z32.cpu().numpy(), z_ref, 1e-4, "colour video")
 
 
 def test_tsvt_errors():
