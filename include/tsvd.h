@@ -170,6 +170,23 @@ tsvd_status tsvd_set_stream(tsvd_handle h, void* hip_stream);
 tsvd_status tsvt(tsvd_handle h, const void* X, tsvd_shape shape, tsvd_dtype dtype, double tau,
                  tsvd_precision precision, void* Z, int32_t* multirank_host);
 
+/* tsvt without any allocation, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, results and errors as tsvt (up to
+ * rounding: the DFT matrices are built on the device here).  No hipMalloc,
+ * hipFree or other allocating call is made: the workspace is a fixed array
+ * of 64 MiB per GPU (a static device array, held by every GPU the library
+ * runs on until the process ends), enough for slices and factors of about
+ * 48 MB, e.g. a 128 x 160 x 64 tensor in FP64 or 256 x 200 x 64 in FP32.
+ * A shape that needs more fails with TSVD_E_NOMEM before any device work.
+ * Every call on a GPU uses that GPU's one array, whatever the handle: calls
+ * that overlap on one GPU (from several threads or streams) race and must
+ * be serialised by the caller; the array keeps the last call's contents,
+ * and each call clears what it needs cleared.  Profiling records nothing
+ * for this call. */
+tsvd_status tsvt_noalloc(tsvd_handle h, const void* X, tsvd_shape shape, tsvd_dtype dtype, double tau,
+                         tsvd_precision precision, void* Z, int32_t* multirank_host);
+
 /* Tensor completion by TNN minimisation (Sec. 4):
  *     min ||X||_TNN  subject to  P_Omega(X) = P_Omega(M),
  * solved by the ADMM of Sec. 4 with a scaled dual Q (X-update = projection

@@ -35,7 +35,7 @@ __all__ = [
     "LibraryNotBuilt", "TsvdError", "Info", "library_path", "load_library", "tsvt",
     "tsvd_complete", "trpca", "Handle", "PREC_FP64", "PREC_FP32", "SHRINK_L1", "SHRINK_L112",
     "Problem", "complete_problem", "trpca_problem", "batch_run", "submit", "poll", "serve_stats",
-    "tsvd_factors", "compress", "COMPRESS_TSVD", "COMPRESS_TUBAL", "SolverState", "cancel",
+    "tsvd_factors", "compress", "COMPRESS_TSVD", "COMPRESS_TUBAL", "SolverState", "cancel", "tsvt_noalloc",
     "close_all",
 ]
 
@@ -139,6 +139,8 @@ _SIGNATURES = {
                              ctypes.c_double, ctypes.c_double, ctypes.c_int,
                              ctypes.POINTER(AdmmOpts), ctypes.c_void_p, ctypes.c_void_p,
                              ctypes.POINTER(Info)]),
+    "tsvt_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, Shape, ctypes.c_int, ctypes.c_double,
+                                    ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
     "tsvd_factors": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, Shape, ctypes.c_int, ctypes.c_int,
                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "tsvd_compress": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, Shape, ctypes.c_int, ctypes.c_int,
@@ -383,6 +385,24 @@ def tsvt(X, tau: float, precision: int = PREC_FP64, handle: Handle | None = None
     ranks = (ctypes.c_int32 * h)()
     _check(load_library().tsvt(handle.ptr, ctypes.c_void_p(X.data_ptr()), _shape(X), _dtype_code(X),
                                float(tau), int(precision), ctypes.c_void_p(Z.data_ptr()), ranks))
+    return Z, list(ranks)
+
+
+def tsvt_noalloc(X, tau: float, precision: int = PREC_FP64, handle: Handle | None = None, Z=None):
+    """t-SVT through the no-allocation entry point (include/tsvd.h,
+    ``tsvt_noalloc``): the library allocates nothing; ``Z`` (optional) is the
+    caller's output tensor.  Returns (Z, multirank)."""
+    import torch
+
+    X = _prepare(X, "X")
+    handle = handle or _handle_for(X)
+    _bind_stream(handle, X)
+    if Z is None:
+        Z = torch.empty_like(X)
+    h = _n_slices(X)
+    ranks = (ctypes.c_int32 * h)()
+    _check(load_library().tsvt_noalloc(handle.ptr, ctypes.c_void_p(X.data_ptr()), _shape(X), _dtype_code(X),
+                                       float(tau), int(precision), ctypes.c_void_p(Z.data_ptr()), ranks))
     return Z, list(ranks)
 
 

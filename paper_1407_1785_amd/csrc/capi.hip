@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -197,6 +198,28 @@ const T* ensure_dft_matrices(tsvd_handle h, const Geometry& g) {
               "hipMemcpy DFT matrices");
     h->dmat_key = key;
     return static_cast<const T*>(h->dmat);
+}
+
+// Scratch of tsvt_noalloc (include/tsvd.h): every GPU the library runs on
+// holds one copy of this array until the process ends, shared by every
+// handle on that GPU.  Host code never takes its name as an address: the
+// device address of each GPU's copy is looked up once per device, with that
+// device current, when the first handle on it is created (scratch_address).
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+std::vector<char*> g_scratch_ptr;   // per device; nullptr until looked up
+
+char* scratch_address(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if ((int)g_scratch_ptr.size() <= device) g_scratch_ptr.resize(device + 1, nullptr);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress scratch");
+        if (!p) fail(TSVD_E_HIP, "no device address for the scratch array");
+        g_scratch_ptr[device] = static_cast<char*>(p);
+    }
+    return g_scratch_ptr[device];
 }
 
 // Kernel families reported by tsvd_profile_read.
@@ -658,9 +681,12 @@ void copy_d2d(void* dst, const void* src, size_t bytes, hipStream_t st) {
 
 }  // namespace
 
+// t-SVT.  scratch == nullptr: workspace and DFT matrices of the handle
+// (allocated or grown as needed); otherwise both are carved from `scratch`
+// (the no-allocation entry point), the DFT matrices built on the device.
 template <typename T>
 void do_tsvt(tsvd_handle h, const void* X, tsvd_shape shape, tsvd_dtype dtype, double tau,
-                 tsvd_precision precision, void* Z, int32_t* multirank_host) {
+                 tsvd_precision precision, void* Z, int32_t* multirank_host, char* scratch = nullptr) {
         check_handle(h);
         if (!X || !Z) fail(TSVD_E_INVALID, "null tensor pointer");
         if (!(tau >= 0.0) || !std::isfinite(tau)) fail(TSVD_E_INVALID, "tau must be finite and >= 0");
@@ -669,10 +695,27 @@ void do_tsvt(tsvd_handle h, const void* X, tsvd_shape shape, tsvd_dtype dtype, d
         if (!jacobi_supported(g.m, g.n, sizeof(T))) fail(TSVD_E_SHAPE, "slice too large for the Jacobi kernels");
         Device dev(h->device);
         const int nparts = (int)dft_grid(g, dft_inverse_tile(g, EPI_STORE));
-        ensure_workspace(h, svt_bytes<T>(g, nparts) + 4096);
-        Carver cv{reinterpret_cast<char*>(h->ws)};
-        SvtBuffers<T> sb = carve_svt<T>(cv, g, nparts);
-        const T* dmat = ensure_dft_matrices<T>(h, g);
+        const T* dmat = nullptr;
+        SvtBuffers<T> sb;
+        if (!scratch) {
+            ensure_workspace(h, svt_bytes<T>(g, nparts) + 4096);
+            Carver cv{reinterpret_cast<char*>(h->ws)};
+            sb = carve_svt<T>(cv, g, nparts);
+            dmat = ensure_dft_matrices<T>(h, g);
+        } else {
+            const int64_t mat_elems = DftDims::of(g.h, g.L).total();
+            const size_t need = svt_bytes<T>(g, nparts) + mat_elems * sizeof(T) + 4096;
+            if (need > kScratchBytes)
+                fail(TSVD_E_NOMEM, "t-SVT of this shape needs " + std::to_string(need) +
+                                       " bytes of workspace, over the no-allocation scratch of " +
+                                       std::to_string(kScratchBytes) + " bytes");
+            Carver cv{scratch};
+            sb = carve_svt<T>(cv, g, nparts);
+            T* mat = cv.take<T>(mat_elems);
+            launch_dft_matrices<T>(mat, g, h->stream);
+            launch_check("dft matrices");
+            dmat = mat;
+        }
         upload_fallback<T>(h, g, sb, 30);
         Ctrl c{};
         c.rho = tau > 0 ? 1.0 / tau : INFINITY;
@@ -1195,12 +1238,27 @@ tsvd_status tsvd_create(int device, size_t hbm_budget_bytes, tsvd_handle* out) {
         if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&h->host_ctrl), sizeof(Ctrl), 0);
         if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&h->rot_counter), 2 * sizeof(unsigned long long));
         if (e == hipSuccess) e = hipMemset(h->rot_counter, 0, 2 * sizeof(unsigned long long));
+        // host staging sized for every shape, so later calls never allocate it
+        if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&h->host_ints), sizeof(int) * kMaxSlices, 0);
+        if (e == hipSuccess) h->host_ints_len = kMaxSlices;
+        if (e == hipSuccess) e = hipHostMalloc(&h->host_stage, 4096, 0);
+        if (e == hipSuccess) h->host_stage_len = 4096;
         h->agg.assign(K_COUNT, tsvd_handle_s::Agg{});
         if (e != hipSuccess) {
             if (h->ctrl) (void)hipFree(h->ctrl);
             if (h->flag) (void)hipFree(h->flag);
+            if (h->rot_counter) (void)hipFree(h->rot_counter);
+            if (h->host_ctrl) (void)hipHostFree(h->host_ctrl);
+            if (h->host_ints) (void)hipHostFree(h->host_ints);
+            if (h->host_stage) (void)hipHostFree(h->host_stage);
             delete h;
             fail(TSVD_E_HIP, std::string("handle allocation: ") + hipGetErrorString(e));
+        }
+        try {
+            h->scratch = scratch_address(device);
+        } catch (...) {
+            tsvd_destroy(h);
+            throw;
         }
         *out = h;
     });
@@ -1248,6 +1306,25 @@ tsvd_status tsvt(tsvd_handle h, const void* X, tsvd_shape shape, tsvd_dtype dtyp
             do_tsvt<float>(h, X, shape, dtype, tau, precision, Z, multirank_host);
         else
             do_tsvt<double>(h, X, shape, dtype, tau, precision, Z, multirank_host);
+    });
+}
+
+tsvd_status tsvt_noalloc(tsvd_handle h, const void* X, tsvd_shape shape, tsvd_dtype dtype, double tau,
+                         tsvd_precision precision, void* Z, int32_t* multirank_host) {
+    return guarded([&] {
+        check_handle(h);
+        // no events are created for this call: profiling records nothing
+        const bool prof = h->prof_on;
+        h->prof_on = false;
+        struct Restore {
+            tsvd_handle h;
+            bool prof;
+            ~Restore() { h->prof_on = prof; }
+        } restore{h, prof};
+        if (check_precision(dtype, precision))
+            do_tsvt<float>(h, X, shape, dtype, tau, precision, Z, multirank_host, h->scratch);
+        else
+            do_tsvt<double>(h, X, shape, dtype, tau, precision, Z, multirank_host, h->scratch);
     });
 }
 

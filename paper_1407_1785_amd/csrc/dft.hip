@@ -35,6 +35,8 @@
 
 #include "kernels.h"
 
+#include <algorithm>
+
 namespace tsvd {
 
 namespace {
@@ -580,6 +582,61 @@ void launch_dft_inverse(int epilogue, const InvArgs<T>& a, hipStream_t st) {
     }
 }
 
+// The DFT matrices of a tube shape (layout in kernels.h, DftDims), built on
+// the device: the twiddle exp(-2 pi i u / L) in FP64 (the quarter points
+// exact, else sincospi), rounded once to the element type.  One thread per
+// entry; entries outside s < h, t < L are zero.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void dft_matrices_kernel(T* out, Geometry g, DftDims d) {
+    const int64_t total = d.total();
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int s, t, part;   // part: 0 forward Re, 1 forward Im, 2 inverse Re, 3 inverse Im
+        if (i < d.fwd_size()) {
+            t = (int)(i / (2 * d.hp));
+            const int col = (int)(i - (int64_t)t * 2 * d.hp);
+            part = col >= d.hp ? 1 : 0;
+            s = col - part * d.hp;
+        } else {
+            const int64_t j = i - d.fwd_size();
+            const int row = (int)(j / d.Lr);
+            t = (int)(j - (int64_t)row * d.Lr);
+            s = row >> 1;
+            part = 2 + (row & 1);
+        }
+        T v = (T)0;
+        if (s < g.h && t < g.L) {
+            const int k3 = s / g.Qh, k4 = s - k3 * g.Qh;
+            const int t3 = t / g.Q, t4 = t - t3 * g.Q;
+            const int64_t u = ((int64_t)t3 * k3 * g.Q + (int64_t)t4 * k4 * g.P) % g.L;
+            double re, im;
+            if ((4 * u) % g.L == 0) {
+                const int q = (int)((4 * u) / g.L);
+                re = q == 0 ? 1.0 : (q == 2 ? -1.0 : 0.0);
+                im = q == 1 ? -1.0 : (q == 3 ? 1.0 : 0.0);
+            } else {
+                sincospi(-2.0 * (double)u / (double)g.L, &im, &re);
+            }
+            if (part < 2) {
+                v = (T)(part ? im : re);
+            } else {
+                const double c = (k4 == 0 || 2 * k4 == g.Q) ? 1.0 : 2.0;
+                v = (T)(c / g.L * (part == 3 ? im : re));
+            }
+        }
+        out[i] = v;
+    }
+}
+
+template <typename T>
+void launch_dft_matrices(T* out, const Geometry& g, hipStream_t st) {
+    const DftDims d = DftDims::of(g.h, g.L);
+    const int64_t blocks = std::min<int64_t>((d.total() + kBlock - 1) / kBlock, 1024);
+    hipLaunchKernelGGL((dft_matrices_kernel<T>), dim3((unsigned)blocks), dim3(kBlock), 0, st, out, g, d);
+}
+
+template void launch_dft_matrices<double>(double*, const Geometry&, hipStream_t);
+template void launch_dft_matrices<float>(float*, const Geometry&, hipStream_t);
 template void prepare_dft_batched<double>(size_t, size_t);
 template void prepare_dft_batched<float>(size_t, size_t);
 template size_t dft_forward_lds<double>(const Geometry&, int);

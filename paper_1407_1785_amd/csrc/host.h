@@ -59,6 +59,7 @@ inline double jacobi_tol(int m, int elem_bytes) {
 constexpr int kMaxTube = 512;
 constexpr int kMaxSlices = 300;
 constexpr int64_t kMaxRows = 1 << 18;   // longer matrix mode of a slice (tall slices: global-memory Jacobi)
+constexpr size_t kScratchBytes = size_t(64) << 20;   // workspace of tsvt_noalloc, per device
 
 struct Server;   // serving engine of a handle (engine.hip)
 
@@ -117,6 +118,7 @@ struct tsvd_handle_s {
     int cus = 0;
     size_t lds_cap = 0;
     tsvd::Server* server = nullptr;   // batch / serving engine, created on first use
+    char* scratch = nullptr;          // device address of this device's no-allocation scratch
 };
 
 namespace tsvd {

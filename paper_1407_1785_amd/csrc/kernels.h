@@ -238,6 +238,10 @@ void launch_dft_forward_batched(const FwdArgs<T>* tab, const int* wg_start, int 
 template <typename T>
 void launch_dft_inverse_batched(const InvArgs<T>* tab, const int* wg_start, int nprob, int nwg, size_t lds,
                                 hipStream_t st);
+// The forward and inverse DFT matrices of g's tube shape, built on the device
+// (DftDims::of(g.h, g.L).total() elements).
+template <typename T>
+void launch_dft_matrices(T* out, const Geometry& g, hipStream_t st);
 int dft_forward_tile(const Geometry& g);
 int dft_inverse_tile(const Geometry& g, int epilogue);
 int64_t dft_grid(const Geometry& g, int tile);
