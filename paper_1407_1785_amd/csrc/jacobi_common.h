@@ -125,20 +125,28 @@ __device__ __forceinline__ bool prot_needed(double al, double be, double g2, dou
     return g2 > (tol * tol) * al * be && g2 > 0.0;
 }
 
+// The rotation through d = beta - alpha and r = sqrt(d^2 + 4 |gamma|^2)
+// rather than the cotangent zeta = d / (2 |gamma|): with D = |d| + r,
+// t = sgn(d) 2 |gamma| / D, c = 1 / sqrt(1 + t^2) = D / sqrt(D^2 + 4 |gamma|^2)
+// = D / sqrt(2 r D), s e = t c gamma / |gamma| = sgn(d) 2 c gamma / D and
+// t |gamma| = sgn(d) 2 |gamma|^2 / D (sgn(0) = +1).  Nothing cancels (|d| and
+// r are both >= 0), and only two reciprocal square roots and a reciprocal
+// are needed, the last two independent of each other: a shorter dependent
+// chain than through zeta.
 template <typename T>
 __device__ __forceinline__ PRot prot_params(double al, double be, double gr, double gi, double g2) {
     constexpr int NS = sizeof(T) == 4 ? 1 : 2;
     PRot r;
-    const double rg = prsqrt<NS>(g2);
-    const double zeta = (be - al) * 0.5 * rg;
-    const double q = 1.0 + zeta * zeta;
-    const double t = prcp(fabs(zeta) + q * prsqrt<NS>(q));
-    const double ts = zeta >= 0.0 ? t : -t;
-    r.c = prsqrt<NS>(1.0 + ts * ts);
-    const double s = r.c * ts;
-    r.a = s * (gr * rg);
-    r.b = s * (gi * rg);
-    r.tg = ts * (g2 * rg);
+    const double d = be - al;
+    const double q = d * d + 4.0 * g2;
+    const double rq = q * prsqrt<NS>(q);
+    const double D = fabs(d) + rq;
+    const double iD = prcp(D);
+    r.c = D * prsqrt<NS>(2.0 * rq * D);
+    const double f = (d >= 0.0 ? 2.0 : -2.0) * iD;
+    r.a = f * r.c * gr;
+    r.b = f * r.c * gi;
+    r.tg = f * g2;
     r.on = true;
     return r;
 }
