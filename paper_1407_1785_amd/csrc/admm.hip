@@ -83,9 +83,12 @@ __global__ __launch_bounds__(kBlock) void admm_ctrl_kernel(Ctrl* c, const double
 __global__ __launch_bounds__(kBlock) void admm_ctrl_batched(const CtrlArgs* tab) {
     const CtrlArgs& a = tab[blockIdx.x];
     if (a.c->done) return;
-    // ring 0 of the round-mode Jacobi flags starts clear for the next SVD
+    // ring 0 of the pairs-parallel Jacobi's sweep flags and its barrier
+    // area start clear for the next SVD
     if (a.rot_ring0)
         for (int s = threadIdx.x; s < a.h; s += blockDim.x) a.rot_ring0[s] = 0;
+    if (a.clr)
+        for (int s = threadIdx.x; s < a.nclr; s += blockDim.x) a.clr[s] = 0;
     admm_ctrl_body(a.c, a.partials, a.nparts, a.rpca);
 }
 

@@ -6,9 +6,10 @@
 // "problem-table launches"):
 //   forward DFT + prologue -> Newton-Schulz V^H V -> Newton-Schulz V update
 //   -> pre-rotation A V -> Jacobi SVD (one launch per block-width / row-count
-//   class, one workgroup per slice; the classes run concurrently on side
-//   streams, forked from and joined back into the engine's stream)
-//   -> singular values -> rebuild
+//   / schedule class: one workgroup per slice, or one per block pair of a
+//   round with the blocks exchanged inside the launch; the classes run
+//   concurrently on side streams, forked from and joined back into the
+//   engine's stream) -> singular values -> rebuild
 //   -> inverse DFT + epilogue -> control step.
 // A problem runs exactly the arithmetic of the single-problem drivers in
 // capi.hip: the first iteration's pre-rotation by V = I is an exact copy, so
@@ -19,7 +20,8 @@
 // Buffers alternate between two parities (the iterates Z/Q, L/S/W and the
 // two V buffers), so two iterations -- one table set per parity -- form one
 // period; the period is captured once into a HIP graph and replayed until the
-// running set changes.  Problems join and leave only between periods.
+// running set changes (no launch depends on a host decision inside a
+// period).  Problems join and leave only between periods.
 //
 // Device memory: each problem's state is one block of a per-engine arena
 // (first-fit allocator, host bookkeeping); admission waits until the block
@@ -106,14 +108,15 @@ struct Slot {
     double* sigma = nullptr;
     double* dk = nullptr;       // shrink factors of the rebuild
     int* sweeps = nullptr;
-    int* rot = nullptr;         // round-mode Jacobi: 3 x h rotation flags
+    int* rot = nullptr;         // pairs-parallel Jacobi: 3 x h rotation flags
+    int* bar = nullptr;         // pairs-parallel Jacobi: barrier counters and block flags
     double* partials = nullptr;
     Ctrl* ctrl = nullptr;
     int* flag = nullptr;
     T* mat = nullptr;           // forward then inverse DFT matrix of the tube shape
     int tile_f = 0, tile_i = 0, inv_parts = 0, pro = 0, epi = 0;
     int bw = 0, rpt = 0, nb = 0;
-    bool round = false;         // Jacobi in round mode (one launch per round)
+    bool pairs = false;         // Jacobi schedule: one workgroup per block pair (else per slice)
 };
 
 template <typename T>
@@ -146,6 +149,8 @@ size_t slot_layout(Slot<T>& sl, char* base) {
     sl.dk = reinterpret_cast<double*>(take((int64_t)g.h * g.n * sizeof(double)));
     sl.sweeps = reinterpret_cast<int*>(take((int64_t)g.h * sizeof(int)));
     sl.rot = reinterpret_cast<int*>(take((int64_t)3 * g.h * sizeof(int)));
+    // sized for the narrowest block width, the most blocks
+    sl.bar = reinterpret_cast<int*>(take(jacobi_pairs_words(g.h, jacobi_num_blocks(g.n, 4)) * sizeof(int)));
     sl.partials = reinterpret_cast<double*>(take((int64_t)nparts * kNumPartials * sizeof(double)));
     sl.ctrl = reinterpret_cast<Ctrl*>(take(sizeof(Ctrl)));
     sl.flag = reinterpret_cast<int*>(take(sizeof(int)));
@@ -164,8 +169,7 @@ struct Tables {
         int nprob = 0, nwg = 0;
         size_t lds = 0;
         int bw = 0, rpt = 0;   // Jacobi classes
-        bool round = false;    // Jacobi classes: round mode
-        int nb_max = 0, sweeps_max = 0;   // round mode: launch schedule
+        bool pairs = false;    // Jacobi classes: pairs-parallel schedule
         double work = 0.0;     // Jacobi classes: sum over slices of n^2 (m + n)
         int lane = 0;          // Jacobi classes: side stream
     };
@@ -197,7 +201,8 @@ public:
         for (int q = 0; q < 2; ++q)
             if (tab_[q].dev) (void)hipFree(tab_[q].dev), tab_[q].dev = nullptr;
         if (host_ctrl_) (void)hipHostFree(host_ctrl_), host_ctrl_ = nullptr;
-        if (flags_) (void)hipHostFree(flags_), flags_ = nullptr, flags_dev_ = nullptr;
+        if (words_) (void)hipFree(words_), words_ = nullptr;
+        if (words_host_) (void)hipHostFree(words_host_), words_host_ = nullptr;
         for (int k = 0; k < kLanes; ++k) {
             if (side_[k]) (void)hipStreamDestroy(side_[k]), side_[k] = nullptr;
             if (ev_join_[k]) (void)hipEventDestroy(ev_join_[k]), ev_join_[k] = nullptr;
@@ -215,13 +220,11 @@ public:
             hip_check(hipEventCreateWithFlags(&ev_join_[k], hipEventDisableTiming), "hipEventCreate");
         }
         hip_check(hipEventCreateWithFlags(&ev_fork_, hipEventDisableTiming), "hipEventCreate");
-        // round mode: one "still rotating" flag per Jacobi class, written by
-        // the device into mapped host memory and read after a stream sync
-        hip_check(hipHostMalloc(reinterpret_cast<void**>(&flags_), sizeof(int) * kMaxClasses,
-                                hipHostMallocMapped | hipHostMallocCoherent),
-                  "hipHostMalloc flags");
-        hip_check(hipHostGetDevicePointer(reinterpret_cast<void**>(&flags_dev_), flags_, 0),
-                  "hipHostGetDevicePointer");
+        // pairs-parallel classes: a role ticket and an error word each,
+        // cleared by a fill kernel at the start of every Jacobi phase
+        hip_check(hipMalloc(reinterpret_cast<void**>(&words_), sizeof(int) * 2 * kMaxClasses), "hipMalloc words");
+        hip_check(hipHostMalloc(reinterpret_cast<void**>(&words_host_), sizeof(int) * 2 * kMaxClasses, 0),
+                  "hipHostMalloc words");
     }
 
     hipStream_t stream() const { return stream_; }
@@ -285,7 +288,11 @@ public:
         for (size_t i = 0; i < n; ++i)
             hip_check(hipMemcpyAsync(host_ctrl_ + i, slots_[i].ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, stream_),
                       "hipMemcpyAsync ctrl");
+        hip_check(hipMemcpyAsync(words_host_, words_, sizeof(int) * 2 * kMaxClasses, hipMemcpyDeviceToHost, stream_),
+                  "hipMemcpyAsync words");
         hip_check(hipStreamSynchronize(stream_), "hipStreamSynchronize");
+        for (int k = 0; k < kMaxClasses; ++k)
+            if (words_host_[2 * k + 1]) fail(TSVD_E_HIP, "a batched Jacobi wait between workgroups gave up");
         std::vector<size_t> stopped;
         for (size_t i = 0; i < n; ++i)
             if (host_ctrl_[i].done) stopped.push_back(i);
@@ -409,6 +416,7 @@ private:
         launch_set_identity<T>(sl.V[0], g.n, g.h, st);
         launch_fill<int>(sl.flag, 0, 1, st);
         launch_fill<int>(sl.rot, 0, 3 * g.h, st);
+        launch_fill<int>(sl.bar, 0, jacobi_pairs_words(g.h, jacobi_num_blocks(g.n, 4)), st);
         launch_sumsq<T>(static_cast<const T*>(p.x), rpca ? nullptr : p.mask, N, sl.partials, 1024, st);
         launch_set_tol(sl.ctrl, sl.partials, 1024, p.tol, st);
         launch_check("problem setup");
@@ -419,11 +427,10 @@ private:
         sl.rpt = jacobi_slice_rpt(g.m, g.n);
         sl.bw = pick_bw(g.m, g.n, sl.rpt);
         sl.nb = jacobi_num_blocks(g.n, sl.bw);
-        // two or more block pairs per slice: one workgroup per pair and a
-        // launch per round (on the 64-problem mix: 5.45 solves/s at a
-        // threshold of 1-3 pairs, 5.33 at 4, 5.15 at 8, 3.0 with every slice
-        // on one workgroup)
-        sl.round = sl.nb / 2 >= env_int("TSVD_ROUND_MIN_PAIRS", 2);
+        // two or more block pairs per slice: one workgroup per block pair,
+        // blocks exchanged between rounds inside the launch; one block pair:
+        // one workgroup per slice with both blocks resident
+        sl.pairs = sl.nb / 2 >= env_int("TSVD_PAIRS_MIN", 2);
     }
 
     void write_outputs(Slot<T>& sl, const Ctrl& c) {
@@ -537,10 +544,6 @@ private:
         for (int q = 0; q < 2; ++q) build_tables(q);
         dirty_ = false;
         if (env_int("TSVD_GRAPH", 1) == 0) return;
-        // round-mode classes size their sweep count from device flags read
-        // by the host mid-iteration: eager launches for such a running set
-        for (const auto& ph : tab_[0].jac)
-            if (ph.round) return;
         hipGraph_t graph = nullptr;
         hip_check(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
         bool ok = true;
@@ -580,10 +583,9 @@ private:
         std::vector<CtrlArgs> ctl;
         std::vector<int> ws_fwd{0}, ws_inv{0}, ws_gram{0}, ws_ns{0}, ws_pre{0}, ws_reb{0}, ws_sig{0};
         size_t lds_f = 0, lds_i = 0;
-        using JKey = std::tuple<int, int, int>;   // (bw, rpt, round)
+        using JKey = std::tuple<int, int, int>;   // (bw, rpt, pairs)
         std::map<JKey, std::pair<std::vector<JacSliceArgs<T>>, std::vector<int>>> jc;
         std::map<JKey, double> jwork;
-        std::map<JKey, std::pair<int, int>> jsched;   // round mode: (max nb, max sweeps)
         for (const Slot<T>& sl : slots_) {
             const Geometry& g = sl.sp.g;
             const tsvd_problem& p = sl.sp.p;
@@ -670,15 +672,13 @@ private:
             ja.ctrl = sl.ctrl;
             ja.max_sweeps = sl.sp.s.max_sweeps;
             ja.rot = sl.rot;
-            const JKey key{sl.bw, sl.rpt, sl.round ? 1 : 0};
+            ja.bar = sl.bar;
+            const JKey key{sl.bw, sl.rpt, sl.pairs ? 1 : 0};
             auto& cls = jc[key];
             if (cls.second.empty()) cls.second.push_back(0);
             cls.first.push_back(ja);
-            cls.second.push_back(cls.second.back() + g.h * (sl.round ? sl.nb / 2 : 1));
+            cls.second.push_back(cls.second.back() + g.h * (sl.pairs ? sl.nb / 2 : 1));
             jwork[key] += (double)g.h * g.n * g.n * (g.m + g.n);
-            auto& sc = jsched[key];
-            sc.first = std::max(sc.first, sl.nb);
-            sc.second = std::max(sc.second, sl.sp.s.max_sweeps);
             // singular values and rebuild A = W diag(d) V'^H
             SigmaArgs<T> sa{sl.W, g.m, g.n, g.h, sl.sigma, sl.dk, sl.ctrl};
             sig.push_back(sa);
@@ -719,8 +719,9 @@ private:
             inv.push_back(ia);
             ws_inv.push_back(ws_inv.back() + sl.inv_parts);
             lds_i = std::max(lds_i, dft_inverse_lds<T>(g, sl.tile_i, sl.epi));
-            ctl.push_back(CtrlArgs{sl.ctrl, sl.partials, sl.inv_parts, rpca ? 1 : 0, sl.round ? sl.rot : nullptr,
-                                   g.h});
+            ctl.push_back(CtrlArgs{sl.ctrl, sl.partials, sl.inv_parts, rpca ? 1 : 0, sl.pairs ? sl.rot : nullptr, g.h,
+                                   sl.pairs ? sl.bar : nullptr,
+                                   sl.pairs ? (int)jacobi_pairs_words(g.h, sl.nb) : 0});
         }
         auto put = [&](typename Tables<T>::Phase& ph, auto& args, std::vector<int>& ws, size_t lds) {
             ph.args_off = append(tb.host, args);
@@ -744,13 +745,12 @@ private:
             put(ph, kv.second.first, kv.second.second, 0);
             ph.bw = std::get<0>(kv.first);
             ph.rpt = std::get<1>(kv.first);
-            ph.round = std::get<2>(kv.first) != 0;
-            ph.nb_max = jsched[kv.first].first;
-            ph.sweeps_max = jsched[kv.first].second;
+            ph.pairs = std::get<2>(kv.first) != 0;
             ph.work = jwork[kv.first];
             hip_check(prepare_jacobi_slice<T>(ph.bw, ph.rpt), "jacobi attribute");
             tb.jac.push_back(ph);
         }
+        if ((int)tb.jac.size() > kMaxClasses) fail(TSVD_E_UNSUPPORTED, "too many Jacobi classes");
         // the classes run concurrently on kLanes streams: largest work first,
         // each to the least loaded stream
         std::sort(tb.jac.begin(), tb.jac.end(), [](const auto& a, const auto& b) { return a.work > b.work; });
@@ -780,63 +780,6 @@ private:
         return reinterpret_cast<const int*>(tb.dev + ph.ws_off);
     }
 
-    // One sweep of a round-mode class: nb - 1 launches, one per round;
-    // converged slices return at once.
-    void round_sweep(const Tables<T>& tb, const typename Tables<T>::Phase& ph, int sw) {
-        for (int rd = 0; rd < ph.nb_max - 1; ++rd)
-            hip_check(launch_jacobi_round<T>(ph.bw, ph.rpt, targs<JacSliceArgs<T>>(tb, ph), tws(tb, ph), ph.nprob,
-                                             ph.nwg, sw, rd, side_[ph.lane]),
-                      "batched jacobi round");
-    }
-
-    // Round-mode classes: launch an estimated number of sweeps per class,
-    // then one sweep at a time while some slice of the class still rotated
-    // in its last sweep (a device flag in mapped host memory, read after a
-    // sync of the side streams) and is below its cap.  The estimate follows
-    // the sweeps the class needed in the previous iteration.
-    void round_sweeps(const Tables<T>& tb) {
-        struct Run {
-            const typename Tables<T>::Phase* ph;
-            int sw, k, slot;
-            int* est;
-        };
-        std::vector<Run> runs;
-        for (const auto& ph : tb.jac) {
-            if (!ph.round) continue;
-            if ((int)runs.size() >= kMaxClasses) fail(TSVD_E_UNSUPPORTED, "too many Jacobi classes");
-            int& est = sweep_est_[{ph.bw, ph.rpt}];
-            if (est <= 0) est = kSweepEstimate0;
-            // at least one sweep, so the flag kernel reads the ring entry of sweep k - 1 >= 0
-            runs.push_back(Run{&ph, 0, std::max(1, std::min(est, ph.sweeps_max)), (int)runs.size(), &est});
-        }
-        if (runs.empty()) return;
-        for (Run& r : runs) {
-            for (; r.sw < r.k; ++r.sw) round_sweep(tb, *r.ph, r.sw);
-            launch_jacobi_round_active<T>(targs<JacSliceArgs<T>>(tb, *r.ph), r.ph->nprob, r.sw - 1,
-                                          flags_dev_ + r.slot, side_[r.ph->lane]);
-        }
-        launch_check("batched jacobi rounds");
-        for (;;) {
-            bool lanes[kLanes] = {};
-            for (const Run& r : runs) lanes[r.ph->lane] = true;
-            for (int k = 0; k < kLanes; ++k)
-                if (lanes[k]) hip_check(hipStreamSynchronize(side_[k]), "hipStreamSynchronize");
-            bool more = false;
-            for (Run& r : runs) {
-                const bool active = reinterpret_cast<volatile int*>(flags_)[r.slot] != 0 && r.sw < r.ph->sweeps_max;
-                if (!active) continue;
-                round_sweep(tb, *r.ph, r.sw);
-                launch_jacobi_round_active<T>(targs<JacSliceArgs<T>>(tb, *r.ph), r.ph->nprob, r.sw,
-                                              flags_dev_ + r.slot, side_[r.ph->lane]);
-                ++r.sw;
-                more = true;
-            }
-            if (!more) break;
-            launch_check("batched jacobi rounds");
-        }
-        for (Run& r : runs) *r.est = r.sw > r.k ? r.sw : std::max(kSweepEstimateMin, r.k - 1);
-    }
-
     void iteration(int par) {
         const Tables<T>& tb = tab_[par];
         hipStream_t st = stream_;
@@ -847,21 +790,26 @@ private:
         launch_zgemm_batched<T>(targs<ZGemmArgs<T>>(tb, tb.ns), tws(tb, tb.ns), tb.ns.nprob, tb.ns.nwg, st);
         launch_zgemm_batched<T>(targs<ZGemmArgs<T>>(tb, tb.pre), tws(tb, tb.pre), tb.pre.nprob, tb.pre.nwg, st);
         launch_check("batched warm start");
+        // role tickets and error words of the pairs-parallel classes
+        launch_fill<int>(words_, 0, 2 * kMaxClasses, st);
         // fork: the Jacobi classes on the side streams, then join
         hip_check(hipEventRecord(ev_fork_, st), "hipEventRecord");
         bool used[kLanes] = {};
         for (const auto& ph : tb.jac) used[ph.lane] = true;
         for (int k = 0; k < kLanes; ++k)
             if (used[k]) hip_check(hipStreamWaitEvent(side_[k], ev_fork_, 0), "hipStreamWaitEvent");
-        for (const auto& ph : tb.jac) {
-            if (!ph.round) {
+        const int spin = std::max(0, env_int("TSVD_PERSIST_SPIN", 1 << 21));
+        for (size_t c = 0; c < tb.jac.size(); ++c) {
+            const auto& ph = tb.jac[c];
+            if (ph.pairs)
+                hip_check(launch_jacobi_pairs<T>(ph.bw, ph.rpt, targs<JacSliceArgs<T>>(tb, ph), tws(tb, ph), ph.nprob,
+                                                 ph.nwg, words_ + 2 * c, spin, side_[ph.lane]),
+                          "batched jacobi pairs");
+            else
                 hip_check(launch_jacobi_slice<T>(ph.bw, ph.rpt, targs<JacSliceArgs<T>>(tb, ph), tws(tb, ph),
                                                  ph.nprob, ph.nwg, 30, side_[ph.lane]),
                           "batched jacobi");
-                continue;
-            }
         }
-        round_sweeps(tb);
         for (int k = 0; k < kLanes; ++k)
             if (used[k]) {
                 hip_check(hipEventRecord(ev_join_[k], side_[k]), "hipEventRecord");
@@ -889,12 +837,9 @@ private:
     hipGraphExec_t graph_exec_ = nullptr;
     Ctrl* host_ctrl_ = nullptr;
     size_t host_ctrl_len_ = 0;
-    static constexpr int kMaxClasses = 64;       // round-mode flags
-    static constexpr int kSweepEstimate0 = 8;    // first sweep estimate of a class
-    static constexpr int kSweepEstimateMin = 2;
-    int* flags_ = nullptr;                        // mapped host memory
-    int* flags_dev_ = nullptr;                    // its device address
-    std::map<std::pair<int, int>, int> sweep_est_;   // (bw, rpt) -> sweeps
+    static constexpr int kMaxClasses = 64;       // Jacobi classes of a running set
+    int* words_ = nullptr;                        // per class: role ticket, error word
+    int* words_host_ = nullptr;                   // pinned copy read by harvest
     int64_t iterations_ = 0;
 };
 

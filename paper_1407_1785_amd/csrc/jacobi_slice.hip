@@ -10,8 +10,8 @@
 // columns: m slice rows, then n rows of V) from global memory into LDS,
 // orthogonalising them against each other (and, in the first round of a
 // sweep, internally) and writing them back.  With nb = 2 the two blocks stay
-// in LDS for the whole SVD.  The slice stops after a sweep that rotated
-// nothing, or after max_sweeps.
+// in LDS for the whole SVD.  The slice stops after a sweep none of whose
+// rotations forces another (rot_forces_sweep), or after max_sweeps.
 //
 // Work split as in jacobi_persist.hip: a column pair per group of PG = 32
 // lanes, BW pairs per step (BW = 4, 8 or 16 columns per block: the block
@@ -19,10 +19,10 @@
 // in LDS), rotation parameters in FP64, norms exact at the start of a round
 // and tracked through it.
 //
-// Round mode (jacobi_round_kernel) for slices with many blocks: one launch
-// per (sweep, round) and one workgroup per block pair, so a large slice is
-// worked on by nb/2 workgroups at once; the launch boundaries order the
-// rounds.
+// Pairs-parallel schedule (jacobi_pairs_kernel) for slices with many
+// blocks: one workgroup per block pair of a round, so a large slice is worked
+// on by nb/2 workgroups at once, all sweeps in one launch (the blocks travel
+// between the workgroups through global memory inside the launch).
 //
 // Launch: a table of problems; workgroup b serves problem p when
 // wg_start[p] <= b < wg_start[p + 1], slice b - wg_start[p].  A problem
@@ -219,83 +219,191 @@ __global__ __launch_bounds__(BW * kPGs) void jacobi_slice_kernel(const JacSliceA
     if (l == 0 && nrot && a.rotations) atomicAdd(a.rotations, (unsigned long long)nrot);
 }
 
-// Round mode: one launch per (sweep, round); workgroup b of problem p takes
-// slice (b - wg_start[p]) / G, block pair (b - wg_start[p]) % G.  A slice
-// whose previous sweep forced no further sweep (rot_forces_sweep) is
-// skipped; sweep k records such rotations in rot[(k % 3) h + s] and clears
-// rot[((k + 1) % 3) h + s], the
-// entry that nobody reads or writes during sweep k (ring 0 is cleared by the
-// control step before every SVD).
+// Pairs-parallel schedule: nb / 2 workgroups per slice, one per block pair
+// of a round, all sweeps in one launch.  Workgroup roles (problem, slice,
+// block pair) come in order from words[0], as in jacobi_persist.hip, so the workgroups of a slice wait only
+// for workgroups that run or start as soon as others finish; between rounds
+// a workgroup writes the blocks that move to their home columns with
+// device-coherent stores, sets their ready flags to the round that takes them
+// next and waits for the flags of the blocks it takes next; at the end of a
+// sweep the slice's workgroups meet at a counter barrier and stop together
+// when no rotation of the sweep forces another.  Every wait between
+// workgroups is bounded (spin_limit polls); one that gives up sets words[1],
+// and every workgroup that meets it writes its resident blocks home and
+// stops.  The rotations, their order and the stopping rule are those of the
+// one-workgroup-per-slice kernel (pair_round per block pair and round), so
+// both schedules give the same results bit for bit.
+__device__ bool pairs_barrier(int* counter, int target, int* err, int spin_limit) {
+    __shared__ int ok;
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ok = 1;
+        __hip_atomic_fetch_add(counter, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int spins = 0;
+        while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(2);
+            if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 || ++spins > spin_limit) {
+                __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = 0;
+                break;
+            }
+        }
+    }
+    __syncthreads();
+    return ok != 0;
+}
+
+__device__ bool pairs_wait_flag(int* flag, int value, int* err, int spin_limit) {
+    int spins = 0;
+    while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < value) {
+        __builtin_amdgcn_s_sleep(1);
+        if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 || ++spins > spin_limit) {
+            __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+    }
+    return true;
+}
+
 template <typename T, int BW, int RPT>
-__global__ __launch_bounds__(BW * kPGs) void jacobi_round_kernel(const JacSliceArgs<T>* tab, const int* wg_start,
-                                                                  int nprob, int sweep, int rd) {
+__global__ __launch_bounds__(BW * kPGs) void jacobi_pairs_kernel(const JacSliceArgs<T>* tab, const int* role_start,
+                                                                  int nprob, int* words, int spin_limit) {
     constexpr int PG = kPGs, NT = BW * PG;
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int rot_any;
+    __shared__ int role_s, rot_any, stop, ok_flag;
     __shared__ double jnorm[BW];
-    const int p = batch_find(wg_start, nprob, (int)blockIdx.x);
+    if (threadIdx.x == 0) role_s = __hip_atomic_fetch_add(words, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const int role = __builtin_amdgcn_readfirstlane(role_s);
+    const int p = batch_find(role_start, nprob, role);
     const JacSliceArgs<T>& a = tab[p];
-    if (a.ctrl && a.ctrl->done) return;
-    if (a.only_if && *a.only_if == 0) return;
-    const int m = a.m, n = a.n, nb = a.nb, G = nb / 2;
-    if (sweep >= (a.max_sweeps > 0 ? a.max_sweeps : 30) || rd >= nb - 1) return;
-    const int local = (int)blockIdx.x - wg_start[p];
+    if (a.ctrl && a.ctrl->done) return;   // every workgroup of the problem returns
+    const int m = a.m, n = a.n, nb = a.nb, G = nb / 2, h = a.h;
+    const int local = role - role_start[p];
     const int s = local / G, gp = local - s * G;
-    int* const rot = a.rot;
-    if (rd == 0 && gp == 0 && threadIdx.x == 0) rot[((sweep + 1) % 3) * a.h + s] = 0;
-    if (sweep > 0 && rot[((sweep + 2) % 3) * a.h + s] == 0) return;   // converged in the previous sweep
     cplx<T>* const A = a.A + (int64_t)s * n * m;
     cplx<T>* const V = a.V + (int64_t)s * n * n;
+    int* const counter = a.bar + s;
+    int* const bf = a.bar + h + (int64_t)s * nb;
+    int* const rot = a.rot;
+    int* const err = words + 1;
     const int ka = (m + PG - 1) / PG;
     const int mp = ka * PG;
     const int ldc = PG * RPT + 1;
     cplx<T>* const blk0 = reinterpret_cast<cplx<T>*>(smem);
     cplx<T>* const blk1 = blk0 + (size_t)BW * ldc;
     const int l = threadIdx.x % PG;
+    const double tol = (double)a.tol;
+    const int msw = a.max_sweeps > 0 ? a.max_sweeps : 30;
+
+    // padding rows stay zero under every rotation
     for (int idx = threadIdx.x; idx < 2 * BW * ldc; idx += NT) blk0[idx] = cplx<T>{(T)0, (T)0};
-    if (threadIdx.x == 0) rot_any = 0;
     __syncthreads();
-    const int player0 = ppos_player(gp, rd, nb), player1 = ppos_player(nb - 1 - gp, rd, nb);
-    load_block<T, NT, BW>(A, V, m, n, nb, player0, mp, ldc, blk0);
-    load_block<T, NT, BW>(A, V, m, n, nb, player1, mp, ldc, blk1);
+    const int pos0 = gp, pos1 = nb - 1 - gp;
+    int player0 = ppos_player(pos0, 0, nb), player1 = ppos_player(pos1, 0, nb);
+    load_block<T, NT, BW, true>(A, V, m, n, nb, player0, mp, ldc, blk0);
+    load_block<T, NT, BW, true>(A, V, m, n, nb, player1, mp, ldc, blk1);
     __syncthreads();
-    const int wi = pblk_start(player0 + 1, n, nb) - pblk_start(player0, n, nb);
-    const int wj = pblk_start(player1 + 1, n, nb) - pblk_start(player1, n, nb);
-    unsigned nbig = 0;
-    const unsigned nrot = pair_round<T, BW, RPT>(blk0, blk1, wi, wj, rd == 0, ka, ldc, (double)a.tol, jnorm, nbig);
-    if (nbig && l == 0) rot_any = 1;
-    __syncthreads();
-    store_block<T, NT, BW>(A, V, m, n, nb, player0, mp, ldc, blk0);
-    store_block<T, NT, BW>(A, V, m, n, nb, player1, mp, ldc, blk1);
-    if (threadIdx.x == 0) {
-        if (rot_any) atomicOr(rot + (sweep % 3) * a.h + s, 1);
-        if (rd == 0 && gp == 0) {
-            if (a.sweeps) a.sweeps[s] = sweep + 1;
-            if (a.ctrl) atomicMax(&a.ctrl->sweep_max, sweep + 1);
+
+    unsigned nrot = 0;
+    int sweeps = 0, arrivals = 0;
+    bool alive = true, home0 = true, home1 = true;
+    for (int sweep = 0; sweep < msw && alive; ++sweep) {
+        if (threadIdx.x == 0) rot_any = 0;
+        if (gp == 0 && threadIdx.x == 0)
+            __hip_atomic_store(rot + ((sweep + 1) % 3) * h + s, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        sweeps = sweep + 1;
+        __syncthreads();
+        unsigned nbig = 0;
+        for (int rd = 0; rd < nb - 1; ++rd) {
+            const int wi = pblk_start(player0 + 1, n, nb) - pblk_start(player0, n, nb);
+            const int wj = pblk_start(player1 + 1, n, nb) - pblk_start(player1, n, nb);
+            nrot += pair_round<T, BW, RPT>(blk0, blk1, wi, wj, rd == 0, ka, ldc, tol, jnorm, nbig);
+            const bool last = rd == nb - 2;
+            __syncthreads();
+            if (last) {
+                if (nbig && l == 0) rot_any = 1;
+                __syncthreads();
+                if (threadIdx.x == 0 && rot_any)
+                    __hip_atomic_fetch_or(rot + (sweep % 3) * h + s, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            // the next round's players (after the last round: round 0 of the next sweep)
+            const int nr = (rd + 1) % (nb - 1);
+            const int next0 = ppos_player(pos0, nr, nb), next1 = ppos_player(pos1, nr, nb);
+            if (next0 != player0) store_block<T, NT, BW, true>(A, V, m, n, nb, player0, mp, ldc, blk0);
+            if (next1 != player1) store_block<T, NT, BW, true>(A, V, m, n, nb, player1, mp, ldc, blk1);
+            if (last) {
+                arrivals += G;
+                if (!pairs_barrier(counter, arrivals, err, spin_limit)) {
+                    home0 = next0 == player0;   // giving up
+                    home1 = next1 == player1;
+                    alive = false;
+                    break;
+                }
+                if (threadIdx.x == 0)
+                    stop = __hip_atomic_load(rot + (sweep % 3) * h + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+                __syncthreads();
+                if (stop) {
+                    home0 = next0 == player0;   // converged
+                    home1 = next1 == player1;
+                    alive = false;
+                    break;
+                }
+            } else {
+                const int R = sweep * (nb - 1) + rd;
+                __builtin_amdgcn_s_waitcnt(0);
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    ok_flag = 1;
+                    if (next0 != player0) __hip_atomic_store(bf + player0, R + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (next1 != player1) __hip_atomic_store(bf + player1, R + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if ((next0 != player0 && !pairs_wait_flag(bf + next0, R + 1, err, spin_limit)) ||
+                        (next1 != player1 && !pairs_wait_flag(bf + next1, R + 1, err, spin_limit)))
+                        ok_flag = 0;
+                }
+                __syncthreads();
+                if (!ok_flag) {
+                    home0 = next0 == player0;   // giving up
+                    home1 = next1 == player1;
+                    alive = false;
+                    break;
+                }
+            }
+            if (next0 != player0) load_block<T, NT, BW, true>(A, V, m, n, nb, next0, mp, ldc, blk0);
+            if (next1 != player1) load_block<T, NT, BW, true>(A, V, m, n, nb, next1, mp, ldc, blk1);
+            player0 = next0;
+            player1 = next1;
+            __syncthreads();
         }
+    }
+    __syncthreads();
+    if (home0) store_block<T, NT, BW, true>(A, V, m, n, nb, player0, mp, ldc, blk0);
+    if (home1) store_block<T, NT, BW, true>(A, V, m, n, nb, player1, mp, ldc, blk1);
+    if (threadIdx.x == 0) {
+        if (gp == 0 && a.sweeps) a.sweeps[s] = sweeps;
+        if (a.ctrl) atomicMax(&a.ctrl->sweep_max, sweeps);
     }
     if (l == 0 && nrot && a.rotations) atomicAdd(a.rotations, (unsigned long long)nrot);
 }
 
-// mode 0: slice kernel (x = max_sweeps); mode 1: round kernel (x = sweep, y = round);
-// prepare: set the LDS limit of both kernels.
+// prepare: set the LDS limit of both kernels; else launch the slice kernel
+// (x = max_sweeps).
 template <typename T, int BW, int RPT>
 hipError_t launch_bw_rpt(bool prepare, int mode, const JacSliceArgs<T>* tab, const int* wg_start, int nprob, int nwg,
                          int x, int y, hipStream_t st) {
     auto* fs = jacobi_slice_kernel<T, BW, RPT>;
-    auto* fr = jacobi_round_kernel<T, BW, RPT>;
     const size_t lds = jacobi_slice_lds(BW, RPT, sizeof(T));
     if (prepare) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fs),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
-        return hipFuncSetAttribute(reinterpret_cast<const void*>(fr), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)lds);
+        return hipFuncSetAttribute(reinterpret_cast<const void*>(jacobi_pairs_kernel<T, BW, RPT>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     }
-    if (mode == 0)
-        hipLaunchKernelGGL(fs, dim3(nwg), dim3(BW * kPGs), lds, st, tab, wg_start, nprob, x);
-    else
-        hipLaunchKernelGGL(fr, dim3(nwg), dim3(BW * kPGs), lds, st, tab, wg_start, nprob, x, y);
+    (void)mode;
+    (void)y;
+    hipLaunchKernelGGL(fs, dim3(nwg), dim3(BW * kPGs), lds, st, tab, wg_start, nprob, x);
     return hipGetLastError();
 }
 
@@ -321,7 +429,46 @@ hipError_t dispatch(bool prepare, int mode, int bw, int rpt, const JacSliceArgs<
     }
 }
 
+template <typename T, int BW, int RPT>
+hipError_t launch_pairs_bw_rpt(const JacSliceArgs<T>* tab, const int* role_start, int nprob, int nroles, int* words,
+                               int spin_limit, hipStream_t st) {
+    const size_t lds = jacobi_slice_lds(BW, RPT, sizeof(T));
+    hipLaunchKernelGGL((jacobi_pairs_kernel<T, BW, RPT>), dim3(nroles), dim3(BW * kPGs), lds, st, tab, role_start, nprob,
+                       words, spin_limit);
+    return hipGetLastError();
+}
+
+template <typename T, int BW, int... R>
+hipError_t dispatch_pairs_rpt(int rpt, std::integer_sequence<int, R...>, const JacSliceArgs<T>* tab,
+                              const int* role_start, int nprob, int nroles, int* words, int spin_limit,
+                              hipStream_t st) {
+    hipError_t e = hipErrorInvalidValue;
+    ((rpt == R + 2 ? (e = launch_pairs_bw_rpt<T, BW, R + 2>(tab, role_start, nprob, nroles, words, spin_limit, st), 0)
+                   : 0),
+     ...);
+    return e;
+}
+
 }  // namespace
+
+template <typename T>
+hipError_t launch_jacobi_pairs(int bw, int rpt, const JacSliceArgs<T>* tab, const int* role_start, int nprob,
+                               int nroles, int* words, int spin_limit, hipStream_t st) {
+    if (rpt < 2 || rpt > 20) return hipErrorInvalidValue;
+    if (nroles <= 0) return hipSuccess;
+    auto seq = std::make_integer_sequence<int, 19>{};
+    switch (bw) {
+        case 4: return dispatch_pairs_rpt<T, 4>(rpt, seq, tab, role_start, nprob, nroles, words, spin_limit, st);
+        case 8: return dispatch_pairs_rpt<T, 8>(rpt, seq, tab, role_start, nprob, nroles, words, spin_limit, st);
+        case 16: return dispatch_pairs_rpt<T, 16>(rpt, seq, tab, role_start, nprob, nroles, words, spin_limit, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template hipError_t launch_jacobi_pairs<double>(int, int, const JacSliceArgs<double>*, const int*, int, int, int*, int,
+                                                hipStream_t);
+template hipError_t launch_jacobi_pairs<float>(int, int, const JacSliceArgs<float>*, const int*, int, int, int*, int,
+                                               hipStream_t);
 
 int jacobi_slice_rpt(int m, int n) {
     const int need = (m + kPGs - 1) / kPGs + (n + kPGs - 1) / kPGs;
@@ -344,45 +491,6 @@ hipError_t launch_jacobi_slice(int bw, int rpt, const JacSliceArgs<T>* tab, cons
                                int nwg, int max_sweeps, hipStream_t st) {
     return dispatch<T>(false, 0, bw, rpt, tab, wg_start, nprob, nwg, max_sweeps, 0, st);
 }
-
-template <typename T>
-hipError_t launch_jacobi_round(int bw, int rpt, const JacSliceArgs<T>* tab, const int* wg_start, int nprob,
-                               int nwg, int sweep, int round, hipStream_t st) {
-    return dispatch<T>(false, 1, bw, rpt, tab, wg_start, nprob, nwg, sweep, round, st);
-}
-
-// Round mode: *flag = 1 when a slice of a running problem of the table
-// rotated in sweep `sweep` and may run another sweep (below its cap), else 0.
-// One workgroup; the flag is written once, after the scan.
-template <typename T>
-__global__ __launch_bounds__(256) void jacobi_round_active_kernel(const JacSliceArgs<T>* tab, int nprob, int sweep,
-                                                                 int* flag) {
-    __shared__ int any;
-    if (threadIdx.x == 0) any = 0;
-    __syncthreads();
-    for (int p = 0; p < nprob; ++p) {
-        const JacSliceArgs<T>& a = tab[p];
-        if (a.ctrl && a.ctrl->done) continue;
-        if (sweep + 1 >= (a.max_sweeps > 0 ? a.max_sweeps : 30)) continue;
-        for (int s = threadIdx.x; s < a.h; s += blockDim.x)
-            if (a.rot[(sweep % 3) * a.h + s]) atomicOr(&any, 1);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) *flag = any;
-}
-
-template <typename T>
-void launch_jacobi_round_active(const JacSliceArgs<T>* tab, int nprob, int sweep, int* flag, hipStream_t st) {
-    hipLaunchKernelGGL((jacobi_round_active_kernel<T>), dim3(1), dim3(256), 0, st, tab, nprob, sweep, flag);
-}
-
-template void launch_jacobi_round_active<double>(const JacSliceArgs<double>*, int, int, int*, hipStream_t);
-template void launch_jacobi_round_active<float>(const JacSliceArgs<float>*, int, int, int*, hipStream_t);
-
-template hipError_t launch_jacobi_round<double>(int, int, const JacSliceArgs<double>*, const int*, int, int, int,
-                                                int, hipStream_t);
-template hipError_t launch_jacobi_round<float>(int, int, const JacSliceArgs<float>*, const int*, int, int, int, int,
-                                               hipStream_t);
 
 template hipError_t prepare_jacobi_slice<double>(int, int);
 template hipError_t prepare_jacobi_slice<float>(int, int);

@@ -185,17 +185,14 @@ struct JacSliceArgs {
     int max_sweeps;      // sweep cap (0: the launch's)
     int* rot;            // round mode: 3 x h ring of per-sweep rotation flags (ring 0 clear before the SVD)
     const int* only_if;  // optional: the problem is skipped unless *only_if != 0
+    int* bar;            // pairs-parallel schedule: h barrier counters, then h x nb block-ready
+                         // flags, all zero before the launch (as is ring 0 of rot)
 };
+// Ints per problem of the pairs-parallel schedule's barrier area (JacSliceArgs::bar).
+inline int64_t jacobi_pairs_words(int h, int nb) { return (int64_t)h * (1 + nb); }
 int jacobi_slice_rpt(int m, int n);
 size_t jacobi_slice_lds(int bw, int rpt, int elem_bytes);
 int jacobi_slice_max_rpt();
-template <typename T>
-hipError_t launch_jacobi_round(int bw, int rpt, const JacSliceArgs<T>* tab, const int* wg_start, int nprob,
-                               int nwg, int sweep, int round, hipStream_t st);
-// Round mode: *flag (e.g. mapped host memory) = 1 when some running slice of
-// the table rotated in `sweep` and is below its sweep cap.
-template <typename T>
-void launch_jacobi_round_active(const JacSliceArgs<T>* tab, int nprob, int sweep, int* flag, hipStream_t st);
 // Sets the kernel's LDS limit; call once per (bw, rpt) before launches
 // (and before any stream capture).
 template <typename T>
@@ -203,6 +200,15 @@ hipError_t prepare_jacobi_slice(int bw, int rpt);
 template <typename T>
 hipError_t launch_jacobi_slice(int bw, int rpt, const JacSliceArgs<T>* tab, const int* wg_start, int nprob,
                                int nwg, int max_sweeps, hipStream_t st);
+// Pairs-parallel schedule over a problem table: one launch runs every sweep
+// of every slice, nb / 2 workgroups per slice (one per block pair of a round)
+// exchanging blocks between rounds; workgroups take their roles in order from
+// words[0] (zero before the launch), and a wait between workgroups that gives
+// up sets words[1] (the SVDs of that launch are then incomplete).
+// role_start: nprob + 1 cumulative role counts (h nb / 2 per problem).
+template <typename T>
+hipError_t launch_jacobi_pairs(int bw, int rpt, const JacSliceArgs<T>* tab, const int* role_start, int nprob,
+                               int nroles, int* words, int spin_limit, hipStream_t st);
 
 template <typename T>
 struct SigmaArgs {
@@ -289,8 +295,10 @@ struct CtrlArgs {
     Ctrl* c;
     const double* partials;
     int nparts, rpca;
-    int* rot_ring0;    // optional: h flags cleared after the step (round-mode Jacobi)
+    int* rot_ring0;    // optional: h flags cleared after the step (pairs-parallel Jacobi)
     int h;
+    int* clr;          // optional: nclr ints cleared after the step (the Jacobi barrier area)
+    int nclr;
 };
 void launch_admm_ctrl_batched(const CtrlArgs* tab, int nprob, hipStream_t st);
 // mirror (optional): a copy of the control block after the update, e.g. in

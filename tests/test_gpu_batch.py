@@ -129,22 +129,21 @@ def test_observed_entries_kept_exactly(batch_result):
 def test_graph_replay_equals_eager():
     """Every replay of the captured two-iteration period must give the eager
     result bit for bit (20 iterations = 10 replays, with host reads of the
-    control blocks between them).  Every slice runs on one workgroup here: a
-    running set with a round-mode Jacobi class reads convergence flags
-    mid-iteration and is never captured."""
+    control blocks between them).  The mix holds both Jacobi schedules (one
+    workgroup per slice, and one per block pair with the blocks exchanged
+    inside the launch), so every running set is captured."""
     torch = torch_cuda()
-    cases = _cases()[:5] + _cases()[-2:]
+    cases = _cases()[:5] + _cases()[-2:] + [("big", "complete", *_completion((150, 140, 4), 7, p=0.4, rank=3),
+                                            np.float64, {})]
     outs = {}
     for mode in ("1", "0"):
         os.environ["TSVD_GRAPH"] = mode
-        os.environ["TSVD_ROUND_MIN_PAIRS"] = "100000"
         try:
             probs = [_problem(torch, c, iters=20) for c in cases]
             announce("graph mode", mode)
             res = lib.batch_run(probs)
         finally:
             os.environ.pop("TSVD_GRAPH", None)
-            os.environ.pop("TSVD_ROUND_MIN_PAIRS", None)
         assert all(st == 0 for st, _ in res)
         outs[mode] = [_outputs(p) for p in probs]
     for a, b in zip(outs["1"], outs["0"]):
@@ -186,21 +185,22 @@ def test_batch_rejects_bad_records():
     assert e.value.status == -2
 
 
-def test_round_mode_equals_slice_mode():
-    """The round-mode Jacobi (a launch per tournament round, one workgroup
-    per block pair) performs the same rotations in the same order as the
-    one-workgroup-per-slice kernel: outputs agree bit for bit."""
+def test_pairs_schedule_equals_slice_schedule():
+    """The pairs-parallel Jacobi schedule (one workgroup per block pair, the
+    blocks exchanged between rounds inside one launch) performs the same
+    rotations in the same order as the one-workgroup-per-slice kernel:
+    outputs agree bit for bit."""
     torch = torch_cuda()
-    cases = _cases()
+    cases = _cases() + [("big", "complete", *_completion((150, 140, 4), 7, p=0.4, rank=3), np.float64, {})]
     outs = {}
     for mode in ("1", "100000"):
-        os.environ["TSVD_ROUND_MIN_PAIRS"] = mode
+        os.environ["TSVD_PAIRS_MIN"] = mode
         try:
             probs = [_problem(torch, c) for c in cases]
-            announce("round-mode threshold", mode)
+            announce("pairs-schedule threshold", mode)
             res = lib.batch_run(probs)
         finally:
-            os.environ.pop("TSVD_ROUND_MIN_PAIRS", None)
+            os.environ.pop("TSVD_PAIRS_MIN", None)
         assert all(st == 0 for st, _ in res)
         outs[mode] = [_outputs(p) for p in probs]
     for a, b in zip(outs["1"], outs["100000"]):
