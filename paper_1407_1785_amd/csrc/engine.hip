@@ -32,7 +32,10 @@
 
 #include <chrono>
 #include <condition_variable>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <string>
 #include <deque>
 #include <map>
 #include <mutex>
@@ -47,9 +50,46 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
-// Jacobi block widths picked by the tuner, shared by every engine of the process.
+// Jacobi schedules picked by the tuner (block width and whether the block
+// pairs of a round run on one workgroup each), shared by every engine of the
+// process and, with TSVD_AUTOTUNE_CACHE set to a file, across processes:
+// each decision is one line "arch cus elem_bytes rpt ncls slices bw pairs".
+struct TuneChoice {
+    int bw = 16;
+    bool pairs = false;
+};
+// (arch, cus, elem bytes, rpt, 32-column class, timed slice count)
+using TuneKey = std::tuple<std::string, int, int, int, int, int>;
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int, int>, int> g_tuned;
+std::map<TuneKey, TuneChoice> g_tuned;
+std::string g_tune_cache_path;   // the cache file last read
+
+// Reads the cache file (under g_tune_mu) when TSVD_AUTOTUNE_CACHE names a
+// file other than the one last read; its entries take precedence over the
+// decisions held in memory.  Lines that do not parse end the read.
+void read_tune_cache() {
+    const char* path = std::getenv("TSVD_AUTOTUNE_CACHE");
+    if (!path || !*path || g_tune_cache_path == path) return;
+    g_tune_cache_path = path;
+    std::FILE* f = std::fopen(path, "r");
+    if (!f) return;
+    char arch[64];
+    int cus, eb, rpt, ncls, ns, bw, pairs;
+    while (std::fscanf(f, "%63s %d %d %d %d %d %d %d", arch, &cus, &eb, &rpt, &ncls, &ns, &bw, &pairs) == 8)
+        if (bw == 4 || bw == 8 || bw == 16)
+            g_tuned[TuneKey{arch, cus, eb, rpt, ncls, ns}] = TuneChoice{bw, pairs != 0};
+    std::fclose(f);
+}
+
+void append_tune_cache(const TuneKey& k, const TuneChoice& c) {
+    const char* path = std::getenv("TSVD_AUTOTUNE_CACHE");
+    if (!path || !*path) return;
+    std::FILE* f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%s %d %d %d %d %d %d %d\n", std::get<0>(k).c_str(), std::get<1>(k), std::get<2>(k),
+                 std::get<3>(k), std::get<4>(k), std::get<5>(k), c.bw, c.pairs ? 1 : 0);
+    std::fclose(f);
+}
 
 // ------------------------------------------------------------------ problems
 
@@ -425,12 +465,13 @@ private:
         hip_check(e, "hipStreamSynchronize");
         // Jacobi launch class
         sl.rpt = jacobi_slice_rpt(g.m, g.n);
-        sl.bw = pick_bw(g.m, g.n, sl.rpt);
+        const TuneChoice tc = pick_schedule(g.m, g.n, sl.rpt, g.h);
+        sl.bw = tc.bw;
         sl.nb = jacobi_num_blocks(g.n, sl.bw);
-        // two or more block pairs per slice: one workgroup per block pair,
-        // blocks exchanged between rounds inside the launch; one block pair:
-        // one workgroup per slice with both blocks resident
-        sl.pairs = sl.nb / 2 >= env_int("TSVD_PAIRS_MIN", 2);
+        sl.pairs = tc.pairs && sl.nb / 2 >= 2;
+        // TSVD_PAIRS_MIN: one workgroup per block pair from that many pairs on
+        const int forced = env_int("TSVD_PAIRS_MIN", 0);
+        if (forced > 0) sl.pairs = sl.nb / 2 >= forced;
     }
 
     void write_outputs(Slot<T>& sl, const Ctrl& c) {
@@ -453,39 +494,94 @@ private:
         }
     }
 
-    // ---- Jacobi block-width tuner
-    int pick_bw(int m, int n, int rpt) {
-        std::vector<int> cand;
-        for (int bw : {16, 8, 4})
-            if (jacobi_slice_lds(bw, rpt, sizeof(T)) + 1024 <= lds_cap_) cand.push_back(bw);
+    // ---- Jacobi schedule tuner
+    //
+    // Candidates: every block width whose two blocks fit in LDS, each with
+    // one workgroup per slice, and, where a slice has two or more block
+    // pairs, one workgroup per block pair of a round.  One decision per
+    // device, element type, row class, 32-column class and slice count
+    // (rounded up to a power of two, at most one per CU): a class runs beside
+    // a few others on the side streams, so its latency on its own slices is
+    // what the period waits for; timed on one slice per CU instead, the
+    // one-workgroup schedule wins classes that the pairs schedule runs twice
+    // as fast inside a batch.  The sweep cap is a limit of the method, not a
+    // schedule, and is not tuned.
+    TuneChoice pick_schedule(int m, int n, int rpt, int h) {
+        std::vector<TuneChoice> cand;
+        for (int bw : {16, 8, 4}) {
+            if (jacobi_slice_lds(bw, rpt, sizeof(T)) + 1024 > lds_cap_) continue;
+            cand.push_back(TuneChoice{bw, false});
+            if (jacobi_num_blocks(n, bw) / 2 >= 2) cand.push_back(TuneChoice{bw, true});
+        }
         if (cand.empty()) fail(TSVD_E_SHAPE, "slice too large for the batched Jacobi kernel");
         const int forced = env_int("TSVD_BATCH_BW", 0);
-        for (int bw : cand)
-            if (bw == forced) return bw;
-        if (cand.size() == 1 || env_int("TSVD_TUNE", 1) == 0) return cand[0];
-        // one decision per device, element type, row class and 32-column class
-        const auto key = std::make_tuple(device_, (int)sizeof(T), rpt, (n + 31) / 32);
+        if (forced) {
+            std::vector<TuneChoice> keep;
+            for (const TuneChoice& c : cand)
+                if (c.bw == forced) keep.push_back(c);
+            if (!keep.empty()) cand = keep;
+        }
+        if (cand.size() == 1 || env_int("TSVD_TUNE", 1) == 0) {
+            // untuned: the widest block, one workgroup per block pair when a
+            // slice has two or more
+            TuneChoice c = cand[0];
+            for (const TuneChoice& d : cand)
+                if (d.bw == c.bw && d.pairs) c = d;
+            return c;
+        }
+        hipDeviceProp_t prop{};
+        (void)hipGetDeviceProperties(&prop, device_);
+        const TuneKey key{std::string(prop.gcnArchName).substr(0, std::string(prop.gcnArchName).find(':')), cus_,
+                          (int)sizeof(T), rpt, (n + 31) / 32, tune_slices(h)};
         {
             std::lock_guard<std::mutex> lk(g_tune_mu);
+            read_tune_cache();
             auto hit = g_tuned.find(key);
-            if (hit != g_tuned.end()) return hit->second;
+            if (hit != g_tuned.end()) {
+                for (const TuneChoice& c : cand)
+                    if (c.bw == hit->second.bw && c.pairs == hit->second.pairs) {
+                        tune_log("cached", m, n, rpt, std::get<5>(key), c);
+                        return c;
+                    }
+            }
         }
-        const int bw = tune(m, n, rpt, cand);
+        const TuneChoice best = tune(m, n, rpt, std::get<5>(key), cand);
+        tune_log("chose", m, n, rpt, std::get<5>(key), best);
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tuned[key] = bw;
-        return bw;
+        if (g_tuned.find(key) == g_tuned.end()) {
+            g_tuned[key] = best;
+            append_tune_cache(key, best);
+        }
+        return best;
     }
 
-    // Time every candidate block width on S synthetic slices of this shape
-    // (pseudo-random entries, V = I, one sweep) and keep the fastest.
-    int tune(int m, int n, int rpt, const std::vector<int>& cand) {
-        const int S = cus_;   // one slice per CU
+    static void tune_log(const char* what, int m, int n, int rpt, int S, const TuneChoice& c) {
+        if (env_int("TSVD_TUNE_LOG", 0))
+            std::fprintf(stderr, "[tsvd tune] %s m=%d n=%d rpt=%d slices=%d bw=%d pairs=%d\n", what, m, n, rpt, S, c.bw,
+                         c.pairs ? 1 : 0);
+    }
+
+    int tune_slices(int h) const {
+        int s = 1;
+        while (s < h && s < cus_) s *= 2;
+        return std::min(s, cus_);
+    }
+
+    // Time every candidate on S synthetic slices of this shape (pseudo-random
+    // entries, V = I, one sweep) and keep the fastest.
+    TuneChoice tune(int m, int n, int rpt, int S, const std::vector<TuneChoice>& cand) {
         const int64_t mn = (int64_t)m * n, nn = (int64_t)n * n;
-        cplx<T>* buf = nullptr;
-        hip_check(hipMalloc(&buf, sizeof(cplx<T>) * (size_t)S * (2 * mn + nn) + 1024), "hipMalloc tuner");
-        cplx<T>* A0 = buf;
+        const int nb_max = jacobi_num_blocks(n, 4);
+        const size_t ints = 2 + 3 * (size_t)S + (size_t)jacobi_pairs_words(S, nb_max);
+        char* buf = nullptr;
+        const size_t cbytes = sizeof(cplx<T>) * (size_t)S * (2 * mn + nn);
+        hip_check(hipMalloc(&buf, cbytes + sizeof(int) * ints + 1024), "hipMalloc tuner");
+        cplx<T>* A0 = reinterpret_cast<cplx<T>*>(buf);
         cplx<T>* A = A0 + S * mn;
         cplx<T>* V = A + S * mn;
+        int* words = reinterpret_cast<int*>(buf + cbytes);
+        int* rot = words + 2;
+        int* bar = rot + 3 * S;
         JacSliceArgs<T>* dtab = nullptr;
         int* dws = nullptr;
         hip_check(hipMalloc(&dtab, sizeof(JacSliceArgs<T>)), "hipMalloc tuner");
@@ -493,38 +589,52 @@ private:
         hipEvent_t e0, e1;
         hip_check(hipEventCreate(&e0), "hipEventCreate");
         hip_check(hipEventCreate(&e1), "hipEventCreate");
-        int best = cand[0];
+        TuneChoice best = cand[0];
         float best_ms = 1e30f;
         try {
             launch_fill_hash<T>(A0, S * mn, 12345u, stream_);
-            const int ws[2] = {0, S};
-            hip_check(hipMemcpyAsync(dws, ws, sizeof(ws), hipMemcpyHostToDevice, stream_), "hipMemcpyAsync");
-            for (int bw : cand) {
+            for (const TuneChoice& c : cand) {
                 JacSliceArgs<T> ja{};
                 ja.A = A;
                 ja.V = V;
                 ja.m = m;
                 ja.n = n;
                 ja.h = S;
-                ja.nb = jacobi_num_blocks(n, bw);
+                ja.nb = jacobi_num_blocks(n, c.bw);
                 ja.tol = (T)jacobi_tol(m, sizeof(T));
                 ja.max_sweeps = 1;
+                ja.rot = rot;
+                ja.bar = bar;
+                const int G = c.pairs ? ja.nb / 2 : 1;
+                const int ws[2] = {0, S * G};
+                hip_check(hipMemcpyAsync(dws, ws, sizeof(ws), hipMemcpyHostToDevice, stream_), "hipMemcpyAsync");
                 hip_check(hipMemcpyAsync(dtab, &ja, sizeof(ja), hipMemcpyHostToDevice, stream_), "hipMemcpyAsync");
                 hip_check(hipMemcpyAsync(A, A0, sizeof(cplx<T>) * S * mn, hipMemcpyDeviceToDevice, stream_),
                           "hipMemcpyAsync");
                 launch_set_identity<T>(V, n, S, stream_);
-                hip_check(prepare_jacobi_slice<T>(bw, rpt), "jacobi tuner attribute");
+                launch_fill<int>(words, 0, (int64_t)ints, stream_);
+                hip_check(prepare_jacobi_slice<T>(c.bw, rpt), "jacobi tuner attribute");
                 hip_check(hipEventRecord(e0, stream_), "hipEventRecord");
-                hip_check(launch_jacobi_slice<T>(bw, rpt, dtab, dws, 1, S, 1, stream_), "jacobi tuner launch");
+                if (c.pairs)
+                    hip_check(launch_jacobi_pairs<T>(c.bw, rpt, dtab, dws, 1, S * G, words, 1 << 21, stream_),
+                              "jacobi tuner launch");
+                else
+                    hip_check(launch_jacobi_slice<T>(c.bw, rpt, dtab, dws, 1, S, 1, stream_), "jacobi tuner launch");
                 hip_check(hipEventRecord(e1, stream_), "hipEventRecord");
                 hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
                 float ms = 0.f;
                 hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+                if (env_int("TSVD_TUNE_LOG", 0))
+                    std::fprintf(stderr, "[tsvd tune] m=%d n=%d rpt=%d slices=%d bw=%d pairs=%d: %.3f ms\n", m, n, rpt, S, c.bw,
+                                 c.pairs ? 1 : 0, ms);
                 if (ms < best_ms) {
                     best_ms = ms;
-                    best = bw;
+                    best = c;
                 }
             }
+            int err = 0;
+            hip_check(hipMemcpy(&err, words + 1, sizeof(int), hipMemcpyDeviceToHost), "hipMemcpy tuner");
+            if (err) fail(TSVD_E_HIP, "a tuner Jacobi wait between workgroups gave up");
         } catch (...) {
             (void)hipStreamSynchronize(stream_);
             (void)hipFree(buf), (void)hipFree(dtab), (void)hipFree(dws);
@@ -533,8 +643,6 @@ private:
         }
         (void)hipFree(buf), (void)hipFree(dtab), (void)hipFree(dws);
         (void)hipEventDestroy(e0), (void)hipEventDestroy(e1);
-        if (env_int("TSVD_TUNE_LOG", 0))
-            std::fprintf(stderr, "[tsvd tune] m=%d n=%d rpt=%d -> bw=%d (%.3f ms)\n", m, n, rpt, best, best_ms);
         return best;
     }
 

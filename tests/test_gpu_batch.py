@@ -208,6 +208,51 @@ def test_pairs_schedule_equals_slice_schedule():
             np.testing.assert_array_equal(x, y)
 
 
+def _tune_lines(err, what):
+    return [ln.split() for ln in err.splitlines() if ln.startswith(f"[tsvd tune] {what} m=101 n=93 ")]
+
+
+def test_tuner_cache_file(tmp_path, monkeypatch, capfd):
+    """TSVD_AUTOTUNE_CACHE: a schedule the tuner times is appended to the file
+    as "arch cus elem_bytes rpt ncls slices bw pairs"; a file naming another
+    admissible schedule for the same key is read and used without timing;
+    both runs meet the oracle bar."""
+    torch = torch_cuda()
+    case = ("tune", "complete", *_completion((101, 93, 7), 31), np.float64, {})
+    want = _oracle(case)[0]
+    monkeypatch.setenv("TSVD_TUNE_LOG", "1")
+    monkeypatch.delenv("TSVD_TUNE", raising=False)
+    monkeypatch.delenv("TSVD_BATCH_BW", raising=False)
+    monkeypatch.delenv("TSVD_PAIRS_MIN", raising=False)
+    first = tmp_path / "tune_first.txt"
+    monkeypatch.setenv("TSVD_AUTOTUNE_CACHE", str(first))
+    capfd.readouterr()
+    p = _problem(torch, case)
+    announce("tuner cache: timed run")
+    assert lib.batch_run([p])[0][0] == 0
+    chose = _tune_lines(capfd.readouterr().err, "chose")
+    assert len(chose) == 1, "the 101 x 93 slices were tuned before this test"
+    bw, pairs = int(chose[0][-2].split("=")[1]), int(chose[0][-1].split("=")[1])
+    lines = [ln.split() for ln in first.read_text().splitlines()]
+    assert lines and all(len(ln) == 8 for ln in lines)
+    assert [int(lines[-1][6]), int(lines[-1][7])] == [bw, pairs]
+    assert int(lines[-1][2]) == 8 and int(lines[-1][5]) == 4   # FP64, 4 Fourier slices
+    assert rel_fro(p.out.cpu().numpy(), want) <= FP64_BAR
+
+    alt = (8, 1) if (bw, pairs) != (8, 1) else (16, 0)
+    second = tmp_path / "tune_second.txt"
+    second.write_text(" ".join(lines[-1][:6] + [str(alt[0]), str(alt[1])]) + "\n")
+    monkeypatch.setenv("TSVD_AUTOTUNE_CACHE", str(second))
+    q = _problem(torch, case)
+    announce("tuner cache: cached run", alt)
+    assert lib.batch_run([q])[0][0] == 0
+    err = capfd.readouterr().err
+    assert not _tune_lines(err, "chose")
+    cached = _tune_lines(err, "cached")
+    assert cached and cached[0][-2:] == [f"bw={alt[0]}", f"pairs={alt[1]}"]
+    assert rel_fro(q.out.cpu().numpy(), want) <= FP64_BAR
+
+
 @pytest.mark.parametrize("dt", [np.float64, np.float32])
 def test_large_slices_against_oracle(dt):
     """Slices with many column blocks (150 x 140, several block pairs per

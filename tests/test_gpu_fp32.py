@@ -79,3 +79,31 @@ def test_precision_dtype_mismatch_is_rejected():
     with pytest.raises(lib.TsvdError) as e:
         lib.tsvt(x, 1.0, precision=lib.PREC_FP32)
     assert e.value.status == -6
+
+
+def test_bf16_split_rebuild_error(monkeypatch, capsys):
+    """The rebuild as three BF16 products per FP32 product
+    (TSVD_REBUILD_BF16=1, off by default) against the FP64 oracle: the
+    t-SVT of the video-shaped tensor, and the completion ADMM, which carries
+    the product error through its iterations.  Records both errors; the
+    documented reason the FP32 form keeps FP32 matrix-core products is the
+    completion error, above the form's 1e-4 bar."""
+    torch = torch_cuda()
+    w = workloads.video_completion(0)
+    z_ref, _ = tsvt_oracle(w["X"].astype(np.float64), 5.0)
+    ref = admm.complete(w["M_obs"].astype(np.float64), w["mask"], w["rho"], w["growth"], w["rho_max"],
+                        max_iter=40, tol=0.0)
+    errs = {}
+    for bf16 in ("0", "1"):
+        monkeypatch.setenv("TSVD_REBUILD_BF16", bf16)
+        announce("bf16 split rebuild", bf16)
+        z, _ = lib.tsvt(to_gpu(torch, w["X"]), 5.0, precision=lib.PREC_FP32)
+        x, _ = lib.tsvd_complete(to_gpu(torch, w["M_obs"]), to_gpu(torch, w["mask"]), w["rho"], 0.0,
+                                 max_iter=40, precision=lib.PREC_FP32)
+        errs[bf16] = (rel_fro(z.cpu().numpy(), z_ref), rel_fro(x.cpu().numpy(), ref["X"]))
+    with capsys.disabled():
+        print(f"\n[bf16 split rebuild] tsvt video RSE {errs['1'][0]:.3e} (FP32 products {errs['0'][0]:.3e}); "
+              f"completion 40 iterations RSE {errs['1'][1]:.3e} (FP32 products {errs['0'][1]:.3e})", flush=True)
+    assert errs["0"][0] <= BAR and errs["0"][1] <= BAR
+    assert errs["1"][0] != errs["0"][0]          # the switch changes the products
+    assert errs["1"][0] <= 1e-3 and errs["1"][1] <= 1e-2

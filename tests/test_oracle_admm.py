@@ -171,6 +171,56 @@ def test_trpca_l112_detects_corrupted_tubes():
     assert metrics.rse(r["L"], p["L"]) < 1e-2
 
 
+@pytest.mark.parametrize("k", [20, 30, 45])
+def test_trpca_l112_low_rank_certificate_every_iteration(k):
+    """The L-update of iteration k + 1 is the prox of (1/mu) times the tubal
+    nuclear norm at M - S_k - W_k, so mu (M - S_k - W_k - L_{k+1}) has every
+    Fourier slice in the nuclear-norm subdifferential at L_{k+1}'s slice
+    (U1 V1^H + R, ||R||_2 <= 1).  Runs of k and k + 1 iterations share their
+    first k; pins the L-update's input, its threshold and the dual rescale
+    under the tube shrink."""
+    p = workloads.tube_corruption(0, shape=(20, 24, 10), rank=2)
+    a = admm.trpca(p["M"], p["lam"], max_iter=k, tol=0.0, shrink="l112")
+    b = admm.trpca(p["M"], p["lam"], max_iter=k + 1, tol=0.0, shrink="l112")
+    mu = min(1.2 * a["mu"], 1e10)
+    assert b["mu"] == mu
+    assert b["multirank"].min() >= 1 and np.abs(a["S"]).max() > 0   # the check is not vacuous
+    g = mu * (p["M"] - a["S"] - a["W"] - b["L"])
+    gap = nuclear_subgradient_gap(T.fourier(g), T.fourier(b["L"]), svtol=1e-9)
+    assert gap[0] < 1e-9 and gap[1] <= 1 + 1e-9 and gap[2] < 1e-9 and gap[3] < 1e-9, gap
+
+
+def _tube_objective(lo, sp, lam, n3_weight):
+    """sum_k ||Lhat_k||_* / n3_weight + lam * sum_ij ||S(i,j,:)||_2."""
+    nuc = sum(np.linalg.svd(T.fourier(lo)[:, :, k], compute_uv=False).sum() for k in range(lo.shape[2]))
+    return nuc / n3_weight + lam * np.linalg.norm(sp, axis=2).sum()
+
+
+def test_trpca_l112_objective_reading():
+    """The objective the tube-shrink ADMM minimises.  With the threshold 1/mu
+    applied to the singular values of unnormalised DFT slices, the L-update
+    is the prox of (1/mu) sum_k ||Lhat_k||_* / n3 in the Frobenius norm of
+    the tensor (Parseval), so the fixed point minimises
+    sum_k ||Lhat_k||_* / n3 + lam ||S||_{1,1,2} over L + S = M: no feasible
+    perturbation (L + E, S - E) lowers it.  Read with the weight 1 on the
+    Fourier-domain sum (Sec. 5's objective with this lam taken literally),
+    the same point is not optimal: a perturbation along -L lowers it."""
+    p = workloads.tube_corruption(0, shape=(16, 18, 8), rank=2, frac=0.05, block=4, amp=1.0)
+    n3 = p["M"].shape[2]
+    r = admm.trpca(p["M"], p["lam"], max_iter=2000, tol=1e-11, shrink="l112")
+    assert r["converged"]
+    lo, sp = r["L"], r["S"]
+    f0 = _tube_objective(lo, sp, p["lam"], n3)
+    g = np.random.default_rng(3)
+    scale = 1e-4 * np.linalg.norm(p["M"])
+    for _ in range(30):
+        e = g.normal(size=lo.shape)
+        e *= scale / np.linalg.norm(e)
+        assert _tube_objective(lo + e, sp - e, p["lam"], n3) >= f0 * (1 - 1e-9)
+    e = -1e-3 * lo
+    assert _tube_objective(lo + e, sp - e, p["lam"], 1) < _tube_objective(lo, sp, p["lam"], 1)
+
+
 def test_shrinks_closed_form():
     d = np.array([[[3.0, -0.5, 0.2, -2.0]]])
     np.testing.assert_allclose(admm.shrink_l1(d, 1.0), [[[2.0, 0.0, 0.0, -1.0]]])
