@@ -13,11 +13,18 @@ FP64 rotation parameters, residual norms and stopping test): iterations/s
 over --steps timed iterations (one tsvd_complete call of --steps iterations,
 inputs resident in HBM, after a --warmup-iteration call).  The plain FP64
 GPU path is timed the same way beside it, and the relative difference of
-the two recovered tensors at the same iteration count is reported (the
-FP64 path matches the FP64 oracle to ~1e-13, see the parity tests and the
-`parity` field).  Also printed: the roofline of the dominant kernel of the
-FP32 form, measured live with HIP events on the library's stream, and the
-FP64 CPU oracle timed on a bounded sample of the same workload.
+the two recovered tensors at the same iteration count is reported.  The
+`parity` field compares both timed outputs with the FP64 oracle run for
+the same --steps iterations (whole tensor, largest Fourier slice, largest
+tube), and `cpu_baseline` is that oracle run's rate on the host's threads,
+with a short single-thread sample beside it.  Also printed: the roofline of
+the dominant kernel of each form (n(n-1)/2 (28m+20n) flops per slice sweep
+from the device's per-slice sweep sums, HIP events on the library's
+stream, HBM traffic from the committed counter record while its source
+digest matches), the DFT passes' HBM fraction and the rebuild's matrix-core
+fraction at the kept rank, and the batched, serving, full-size RPCA,
+compression, sampling-sweep and tube-RPCA legs.  `--gpus N` with N > 1
+exits with a message: this build runs on one GPU.
 """
 
 from __future__ import annotations
@@ -97,7 +104,9 @@ def roofline(stats: dict, fp32: bool, m: int, n: int):
     try:
         with open(TRAFFIC_FILE) as f:
             tr = json.load(f)
-        if tr.get("kernel") == name and tr.get("source_digest") == source_digest(tr["source_files"]):
+        form = "fp32" if fp32 else "fp64"
+        if (tr.get("kernel") == name and tr.get("precision") == form
+                and tr.get("source_digest") == source_digest(tr["source_files"])):
             out["traffic"] = tr["bytes_per_launch"]
     except (OSError, ValueError, KeyError):
         pass
