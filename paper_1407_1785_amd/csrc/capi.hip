@@ -532,6 +532,7 @@ SweepStats run_svt(tsvd_handle h, const Geometry& g, const SvtBuffers<T>& sb, in
     gr.alpha = (T)1; gr.beta = (T)0; gr.opA = 0; gr.opB = 1; gr.batch = g.h;
     gr.dk = sb.dk; gr.sdk = g.n; gr.ctrl = h->ctrl;
     gr.bf16x3 = env_int("TSVD_REBUILD_BF16", 0);
+    gr.kcompact = env_int("TSVD_REBUILD_KEPT", 1);   // sum over the kept columns only
     if (rebuild) {
         const int ip = prof_launch(h, K_SVT_REBUILD, 8.0 * g.m * g.n * g.n * g.h, [&] { launch_zgemm(gr, st); });
         launch_check("svt_rebuild");

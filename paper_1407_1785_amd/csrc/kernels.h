@@ -153,7 +153,11 @@ struct ZGemmArgs {
     int herm;              // C = A^H A (B == A, opA = H, opB = N, no D): the split-K
                            // form computes the tiles on and above the diagonal and
                            // mirrors them; other forms compute every tile
+    int kcompact;          // with dk: the split-K form sums only over the k with
+                           // dk[k] > 0 (the kept columns of a thresholded rebuild;
+                           // the others contribute exact zeros), K <= kMaxCompactK
 };
+constexpr int kMaxCompactK = 1024;
 
 template <typename T>
 void launch_zgemm(const ZGemmArgs<T>& g, hipStream_t st);

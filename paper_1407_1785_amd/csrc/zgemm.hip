@@ -443,9 +443,31 @@ __device__ __forceinline__ void zgemm_sk_body(const ZGemmArgs<T>& g, int bx, int
 #pragma unroll
         for (int b = 0; b < 2; ++b) cr[a][b] = ci[a][b] = acc_t{(T)0, (T)0, (T)0, (T)0};
 
-    const int nks = (g.K + 3) / 4, per = (nks + 3) / 4;
+    // kept-column form: the k with dk[k] > 0 in increasing order, found by
+    // wave 0 with ballots (every workgroup of the slice finds the same list)
+    __shared__ int klist[kMaxCompactK];
+    __shared__ int kcount;
+    const bool compact = g.kcompact && dk && g.K <= kMaxCompactK;
+    int Kv = g.K;
+    if (compact) {
+        if (w == 0) {
+            int run = 0;
+            for (int base = 0; base < g.K; base += 64) {
+                const int kk = base + lane;
+                const bool keep = kk < g.K && dk[kk] > 0.0;
+                const unsigned long long mask = __ballot(keep);
+                if (keep) klist[run + __popcll(mask & ((1ull << lane) - 1ull))] = kk;
+                run += __popcll(mask);
+            }
+            if (lane == 0) kcount = run;
+        }
+        __syncthreads();
+        Kv = kcount;
+    }
+    auto kmap = [&](int k) { return compact ? klist[min(k, Kv - 1)] : k; };
+    const int nks = (Kv + 3) / 4, per = (nks + 3) / 4;
     const int ks0 = w * per, ks1 = min(ks0 + per, nks);
-    const int kend = min(4 * ks1, g.K);
+    const int kend = min(4 * ks1, Kv);
     constexpr int SKB = sk_batch<T>();
     for (int kb = ks0; kb < ks1; kb += SKB) {
         cplx<T> va[SKB][2], vb[SKB][2];
@@ -453,12 +475,13 @@ __device__ __forceinline__ void zgemm_sk_body(const ZGemmArgs<T>& g, int bx, int
 #pragma unroll
         for (int j = 0; j < SKB; ++j) {
             const int k = 4 * (kb + j) + lk;
+            const int kk = kmap(k);
 #pragma unroll
             for (int x = 0; x < 2; ++x) {
-                va[j][x] = view_load<T>(A, g.lda, akc, row0 + 16 * x + l16, k, g.M, g.K);
-                vb[j][x] = view_load<T>(B, g.ldb, bkc, col0 + 16 * x + l16, k, g.N, g.K);
+                va[j][x] = view_load<T>(A, g.lda, akc, row0 + 16 * x + l16, kk, g.M, g.K);
+                vb[j][x] = view_load<T>(B, g.ldb, bkc, col0 + 16 * x + l16, kk, g.N, g.K);
             }
-            dv[j] = dk ? dk[min(k, g.K - 1)] : 1.0;
+            dv[j] = dk ? dk[min(kk, g.K - 1)] : 1.0;
         }
 #pragma unroll
         for (int j = 0; j < SKB; ++j) {
