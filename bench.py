@@ -113,11 +113,33 @@ def roofline(stats: dict, fp32: bool, m: int, n: int):
     return out
 
 
-def side_rooflines(stats: dict, fp32: bool, m: int, n: int):
+def device_copy_gbs(torch, nbytes: int = 1 << 30, reps: int = 5) -> float:
+    """Read + write rate of a plain device-to-device copy of `nbytes` (the
+    best of `reps`, HIP events on torch's stream): the practical ceiling the
+    HBM-bound passes are also compared with."""
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = float("inf")
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        best = min(best, a.elapsed_time(b) * 1e-3)
+    del src, dst
+    return 2.0 * nbytes / best / 1e9
+
+
+def side_rooflines(stats: dict, fp32: bool, m: int, n: int, h: int, copy_gbs: float = 0.0):
     """The HBM fraction of the two DFT passes (with the fused prologue and
     epilogue; algorithmic bytes per launch) and the matrix-core fraction of
     the rebuild W diag(d) V^H, counted at the kept rank (8 m n r_k flops per
-    slice, the useful product) and dense (8 m n^2, what it computes)."""
+    slice, the useful product) and dense (8 m n^2, what it computes), and,
+    since at these ranks it is memory-bound, its bytes (W, V read, Zhat
+    written, h slices) against the HBM peak.  The DFT passes are also given
+    against `copy_gbs`, the rate of a plain device copy measured here."""
     out = {}
     for fam in ("dft_forward", "dft_inverse"):
         st = stats.get(fam)
@@ -126,6 +148,9 @@ def side_rooflines(stats: dict, fp32: bool, m: int, n: int):
             out[fam] = {"achieved_GBs": gbs, "peak_GBs": PEAK_HBM_GBS, "frac": gbs / PEAK_HBM_GBS,
                         "avg_launch_us": st["total_ms"] * 1e3 / max(1, st["launches"]),
                         "bytes_per_launch": st["work"] / max(1, st["launches"])}
+            if copy_gbs > 0:
+                out[fam]["copy_GBs"] = copy_gbs
+                out[fam]["frac_of_copy"] = gbs / copy_gbs
     st = stats.get("svt_rebuild")
     if st and st["total_ms"] > 0:
         secs = st["total_ms"] * 1e-3
@@ -138,6 +163,13 @@ def side_rooflines(stats: dict, fp32: bool, m: int, n: int):
                               "achieved_TFs_dense": st["work"] / secs / 1e12,
                               "frac_dense": st["work"] / secs / 1e12 / peak,
                               "avg_launch_us": st["total_ms"] * 1e3 / max(1, st["launches"])}
+        # at these ranks the product is memory-bound: W (m x n) and V (n x n)
+        # read, Zhat (m x n) written, complex, per slice
+        b = 4 if fp32 else 8
+        byt = st["launches"] * h * (2.0 * m * n + n * n) * 2 * b
+        out["svt_rebuild"]["bytes_per_launch"] = byt / max(1, st["launches"])
+        out["svt_rebuild"]["achieved_GBs"] = byt / secs / 1e9
+        out["svt_rebuild"]["frac_hbm"] = byt / secs / 1e9 / PEAK_HBM_GBS
     return out
 
 
@@ -467,11 +499,39 @@ def cpu_baseline(w, cases: dict, single_iters: int):
         t1 = time.perf_counter()
         admm.complete(m_obs, w["mask"], w["rho"], w["growth"], w["rho_max"], max_iter=single_iters, tol=0.0)
         dt1 = time.perf_counter() - t1
+    cpu_model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu_model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), cpu_model)
+    except OSError:
+        pass
     base = dict(value=c["iters"] / dt, unit="iters/s", cores=threads, kind="oracle",
+                cpu_model=cpu_model, nproc=os.cpu_count(),
                 sample=f"the same {c['iters']} ADMM iterations of the 128x160x64 completion as the timed GPU steps "
                        f"({dt:.1f} s, NumPy FP64, BLAS threads={threads})",
                 single_core={"value": single_iters / dt1, "unit": "iters/s", "cores": 1,
                              "sample": f"first {single_iters} iterations, BLAS threads=1 ({dt1:.1f} s)"})
+    if "serving" in cases:
+        # the serving mix is not served on the host: the oracle's solve time
+        # per request instead, from two timed iterations of each of the first
+        # requests, scaled to the iterations the GPU leg ran on average
+        c = cases["serving"]
+        per_iter, solve = [], []
+        for d in c["requests"]:
+            t2 = time.perf_counter()
+            if d["kind"] == "complete":
+                admm.complete(d["M_obs"], d["mask"], d["rho"], d["growth"], d["rho_max"], max_iter=2, tol=0.0)
+            else:
+                admm.trpca(d["M"], d["lam"], d["mu"], d["growth"], d["mu_max"], max_iter=2, tol=0.0)
+            pi = (time.perf_counter() - t2) / 2
+            per_iter.append(pi)
+            solve.append(pi * c["iters"])
+        solve = np.asarray(solve)
+        base["serving_oracle"] = {
+            "requests": len(solve), "iters_per_request": c["iters"],
+            "solve_s_p50": float(np.percentile(solve, 50)), "solve_s_max": float(solve.max()),
+            "per_iter_s": [round(x, 4) for x in per_iter],
+            "sample": "the first requests of the 50 req/s trace, 2 oracle iterations each, scaled"}
     if "batched" in cases:
         c = cases["batched"]
         d = c["data"]
@@ -513,7 +573,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--cpu-single-iters", type=int, default=3,
+    ap.add_argument("--cpu-single-iters", type=int, default=10,
                     help="oracle iterations timed with one BLAS thread")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
@@ -638,20 +698,22 @@ def main() -> int:
     }
 
     m_dim, n_dim = max(SHAPE[0], SHAPE[1]), min(SHAPE[0], SHAPE[1])
+    h_dim = SHAPE[2] // 2 + 1
     if not args.no_profile:
+        copy_gbs = device_copy_gbs(torch)
         handle.profile(True)
         lib.tsvd_complete(obs32, mask, max_iter=args.steps, **kw, **fp32)
         handle.profile(False)
         stats = handle.profile_read()
         result["roofline"] = roofline(stats, True, m_dim, n_dim)
-        result["side_rooflines"] = side_rooflines(stats, True, m_dim, n_dim)
+        result["side_rooflines"] = side_rooflines(stats, True, m_dim, n_dim, h_dim, copy_gbs)
         result["kernels_ms_per_step"] = {k: v["total_ms"] / args.steps for k, v in stats.items()}
         handle.profile(True)
         lib.tsvd_complete(obs64, mask, max_iter=args.steps, **kw)
         handle.profile(False)
         stats64 = handle.profile_read()
         result["fp64_plain"]["roofline"] = roofline(stats64, False, m_dim, n_dim)
-        result["fp64_plain"]["side_rooflines"] = side_rooflines(stats64, False, m_dim, n_dim)
+        result["fp64_plain"]["side_rooflines"] = side_rooflines(stats64, False, m_dim, n_dim, h_dim, copy_gbs)
 
     # the timed runs' outputs, compared with the oracle at the same iteration count by the CPU leg
     cases = {"video": {"iters": args.steps, "got64": x64n, "got32": x32.cpu().numpy().astype(np.float64)}}
@@ -672,6 +734,9 @@ def main() -> int:
                                         args.serve_budget_gb, args.serve_limit)
         result["serving"]["trace_cap"] = (f"first {args.serve_window:g} s of the 60-s trace: at the engine's "
                                           "capacity the full trace would take about ten minutes to drain")
+        cases["serving"] = {"requests": [workloads.serve_request(r)
+                                         for r in workloads.arrivals(0, args.serve_rate, args.serve_window)[:6]],
+                            "iters": max(1, int(round(result["serving"]["mean_iters"])))}
         if args.serve_sustained_rate > 0:
             # below capacity: latency is the service time in the mix, not queueing
             result["serving_sustained"] = serving_leg(lib, torch, np, workloads, args.serve_sustained_rate,
