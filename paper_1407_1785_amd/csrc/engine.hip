@@ -628,6 +628,14 @@ private:
                     hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
                     float one = 0.f;
                     hip_check(hipEventElapsedTime(&one, e0, e1), "hipEventElapsedTime");
+                    if (c.pairs) {
+                        // a wait between workgroups that gave up (other work on the device):
+                        // this timing does not count
+                        int gave_up = 0;
+                        hip_check(hipMemcpy(&gave_up, words + 1, sizeof(int), hipMemcpyDeviceToHost),
+                                  "hipMemcpy tuner");
+                        if (gave_up) one = 1e30f;
+                    }
                     ms = std::min(ms, one);
                 }
                 if (env_int("TSVD_TUNE_LOG", 0))
@@ -638,9 +646,6 @@ private:
                     best = c;
                 }
             }
-            int err = 0;
-            hip_check(hipMemcpy(&err, words + 1, sizeof(int), hipMemcpyDeviceToHost), "hipMemcpy tuner");
-            if (err) fail(TSVD_E_HIP, "a tuner Jacobi wait between workgroups gave up");
         } catch (...) {
             (void)hipStreamSynchronize(stream_);
             (void)hipFree(buf), (void)hipFree(dtab), (void)hipFree(dws);
