@@ -53,6 +53,7 @@ struct SvtBuffers {
     int* sweeps;
     int* pbar;        // persistent Jacobi: h barrier counters, 3h flags, the error word, the role
                       // ticket, h x nb block flags
+    double* fro;      // persistent Jacobi: h x (nb / 2) parts of the slices' Frobenius norms
     double* partials;
     int nparts;
     double* tall;     // tall slices: the Jacobi partial sums (jacobi_tall_plan)
@@ -65,6 +66,8 @@ struct SvtBuffers {
 
 // pbar words of a geometry: barriers, rotation flags, error word, ticket, block flags
 inline int64_t pbar_words(const Geometry& g) { return 4 * (int64_t)g.h + 2 + (int64_t)g.h * (g.n + 2); }
+// doubles of the per-workgroup Frobenius parts (at most n / 2 block pairs per slice)
+inline int64_t fro_doubles(const Geometry& g) { return (int64_t)g.h * (g.n / 2 + 1); }
 
 // Warm-start state carried across the iterations of one solve.
 struct WarmState {
@@ -85,6 +88,7 @@ size_t svt_bytes(const Geometry& g, int nparts) {
     b += 2 * (int64_t)g.h * g.n * sizeof(double) + 512;
     b += (int64_t)g.h * 5 * sizeof(int) + 768;
     b += pbar_words(g) * sizeof(int) + 256;
+    b += fro_doubles(g) * sizeof(double) + 256;
     b += (int64_t)nparts * kNumPartials * sizeof(double) + 256;
     b += 4 * sizeof(JacSliceArgs<T>) + 2 * sizeof(int) + 512;
     if (jacobi_tall(g.m, g.n, sizeof(T))) b += jacobi_tall_plan(g.m, g.n, g.h).part_doubles * sizeof(double) + 256;
@@ -107,6 +111,7 @@ SvtBuffers<T> carve_svt(Carver& c, const Geometry& g, int nparts) {
     s.rot = c.take<int>(3 * g.h);
     s.sweeps = c.take<int>(g.h);
     s.pbar = c.take<int>(pbar_words(g));
+    s.fro = c.take<double>(fro_doubles(g));
     s.partials = c.take<double>((int64_t)nparts * kNumPartials);
     s.nparts = nparts;
     s.tall = jacobi_tall(g.m, g.n, sizeof(T)) ? c.take<double>(jacobi_tall_plan(g.m, g.n, g.h).part_doubles)
@@ -169,6 +174,7 @@ void upload_fallback(tsvd_handle h, const Geometry& g, const SvtBuffers<T>& sb, 
         a.ctrl = h->ctrl;
         a.rotations = h->rot_counter + 1;
         a.max_sweeps = max_sweeps;
+        a.floor_scale = jacobi_floor_scale(g.m, sizeof(T));
         a.only_if = sb.pbar + 4 * g.h;
     }
     const int ws[2] = {0, g.h};
@@ -405,6 +411,8 @@ SweepStats run_svt(tsvd_handle h, const Geometry& g, const SvtBuffers<T>& sb, in
         ja.clr[0] = ja.clr[1] = nullptr;
         PersistArgs pa{};
         pa.pbar = sb.pbar;
+        pa.fro = sb.fro;
+        pa.floor_scale = jacobi_floor_scale(g.m, sizeof(T));
         pa.max_sweeps = max_sweeps;
         // about a second of polling; TSVD_PERSIST_SPIN lowers it (tests of the fallback)
         pa.spin_limit = std::max(0, env_int("TSVD_PERSIST_SPIN", 1 << 21));

@@ -150,6 +150,7 @@ struct Slot {
     int* sweeps = nullptr;
     int* rot = nullptr;         // pairs-parallel Jacobi: 3 x h rotation flags
     int* bar = nullptr;         // pairs-parallel Jacobi: barrier counters and block flags
+    double* fro = nullptr;      // pairs-parallel Jacobi: parts of the slices' Frobenius norms
     double* partials = nullptr;
     Ctrl* ctrl = nullptr;
     int* flag = nullptr;
@@ -191,6 +192,7 @@ size_t slot_layout(Slot<T>& sl, char* base) {
     sl.rot = reinterpret_cast<int*>(take((int64_t)3 * g.h * sizeof(int)));
     // sized for the narrowest block width, the most blocks
     sl.bar = reinterpret_cast<int*>(take(jacobi_pairs_words(g.h, jacobi_num_blocks(g.n, 4)) * sizeof(int)));
+    sl.fro = reinterpret_cast<double*>(take(jacobi_pairs_fro(g.h, g.n) * sizeof(double)));
     sl.partials = reinterpret_cast<double*>(take((int64_t)nparts * kNumPartials * sizeof(double)));
     sl.ctrl = reinterpret_cast<Ctrl*>(take(sizeof(Ctrl)));
     sl.flag = reinterpret_cast<int*>(take(sizeof(int)));
@@ -792,6 +794,8 @@ private:
             ja.max_sweeps = sl.sp.s.max_sweeps;
             ja.rot = sl.rot;
             ja.bar = sl.bar;
+            ja.floor_scale = jacobi_floor_scale(g.m, sizeof(T));
+            ja.fro = sl.fro;
             const JKey key{sl.bw, sl.rpt, sl.pairs ? 1 : 0};
             auto& cls = jc[key];
             if (cls.second.empty()) cls.second.push_back(0);

@@ -55,6 +55,14 @@ inline double jacobi_tol(int m, int elem_bytes) {
     return env_double(elem_bytes == 4 ? "TSVD_JACOBI_TOL32" : "TSVD_JACOBI_TOL", std::sqrt((double)m) * eps);
 }
 
+// Scale of the stopping rule's rounding floor (rot_forces_sweep): m eps^2 of
+// the element type, so that the floor is sqrt(m) eps ||A||_F for a slice A.
+// TSVD_SWEEP_FLOOR=0 drops the floor (the plain rule).
+inline double jacobi_floor_scale(int m, int elem_bytes) {
+    const double eps = elem_bytes == 4 ? 1.1920928955078125e-07 : 2.220446049250313e-16;
+    return env_int("TSVD_SWEEP_FLOOR", 1) ? (double)m * eps * eps : 0.0;
+}
+
 // Largest supported sizes (LDS staging of the DFT tiles and Jacobi blocks).
 constexpr int kMaxTube = 512;
 constexpr int kMaxSlices = 300;

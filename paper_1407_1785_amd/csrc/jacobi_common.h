@@ -158,26 +158,19 @@ __device__ __forceinline__ PRot prot(double al, double be, double gr, double gi,
     return prot_params<T>(al, be, gr, gi, g2);
 }
 
-// x <- c x - s conj(e) y,  y <- s e x + c y   with s e = a + i b
-template <typename T>
-__device__ __forceinline__ void prot_apply(const PRot& rd, cplx<T>& x, cplx<T>& y) {
-    const T c = (T)rd.c, a = (T)rd.a, b = (T)rd.b;
-    const cplx<T> xn{c * x.re - a * y.re - b * y.im, c * x.im - a * y.im + b * y.re};
-    const cplx<T> yn{c * y.re + a * x.re - b * x.im, c * y.im + a * x.im + b * x.re};
-    x = xn;
-    y = yn;
-}
-
 // Partial sums over the first K row groups (the slice rows; the V rows
-// below them take part in the rotations only).  The number of slice row
+// below them take part in the rotations only), as chains of fused
+// multiply-adds.  The number of slice row
 // groups ka is a runtime value: a uniform branch picks the unrolled
 // instance, so no per-row select is needed.
 template <typename T, int RPT, int K>
 __device__ __forceinline__ void dot_first(const cplx<T> (&x)[RPT], const cplx<T> (&y)[RPT], T& gr, T& gi) {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        gr += x[k].re * y[k].re + x[k].im * y[k].im;
-        gi += x[k].re * y[k].im - x[k].im * y[k].re;
+        gr = fma(x[k].re, y[k].re, gr);
+        gr = fma(x[k].im, y[k].im, gr);
+        gi = fma(x[k].re, y[k].im, gi);
+        gi = fma(-x[k].im, y[k].re, gi);
     }
 }
 
@@ -210,6 +203,42 @@ __device__ __forceinline__ double pnorm2(const cplx<T> (&x)[RPT], int ka) {
     return (double)group_sum<PG>(acc);
 }
 
+// Device-coherent FP64 store and load (the Frobenius parts of a slice).
+__device__ __forceinline__ void coh_store_f64(double* dst, double v) {
+    __hip_atomic_store(reinterpret_cast<unsigned long long*>(dst), (unsigned long long)__double_as_longlong(v),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ double coh_load_f64(const double* src) {
+    return __longlong_as_double((long long)__hip_atomic_load(reinterpret_cast<const unsigned long long*>(src),
+                                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+
+// The part of a slice's squared Frobenius norm (slice rows) held by the
+// block pair in LDS: per column slot g the squared norms of the two blocks'
+// columns g, added over g in order.  Every thread returns the same value.
+// The Jacobi variants add the parts of a slice's block pairs of round 0 in
+// pair order, so all of them derive the same rounding floor bit for bit.
+// scratch: BW doubles of LDS.
+template <typename T, int PG, int RPT, int BW>
+__device__ __forceinline__ double pair_fro_part(const cplx<T>* blk0, const cplx<T>* blk1, int ldc, int ka,
+                                                double* scratch) {
+    const int g = threadIdx.x / PG, l = threadIdx.x - g * PG;
+    cplx<T> c0[RPT], c1[RPT];
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+        c0[k] = blk0[g * ldc + l + PG * k];
+        c1[k] = blk1[g * ldc + l + PG * k];
+    }
+    const double part = pnorm2<T, PG, RPT>(c0, ka) + pnorm2<T, PG, RPT>(c1, ka);
+    if (l == 0) scratch[g] = part;
+    __syncthreads();
+    double sum = 0.0;
+    for (int i = 0; i < BW; ++i) sum += scratch[i];
+    __syncthreads();
+    return sum;
+}
+
 // Orthogonalise column x (registers) against column y in LDS.  Lane l of
 // the pair group holds rows l + PG k; the first ka row groups (1 <= ka < RPT)
 // are slice rows, the rest V rows, padding rows are zero; only the slice rows
@@ -217,10 +246,10 @@ __device__ __forceinline__ double pnorm2(const cplx<T> (&x)[RPT], int ka) {
 // exact at the start of a round (or internal level) and tracked through it:
 // on a rotation they are updated in place (al -= t|gamma|, be += t|gamma|).
 // Returns 0 (not rotated), 1 (rotated) or 2 (rotated, and the rotation
-// forces another sweep: rot_forces_sweep).
+// forces another sweep: rot_forces_sweep with the rounding floor floor2).
 template <typename T, int PG, int RPT>
 __device__ __forceinline__ unsigned ppair(cplx<T> (&x)[RPT], cplx<T>* y_lds, double& al, double& be, int ka,
-                                          int l, double tol) {
+                                          int l, double tol, double floor2 = 0.0) {
     cplx<T> y[RPT];
 #pragma unroll
     for (int k = 0; k < RPT; ++k) y[k] = y_lds[l + PG * k];
@@ -230,11 +259,19 @@ __device__ __forceinline__ unsigned ppair(cplx<T> (&x)[RPT], cplx<T>* y_lds, dou
     const double dgr = (double)gr, dgi = (double)gi;
     const PRot rt = prot<T>(al, be, dgr, dgi, tol);
     if (!rt.on) return 0u;
-    const unsigned code = rot_forces_sweep(al, be, dgr * dgr + dgi * dgi, tol) ? 2u : 1u;
+    const unsigned code = rot_forces_sweep(al, be, dgr * dgr + dgi * dgi, tol, floor2) ? 2u : 1u;
+    // y <- s e x + c y, then x <- c x - s conj(e) y in place (s e = a + i b):
+    // the new y is formed and stored while the old x is still there, so the
+    // loop-carried x needs no copies
+    {
+        const T c = (T)rt.c, a = (T)rt.a, b = (T)rt.b;
 #pragma unroll
-    for (int k = 0; k < RPT; ++k) {
-        prot_apply(rt, x[k], y[k]);
-        y_lds[l + PG * k] = y[k];
+        for (int k = 0; k < RPT; ++k) {
+            const cplx<T> yn{c * y[k].re + a * x[k].re - b * x[k].im, c * y[k].im + a * x[k].im + b * x[k].re};
+            y_lds[l + PG * k] = yn;
+            x[k].re = c * x[k].re - a * y[k].re - b * y[k].im;
+            x[k].im = c * x[k].im - a * y[k].im + b * y[k].re;
+        }
     }
     al -= rt.tg;
     be += rt.tg;

@@ -46,7 +46,10 @@
 // Convergence: workgroups OR a per-slice flag when a rotation of the sweep
 // forces another sweep (rot_forces_sweep); after the sweep's last barrier all
 // workgroups of the slice read the same flag and stop together when it is
-// clear.
+// clear.  The rounding floor of that test needs the slice's Frobenius norm:
+// each workgroup writes the part of its two starting blocks, and the
+// workgroups of a slice meet once before the first sweep, after which every
+// one adds the same parts in the same order.
 
 #include "jacobi_common.h"
 
@@ -263,6 +266,24 @@ __global__ __launch_bounds__(PBW * PG) void jacobi_persistent_kernel(JacArgs<T> 
     // the sweep cap; after a stop or a give-up, only those that did not move
     // (the moving ones were written before the exchange)
     bool home0 = true, home1 = true;
+    double floor2 = 0.0;   // rounding floor of rot_forces_sweep
+    if (p.floor_scale > 0.0) {
+        const double part = pair_fro_part<T, PG, RPT, PBW>(blk0, blk1, ldc, ka, inorm);
+        if (threadIdx.x == 0) coh_store_f64(p.fro + (int64_t)s * G + wg, part);
+        arrivals += G;
+        if (!slice_barrier(counter, arrivals, err, p.spin_limit)) {
+            alive = false;   // giving up before any rotation: both blocks are still home
+        } else {
+            if (threadIdx.x == 0) {
+                double fro2 = 0.0;
+                for (int i = 0; i < G; ++i) fro2 += coh_load_f64(p.fro + (int64_t)s * G + i);
+                inorm[0] = p.floor_scale * fro2;
+            }
+            __syncthreads();
+            floor2 = inorm[0];
+            __syncthreads();
+        }
+    }
     for (int sweep = 0; sweep < p.max_sweeps && alive; ++sweep) {
         if (threadIdx.x == 0) rot_any = 0;
         if (wg == 0 && threadIdx.x == 0) {
@@ -313,7 +334,7 @@ __global__ __launch_bounds__(PBW * PG) void jacobi_persistent_kernel(JacArgs<T> 
                     const int ycol = ybase + ((q + st) & (k - 1));
                     if (xcol < w && ycol < w) {
                         double be = jn[ycol];
-                        if (const unsigned code = ppair<T, PG, RPT>(xr, base + ycol * ldc, al, be, ka, l, tol)) {
+                        if (const unsigned code = ppair<T, PG, RPT>(xr, base + ycol * ldc, al, be, ka, l, tol, floor2)) {
                             ++nrot;
                             nbig += code >> 1;
                             if (l == 0) jn[ycol] = be;
@@ -353,7 +374,7 @@ __global__ __launch_bounds__(PBW * PG) void jacobi_persistent_kernel(JacArgs<T> 
                 const int jc = (g + st) & (PBW - 1);
                 if (g < wi && jc < wj) {
                     double be = jnorm[jc];
-                    if (const unsigned code = ppair<T, PG, RPT>(xi, blk1 + jc * ldc, al, be, ka, l, tol)) {
+                    if (const unsigned code = ppair<T, PG, RPT>(xi, blk1 + jc * ldc, al, be, ka, l, tol, floor2)) {
                         ++nrot;
                         nbig += code >> 1;
                         if (l == 0) jnorm[jc] = be;

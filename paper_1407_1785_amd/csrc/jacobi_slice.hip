@@ -49,7 +49,8 @@ constexpr int kPGs = 32;
 // force another sweep to nbig.
 template <typename T, int BW, int RPT>
 __device__ __forceinline__ unsigned pair_round(cplx<T>* blk0, cplx<T>* blk1, int wi, int wj, bool self_phase,
-                                               int ka, int ldc, double tol, double* jnorm, unsigned& nbig) {
+                                               int ka, int ldc, double tol, double floor2, double* jnorm,
+                                               unsigned& nbig) {
     constexpr int PG = kPGs;
     const int g = threadIdx.x / PG, l = threadIdx.x - g * PG;
     unsigned nrot = 0;
@@ -96,7 +97,7 @@ __device__ __forceinline__ unsigned pair_round(cplx<T>* blk0, cplx<T>* blk1, int
                 const int ycol = ybase + ((q + st) & (k - 1));
                 if (xcol < w && ycol < w) {
                     double be = jn[ycol];
-                    if (const unsigned code = ppair<T, PG, RPT>(xr, base + ycol * ldc, ax, be, ka, l, tol)) {
+                    if (const unsigned code = ppair<T, PG, RPT>(xr, base + ycol * ldc, ax, be, ka, l, tol, floor2)) {
                         ++nrot;
                         nbig += code >> 1;
                         if (l == 0) jn[ycol] = be;
@@ -130,7 +131,7 @@ __device__ __forceinline__ unsigned pair_round(cplx<T>* blk0, cplx<T>* blk1, int
         const int jc = (g + st) & (BW - 1);
         if (g < wi && jc < wj) {
             double be = jnorm[jc];
-            if (const unsigned code = ppair<T, PG, RPT>(xi, blk1 + jc * ldc, al, be, ka, l, tol)) {
+            if (const unsigned code = ppair<T, PG, RPT>(xi, blk1 + jc * ldc, al, be, ka, l, tol, floor2)) {
                 ++nrot;
                 nbig += code >> 1;
                 if (l == 0) jnorm[jc] = be;
@@ -174,6 +175,22 @@ __global__ __launch_bounds__(BW * kPGs) void jacobi_slice_kernel(const JacSliceA
         load_block<T, NT, BW>(A, V, m, n, nb, 0, mp, ldc, blk0);
         load_block<T, NT, BW>(A, V, m, n, nb, 1, mp, ldc, blk1);
     }
+    // rounding floor of the stopping rule: the parts of the round-0 block
+    // pairs in pair order (as the pairs-parallel and persistent kernels add them)
+    double floor2 = 0.0;
+    if (a.floor_scale > 0.0) {
+        double fro2 = 0.0;
+        for (int gp = 0; gp < G; ++gp) {
+            if (G > 1) {
+                __syncthreads();
+                load_block<T, NT, BW>(A, V, m, n, nb, ppos_player(gp, 0, nb), mp, ldc, blk0);
+                load_block<T, NT, BW>(A, V, m, n, nb, ppos_player(nb - 1 - gp, 0, nb), mp, ldc, blk1);
+            }
+            __syncthreads();
+            fro2 += pair_fro_part<T, PG, RPT, BW>(blk0, blk1, ldc, ka, jnorm);
+        }
+        floor2 = a.floor_scale * fro2;
+    }
 
     unsigned nrot = 0;
     int sweeps = 0;
@@ -192,7 +209,8 @@ __global__ __launch_bounds__(BW * kPGs) void jacobi_slice_kernel(const JacSliceA
                 __syncthreads();
                 const int wi = pblk_start(player0 + 1, n, nb) - pblk_start(player0, n, nb);
                 const int wj = pblk_start(player1 + 1, n, nb) - pblk_start(player1, n, nb);
-                nrot_sweep += pair_round<T, BW, RPT>(blk0, blk1, wi, wj, rd == 0, ka, ldc, tol, jnorm, nbig_sweep);
+                nrot_sweep += pair_round<T, BW, RPT>(blk0, blk1, wi, wj, rd == 0, ka, ldc, tol, floor2, jnorm,
+                                                     nbig_sweep);
                 if (G > 1) {
                     __syncthreads();
                     store_block<T, NT, BW>(A, V, m, n, nb, player0, mp, ldc, blk0);
@@ -309,6 +327,27 @@ __global__ __launch_bounds__(BW * kPGs) void jacobi_pairs_kernel(const JacSliceA
     unsigned nrot = 0;
     int sweeps = 0, arrivals = 0;
     bool alive = true, home0 = true, home1 = true;
+    // rounding floor of the stopping rule: every workgroup writes the part of
+    // its round-0 block pair, the slice's workgroups meet once, and each adds
+    // the parts in pair order (as the one-workgroup-per-slice kernel does)
+    double floor2 = 0.0;
+    if (a.floor_scale > 0.0) {
+        __shared__ double fro_s;
+        const double part = pair_fro_part<T, PG, RPT, BW>(blk0, blk1, ldc, ka, jnorm);
+        if (threadIdx.x == 0) coh_store_f64(a.fro + (int64_t)s * G + gp, part);
+        arrivals += G;
+        if (!pairs_barrier(counter, arrivals, err, spin_limit)) {
+            alive = false;   // giving up before any rotation: both blocks are still home
+        } else {
+            if (threadIdx.x == 0) {
+                double fro2 = 0.0;
+                for (int i = 0; i < G; ++i) fro2 += coh_load_f64(a.fro + (int64_t)s * G + i);
+                fro_s = a.floor_scale * fro2;
+            }
+            __syncthreads();
+            floor2 = fro_s;
+        }
+    }
     for (int sweep = 0; sweep < msw && alive; ++sweep) {
         if (threadIdx.x == 0) rot_any = 0;
         if (gp == 0 && threadIdx.x == 0)
@@ -319,7 +358,7 @@ __global__ __launch_bounds__(BW * kPGs) void jacobi_pairs_kernel(const JacSliceA
         for (int rd = 0; rd < nb - 1; ++rd) {
             const int wi = pblk_start(player0 + 1, n, nb) - pblk_start(player0, n, nb);
             const int wj = pblk_start(player1 + 1, n, nb) - pblk_start(player1, n, nb);
-            nrot += pair_round<T, BW, RPT>(blk0, blk1, wi, wj, rd == 0, ka, ldc, tol, jnorm, nbig);
+            nrot += pair_round<T, BW, RPT>(blk0, blk1, wi, wj, rd == 0, ka, ldc, tol, floor2, jnorm, nbig);
             const bool last = rd == nb - 2;
             __syncthreads();
             if (last) {

@@ -105,9 +105,19 @@ struct InvArgs {
 // sweep are still applied.)  Margins 0.01 / 0.1 / 1 gave 4.75 / 4.34 / 4.13
 // sweeps per iteration on the video-shaped FP32 form at the same accuracy.
 constexpr double kSweepMargin = 1.0;
-
-__device__ __forceinline__ bool rot_forces_sweep(double al, double be, double g2, double tol) {
-    return g2 > (kSweepMargin * tol) * al * be;
+//
+// Rounding floor.  A column whose squared norm is at most floor2 =
+// m eps^2 ||A||_F^2 (eps of the element type, ||A||_F of the slice, which
+// the rotations leave unchanged) lies at the rounding level of length-m
+// inner products of the slice's entries: its direction relative to the
+// other columns is set by rounding (already the product A V of the warm
+// start moves every column by about eps ||A||_F), so rotations that involve
+// it do not force another sweep (they are still applied).  Leaving such a
+// coupling unresolved moves the thresholded result by O(floor) in norm, the
+// rounding level of the slice itself.  floor2 = 0 keeps the plain rule.
+__device__ __forceinline__ bool rot_forces_sweep(double al, double be, double g2, double tol,
+                                                 double floor2 = 0.0) {
+    return g2 > (kSweepMargin * tol) * al * be && fmin(al, be) > floor2;
 }
 
 template <typename T>
@@ -191,7 +201,12 @@ struct JacSliceArgs {
     const int* only_if;  // optional: the problem is skipped unless *only_if != 0
     int* bar;            // pairs-parallel schedule: h barrier counters, then h x nb block-ready
                          // flags, all zero before the launch (as is ring 0 of rot)
+    double floor_scale;  // the rounding floor of rot_forces_sweep is floor_scale ||A||_F^2 (0: none)
+    double* fro;         // pairs-parallel schedule with a floor: h x (nb / 2) doubles, the
+                         // parts of the slices' squared Frobenius norms
 };
+// Doubles per problem of the pairs-parallel schedule's Frobenius parts (JacSliceArgs::fro).
+inline int64_t jacobi_pairs_fro(int h, int n) { return (int64_t)h * (n / 2 + 1); }
 // Ints per problem of the pairs-parallel schedule's barrier area (JacSliceArgs::bar).
 inline int64_t jacobi_pairs_words(int h, int nb) { return (int64_t)h * (1 + nb); }
 int jacobi_slice_rpt(int m, int n);
@@ -286,6 +301,10 @@ struct PersistArgs {
                       // sweep flags, the error word (bit 1: a wait between workgroups
                       // gave up; bit 2: a wait inside one ran out), the role ticket,
                       // h x nb block-ready flags
+    double* fro;      // h x (nb / 2) doubles: each workgroup's part of its slice's squared
+                      // Frobenius norm (written at the start of the launch)
+    double floor_scale;   // m eps^2 of the element type: the rounding floor of
+                          // rot_forces_sweep is floor_scale ||A||_F^2 (0: plain rule)
     int max_sweeps;
     int spin_limit;   // polls of a wait between workgroups before it gives up
     int spread;       // 1: reserve over half a CU's LDS, so no two workgroups share a CU

@@ -107,3 +107,65 @@ def test_bf16_split_rebuild_error(monkeypatch, capsys):
     assert errs["0"][0] <= BAR and errs["0"][1] <= BAR
     assert errs["1"][0] != errs["0"][0]          # the switch changes the products
     assert errs["1"][0] <= 1e-3 and errs["1"][1] <= 1e-2
+
+
+def _graded_tensor(rng, n1, n2, n3, top, bottom):
+    """Real tensor whose half-spectrum Fourier slices have singular values
+    spaced geometrically from `top` to `bottom` (random unitary factors; the
+    zero and Nyquist bins real, as a real tensor requires)."""
+    h = n3 // 2 + 1
+    r = min(n1, n2)
+    s = np.geomspace(top, bottom, r)
+    spec = np.empty((n1, n2, h), dtype=np.complex128)
+    for k in range(h):
+        real = k == 0 or (n3 % 2 == 0 and k == h - 1)
+
+        def factor(rows):
+            g = rng.normal(size=(rows, r)) + (0 if real else 1j * rng.normal(size=(rows, r)))
+            return np.linalg.qr(g)[0]
+
+        spec[:, :, k] = (factor(n1) * s) @ np.conj(factor(n2)).T
+    return np.fft.irfft(spec, n=n3, axis=2)
+
+
+@pytest.mark.parametrize("tau", [3.0, 1e-5])
+def test_tsvt_fp32_rounding_floor(tau, monkeypatch):
+    """Slices whose singular values run from 1e3 down to 1e-6, far below the
+    FP32 rounding floor sqrt(m) eps32 ||A||_F (about 5e-3 here).  The columns
+    under the floor do not force sweeps of the stopping rule; the result still
+    meets the form's bar against the FP64 oracle (tau = 1e-5 keeps columns
+    that lie under the floor), and so does the plain rule."""
+    torch = torch_cuda()
+    rng = np.random.default_rng(77)
+    x = _graded_tensor(rng, 48, 40, 8, 1e3, 1e-6)
+    z_ref, ranks_ref = tsvt_oracle(x, tau)
+    for floor in ("1", "0"):
+        monkeypatch.setenv("TSVD_SWEEP_FLOOR", floor)
+        announce("tsvt fp32 graded spectrum", tau, "floor", floor)
+        z, ranks = lib.tsvt(to_gpu(torch, x.astype(np.float32)), tau, precision=lib.PREC_FP32)
+        assert_close_fp32(z.cpu().numpy(), z_ref, BAR, f"graded tau {tau} floor {floor}")
+
+
+def test_completion_fp32_rounding_floor_sweeps(monkeypatch):
+    """The video-shaped completion, 160 iterations of the FP32 form with and
+    without the rounding floor of the stopping rule: the floor saves sweeps
+    where the penalty has reached its cap (the singular values then span more
+    than FP32 resolves), and both results stay within the form's bar of the
+    FP64 path, which the FP64 tests pin to the oracle."""
+    torch = torch_cuda()
+    w = workloads.video_completion(0)
+    kw = dict(rho=w["rho"], tol=0.0, growth=w["growth"], rho_max=w["rho_max"], max_iter=160)
+    mask = to_gpu(torch, w["mask"])
+    announce("complete fp64 video 160")
+    x64, _ = lib.tsvd_complete(to_gpu(torch, w["M_obs"].astype(np.float64)), mask, **kw)
+    x64 = x64.cpu().numpy()
+    out = {}
+    for floor in ("1", "0"):
+        monkeypatch.setenv("TSVD_SWEEP_FLOOR", floor)
+        announce("complete fp32 video 160 floor", floor)
+        x, info = lib.tsvd_complete(to_gpu(torch, w["M_obs"]), mask, precision=lib.PREC_FP32, **kw)
+        out[floor] = (x.cpu().numpy().astype(np.float64), info.sweeps_total)
+        assert_close_fp32(out[floor][0], x64, BAR, f"video 160 floor {floor}")
+    print(f"[sweeps] floor {out['1'][1]} plain {out['0'][1]}", flush=True)
+    assert out["1"][1] < 0.85 * out["0"][1]
+    assert rel_fro(out["1"][0], out["0"][0]) < 1e-5
