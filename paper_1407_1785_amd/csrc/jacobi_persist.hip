@@ -69,18 +69,23 @@ __device__ void pload_block(const JacArgs<T>& a, int s, int blk, int mp, int ldc
                                  mp, ldc, lds);
 }
 
-// The blocks blk0 and blk1 (-1: none) into LDS.  FP64: every load in flight
-// before the first LDS store, one memory round trip for both blocks, slice
-// and V rows, instead of one per block and row segment (+2% iterations/s on
-// the video shape).  FP32 keeps the per-block loads: the combined loader
-// raised the kernel's scalar register spills and slowed its step loop by 5%.
-// Thread team c (PG lanes) takes column c of each block, lane t the stacked
-// rows t + PG r: slice rows below m, V rows from mp (the padding rows
-// between stay zero).
+// The blocks blk0 and blk1 (-1: none) into LDS.  Up to 10 rows per lane
+// every load is in flight before the first LDS store, one memory round trip
+// for both blocks, slice and V rows, instead of one per block and row
+// segment, with one address and one predicate per row (a select between
+// the slice and the V part): +2.9% iterations/s in the FP32 form and +4.5%
+// in FP64 on the video shape (9 rows per lane).  Wider columns keep the
+// earlier loaders, which hold fewer registers: FP64 the combined loader with
+// a branch per row segment, FP32 the per-block loads (the combined loaders
+// double the wide FP32 kernels' scalar register spills).  Reading both
+// blocks from LDS before the first store of an exchange was 5% slower, so
+// the stores stay per block.  Thread team c (PG lanes) takes column c of
+// each block, lane t the stacked rows t + PG r: slice rows below m, V rows
+// from mp (the padding rows between stay zero).
 template <typename T, int PG, int RPT>
 __device__ __forceinline__ void pload_pair(const JacArgs<T>& a, int s, int mp, int ldc, int blk0, cplx<T>* lds0,
                                            int blk1, cplx<T>* lds1) {
-    if constexpr (sizeof(T) == 4) {
+    if constexpr (sizeof(T) == 4 && RPT > 10) {
         constexpr int NT = PBW * PG;
         if (blk0 >= 0) pload_block<T, NT>(a, s, blk0, mp, ldc, lds0);
         if (blk1 >= 0) pload_block<T, NT>(a, s, blk1, mp, ldc, lds1);
@@ -96,6 +101,26 @@ __device__ __forceinline__ void pload_pair(const JacArgs<T>& a, int s, int mp, i
         return c < pblk_start(blk + 1, n, a.nb) - c0 ? c0 + c : -1;
     };
     const int col0 = col(blk0), col1 = col(blk1);
+    if constexpr (RPT <= 10) {
+        auto addr = [&](int cl, int R) {
+            return R < m ? A + (int64_t)cl * m + R : V + (int64_t)cl * n + (R - mp);
+        };
+        auto live = [&](int cl, int R) { return cl >= 0 && (R < m || (R >= mp && R - mp < n)); };
+        cplx<T> v0[RPT], v1[RPT];
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            const int R = t + PG * r;
+            if (live(col0, R)) v0[r] = coh_load<T>(addr(col0, R));
+            if (live(col1, R)) v1[r] = coh_load<T>(addr(col1, R));
+        }
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            const int R = t + PG * r;
+            if (live(col0, R)) lds0[c * ldc + R] = v0[r];
+            if (live(col1, R)) lds1[c * ldc + R] = v1[r];
+        }
+        return;
+    }
     cplx<T> v0[RPT], v1[RPT];
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
