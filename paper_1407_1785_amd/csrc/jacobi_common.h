@@ -215,14 +215,17 @@ __device__ __forceinline__ double coh_load_f64(const double* src) {
 }
 
 // The part of a slice's squared Frobenius norm (slice rows) held by the
-// block pair in LDS: per column slot g the squared norms of the two blocks'
-// columns g, added over g in order.  Every thread returns the same value.
-// The Jacobi variants add the parts of a slice's block pairs of round 0 in
-// pair order, so all of them derive the same rounding floor bit for bit.
-// scratch: BW doubles of LDS.
-template <typename T, int PG, int RPT, int BW>
-__device__ __forceinline__ double pair_fro_part(const cplx<T>* blk0, const cplx<T>* blk1, int ldc, int ka,
-                                                double* scratch) {
+// block pair in LDS (widths w0 and w1): per column slot g the squared norms
+// of the two blocks' columns g, added over g in order.  Every thread returns
+// the same value.  The Jacobi variants add the parts of a slice's block
+// pairs of round 0 in pair order, so all of them derive the same rounding
+// floor bit for bit.  Column slots past a block's width are not counted
+// (they may hold an earlier block's column); with ZERO_PAST_WIDTH the caller
+// guarantees that they hold zeros, and every slot is summed (adding an
+// exact 0, so the value is the same).  scratch: BW doubles of LDS.
+template <typename T, int PG, int RPT, int BW, bool ZERO_PAST_WIDTH = false>
+__device__ __forceinline__ double pair_fro_part(const cplx<T>* blk0, const cplx<T>* blk1, int w0, int w1, int ldc,
+                                                int ka, double* scratch) {
     const int g = threadIdx.x / PG, l = threadIdx.x - g * PG;
     cplx<T> c0[RPT], c1[RPT];
 #pragma unroll
@@ -230,7 +233,8 @@ __device__ __forceinline__ double pair_fro_part(const cplx<T>* blk0, const cplx<
         c0[k] = blk0[g * ldc + l + PG * k];
         c1[k] = blk1[g * ldc + l + PG * k];
     }
-    const double part = pnorm2<T, PG, RPT>(c0, ka) + pnorm2<T, PG, RPT>(c1, ka);
+    const double n0 = pnorm2<T, PG, RPT>(c0, ka), n1 = pnorm2<T, PG, RPT>(c1, ka);
+    const double part = ZERO_PAST_WIDTH ? n0 + n1 : (g < w0 ? n0 : 0.0) + (g < w1 ? n1 : 0.0);
     if (l == 0) scratch[g] = part;
     __syncthreads();
     double sum = 0.0;

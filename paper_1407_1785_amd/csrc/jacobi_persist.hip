@@ -293,7 +293,8 @@ __global__ __launch_bounds__(PBW * PG) void jacobi_persistent_kernel(JacArgs<T> 
     bool home0 = true, home1 = true;
     double floor2 = 0.0;   // rounding floor of rot_forces_sweep
     if (p.floor_scale > 0.0) {
-        const double part = pair_fro_part<T, PG, RPT, PBW>(blk0, blk1, ldc, ka, inorm);
+        // the slots past a block's width were zeroed before the first load
+        const double part = pair_fro_part<T, PG, RPT, PBW, true>(blk0, blk1, PBW, PBW, ldc, ka, inorm);
         if (threadIdx.x == 0) coh_store_f64(p.fro + (int64_t)s * G + wg, part);
         arrivals += G;
         if (!slice_barrier(counter, arrivals, err, p.spin_limit)) {

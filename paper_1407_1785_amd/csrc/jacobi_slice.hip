@@ -181,13 +181,16 @@ __global__ __launch_bounds__(BW * kPGs) void jacobi_slice_kernel(const JacSliceA
     if (a.floor_scale > 0.0) {
         double fro2 = 0.0;
         for (int gp = 0; gp < G; ++gp) {
+            const int p0 = ppos_player(gp, 0, nb), p1 = ppos_player(nb - 1 - gp, 0, nb);
             if (G > 1) {
                 __syncthreads();
-                load_block<T, NT, BW>(A, V, m, n, nb, ppos_player(gp, 0, nb), mp, ldc, blk0);
-                load_block<T, NT, BW>(A, V, m, n, nb, ppos_player(nb - 1 - gp, 0, nb), mp, ldc, blk1);
+                load_block<T, NT, BW>(A, V, m, n, nb, p0, mp, ldc, blk0);
+                load_block<T, NT, BW>(A, V, m, n, nb, p1, mp, ldc, blk1);
             }
             __syncthreads();
-            fro2 += pair_fro_part<T, PG, RPT, BW>(blk0, blk1, ldc, ka, jnorm);
+            fro2 += pair_fro_part<T, PG, RPT, BW>(blk0, blk1, pblk_start(p0 + 1, n, nb) - pblk_start(p0, n, nb),
+                                                  pblk_start(p1 + 1, n, nb) - pblk_start(p1, n, nb), ldc, ka,
+                                                  jnorm);
         }
         floor2 = a.floor_scale * fro2;
     }
@@ -333,7 +336,9 @@ __global__ __launch_bounds__(BW * kPGs) void jacobi_pairs_kernel(const JacSliceA
     double floor2 = 0.0;
     if (a.floor_scale > 0.0) {
         __shared__ double fro_s;
-        const double part = pair_fro_part<T, PG, RPT, BW>(blk0, blk1, ldc, ka, jnorm);
+        const double part = pair_fro_part<T, PG, RPT, BW>(
+            blk0, blk1, pblk_start(player0 + 1, n, nb) - pblk_start(player0, n, nb),
+            pblk_start(player1 + 1, n, nb) - pblk_start(player1, n, nb), ldc, ka, jnorm);
         if (threadIdx.x == 0) coh_store_f64(a.fro + (int64_t)s * G + gp, part);
         arrivals += G;
         if (!pairs_barrier(counter, arrivals, err, spin_limit)) {
