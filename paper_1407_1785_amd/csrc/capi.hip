@@ -955,7 +955,8 @@ void do_complete(tsvd_handle h, const void* X_obs, const uint8_t* mask, tsvd_sha
         upload_fallback<T>(h, g, sb, s.max_sweeps);
         WarmState warm;
         warm.enabled = env_int("TSVD_WARM", 1) != 0;
-        warm.reorth_every = env_int("TSVD_REORTH_EVERY", sizeof(T) == 4 ? 1 : 4);
+        // one Newton-Schulz refresh of V every 2 iterations in the FP32 form, every 4 in FP64
+        warm.reorth_every = env_int("TSVD_REORTH_EVERY", sizeof(T) == 4 ? 2 : 4);
         if (load) {
             copy_d2d(Zb[0], state->z, N * sizeof(T), st);
             copy_d2d(Qb[0], state->dual, N * sizeof(T), st);
@@ -1103,7 +1104,8 @@ void do_trpca(tsvd_handle h, const void* X, tsvd_shape shape, tsvd_dtype dtype, 
         upload_fallback<T>(h, g, sb, s.max_sweeps);
         WarmState warm;
         warm.enabled = env_int("TSVD_WARM", 1) != 0;
-        warm.reorth_every = env_int("TSVD_REORTH_EVERY", sizeof(T) == 4 ? 1 : 4);
+        // one Newton-Schulz refresh of V every 2 iterations in the FP32 form, every 4 in FP64
+        warm.reorth_every = env_int("TSVD_REORTH_EVERY", sizeof(T) == 4 ? 2 : 4);
         if (load) {
             copy_d2d(Lb[0], state->z, N * sizeof(T), st);
             copy_d2d(Sb[0], state->s, N * sizeof(T), st);
