@@ -90,7 +90,7 @@ size_t svt_bytes(const Geometry& g, int nparts) {
     b += pbar_words(g) * sizeof(int) + 256;
     b += fro_doubles(g) * sizeof(double) + 256;
     b += (int64_t)nparts * kNumPartials * sizeof(double) + 256;
-    b += 4 * sizeof(JacSliceArgs<T>) + 2 * sizeof(int) + 512;
+    b += 8 * sizeof(JacSliceArgs<T>) + 4 * sizeof(int) + 512;
     if (jacobi_tall(g.m, g.n, sizeof(T))) b += jacobi_tall_plan(g.m, g.n, g.h).part_doubles * sizeof(double) + 256;
     return b;
 }
@@ -116,8 +116,8 @@ SvtBuffers<T> carve_svt(Carver& c, const Geometry& g, int nparts) {
     s.nparts = nparts;
     s.tall = jacobi_tall(g.m, g.n, sizeof(T)) ? c.take<double>(jacobi_tall_plan(g.m, g.n, g.h).part_doubles)
                                               : nullptr;
-    s.ftab = c.take<JacSliceArgs<T>>(4);
-    s.fws = c.take<int>(2);
+    s.ftab = c.take<JacSliceArgs<T>>(8);
+    s.fws = c.take<int>(4);
     return s;
 }
 
@@ -152,39 +152,92 @@ void* ensure_host_stage(tsvd_handle h, size_t bytes) {
     return h->host_stage;
 }
 
-// The argument table of the fallback after a persistent Jacobi launch that
-// gave up: the one-workgroup-per-slice kernel on the same slices (work
-// buffer A or Z, V buffer 0 or 1), gated on the persistent kernel's error
-// word.  Uploaded once per call; sets the kernel's LDS limit.
+// How the single-problem drivers run the Jacobi sweeps of a geometry:
+// PERSIST, the persistent kernel (one workgroup per block pair of 16
+// columns, every workgroup resident); PAIRS, the block-pair kernel of the
+// batched form when the persistent grid would exceed the CUs or its blocks
+// the LDS (one workgroup per block pair of bw columns, all sweeps in one
+// launch, roles in ticket order so that more workgroups than CUs are fine);
+// ROUNDS, one launch per round (or the tall kernels).  TSVD_PERSIST=0 and
+// TSVD_PAIRS_SINGLE=0 turn the first two off.
+enum class JacMode { PERSIST, PAIRS, ROUNDS };
+
+struct JacPlan {
+    JacMode mode = JacMode::ROUNDS;
+    int bw = 16;    // block width of the block-pair kernel and of the fallback
+    int rpt = 0;    // rows per lane of the one-workgroup-per-slice / block-pair kernels
+    int nb = 0;     // blocks per slice of the block-pair kernel
+};
+
+template <typename T>
+JacPlan jacobi_plan(tsvd_handle h, const Geometry& g) {
+    JacPlan p;
+    p.rpt = jacobi_slice_rpt(g.m, g.n);
+    if (jacobi_tall(g.m, g.n, sizeof(T))) return p;
+    if (env_int("TSVD_PERSIST", 1) != 0 && jacobi_persistent_fits(g.m, g.n, g.h, sizeof(T), h->cus, h->lds_cap)) {
+        p.mode = JacMode::PERSIST;
+        return p;
+    }
+    if (env_int("TSVD_PAIRS_SINGLE", 1) == 0 || p.rpt > jacobi_slice_max_rpt()) return p;
+    for (int bw : {16, 8, 4}) {
+        if (jacobi_slice_lds(bw, p.rpt, sizeof(T)) + 256 > h->lds_cap) continue;
+        const int nb = jacobi_num_blocks(g.n, bw);
+        if (nb / 2 < 2) break;   // one block pair per slice: nothing to run in parallel
+        p.mode = JacMode::PAIRS;
+        p.bw = bw;
+        p.nb = nb;
+        return p;
+    }
+    return p;
+}
+
+// The argument tables of the Jacobi sweeps that run as one launch, uploaded
+// once per call (with the kernels' LDS limit):
+//  entries 0-3, the fallback after a persistent or block-pair launch that
+//  gave up: the one-workgroup-per-slice kernel on the same slices (work
+//  buffer A or Z, V buffer 0 or 1), gated on the error word at pbar + 4h;
+//  entries 4-7 (PAIRS only), the block-pair kernel on the same buffers.
+// In PAIRS mode the persistent kernel's int words hold the block-pair
+// kernel's: the rotation-flag ring at pbar, the role ticket at pbar + 4h - 1
+// and the error word at pbar + 4h (the fallback's gate), the barrier
+// counters and block flags from pbar + 4h + 1.
 template <typename T>
 void upload_fallback(tsvd_handle h, const Geometry& g, const SvtBuffers<T>& sb, int max_sweeps) {
-    if (!jacobi_persistent_fits(g.m, g.n, g.h, sizeof(T), h->cus, h->lds_cap)) return;
-    JacSliceArgs<T> tab[4];
-    for (int k = 0; k < 4; ++k) {
+    const JacPlan plan = jacobi_plan<T>(h, g);
+    if (plan.mode == JacMode::ROUNDS) return;
+    const bool pairs = plan.mode == JacMode::PAIRS;
+    JacSliceArgs<T> tab[8];
+    for (int k = 0; k < 8; ++k) {
         JacSliceArgs<T>& a = tab[k];
         a = JacSliceArgs<T>{};
-        a.A = k >= 2 ? sb.Z : sb.A;
+        a.A = (k & 2) ? sb.Z : sb.A;
         a.V = sb.V[k & 1];
         a.m = g.m;
         a.n = g.n;
         a.h = g.h;
-        a.nb = jacobi_persistent_blocks(g.n);
+        a.nb = pairs ? plan.nb : jacobi_persistent_blocks(g.n);
         a.tol = (T)jacobi_tol(g.m, sizeof(T));
         a.sweeps = sb.sweeps;
         a.ctrl = h->ctrl;
         a.rotations = h->rot_counter + 1;
         a.max_sweeps = max_sweeps;
         a.floor_scale = jacobi_floor_scale(g.m, sizeof(T));
-        a.only_if = sb.pbar + 4 * g.h;
+        if (k < 4) {
+            a.only_if = sb.pbar + 4 * g.h;
+        } else {
+            a.rot = sb.pbar;
+            a.bar = sb.pbar + 4 * g.h + 1;
+            a.fro = sb.fro;
+        }
     }
-    const int ws[2] = {0, g.h};
+    const int ws[4] = {0, g.h, 0, pairs ? g.h * (plan.nb / 2) : 0};
     char* stage = static_cast<char*>(ensure_host_stage(h, sizeof(tab) + sizeof(ws)));
     std::memcpy(stage, tab, sizeof(tab));
     std::memcpy(stage + sizeof(tab), ws, sizeof(ws));
     hip_check(hipMemcpyAsync(sb.ftab, stage, sizeof(tab), hipMemcpyHostToDevice, h->stream), "hipMemcpyAsync");
     hip_check(hipMemcpyAsync(sb.fws, stage + sizeof(tab), sizeof(ws), hipMemcpyHostToDevice, h->stream),
               "hipMemcpyAsync");
-    hip_check(prepare_jacobi_slice<T>(16, jacobi_slice_rpt(g.m, g.n)), "jacobi fallback attribute");
+    hip_check(prepare_jacobi_slice<T>(plan.bw, plan.rpt), "jacobi fallback attribute");
     hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
 }
 
@@ -392,8 +445,8 @@ SweepStats run_svt(tsvd_handle h, const Geometry& g, const SvtBuffers<T>& sb, in
     SweepStats stats;
     const double pair_flops = 28.0 * g.m + 20.0 * g.n;
     const double slice_pairs = 0.5 * g.n * (g.n - 1.0);
-    const bool persist = env_int("TSVD_PERSIST", 1) != 0 &&
-                         jacobi_persistent_fits(g.m, g.n, g.h, sizeof(T), h->cus, h->lds_cap);
+    const JacPlan plan = jacobi_plan<T>(h, g);
+    const bool persist = plan.mode == JacMode::PERSIST;
     bool done_persist = false;
     if (persist) {
         // one launch runs every sweep
@@ -422,7 +475,7 @@ SweepStats run_svt(tsvd_handle h, const Geometry& g, const SvtBuffers<T>& sb, in
                                    [&] { e = launch_jacobi_persistent(ja, pa, h->cus, st); });
         if (e == hipSuccess) {
             // finishes the SVD only if a wait of the persistent launch gave up
-            hip_check(launch_jacobi_slice<T>(16, jacobi_slice_rpt(g.m, g.n), sb.ftab + (work == sb.Z ? 2 : 0) + vc,
+            hip_check(launch_jacobi_slice<T>(plan.bw, plan.rpt, sb.ftab + (work == sb.Z ? 2 : 0) + vc,
                                              sb.fws, 1, g.h, max_sweeps, st),
                       "jacobi fallback");
         }
@@ -456,6 +509,51 @@ SweepStats run_svt(tsvd_handle h, const Geometry& g, const SvtBuffers<T>& sb, in
                 h->ev_pool.push_back(h->pending[ip].b);
                 h->pending.erase(h->pending.begin() + ip);
             }
+        }
+    }
+    if (plan.mode == JacMode::PAIRS) {
+        // one launch runs every sweep, one workgroup per block pair; the init
+        // clears the rotation-flag ring, the role ticket, the barrier counters
+        // and the block flags (the error word is cleared once per call)
+        ja.nb = plan.nb;
+        ja.rotations = h->rot_counter + 1;
+        ja.clr[0] = sb.pbar;
+        ja.nclr[0] = 4 * g.h;
+        ja.clr[1] = sb.pbar + 4 * g.h + 1;
+        ja.nclr[1] = g.h * (1 + plan.nb);
+        prof_launch(h, K_JAC_INIT, (double)g.h * g.n * g.n * sizeof(cplx<T>),
+                    [&] { launch_jacobi_init(ja, st); });
+        launch_check("jacobi_init");
+        ja.clr[0] = ja.clr[1] = nullptr;
+        const int entry = (work == sb.Z ? 2 : 0) + vc;
+        const int spin = std::max(0, env_int("TSVD_PERSIST_SPIN", 1 << 21));
+        const int ip = prof_launch(h, K_JAC_PERSIST, 0.0, [&] {
+            hip_check(launch_jacobi_pairs<T>(plan.bw, plan.rpt, sb.ftab + 4 + entry, sb.fws + 2, 1,
+                                             g.h * (plan.nb / 2), sb.pbar + 4 * g.h - 1, spin, st),
+                      "jacobi block pairs");
+        });
+        // finishes the SVD only if a wait between the workgroups gave up
+        hip_check(launch_jacobi_slice<T>(plan.bw, plan.rpt, sb.ftab + entry, sb.fws, 1, g.h, max_sweeps, st),
+                  "jacobi fallback");
+        done_persist = true;
+        stats.sweeps = -1;   // known on the device only
+        stats.on_device = true;
+        if (h->prof_on) {
+            hip_check(hipMemcpyAsync(h->host_ints, sb.sweeps, sizeof(int) * g.h, hipMemcpyDeviceToHost, st),
+                      "hipMemcpyAsync sweeps");
+            hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+            int64_t sw = 0;
+            int smax = 0;
+            for (int s = 0; s < g.h; ++s) {
+                sw += h->host_ints[s];
+                smax = std::max(smax, h->host_ints[s]);
+            }
+            if (ip >= 0) {
+                h->pending[ip].work = pair_flops * slice_pairs * (double)sw;
+                h->pending[ip].sweeps = (double)sw;
+                h->pending[ip].pairs = slice_pairs * (double)sw;
+            }
+            stats.sweeps = smax;
         }
     }
     if (!done_persist && sb.tall) {

@@ -128,3 +128,38 @@ def test_persistent_jacobi_fallback(monkeypatch):
     announce("persistent fallback completion")
     xo, _ = lib.tsvd_complete(to_gpu(torch, w["M_obs"]), to_gpu(torch, w["mask"]), 1e-2, 0.0, max_iter=6)
     assert rel_fro(xo.cpu().numpy(), ref["X"]) <= 1e-10
+
+
+@pytest.mark.parametrize("schedule", ["pairs", "rounds", "pairs-fallback"])
+def test_jacobi_schedule_when_persistent_grid_exceeds_cus(schedule, monkeypatch):
+    """251 Fourier slices of 40 x 36: the persistent Jacobi would need 502
+    co-resident workgroups, more than the CUs, so the single-problem drivers
+    take the block-pair kernel (one workgroup per block pair, roles in ticket
+    order, all sweeps in one launch); TSVD_PAIRS_SINGLE=0 takes one launch
+    per round instead; a spin limit of zero makes every wait between the
+    block-pair workgroups give up, and the gated one-workgroup-per-slice
+    kernel finishes the SVDs.  Each against the oracle: t-SVT in FP64 and in
+    the FP32 form, and 8 completion iterations (warm-started SVDs)."""
+    torch = torch_cuda()
+    if schedule == "rounds":
+        monkeypatch.setenv("TSVD_PAIRS_SINGLE", "0")
+    if schedule == "pairs-fallback":
+        monkeypatch.setenv("TSVD_PERSIST_SPIN", "0")
+    rng = np.random.default_rng(251)
+    x = rng.normal(size=(40, 36, 500))
+    z_ref, r_ref = tsvt_oracle(x, 6.0)
+    announce("many-slice tsvt fp64", schedule)
+    z, ranks = lib.tsvt(to_gpu(torch, x), 6.0)
+    assert rel_fro(z.cpu().numpy(), z_ref) <= 1e-10 and ranks == list(r_ref)
+    announce("many-slice tsvt fp32", schedule)
+    z32, _ = lib.tsvt(to_gpu(torch, x.astype(np.float32)), 6.0, precision=lib.PREC_FP32)
+    assert rel_fro(z32.cpu().numpy().astype(np.float64), z_ref) <= 1e-4
+    a = rng.normal(size=(40, 3, 500))
+    b = rng.normal(size=(3, 36, 500))
+    m = np.real(np.fft.ifft(np.einsum("ikt,kjt->ijt", np.fft.fft(a, axis=2), np.fft.fft(b, axis=2)), axis=2))
+    mask = (rng.random(m.shape) < 0.5).astype(np.uint8)
+    ref = admm.complete(m * mask, mask, 1e-2, 1.1, 1e3, max_iter=8, tol=0.0)
+    announce("many-slice completion", schedule)
+    xo, info = lib.tsvd_complete(to_gpu(torch, m * mask), to_gpu(torch, mask), 1e-2, 0.0, max_iter=8)
+    assert info.iters == 8
+    assert rel_fro(xo.cpu().numpy(), ref["X"]) <= 1e-10
