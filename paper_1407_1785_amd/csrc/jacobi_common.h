@@ -423,6 +423,48 @@ __device__ __forceinline__ void load_block(const cplx<T>* A, const cplx<T>* V, i
     }
 }
 
+// Block blk into LDS with all of a lane's loads in flight before its first
+// LDS store (one memory round trip per block): pair group c (PG lanes) takes
+// column c, lane t the stacked rows t + PG r (slice rows below m, V rows
+// from mp), one address and one predicate per row.  The FP32 block-pair
+// kernel takes its incoming blocks with it between rounds (the 64-problem
+// batch 3% faster than with the per-segment copies); in FP64 the unrolled
+// rows take too many registers, and in the one-workgroup-per-slice kernel
+// it brought no clear gain for many more scalar spills.
+template <typename T, int PG, int RPT, bool COH>
+__device__ __forceinline__ void load_block_rows(const cplx<T>* A, const cplx<T>* V, int m, int n, int nb, int blk,
+                                                int mp, int ldc, cplx<T>* lds) {
+    const int c = threadIdx.x / PG, t = threadIdx.x - c * PG;
+    const int c0 = pblk_start(blk, n, nb);
+    const int col = c < pblk_start(blk + 1, n, nb) - c0 ? c0 + c : -1;
+    cplx<T> v[RPT];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        const int R = t + PG * r;
+        if (col >= 0 && (R < m || (R >= mp && R - mp < n))) {
+            const cplx<T>* p = R < m ? A + (int64_t)col * m + R : V + (int64_t)col * n + (R - mp);
+            if constexpr (COH) v[r] = coh_load<T>(p);
+            else v[r] = *p;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        const int R = t + PG * r;
+        if (col >= 0 && (R < m || (R >= mp && R - mp < n))) lds[c * ldc + R] = v[r];
+    }
+}
+
+// Block blk into LDS: load_block_rows in FP32, the per-segment copies
+// (load_block) in FP64.
+template <typename T, int PG, int RPT, int BW, bool COH = false>
+__device__ __forceinline__ void load_block_any(const cplx<T>* A, const cplx<T>* V, int m, int n, int nb, int blk,
+                                               int mp, int ldc, cplx<T>* lds) {
+    if constexpr (sizeof(T) == 4)
+        load_block_rows<T, PG, RPT, COH>(A, V, m, n, nb, blk, mp, ldc, lds);
+    else
+        load_block<T, BW * PG, BW, COH>(A, V, m, n, nb, blk, mp, ldc, lds);
+}
+
 template <typename T, int NT, int BW, bool COH = false>
 __device__ __forceinline__ void store_block(cplx<T>* A, cplx<T>* V, int m, int n, int nb, int blk, int mp,
                                             int ldc, const cplx<T>* lds) {

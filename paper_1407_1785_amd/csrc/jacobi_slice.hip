@@ -414,8 +414,9 @@ __global__ __launch_bounds__(BW * kPGs) void jacobi_pairs_kernel(const JacSliceA
                     break;
                 }
             }
-            if (next0 != player0) load_block<T, NT, BW, true>(A, V, m, n, nb, next0, mp, ldc, blk0);
-            if (next1 != player1) load_block<T, NT, BW, true>(A, V, m, n, nb, next1, mp, ldc, blk1);
+            // the incoming blocks: one memory round trip per block in FP32
+            if (next0 != player0) load_block_any<T, PG, RPT, BW, true>(A, V, m, n, nb, next0, mp, ldc, blk0);
+            if (next1 != player1) load_block_any<T, PG, RPT, BW, true>(A, V, m, n, nb, next1, mp, ldc, blk1);
             player0 = next0;
             player1 = next1;
             __syncthreads();
