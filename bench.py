@@ -24,7 +24,7 @@ stream, HBM traffic from the committed counter record while its source
 digest matches), the DFT passes' HBM fraction and the rebuild's matrix-core
 fraction at the kept rank, and the batched, serving, full-size RPCA,
 compression, sampling-sweep and tube-RPCA legs.  `--gpus N` with N > 1
-exits with a message: this build runs on one GPU.
+exits with a message: the library runs on one GPU.
 """
 
 from __future__ import annotations
@@ -76,7 +76,7 @@ def roofline(stats: dict, fp32: bool, m: int, n: int):
     per-slice sweep counts the library records; the figure that counts only
     what was applied (16 m per visited pair, 16 (m + n) per applied rotation)
     is given beside it.  Peaks: FP32 vector 157.3 TFLOP/s (packed two-wide
-    FMAs), 78.6 without packing (what this build emits), FP64 78.6."""
+    FMAs), 78.6 without packing (what these kernels are compiled to), FP64 78.6."""
     name, st = max(stats.items(), key=lambda kv: kv[1]["total_ms"])
     secs = st["total_ms"] * 1e-3
     launches = max(1, st["launches"])
@@ -603,7 +603,7 @@ def main() -> int:
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
               "(independent problems would shard with no communication).", file=sys.stderr)
         return 2
 

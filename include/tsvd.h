@@ -54,7 +54,7 @@ typedef enum {
     TSVD_E_NOMEM = -3,     /* workspace does not fit the handle's budget    */
     TSVD_E_HIP = -4,       /* a HIP runtime call failed                     */
     TSVD_E_NONFINITE = -5, /* NaN or Inf met in the input or an iterate      */
-    TSVD_E_UNSUPPORTED = -6, /* valid request this build does not serve      */
+    TSVD_E_UNSUPPORTED = -6, /* valid request the library does not serve     */
     TSVD_E_BUSY = -7,      /* tsvd_poll: the problem has not finished yet   */
     TSVD_E_CANCELLED = -8, /* serving: the request was cancelled            */
     TSVD_E_TIMEOUT = -9    /* serving: the request passed its deadline      */
