@@ -57,10 +57,10 @@ inline double jacobi_tol(int m, int elem_bytes) {
 
 // Scale of the stopping rule's rounding floor (rot_forces_sweep): m eps^2 of
 // the element type, so that the floor is sqrt(m) eps ||A||_F for a slice A.
-// TSVD_SWEEP_FLOOR=0 drops the floor (the plain rule).
+// TSVD_SWEEP_FLOOR scales it (0 drops the floor: the plain rule).
 inline double jacobi_floor_scale(int m, int elem_bytes) {
     const double eps = elem_bytes == 4 ? 1.1920928955078125e-07 : 2.220446049250313e-16;
-    return env_int("TSVD_SWEEP_FLOOR", 1) ? (double)m * eps * eps : 0.0;
+    return std::max(0.0, env_double("TSVD_SWEEP_FLOOR", 1.0)) * (double)m * eps * eps;
 }
 
 // Largest supported sizes (LDS staging of the DFT tiles and Jacobi blocks).

@@ -106,18 +106,20 @@ struct InvArgs {
 // sweeps per iteration on the video-shaped FP32 form at the same accuracy.
 constexpr double kSweepMargin = 1.0;
 //
-// Rounding floor.  A column whose squared norm is at most floor2 =
-// m eps^2 ||A||_F^2 (eps of the element type, ||A||_F of the slice, which
-// the rotations leave unchanged) lies at the rounding level of length-m
-// inner products of the slice's entries: its direction relative to the
-// other columns is set by rounding (already the product A V of the warm
-// start moves every column by about eps ||A||_F), so rotations that involve
-// it do not force another sweep (they are still applied).  Leaving such a
-// coupling unresolved moves the thresholded result by O(floor) in norm, the
-// rounding level of the slice itself.  floor2 = 0 keeps the plain rule.
+// Rounding floor.  floor2 = m eps^2 ||A||_F^2 (eps of the element type,
+// ||A||_F of the slice, which the rotations leave unchanged) is the squared
+// rounding level of length-m inner products of the slice's entries: already
+// the product A V of the warm start moves every column by about
+// eps ||A||_F.  Leaving the coupling gamma of two columns unresolved moves
+// the thresholded result by about |gamma| / max(||x||, ||y||) in norm (the
+// rotation angle times the larger column), so a rotation with
+// |gamma|^2 <= floor2 max(alpha, beta) does not force another sweep (it is
+// still applied): what it leaves is at the slice's own rounding level.  By
+// Cauchy-Schwarz this covers every pair with a column under the floor, whose
+// direction is set by rounding.  floor2 = 0 keeps the plain rule.
 __device__ __forceinline__ bool rot_forces_sweep(double al, double be, double g2, double tol,
                                                  double floor2 = 0.0) {
-    return g2 > (kSweepMargin * tol) * al * be && fmin(al, be) > floor2;
+    return g2 > (kSweepMargin * tol) * al * be && g2 > floor2 * fmax(al, be);
 }
 
 template <typename T>
