@@ -590,7 +590,7 @@ def main() -> int:
     ap.add_argument("--serve-rate", type=float, default=50.0)
     ap.add_argument("--serve-window", type=float, default=4.0,
                     help="seconds of arrivals replayed: the first 4 s of the 60-s trace by default, since "
-                         "the trace's 3000 requests at ~5 solves/s would take about ten minutes to drain")
+                         "the trace's 3000 requests at ~12 solves/s would take about four minutes to drain")
     ap.add_argument("--serve-limit", type=float, default=240.0,
                     help="wall-clock limit of a serving window; open requests are then cancelled")
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
@@ -733,7 +733,7 @@ def main() -> int:
         result["serving"] = serving_leg(lib, torch, np, workloads, args.serve_rate, args.serve_window,
                                         args.serve_budget_gb, args.serve_limit)
         result["serving"]["trace_cap"] = (f"first {args.serve_window:g} s of the 60-s trace: at the engine's "
-                                          "capacity the full trace would take about ten minutes to drain")
+                                          "capacity the full trace would take about four minutes to drain")
         cases["serving"] = {"requests": [workloads.serve_request(r)
                                          for r in workloads.arrivals(0, args.serve_rate, args.serve_window)[:6]],
                             "iters": max(1, int(round(result["serving"]["mean_iters"])))}
