@@ -131,10 +131,11 @@ def _graded_tensor(rng, n1, n2, n3, top, bottom):
 @pytest.mark.parametrize("tau", [3.0, 1e-5])
 def test_tsvt_fp32_rounding_floor(tau, monkeypatch):
     """Slices whose singular values run from 1e3 down to 1e-6, far below the
-    FP32 rounding floor sqrt(m) eps32 ||A||_F (about 5e-3 here).  The columns
-    under the floor do not force sweeps of the stopping rule; the result still
-    meets the form's bar against the FP64 oracle (tau = 1e-5 keeps columns
-    that lie under the floor), and so does the plain rule."""
+    FP32 rounding floor sqrt(m) eps32 ||A||_F (about 5e-3 here).  Couplings
+    that move the result by less than the floor (every pair with a column
+    under it among them) do not force sweeps of the stopping rule; the result
+    still meets the form's bar against the FP64 oracle (tau = 1e-5 keeps
+    columns that lie under the floor), and so does the plain rule."""
     torch = torch_cuda()
     rng = np.random.default_rng(77)
     x = _graded_tensor(rng, 48, 40, 8, 1e3, 1e-6)
@@ -148,10 +149,10 @@ def test_tsvt_fp32_rounding_floor(tau, monkeypatch):
 
 def test_completion_fp32_rounding_floor_sweeps(monkeypatch):
     """The video-shaped completion, 160 iterations of the FP32 form with and
-    without the rounding floor of the stopping rule: the floor saves sweeps
-    where the penalty has reached its cap (the singular values then span more
-    than FP32 resolves), and both results stay within the form's bar of the
-    FP64 path, which the FP64 tests pin to the oracle."""
+    without the rounding floor of the stopping rule: the floor saves sweeps,
+    most where the penalty has reached its cap (the singular values then span
+    more than FP32 resolves), and both results stay within the form's bar of
+    the FP64 path, which the FP64 tests pin to the oracle."""
     torch = torch_cuda()
     w = workloads.video_completion(0)
     kw = dict(rho=w["rho"], tol=0.0, growth=w["growth"], rho_max=w["rho_max"], max_iter=160)
@@ -167,5 +168,7 @@ def test_completion_fp32_rounding_floor_sweeps(monkeypatch):
         out[floor] = (x.cpu().numpy().astype(np.float64), info.sweeps_total)
         assert_close_fp32(out[floor][0], x64, BAR, f"video 160 floor {floor}")
     print(f"[sweeps] floor {out['1'][1]} plain {out['0'][1]}", flush=True)
-    assert out["1"][1] < 0.85 * out["0"][1]
+    # the coupling form of the floor: about 0.6 of the plain rule's sweeps here
+    # (a floor on the column norms alone saved a fifth)
+    assert out["1"][1] < 0.75 * out["0"][1]
     assert rel_fro(out["1"][0], out["0"][0]) < 1e-5
