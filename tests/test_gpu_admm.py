@@ -140,3 +140,25 @@ def test_completion_large_slices():
     out, info = lib.tsvd_complete(to_gpu(torch, x * mask), to_gpu(torch, mask), 1e-2, 0.0, max_iter=4)
     assert info.iters == 4
     assert rel_fro(out.cpu().numpy(), ref["X"]) <= TOL
+
+
+def test_fp64_unchanged_by_the_sweep_floor(monkeypatch):
+    """The stopping rule's rounding floor in FP64 lies far below every
+    coupling that moves the video-shaped completion: 60 iterations with and
+    without it run the same sweeps and return the same tensor, bit for bit,
+    and both meet the oracle."""
+    torch = torch_cuda()
+    w = workloads.video_completion(0)
+    kw = dict(rho=w["rho"], tol=0.0, growth=w["growth"], rho_max=w["rho_max"], max_iter=60)
+    ref = admm.complete(w["M_obs"].astype(np.float64), w["mask"], w["rho"], w["growth"], w["rho_max"],
+                        max_iter=60, tol=0.0)
+    obs, mask = to_gpu(torch, w["M_obs"].astype(np.float64)), to_gpu(torch, w["mask"])
+    out = {}
+    for floor in ("1", "0"):
+        monkeypatch.setenv("TSVD_SWEEP_FLOOR", floor)
+        announce("complete fp64 video 60 floor", floor)
+        x, info = lib.tsvd_complete(obs, mask, **kw)
+        out[floor] = (x.cpu().numpy(), info.sweeps_total)
+        assert rel_fro(out[floor][0], ref["X"]) <= TOL
+    assert out["1"][1] == out["0"][1]
+    np.testing.assert_array_equal(out["1"][0], out["0"][0])
